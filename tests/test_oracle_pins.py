@@ -1,0 +1,424 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, invariants stated in the paper, a library routine, an independent
+sequential loop, or finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special
+import torch
+
+import scenegen
+from oracle import render4d as O
+
+F64 = torch.float64
+
+
+def rand_quats(rng, n):
+    q = rng.normal(size=(n, 4))
+    return torch.as_tensor(q / np.linalg.norm(q, axis=1, keepdims=True))
+
+
+def hamilton(p, q):
+    """Quaternion product in scalar/vector form: (s1,v1)(s2,v2) =
+    (s1 s2 - v1.v2, s1 v2 + s2 v1 + v1 x v2)."""
+    s1, v1 = p[..., 0], p[..., 1:]
+    s2, v2 = q[..., 0], q[..., 1:]
+    s = s1 * s2 - (v1 * v2).sum(-1)
+    v = s1[..., None] * v2 + s2[..., None] * v1 + torch.cross(v1, v2, dim=-1)
+    return torch.cat([s[..., None], v], -1)
+
+
+# --- Sec. 3.2: 4D rotation from a left and a right isoclinic rotation --------
+def test_rotation_orthonormal_det_one():
+    rng = np.random.default_rng(0)
+    ql, qr = rand_quats(rng, 256), rand_quats(rng, 256)
+    R = O.rotation_4d(ql, qr)
+    eye = torch.eye(4, dtype=F64).expand(256, 4, 4)
+    assert torch.allclose(R.transpose(-1, -2) @ R, eye, atol=1e-14)
+    assert torch.allclose(torch.linalg.det(R), torch.ones(256, dtype=F64), atol=1e-13)
+
+
+def test_left_right_commute_and_hamilton_form():
+    rng = np.random.default_rng(1)
+    ql, qr = rand_quats(rng, 64), rand_quats(rng, 64)
+    L, Rr = O.left_isoclinic(ql), O.right_isoclinic(qr)
+    assert torch.allclose(L @ Rr, Rr @ L, atol=1e-14)
+    v = torch.as_tensor(rng.normal(size=(64, 4)))
+    rv = (O.rotation_4d(ql, qr) @ v[..., None])[..., 0]
+    ref = hamilton(hamilton(ql, v), qr)        # R v = q_l * v * q_r
+    assert torch.allclose(rv, ref, atol=1e-14)
+
+
+def test_identity_quaternions_give_identity():
+    one = torch.tensor([[1.0, 0.0, 0.0, 0.0]], dtype=F64)
+    assert torch.equal(O.rotation_4d(one, one)[0], torch.eye(4, dtype=F64))
+
+
+def test_unnormalised_quaternions_are_normalised():
+    rng = np.random.default_rng(2)
+    ql, qr = rand_quats(rng, 8), rand_quats(rng, 8)
+    a = O.rotation_4d(ql, qr)
+    b = O.rotation_4d(3.7 * ql, 0.2 * qr)
+    assert torch.allclose(a, b, atol=1e-14)
+
+
+# --- Sec. 3.2: Sigma = R S S^T R^T -----------------------------------------------
+def test_covariance_eigenvalues_are_squared_scales():
+    rng = np.random.default_rng(3)
+    ls = torch.as_tensor(rng.normal(-1.0, 0.5, size=(32, 4)))
+    cov = O.covariance_4d(ls, rand_quats(rng, 32), rand_quats(rng, 32))
+    assert torch.allclose(cov, cov.transpose(-1, -2), atol=1e-15)
+    ev = np.linalg.eigvalsh(cov.numpy())
+    ref = np.sort(np.exp(2 * ls.numpy()), axis=1)
+    assert np.allclose(ev, ref, rtol=1e-12)
+
+
+# --- Sec. 3.2 conditional Gaussian; Appendix B factorisation --------------------
+def _random_gauss(seed, n=64):
+    rng = np.random.default_rng(seed)
+    ls = torch.as_tensor(rng.normal(-1.0, 0.6, size=(n, 4)))
+    ql, qr = rand_quats(rng, n), rand_quats(rng, n)
+    cov = O.covariance_4d(ls, ql, qr)
+    mean = torch.as_tensor(rng.normal(size=(n, 4)))
+    return rng, ls, ql, qr, cov, mean
+
+
+def test_conditional_covariance_is_precision_block_inverse():
+    """Sigma_xyz|t equals the inverse of the xyz block of the precision
+    R diag(s^-2) R^T (an independent route to the Schur complement)."""
+    rng, ls, ql, qr, cov, mean = _random_gauss(4)
+    _, cov_c = O.slice_at(mean, cov, 0.3)
+    R = O.rotation_4d(ql, qr)
+    prec = R @ torch.diag_embed(torch.exp(-2 * ls)) @ R.transpose(-1, -2)
+    ref = torch.linalg.inv(prec[:, :3, :3])
+    assert torch.allclose(cov_c, ref, rtol=1e-10, atol=1e-13)
+    assert (torch.linalg.eigvalsh(cov_c) > 0).all()
+
+
+def test_determinant_factorisation():
+    """det Sigma = Sigma_44 det Sigma_xyz|t = prod s_k^2 (Appendix B)."""
+    rng, ls, ql, qr, cov, mean = _random_gauss(5)
+    _, cov_c = O.slice_at(mean, cov, -0.7)
+    lhs = torch.linalg.det(cov)
+    mid = cov[:, 3, 3] * torch.linalg.det(cov_c)
+    ref = torch.exp(2 * ls.sum(-1))
+    assert torch.allclose(lhs, ref, rtol=1e-10)
+    assert torch.allclose(mid, ref, rtol=1e-10)
+
+
+def test_exponent_factorisation():
+    """p(x,t) = p(t) p(x|t) for the unnormalised Gaussian (Appendix B)."""
+    rng, ls, ql, qr, cov, mean = _random_gauss(6)
+    t = torch.as_tensor(rng.normal(size=64))
+    xyz = torch.as_tensor(rng.normal(size=(64, 3)))
+    lhs_vec = torch.cat([xyz, t[:, None]], 1) - mean
+    lhs = (lhs_vec[:, None, :] @ torch.linalg.inv(cov) @ lhs_vec[:, :, None])[:, 0, 0]
+    rhs = torch.empty(64, dtype=F64)
+    for i in range(64):
+        mu_c, cov_c = O.slice_at(mean[i:i + 1], cov[i:i + 1], float(t[i]))
+        d = xyz[i] - mu_c[0]
+        rhs[i] = (t[i] - mean[i, 3]) ** 2 / cov[i, 3, 3] + d @ torch.linalg.inv(cov_c[0]) @ d
+    assert torch.allclose(lhs, rhs, rtol=1e-10)
+
+
+def test_conditional_mean_linear_in_t():
+    rng, ls, ql, qr, cov, mean = _random_gauss(7)
+    mu0, _ = O.slice_at(mean, cov, 0.0)
+    mu1, _ = O.slice_at(mean, cov, 1.0)
+    mu_half, c_half = O.slice_at(mean, cov, 0.5)
+    assert torch.allclose(mu_half, 0.5 * (mu0 + mu1), atol=1e-13)
+    at_mean = torch.stack([O.slice_at(mean[i:i + 1], cov[i:i + 1], float(mean[i, 3]))[0][0] for i in range(8)])
+    assert torch.allclose(at_mean, mean[:8, :3], atol=1e-14)
+    vel = cov[:, :3, 3] / cov[:, 3, 3:4]
+    assert torch.allclose(mu1 - mu0, vel, atol=1e-13)
+
+
+def test_block_diagonal_case_is_static_3d():
+    """With identity rotations space and time decouple: the slice is the
+    static 3D Gaussian at every t and only p(t) varies (the independent
+    space-time baseline of Sec. 3.2)."""
+    one = torch.tensor([[1.0, 0.0, 0.0, 0.0]], dtype=F64)
+    ls = torch.tensor([[-1.0, -0.5, -2.0, -1.5]], dtype=F64)
+    cov = O.covariance_4d(ls, one, one)
+    mean = torch.tensor([[0.1, 0.2, 0.3, 0.4]], dtype=F64)
+    for t in (-1.0, 0.4, 2.0):
+        mu_c, cov_c = O.slice_at(mean, cov, t)
+        assert torch.allclose(mu_c, mean[:, :3], atol=0)
+        assert torch.allclose(cov_c[0], torch.diag(torch.exp(2 * ls[0, :3])), atol=1e-15)
+        pt = O.temporal_marginal(mean[:, 3], cov[:, 3, 3], t)
+        assert torch.allclose(pt, torch.exp(-0.5 * (t - 0.4) ** 2 / torch.exp(2 * ls[:, 3])), rtol=1e-14)
+
+
+def test_time_axis_fixing_pair_gives_block_rotation():
+    """q_r = -k conj(q_l) k gives R = diag(R3, 1): S_xt = 0 for any scales."""
+    rng = np.random.default_rng(8)
+    ql = rand_quats(rng, 16)
+    k = torch.tensor([0.0, 0.0, 0.0, 1.0], dtype=F64).expand(16, 4)
+    conj = ql * torch.tensor([1.0, -1.0, -1.0, -1.0], dtype=F64)
+    qr = -hamilton(hamilton(k, conj), k)
+    R = O.rotation_4d(ql, qr)
+    assert torch.allclose(R[:, 3, :3], torch.zeros(16, 3, dtype=F64), atol=1e-14)
+    assert torch.allclose(R[:, :3, 3], torch.zeros(16, 3, dtype=F64), atol=1e-14)
+    assert torch.allclose(R[:, 3, 3], torch.ones(16, dtype=F64), atol=1e-14)
+    ls = torch.as_tensor(rng.normal(-1, 0.5, size=(16, 4)))
+    cov = O.covariance_4d(ls, ql, qr)
+    assert torch.allclose(cov[:, :3, 3], torch.zeros(16, 3, dtype=F64), atol=1e-15)
+
+
+# --- Sec. 3.2 marginal p(t); Sec. 4.2 temporal filter ------------------------------
+def test_marginal_integrates_to_one_when_normalised():
+    mu, var = 0.3, 0.02 ** 2
+    t = np.linspace(mu - 1, mu + 1, 200001)
+    pt = O.temporal_marginal(torch.tensor(mu, dtype=F64), torch.tensor(var, dtype=F64),
+                             torch.as_tensor(t)).numpy()
+    integral = np.trapezoid(pt, t) / math.sqrt(2 * math.pi * var)
+    assert abs(integral - 1.0) < 1e-9
+    assert float(O.temporal_marginal(torch.tensor(mu, dtype=F64), torch.tensor(var, dtype=F64), mu)) == 1.0
+
+
+def test_temporal_filter_threshold_closed_form():
+    """Kept iff |t - mu_t| <= sigma_t sqrt(2 ln 20)."""
+    sc = scenegen.random_scene(9, 1)
+    sc.q_left[:] = [1, 0, 0, 0]
+    sc.q_right[:] = [1, 0, 0, 0]
+    sc.means4[0] = [0.0, 0.0, 0.0, 0.5]
+    sc.log_scales4[0] = [-2.0, -2.0, -2.0, math.log(0.1)]
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 32, 32)
+    lim = 0.1 * math.sqrt(2 * math.log(20.0))
+    for dt, keep in ((lim * 0.999, True), (lim * 1.001, False), (-lim * 0.999, True), (-lim * 1.001, False)):
+        pre = O.preprocess(O.params_from_scene(sc), O.to_ocamera(cam), 0.5 + dt, 1, 1)
+        assert bool(pre["active"][0]) == keep
+
+
+# --- Sec. 3.2 4D spherindrical harmonics ------------------------------------------
+def test_real_sh_matches_scipy_complex_harmonics():
+    rng = np.random.default_rng(10)
+    d = rng.normal(size=(200, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    theta = np.arccos(np.clip(d[:, 2], -1, 1))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    ours = O.real_sh(torch.as_tensor(d), 3).numpy()
+    for l in range(4):
+        for m in range(-l, l + 1):
+            ylm = scipy.special.sph_harm_y(l, abs(m), theta, phi)   # Condon-Shortley phase included
+            if m == 0:
+                ref = ylm.real
+            elif m > 0:
+                ref = math.sqrt(2) * ylm.real
+            else:
+                ref = math.sqrt(2) * ylm.imag
+            assert np.allclose(ours[:, l * l + l + m], ref, atol=1e-13), (l, m)
+
+
+def test_real_sh_low_degree_closed_forms():
+    d = torch.tensor([[0.48, -0.6, 0.64]], dtype=F64)
+    y = O.real_sh(d, 1)[0]
+    c0 = 0.5 / math.sqrt(math.pi)
+    c1 = math.sqrt(3.0 / (4 * math.pi))
+    ref = torch.tensor([c0, -c1 * -0.6, c1 * 0.64, -c1 * 0.48], dtype=F64)
+    assert torch.allclose(y, ref, atol=1e-15)
+
+
+def test_real_sh_orthonormal_by_quadrature():
+    """Gauss-Legendre in cos(theta) x uniform in phi integrates degree <= 6
+    products exactly."""
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    z = np.repeat(xg, nphi)
+    w = np.repeat(wg, nphi) * (2 * np.pi / nphi)
+    ph = np.tile(phi, len(xg))
+    s = np.sqrt(1 - z * z)
+    d = np.stack([s * np.cos(ph), s * np.sin(ph), z], 1)
+    Y = O.real_sh(torch.as_tensor(d), 3).numpy()
+    gram = (Y * w[:, None]).T @ Y
+    assert np.allclose(gram, np.eye(16), atol=1e-12)
+
+
+def test_fourier_terms_orthogonal_over_period():
+    T = 1.0
+    t = (np.arange(4096) + 0.5) / 4096 * T
+    f = O.fourier_cos(torch.as_tensor(t), 2, T).numpy()
+    gram = f.T @ f / len(t)
+    assert np.allclose(gram, np.diag([1.0, 0.5, 0.5]), atol=1e-12)
+
+
+def test_color_order_zero_reduces_to_sh_and_is_even_in_dt():
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=(10, 3))
+    d = torch.as_tensor(d / np.linalg.norm(d, axis=1, keepdims=True))
+    k1 = torch.as_tensor(rng.normal(0, 0.3, size=(10, 4 * 2, 3)))
+    dt = torch.as_tensor(rng.uniform(-1, 1, size=10))
+    c_pos, _ = O.color_4dsh(k1, d, dt, 1, 1, 1.0)
+    c_neg, _ = O.color_4dsh(k1, d, -dt, 1, 1, 1.0)
+    assert torch.allclose(c_pos, c_neg, atol=1e-15)
+    k0 = k1[:, :4]
+    c0, raw0 = O.color_4dsh(k0, d, dt, 1, 0, 1.0)
+    Y = O.real_sh(d, 1)
+    ref = 0.5 + (Y[:, :, None] * k0).sum(1)
+    assert torch.allclose(raw0, ref, atol=1e-15)
+    # the n = 1 term at dt = T/2 flips sign: cos(pi) = -1
+    half = torch.full((10,), 0.5, dtype=F64)
+    _, raw_h = O.color_4dsh(k1, d, half, 1, 1, 1.0)
+    ref_h = 0.5 + (Y[:, :, None] * k1[:, :4]).sum(1) - (Y[:, :, None] * k1[:, 4:]).sum(1)
+    assert torch.allclose(raw_h, ref_h, atol=1e-14)
+
+
+# --- Eqs. (3)-(4): EWA projection ------------------------------------------------
+def test_centred_isotropic_gaussian_projects_to_circle():
+    """A centred isotropic Gaussian at distance D projects to the principal
+    point with sigma_2d^2 = f^2 s^2 / D^2 + 0.3 (low-pass)."""
+    sc = scenegen.random_scene(12, 1)
+    s = 0.05
+    sc.means4[0] = [0, 0, 0, 0.5]
+    sc.log_scales4[0] = [math.log(s)] * 3 + [0.0]
+    sc.q_left[0] = [1, 0, 0, 0]
+    sc.q_right[0] = [1, 0, 0, 0]
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 64, 48)
+    pre = O.preprocess(O.params_from_scene(sc), O.to_ocamera(cam), 0.5, 1, 1)
+    f = cam.fx
+    s = math.exp(float(sc.log_scales4[0, 0]))          # the float32-stored scale
+    var = f * f * s * s / 16.0 + 0.3
+    assert abs(float(pre["u"][0]) - 32.0) < 1e-12 and abs(float(pre["v"][0]) - 24.0) < 1e-12
+    assert torch.allclose(pre["cov2"][0], torch.tensor([var, 0.0, var], dtype=F64), rtol=1e-12, atol=1e-14)
+    assert torch.allclose(pre["conic"][0], torch.tensor([1 / var, 0.0, 1 / var], dtype=F64), rtol=1e-12, atol=1e-14)
+    assert float(pre["radius"][0]) == math.ceil(3 * math.sqrt(var))
+    assert abs(float(pre["z"][0]) - 4.0) < 1e-12
+
+
+# --- Eqs. (5)-(6): compositing ----------------------------------------------------
+def sequential_pixel(px, py, gauss, bg):
+    """Independent front-to-back loop for one pixel over a list of
+    (z, idx, u, v, conic, opac, color, rect) already restricted to the pixel's
+    tile; pure Python scalars."""
+    T, C, D, last = 1.0, [0.0, 0.0, 0.0], 0.0, 0
+    for pos, g in enumerate(sorted(gauss, key=lambda g: (g["z"], g["idx"])), start=1):
+        dx, dy = px - g["u"], py - g["v"]
+        a_, b_, c_ = g["conic"]
+        power = -0.5 * (a_ * dx * dx + c_ * dy * dy) - b_ * dx * dy
+        G = g["opac"] * math.exp(power)
+        alpha = min(0.99, G)
+        if G < 1.0 / 255.0:
+            continue
+        if T * (1.0 - alpha) < 1e-4:
+            break
+        for k in range(3):
+            C[k] += alpha * T * g["color"][k]
+        D += alpha * T * g["z"]
+        T *= 1.0 - alpha
+        last = pos
+    return [C[k] + T * bg[k] for k in range(3)], D, 1.0 - T, T, last
+
+
+@pytest.mark.parametrize("seed,n,spread,grow", [(20, 12, 0.3, 1.0), (21, 40, 1.0, 1.0), (22, 80, 0.3, 1.5)])
+def test_tile_composite_equals_sequential_loop(seed, n, spread, grow):
+    sc = scenegen.random_scene(seed, n, spread=spread, mu_log_t=-1.0)
+    sc.log_scales4[:, :3] += grow         # large splats: overlaps and early stops
+    sc.opacity_logit[:] += 2.0
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 32, 32)
+    bg = (0.1, 0.2, 0.3)
+    out = O.render_full(sc, cam, 0.5, bg=bg, with_flags=False)
+    pre = out["pre"]
+    ocam = O.to_ocamera(cam)
+    rgb = O.assemble(out, cam, "rgb", 3).detach()
+    depth = O.assemble(out, cam, "depth").detach()
+    last = O.assemble(out, cam, "last")
+    stopped = 0
+    for py in range(0, 32, 2):
+        for px in range(0, 32, 2):
+            tx, ty = px // 16, py // 16
+            gauss = []
+            for i in range(n):
+                r = pre["rect"][i]
+                if bool(pre["active"][i]) and r[0] <= tx < r[2] and r[1] <= ty < r[3]:
+                    gauss.append(dict(z=float(pre["z"][i]), idx=i, u=float(pre["u"][i]), v=float(pre["v"][i]),
+                                      conic=[float(c) for c in pre["conic"][i]], opac=float(pre["opac"][i]),
+                                      color=[float(c) for c in pre["color"][i]]))
+            c, d, a, T, lst = sequential_pixel(px + 0.5, py + 0.5, gauss, bg)
+            stopped += T < 1e-3
+            assert np.allclose(rgb[:, py, px].numpy(), c, atol=1e-12)
+            assert abs(float(depth[py, px]) - d) < 1e-12
+            assert int(last[py, px]) == lst
+    if seed == 22:
+        assert stopped > 0     # the early-stop rule was exercised
+
+
+def test_two_gaussian_pixel_by_hand():
+    """Two coincident-axis isotropic Gaussians in front of the camera; the
+    centre pixel's colour follows Eq. (6) written out by hand."""
+    sc = scenegen.random_scene(30, 2, sh_degree=0, t_order=0)
+    sc.q_left[:] = [1, 0, 0, 0]
+    sc.q_right[:] = [1, 0, 0, 0]
+    sc.means4[:] = [[0, 0, 0.5, 0.5], [0, 0, -0.5, 0.7]]   # front one at z_cam = 3.5
+    sc.log_scales4[:] = [[math.log(0.2)] * 3 + [math.log(0.3)]] * 2
+    sc.opacity_logit[:] = [0.0, 1.0]
+    sc.coeffs[:] = 0.0
+    sc.coeffs[0, 0] = [0.4, 0.0, -0.2]
+    sc.coeffs[1, 0] = [0.0, 0.6, 0.2]
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 32, 32)
+    t = 0.5
+    out = O.render_full(sc, cam, t, with_flags=False, tiles=[0, 1, 2, 3])
+    rgb = O.assemble(out, cam, "rgb", 3).detach()
+    f = cam.fx
+    y00 = 0.5 / math.sqrt(math.pi)
+    s2 = math.exp(2 * float(sc.log_scales4[0, 0]))
+    st2 = math.exp(2 * float(sc.log_scales4[0, 3]))
+    def contrib(zc, logit, mu_t, k):
+        var = f * f * s2 / zc ** 2 + 0.3
+        power = -0.5 * (0.5 * 0.5 + 0.5 * 0.5) / var          # pixel (16,16) centre is 0.5 px off
+        pt = math.exp(-0.5 * (t - float(np.float32(mu_t))) ** 2 / st2)
+        a = min(0.99, 1 / (1 + math.exp(-logit)) * pt * math.exp(power))
+        col = [max(0.0, 0.5 + kk * y00) for kk in k]
+        return a, col
+    a1, c1 = contrib(3.5, 0.0, 0.5, [0.4, 0.0, -0.2])
+    a2, c2 = contrib(4.5, 1.0, 0.7, [0.0, 0.6, 0.2])
+    ref = [a1 * c1[i] + a2 * (1 - a1) * c2[i] for i in range(3)]
+    assert np.allclose(rgb[:, 16, 16].numpy(), ref, atol=1e-13)
+
+
+# --- gradients: autograd of the definition vs central finite differences ------------
+def test_gradient_matches_finite_differences():
+    sc = scenegen.random_scene(40, 24, sh_degree=2, t_order=2, spread=0.4, mu_log_t=-1.5)
+    sc.log_scales4[:, :3] += 1.0
+    cam = scenegen.look_at_camera((0.3, 0.2, 3.0), 32, 32)
+    t = 0.45
+    rng = np.random.default_rng(41)
+    dl = torch.as_tensor(rng.normal(size=(3, 32, 32)))
+    dd = torch.as_tensor(rng.normal(size=(32, 32))) * 0.1
+    da = torch.as_tensor(rng.normal(size=(32, 32)))
+
+    def loss_of(params, flags=False):
+        out = O.render_view(params, cam, t, 2, 2, 1.0, with_flags=flags)
+        return O.tile_linear_loss(out, dl, dd, da, cam), out
+
+    params = O.params_from_scene(sc, requires_grad=True)
+    L, out = loss_of(params, flags=True)
+    assert not bool(O.assemble(out, cam, "uncertain_grad").any())
+    L.backward()
+    base = {k: v.detach().clone() for k, v in params.items()}
+    h = 1e-6
+    checked = 0
+    for name in ["means4", "log_scales4", "q_left", "q_right", "opacity_logit", "coeffs"]:
+        flat_idx = rng.choice(base[name].numel(), size=8, replace=False)
+        for fi in flat_idx:
+            vals = []
+            for sgn in (1.0, -1.0):
+                p2 = {k: v.clone() for k, v in base.items()}
+                p2[name].view(-1)[fi] += sgn * h
+                vals.append(float(loss_of(p2)[0]))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            g = float(params[name].grad.view(-1)[fi])
+            assert abs(fd - g) <= 1e-5 * (1 + abs(g)), (name, fi, fd, g)
+            checked += 1
+    assert checked == 48
+
+
+def test_config0_renders_with_no_uncertain_pixels():
+    wl = scenegen.make_workload(0)
+    out = O.render_full(wl.scene, wl.cameras[0], float(wl.times[0]))
+    assert int(out["pre"]["active"].sum()) > 0
+    assert not bool(O.assemble(out, wl.cameras[0], "uncertain").any())
