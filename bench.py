@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of the 4D Gaussian render hot path on one MI355X.
+
+One step = render a batch of (camera, time) views of a 300k-primitive scene
+(1352x1014, SH degree 3 x Fourier order 2), L1 loss against seeded targets,
+and the full backward to every primitive parameter. The batched step renders
+all views in one library call; the per-view step issues one call per view
+(gradients accumulated in place). Inputs are resident in HBM before timing.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+# Algorithmic work per evaluated fragment (one pixel x one list entry up to the
+# pixel's last contributor), counted in FP32 lane operations (an FMA is one):
+#   forward:  offset 2, quadratic form 5, floor test 1, exp 1, clamp 1,
+#             transmittance 1, weight 1, colour+depth accumulation 4      = 16
+#   backward: recompute 10, T recovery 1, weight 1, dL/dalpha 11,
+#             behind-accumulators 5, dL/dpower 2, per-primitive sums 9    = 39
+OPS_FWD = 16
+OPS_BWD = 39
+# FP32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_oracle_baseline(wl, seconds: float):
+    """Times the FP64 oracle (forward + autograd backward) on one view of the
+    workload for two tile-sample sizes; a linear fit over the sample size
+    extrapolates to the full view (fixed cost: preprocessing all primitives)."""
+    import numpy as np
+    import torch
+    from oracle import render4d as O
+
+    cam, t = wl.cameras[0], float(wl.times[0])
+    ocam = O.to_ocamera(cam)
+    n_tiles = ocam.tiles_x * ocam.tiles_y
+    rng = np.random.default_rng(5)
+    order = rng.permutation(n_tiles)
+
+    def run(k):
+        t0 = time.perf_counter()
+        params = O.params_from_scene(wl.scene, requires_grad=True)
+        pre = O.preprocess(params, ocam, t, wl.scene.sh_degree, wl.scene.t_order, wl.scene.t_period)
+        loss = torch.zeros((), dtype=torch.float64)
+        for tid in order[:k]:
+            part = O.composite_tile(pre, ocam, int(tid), (0.0, 0.0, 0.0), with_flags=False)
+            loss = loss + part["rgb"].sum()
+        loss.backward()
+        return time.perf_counter() - t0
+
+    k1 = 2
+    t1 = run(k1)
+    per_tile_guess = max(t1 / 4, 0.05)
+    k2 = int(max(k1 + 4, min(64, (seconds - t1) / (2 * per_tile_guess))))
+    t2 = run(k2)
+    b = max((t2 - t1) / (k2 - k1), 1e-9)
+    a = max(t1 - b * k1, 0.0)
+    full = a + b * n_tiles
+    px = cam.width * cam.height
+    return dict(value=px / full / 1e6, unit="Mpix/s (fwd+bwd, one view, extrapolated)",
+                cores=int(torch.get_num_threads()), kind="oracle",
+                sample=(f"1 of {len(wl.cameras)} views at {cam.width}x{cam.height}, {wl.scene.n} primitives: "
+                        f"FP64 preprocess of all primitives + fwd/bwd of {k1} and {k2} random 16x16 tiles "
+                        f"({t1:.1f}s, {t2:.1f}s); full view = {a:.2f}s + {b:.3f}s x {n_tiles} tiles"),
+                seconds=round(t1 + t2, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-per-view", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by view "
+              f"with one process per GPU, which this build does not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2310_10642_amd import g4d
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"[bench] building workload ({args.views} views)")
+    wl = scenegen.bench_workload(args.views)
+    sc = wl.scene
+    r = g4d.Renderer(sc.sh_degree, sc.t_order, sc.t_period)
+    params = [torch.from_numpy(a).to(dev) for a in (sc.means4, sc.log_scales4, sc.q_left, sc.q_right,
+                                                       sc.opacity_logit, sc.coeffs)]
+    r.set_primitives(*params)
+    cams, times = wl.cameras, [float(x) for x in wl.times]
+    V = len(cams)
+    hw = [(c.height, c.width) for c in cams]
+    P_total = sum(h * w for h, w in hw)
+    target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).to(dev)
+    tgt_v = []
+    o = 0
+    for h, w in hw:
+        tgt_v.append(target[o:o + 3 * h * w])
+        o += 3 * h * w
+    scale = 1.0 / (3 * hw[0][0] * hw[0][1])   # per-view mean L1, summed over views
+    grads = r.grad_buffers(dev)
+    loss = torch.zeros(1, device=dev)
+    dl = torch.empty(3 * P_total, device=dev)
+    dl_v = [torch.empty(3 * h * w, device=dev) for h, w in hw]
+
+    def step_batched():
+        rgb, _, _ = r.render(cams, times, depth=False, alpha=False)
+        r.image_loss(g4d.G4D_LOSS_L1, rgb, target, scale, loss, dl)
+        r.backward(dl, out=grads)
+
+    def step_per_view():
+        for v in range(V):
+            rgb, _, _ = r.render([cams[v]], [times[v]], depth=False, alpha=False)
+            r.image_loss(g4d.G4D_LOSS_L1, rgb, tgt_v[v], scale, loss, dl_v[v])
+            r.backward(dl_v[v], out=grads, accumulate=v > 0)
+
+    def forward_batched():
+        r.render(cams, times, depth=False, alpha=False)
+
+    def forward_per_view():
+        for v in range(V):
+            r.render([cams[v]], [times[v]], depth=False, alpha=False)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    log("[bench] warmup + timed batched fwd+bwd")
+    for _ in range(args.warmup):
+        step_batched()
+    torch.cuda.synchronize()
+    r.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_batched()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    stages = r.stage_times()
+    r.stage_timing(False)
+    stats = r.stats()
+    log(f"[bench] batched step {sec * 1e3:.3f} ms; stages {stages}; stats {stats}")
+
+    fwd_b = timed(forward_batched, max(3, args.steps // 2), 2)
+    extra = {}
+    if not args.no_per_view:
+        log("[bench] per-view comparison")
+        fwd_pv = timed(forward_per_view, max(3, args.steps // 2), 2)
+        step_pv = timed(step_per_view, max(3, args.steps // 2), 2)
+        extra = dict(per_view_fwd_bwd_mpix_per_s=P_total / step_pv / 1e6,
+                     per_view_fwd_bwd_steps_per_s=1.0 / step_pv,
+                     per_view_forward_mpix_per_s=P_total / fwd_pv / 1e6,
+                     batched_over_per_view_fwd_bwd=step_pv / sec)
+
+    # roofline of the dominant stage
+    per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
+    dom = max(per_launch, key=lambda k: per_launch[k])
+    frag = stats["fragments"]
+    if dom in ("raster_bwd", "raster_fwd"):
+        ops = frag * (OPS_BWD if dom == "raster_bwd" else OPS_FWD)
+        achieved = ops / (per_launch[dom] * 1e-3)
+        roof = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=ALU_PEAK_OPS / 1e12,
+                    unit="Tops/s (FP32 lane ops)", frac=achieved / ALU_PEAK_OPS, traffic=None,
+                    ms_per_launch=per_launch[dom], units=frag,
+                    units_name="evaluated fragments (pixel x list entry up to the last contributor)")
+    else:
+        # preprocess / binning: bytes the method must move, per launch
+        A, I, N = stats["active_total"], stats["instances"], sc.n
+        K3 = sc.coeffs.shape[1] * 3
+        if dom == "preprocess":
+            byts = 68 * N + (4 * K3 + 48) * A
+        elif dom == "preprocess_bwd":
+            byts = (68 + 4 * K3) * N * 2 + 48 * A
+        else:
+            byts = 28 * I
+        achieved = byts / (per_launch[dom] * 1e-3)
+        roof = dict(kernel=dom, bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / HBM_PEAK, traffic=None, ms_per_launch=per_launch[dom])
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        torch.set_num_threads(os.cpu_count() or 1)
+        cpu = cpu_oracle_baseline(wl, args.cpu_seconds)
+        log(f"[bench] cpu {cpu}")
+
+    out = {
+        "metric": "Mpix/s render and fwd+bwd steps/s, 300k 4D Gaussians, batched vs per-view",
+        "value": P_total / sec / 1e6,
+        "unit": "Mpix/s (fwd+bwd training step, batched)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "primitives": sc.n, "views": V, "resolution": f"{hw[0][1]}x{hw[0][0]}",
+                   "sh_degree": sc.sh_degree, "t_order": sc.t_order, "loss": "l1", "batched": True},
+        "fwd_bwd_steps_per_s": 1.0 / sec,
+        "forward_mpix_per_s": P_total / fwd_b / 1e6,
+        **extra,
+        "stage_ms_per_step": {k: ms / args.steps for k, (ms, n) in stages.items()},
+        "active_per_view": stats["active_per_view"], "instances": stats["instances"],
+        "fragments": frag, "max_tile_list": stats["max_tile_list"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * g4d.h -- C ABI of the MI355X (gfx950) 4D Gaussian renderer.
+ *
+ * The operation is the rendering routine of "Real-time Photorealistic Dynamic
+ * Scene Representation and Rendering with 4D Gaussian Splatting" (Yang et al.,
+ * ICLR 2024), Sec. 3.2: a pixel (u, v) of view I at time t is
+ *
+ *     I(u,v,t) = sum_i p_i(t) p_i(u,v|t) alpha_i c_i(d,t)
+ *                      prod_{j<i} (1 - p_j(t) p_j(u,v|t) alpha_j)      (Eq. 6)
+ *
+ * where each primitive is a 4D Gaussian with covariance R S S^T R^T,
+ * R = L(q_l) R(q_r) (Sec. 3.2, "Representation of 4D Gaussian"), sliced at t
+ * into a conditional 3D Gaussian weighted by its temporal marginal p_i(t),
+ * projected by EWA splatting (Eqs. 3-4) and coloured by 4D spherindrical
+ * harmonics (Sec. 3.2, "4D spherindrical harmonics"). render_backward returns
+ * the gradient of a scalar loss with respect to every primitive parameter,
+ * given dL/d(image).
+ *
+ * Conventions where the paper is silent (shared as specification, not code,
+ * with the test oracle): unnormalised p(t) with the Sec. 4.2 filter p(t) >= t_cull;
+ * near plane; 0.3 px^2 EWA low-pass; Jacobian evaluated at x/z clamped to 1.3x
+ * the half field of view; footprint radius ceil(3 sqrt(lambda_max)) px; 16x16
+ * tiles, a primitive covers the tiles overlapping [u-r, u+r] x [v-r, v+r];
+ * front-to-back order by camera-space z, ties by primitive index; fragments with
+ * alpha < 1/255 are skipped; alpha is clamped to 0.99; blending stops before a
+ * fragment that would bring the transmittance below 1e-4; pixel centres at +0.5;
+ * colour = max(0, 0.5 + 4DSH sum); real SH orthonormal with the Condon-Shortley
+ * phase, index l*l + l + m; Fourier terms cos(2 pi n (t - mu_t) / T), n = 0..t_order.
+ *
+ * Memory: every tensor pointer is a DEVICE pointer to contiguous float32 data
+ * with 16-byte alignment unless noted. All work is enqueued on the context's
+ * HIP stream. The caller owns every tensor; the context owns only its scratch.
+ *
+ * Errors: every entry point returns a g4d_status. Argument validation happens
+ * before any HIP call. G4D_EHIP is sticky for the context (destroy it).
+ * On error the outputs are undefined. g4d_last_error() gives a message.
+ *
+ * Threading: a context is not thread-safe; use one context per host thread.
+ */
+#ifndef G4D_H
+#define G4D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t g4d_status;
+enum {
+  G4D_OK = 0,
+  G4D_EINVAL = -1,     /* bad argument */
+  G4D_ENOMEM = -2,     /* device allocation failed */
+  G4D_EHIP = -3,       /* a HIP call failed (sticky) */
+  G4D_ESTATE = -4,     /* call out of order, e.g. backward without a render */
+  G4D_ECAPACITY = -5   /* a size exceeds a fixed limit of the library */
+};
+
+typedef struct g4d_ctx g4d_ctx;
+
+/* Rendering options, fixed for the life of a context. */
+typedef struct {
+  int32_t sh_degree;   /* spatial SH degree L, 0..3 */
+  int32_t t_order;     /* Fourier order N_t, 0..2 (terms n = 0..N_t) */
+  float t_period;      /* Fourier period T (> 0); 1 = normalised duration */
+  float t_cull;        /* temporal filter: keep iff exp(-(t-mu_t)^2/(2 Sigma_44)) >= t_cull (Sec. 4.2: 0.05) */
+  float near_plane;    /* keep iff camera-space z > near_plane (0.2) */
+  float bg[3];         /* background colour composited with the final transmittance */
+} g4d_options;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward). Host struct. */
+typedef struct {
+  int32_t width, height;     /* pixels, 1..16384 */
+  float fx, fy, cx, cy;      /* intrinsics K (Eq. 3), pixels */
+  float world_to_cam[12];    /* extrinsic E, row-major 3x4 [R | t]: x_cam = R x_world + t */
+  float center[3];           /* camera position in world frame (for the view direction d) */
+} g4d_camera;
+
+/* Counters of the last render. */
+typedef struct {
+  int64_t n_views;
+  int64_t active_total;   /* (view, primitive) pairs that passed every cull */
+  int64_t instances;      /* (tile, primitive) pairs sorted for rasterisation */
+  int64_t tiles;          /* 16x16 tiles over all views */
+  int64_t max_tile_list;  /* longest per-tile list */
+  int64_t fragments;      /* list entries visited per pixel up to its last contributor, summed */
+} g4d_stats;
+
+/* Fills the defaults: L=3, N_t=2, T=1, t_cull=0.05, near=0.2, black background. */
+void g4d_default_options(g4d_options* out);
+
+/* Creates a context bound to `hip_stream` (a hipStream_t; NULL = default stream)
+ * on the current HIP device. */
+g4d_status g4d_create(const g4d_options* opts, void* hip_stream, g4d_ctx** out);
+g4d_status g4d_destroy(g4d_ctx* ctx);
+/* Rebinds the context to another stream (e.g. torch's current stream). */
+g4d_status g4d_set_stream(g4d_ctx* ctx, void* hip_stream);
+
+/* Borrows the primitive parameters (Sec. 3.2). The pointers must stay valid
+ * and unchanged until the render_backward of every render that used them
+ * has returned. n may be 0.
+ *   means4        [n][4]  (mu_x, mu_y, mu_z, mu_t)
+ *   log_scales4   [n][4]  s = exp(log_scales4), S = diag(s)
+ *   q_left        [n][4]  (a, b, c, d), normalised inside
+ *   q_right       [n][4]  (p, q, r, s), normalised inside
+ *   opacity_logit [n]     alpha = sigmoid(logit)   (4-byte alignment suffices)
+ *   coeffs        [n][K][3], K = (t_order+1)(sh_degree+1)^2, k = n_f*(L+1)^2 + l*l+l+m
+ *                 (4-byte alignment suffices)
+ * Invalidates the state kept for render_backward. */
+g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, const float* log_scales4,
+                              const float* q_left, const float* q_right, const float* opacity_logit,
+                              const float* coeffs);
+
+/* Renders n_views (camera, time) pairs in one batch.
+ *   cams   host array [n_views]
+ *   times  host array [n_views]
+ *   out_rgb    device [sum_v 3*H_v*W_v], per view planar [3][H][W], views concatenated
+ *   out_depth  device [sum_v H_v*W_v] or NULL: sum_i a_i T_i z_i (not normalised)
+ *   out_alpha  device [sum_v H_v*W_v] or NULL: 1 - final transmittance
+ * Keeps per-pixel final transmittance and last-contributor count for backward.
+ * Synchronises the stream once, mid-call, to size the tile-instance arena. */
+g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
+                      float* out_rgb, float* out_depth, float* out_alpha);
+
+/* Gradient of the last render. dL_drgb is required; dL_ddepth and dL_dalpha may
+ * be NULL (treated as zero). Layouts match render's outputs. The gradient
+ * buffers (layouts as set_primitives) receive the sum over the views of the
+ * last render: overwritten (primitives active in no view get zeros), or added
+ * to their contents when flags has G4D_GRAD_ACCUMULATE.
+ * Returns G4D_ESTATE if no render happened since the last set_primitives. */
+enum { G4D_GRAD_ACCUMULATE = 1 };
+g4d_status g4d_render_backward(g4d_ctx* ctx, const float* dL_drgb, const float* dL_ddepth,
+                               const float* dL_dalpha, float* g_means4, float* g_log_scales4,
+                               float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
+                               int32_t flags);
+
+/* Image loss and its gradient dL/dI (Sec. 3.3: optimisation is supervised by
+ * a rendering loss only), on the context's stream: over n values,
+ *   G4D_LOSS_L1: loss += scale * sum |img - target|,  grad = scale * sign(img - target)
+ *   G4D_LOSS_L2: loss += scale * sum (img - target)^2, grad = 2 scale (img - target)
+ * loss_out is one device float that is ADDED to (clear it first); grad_out
+ * (device, n values) is overwritten and may alias neither input. */
+enum { G4D_LOSS_L1 = 1, G4D_LOSS_L2 = 2 };
+g4d_status g4d_image_loss(g4d_ctx* ctx, int32_t kind, int64_t n, const float* img, const float* target,
+                          float scale, float* loss_out, float* grad_out);
+
+/* Counters of the last render; active_per_view (host [n_views]) may be NULL.
+ * `fragments` is computed on demand and synchronises the stream. */
+g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view);
+
+/* Tuning knobs (key, value); unknown keys give G4D_EINVAL.
+ *   G4D_TUNE_SORT_BLOCKS   max workgroups of each radix-sort pass (>= 1)
+ *   G4D_TUNE_STAGE_TIMING  1: bracket every stage with HIP events on the
+ *                          context's stream (resets the totals); 0: off     */
+enum { G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2 };
+g4d_status g4d_set_tuning(g4d_ctx* ctx, int32_t key, int32_t value);
+
+/* Per-stage GPU time accumulated since stage timing was switched on
+ * (synchronises the stream). ms_out and launches_out: host [G4D_NUM_STAGES]. */
+enum {
+  G4D_STAGE_PREPROCESS = 0,   /* slice, project, colour, cull */
+  G4D_STAGE_BINNING = 1,      /* compaction, depth sort, emission, tile sort, ranges */
+  G4D_STAGE_RASTER_FWD = 2,
+  G4D_STAGE_RASTER_BWD = 3,
+  G4D_STAGE_PREPROCESS_BWD = 4,
+  G4D_STAGE_LOSS = 5,
+  G4D_NUM_STAGES = 6
+};
+g4d_status g4d_stage_times(g4d_ctx* ctx, double* ms_out, int64_t* launches_out);
+
+/* Message of the last error on this context (owned by the context). */
+const char* g4d_last_error(const g4d_ctx* ctx);
+
+/* Copies an intermediate of the last render to host memory, for inspection
+ * by tests. Synchronises the stream. `bytes` must equal the size reported by
+ * g4d_debug_size for the same `what`.
+ *   G4D_DBG_RECORDS   per active pair in depth order, 12 x float32:
+ *                     u, v, z, opacity*p(t), conic00, conic01, conic11, rect x (x0 | x1<<16 as bits),
+ *                     r, g, b, rect y (y0 | y1<<16 as bits)
+ *   G4D_DBG_IDS       per active pair in depth order, uint32 view*n + primitive
+ *   G4D_DBG_TILE_KEYS sorted instances, uint32 global tile id
+ *   G4D_DBG_TILE_VALS sorted instances, uint32 depth-order record index
+ *   G4D_DBG_RANGES    per global tile, uint32 [start, end)
+ *   G4D_DBG_PIX_T     per pixel (views concatenated), float32 final transmittance
+ *   G4D_DBG_PIX_LAST  per pixel, uint32 list entries up to the last contributor
+ *   G4D_DBG_GRAD2D    after a backward: per active pair, 12 x float32
+ *                     dL/du, dL/dv, dL/dconic00, 01, 11, dL/d(opacity*p), dL/dr, g, b, dL/dz, 0, 0 */
+enum {
+  G4D_DBG_RECORDS = 1, G4D_DBG_IDS = 2, G4D_DBG_TILE_KEYS = 3, G4D_DBG_TILE_VALS = 4,
+  G4D_DBG_RANGES = 5, G4D_DBG_PIX_T = 6, G4D_DBG_PIX_LAST = 7, G4D_DBG_GRAD2D = 8
+};
+g4d_status g4d_debug_size(g4d_ctx* ctx, int32_t what, int64_t* bytes);
+g4d_status g4d_debug_copy(g4d_ctx* ctx, int32_t what, void* host_dst, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* G4D_H */

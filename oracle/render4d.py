@@ -40,6 +40,7 @@ TILE = 16
 # their threshold may be taken either way by a float32 implementation.
 MARGIN_REL = 1e-5   # relative, for p(t), z, alpha floor, stop threshold
 MARGIN_PX = 2e-3    # pixels, for footprint radius and tile-edge decisions
+IMG_TOL = 1e-4      # image tolerance the flags are sized for
 
 # Readings of points the paper leaves open (the same constants are restated,
 # not shared, by the GPU path):
@@ -322,7 +323,7 @@ class Margins:
     """Relative/absolute thresholds below which a decision counts as one that
     FP32 arithmetic may legitimately take the other way."""
     rel: float = MARGIN_REL  # alpha vs floor, T vs stop (fragment level)
-    depth_rel: float = 2e-6  # relative depth gap between two overlapping primitives
+    depth_rel: float = 5e-7  # relative depth gap within which FP32 may order two primitives either way
     clamp_rel: float = 1e-4  # alpha clamp / colour clamp / Jacobian clamp (gradients only)
 
 
@@ -424,14 +425,28 @@ def _tile_flags(pre, cam, tx, ty, pxc, pyc, ids, mg: Margins, h, w):
             flag_v |= near_stop.any(1)
             alive = t_incl >= C["t_stop"] * (1 - mg.rel)
             contrib = valid & alive
-            # depth near-ties between overlapping contributors
-            z = pre["z"][ids]
+            # Depth near-ties: two consecutive contributors of a pixel whose
+            # depths are within FP32 reach may be blended in either order.
+            # Swapping adjacent contributors i, j changes the pixel by exactly
+            # a_i a_j T_i (c_i - c_j); flag the value when that can exceed a
+            # tenth of the image tolerance, the gradient when a_i a_j T_i does.
+            z = pre["z"].detach()[ids]
             if ids.numel() > 1:
-                gap = (z[1:] - z[:-1]).abs() / z[1:].abs()
-                tie = gap < mg.depth_rel
+                zc = torch.where(contrib, z[None, :], torch.full_like(a, float("inf")))
+                nz, nidx = torch.cummin(torch.flip(zc, [1]), dim=1)
+                nz, nidx = torch.flip(nz, [1]), (zc.shape[1] - 1) - torch.flip(nidx, [1])
+                nxt_z = torch.cat([nz[:, 1:], torch.full_like(nz[:, :1], float("inf"))], 1)
+                nxt_i = torch.cat([nidx[:, 1:], torch.zeros_like(nidx[:, :1])], 1)
+                tie = contrib & ((nxt_z - z[None, :]) < mg.depth_rel * z[None, :])
                 if tie.any():
-                    both = contrib[:, 1:] & contrib[:, :-1] & tie[None, :]
-                    flag_v |= both.any(1)
+                    a_c = torch.where(contrib, a, torch.zeros_like(a))
+                    t_ex = torch.cat([torch.ones_like(a_c[:, :1]), torch.cumprod(1.0 - a_c, 1)[:, :-1]], 1)
+                    a_n = torch.gather(a_c, 1, nxt_i)
+                    col = pre["color"].detach()[ids]
+                    dc = (col[None, :, :] - col[nxt_i]).abs().amax(-1)
+                    w2 = a_c * a_n * t_ex
+                    flag_v |= (tie & (w2 * dc > 0.1 * IMG_TOL)).any(1)
+                    flag_g |= (tie & (w2 > 0.01 * IMG_TOL)).any(1)
             # gradient-only: alpha clamp, colour clamp, Jacobian clamp
             near_clamp = ((gv - C["alpha_max"]).abs() < mg.clamp_rel) & contrib
             col_m = (pre["color_raw"][ids].abs() < mg.clamp_rel).any(1)

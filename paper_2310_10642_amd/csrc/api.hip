@@ -1,0 +1,561 @@
+// C ABI of libg4d: context, argument validation, scratch management and the
+// enqueue order of the render and backward passes.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/g4d.h"
+#include "g4d_common.h"
+
+using namespace g4d;
+
+namespace {
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct g4d_ctx {
+  g4d_options opts{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  bool hip_failed = false;
+
+  // borrowed primitives
+  int64_t n = -1;
+  const float *means4 = nullptr, *log_scales4 = nullptr, *q_left = nullptr, *q_right = nullptr;
+  const float *opacity_logit = nullptr, *coeffs = nullptr;
+
+  // last render
+  bool have_render = false;
+  int n_views = 0;
+  std::vector<ViewDev> views_h;
+  int total_tiles = 0;
+  int64_t total_pix = 0;
+  uint32_t A = 0, I = 0;
+  std::vector<uint32_t> view_active;
+  int sort_blocks = 1024;
+
+  DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
+  DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
+  uint32_t* counters_h = nullptr;  // pinned
+
+  // stage timing (HIP events on the context's stream)
+  bool timing = false;
+  struct EvPair {
+    hipEvent_t a, b;
+    int stage;
+  };
+  std::vector<EvPair> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open_ev = nullptr;
+  double stage_ms[G4D_NUM_STAGES] = {};
+  int64_t stage_n[G4D_NUM_STAGES] = {};
+};
+
+namespace {
+
+// counters layout (uint32 words)
+constexpr int kCntA = 0;          // active records
+constexpr int kCntI = 1;          // instances
+constexpr int kCntInst64 = 2;     // 64-bit instance total (words 2, 3)
+constexpr int kCntFrag = 4;       // 64-bit fragment sum (words 4, 5)
+constexpr int kCntViews = 8;      // per-view active counts follow
+constexpr int kMaxViews = 4096;
+
+g4d_status fail(g4d_ctx* c, g4d_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+g4d_status check_hip(g4d_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return G4D_OK;
+  c->hip_failed = true;
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return G4D_EHIP;
+}
+
+#define HIPCHK(c, expr)                                   \
+  do {                                                    \
+    g4d_status _s = check_hip((c), (expr), #expr);        \
+    if (_s != G4D_OK) return _s;                          \
+  } while (0)
+
+g4d_status ensure(g4d_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.cap >= bytes) return G4D_OK;
+  if (b.ptr) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(b.ptr));
+    b.ptr = nullptr;
+    b.cap = 0;
+  }
+  const size_t want = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&b.ptr, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.ptr = nullptr;
+    return fail(c, G4D_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  b.cap = want;
+  return G4D_OK;
+}
+
+template <typename T>
+T* P(DevBuf& b) { return reinterpret_cast<T*>(b.ptr); }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+int ceil_log2(uint32_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+hipEvent_t take_event(g4d_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void stage_begin(g4d_ctx* c) {
+  if (!c->timing) return;
+  c->open_ev = take_event(c);
+  if (c->open_ev) (void)hipEventRecord(c->open_ev, c->stream);
+}
+
+void stage_end(g4d_ctx* c, int stage) {
+  if (!c->timing || !c->open_ev) return;
+  hipEvent_t e = take_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, c->stream);
+  c->pending.push_back({c->open_ev, e, stage});
+  c->open_ev = nullptr;
+}
+
+g4d_status collect_times(g4d_ctx* c) {
+  if (c->pending.empty()) return G4D_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+    c->stage_ms[p.stage] += ms;
+    c->stage_n[p.stage] += 1;
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return G4D_OK;
+}
+
+RenderParams make_params(g4d_ctx* c) {
+  RenderParams p{};
+  p.n = (int)c->n;
+  p.n_views = c->n_views;
+  p.sh_degree = c->opts.sh_degree;
+  p.t_order = c->opts.t_order;
+  p.t_period = c->opts.t_period;
+  p.t_cull = c->opts.t_cull;
+  p.near_plane = c->opts.near_plane;
+  for (int i = 0; i < 3; ++i) p.bg[i] = c->opts.bg[i];
+  p.means4 = reinterpret_cast<const float4*>(c->means4);
+  p.log_scales4 = reinterpret_cast<const float4*>(c->log_scales4);
+  p.q_left = reinterpret_cast<const float4*>(c->q_left);
+  p.q_right = reinterpret_cast<const float4*>(c->q_right);
+  p.opacity_logit = c->opacity_logit;
+  p.coeffs = c->coeffs;
+  p.views = P<ViewDev>(c->views_d);
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void g4d_default_options(g4d_options* o) {
+  if (!o) return;
+  o->sh_degree = 3;
+  o->t_order = 2;
+  o->t_period = 1.0f;
+  o->t_cull = 0.05f;
+  o->near_plane = 0.2f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+}
+
+g4d_status g4d_create(const g4d_options* opts, void* hip_stream, g4d_ctx** out) {
+  if (!opts || !out) return G4D_EINVAL;
+  if (opts->sh_degree < 0 || opts->sh_degree > 3 || opts->t_order < 0 || opts->t_order > 2) return G4D_EINVAL;
+  if (!(opts->t_period > 0.f) || !std::isfinite(opts->t_period) || !(opts->t_cull >= 0.f) ||
+      !(opts->t_cull <= 1.f) || !(opts->near_plane > 0.f) || !std::isfinite(opts->near_plane))
+    return G4D_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(opts->bg[i])) return G4D_EINVAL;
+  g4d_ctx* c = new g4d_ctx();
+  c->opts = *opts;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return G4D_EHIP;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->counters_h), (kCntViews + kMaxViews) * sizeof(uint32_t),
+                    hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return G4D_ENOMEM;
+  }
+  *out = c;
+  return G4D_OK;
+}
+
+g4d_status g4d_destroy(g4d_ctx* c) {
+  if (!c) return G4D_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->views_d, &c->act, &c->pos, &c->dkey, &c->rec, &c->slot, &c->ckey, &c->cval, &c->ckey2,
+                    &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
+                    &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
+                    &c->counters};
+  for (DevBuf* b : bufs)
+    if (b->ptr) (void)hipFree(b->ptr);
+  if (c->counters_h) (void)hipHostFree(c->counters_h);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->open_ev) (void)hipEventDestroy(c->open_ev);
+  delete c;
+  return G4D_OK;
+}
+
+g4d_status g4d_set_stream(g4d_ctx* c, void* hip_stream) {
+  if (!c) return G4D_EINVAL;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return G4D_OK;
+}
+
+g4d_status g4d_set_primitives(g4d_ctx* c, int64_t n, const float* means4, const float* log_scales4,
+                              const float* q_left, const float* q_right, const float* opacity_logit,
+                              const float* coeffs) {
+  if (!c) return G4D_EINVAL;
+  if (n < 0) return fail(c, G4D_EINVAL, "n must be >= 0");
+  if (n > (int64_t)0x7FFFFFFF) return fail(c, G4D_ECAPACITY, "n exceeds 2^31-1");
+  if (n > 0) {
+    if (!means4 || !log_scales4 || !q_left || !q_right || !opacity_logit || !coeffs)
+      return fail(c, G4D_EINVAL, "null parameter pointer");
+    if (!aligned16(means4) || !aligned16(log_scales4) || !aligned16(q_left) || !aligned16(q_right))
+      return fail(c, G4D_EINVAL, "means4/log_scales4/q_left/q_right must be 16-byte aligned");
+    if (!aligned4(opacity_logit) || !aligned4(coeffs)) return fail(c, G4D_EINVAL, "misaligned pointer");
+  }
+  c->n = n;
+  c->means4 = means4;
+  c->log_scales4 = log_scales4;
+  c->q_left = q_left;
+  c->q_right = q_right;
+  c->opacity_logit = opacity_logit;
+  c->coeffs = coeffs;
+  c->have_render = false;
+  return G4D_OK;
+}
+
+g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times, float* out_rgb,
+                      float* out_depth, float* out_alpha) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
+  if (n_views < 1 || n_views > kMaxViews) return fail(c, G4D_EINVAL, "n_views must be in [1, 4096]");
+  if (!cams || !times || !out_rgb) return fail(c, G4D_EINVAL, "null cams/times/out_rgb");
+  if ((uint64_t)c->n * (uint64_t)n_views > 0xFFFFFFF0ull)
+    return fail(c, G4D_ECAPACITY, "n * n_views exceeds 2^32");
+
+  // ---- views (host) ----
+  std::vector<ViewDev> vh(n_views);
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const g4d_camera& cm = cams[v];
+    if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
+      return fail(c, G4D_EINVAL, "camera size out of [1, 16384]");
+    if (!(cm.fx > 0.f) || !(cm.fy > 0.f) || !std::isfinite(cm.fx) || !std::isfinite(cm.fy) || !std::isfinite(cm.cx) ||
+        !std::isfinite(cm.cy))
+      return fail(c, G4D_EINVAL, "camera intrinsics must be finite with fx, fy > 0");
+    for (int i = 0; i < 12; ++i)
+      if (!std::isfinite(cm.world_to_cam[i])) return fail(c, G4D_EINVAL, "non-finite world_to_cam");
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(cm.center[i])) return fail(c, G4D_EINVAL, "non-finite camera center");
+    if (!std::isfinite(times[v])) return fail(c, G4D_EINVAL, "non-finite time");
+    ViewDev& d = vh[v];
+    d.width = cm.width;
+    d.height = cm.height;
+    d.tiles_x = (cm.width + kTile - 1) / kTile;
+    d.tiles_y = (cm.height + kTile - 1) / kTile;
+    d.tile_base = (int)tiles;
+    d.pad0 = 0;
+    d.pix_base = pix;
+    d.fx = cm.fx; d.fy = cm.fy; d.cx = cm.cx; d.cy = cm.cy;
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) d.rot[3 * r + k] = cm.world_to_cam[4 * r + k];
+      d.trans[r] = cm.world_to_cam[4 * r + 3];
+      d.center[r] = cm.center[r];
+    }
+    d.t = times[v];
+    d.lim_x = kFrustumSlack * (0.5f * (float)cm.width) / cm.fx;
+    d.lim_y = kFrustumSlack * (0.5f * (float)cm.height) / cm.fy;
+    tiles += (int64_t)d.tiles_x * d.tiles_y;
+    pix += (int64_t)cm.width * cm.height;
+  }
+  if (tiles > (int64_t)0x7FFFFFFF) return fail(c, G4D_ECAPACITY, "too many tiles");
+
+  hipStream_t s = c->stream;
+  const uint64_t vn = (uint64_t)c->n * n_views;
+  g4d_status st;
+  // ---- scratch ----
+  if ((st = ensure(c, c->views_d, sizeof(ViewDev) * n_views))) return st;
+  if ((st = ensure(c, c->counters, sizeof(uint32_t) * (kCntViews + kMaxViews)))) return st;
+  if ((st = ensure(c, c->act, 4 * vn))) return st;
+  if ((st = ensure(c, c->pos, 4 * vn))) return st;
+  if ((st = ensure(c, c->dkey, 4 * vn))) return st;
+  if ((st = ensure(c, c->slot, 4 * vn))) return st;
+  if ((st = ensure(c, c->rec, sizeof(Record) * vn))) return st;
+  if ((st = ensure(c, c->ckey, 4 * vn))) return st;
+  if ((st = ensure(c, c->cval, 4 * vn))) return st;
+  if ((st = ensure(c, c->ckey2, 4 * vn))) return st;
+  if ((st = ensure(c, c->cval2, 4 * vn))) return st;
+  if ((st = ensure(c, c->rec_sorted, sizeof(Record) * vn))) return st;
+  if ((st = ensure(c, c->tcount, 4 * vn))) return st;
+  if ((st = ensure(c, c->toff, 4 * vn))) return st;
+  if ((st = ensure(c, c->scan_scratch, 4 * scan_scratch_words(vn)))) return st;
+  if ((st = ensure(c, c->ranges, sizeof(uint2) * tiles))) return st;
+  if ((st = ensure(c, c->pix_t, 4 * pix))) return st;
+  if ((st = ensure(c, c->pix_last, 4 * pix))) return st;
+
+  c->have_render = false;
+  c->n_views = n_views;
+  c->views_h = vh;
+  c->total_tiles = (int)tiles;
+  c->total_pix = pix;
+  RenderParams p = make_params(c);
+  uint32_t* cnt = P<uint32_t>(c->counters);
+
+  HIPCHK(c, hipMemcpyAsync(c->views_d.ptr, c->views_h.data(), sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * kCntViews, s));
+  // 1. per (view, primitive): cull, slice, project, colour
+  stage_begin(c);
+  launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot), s);
+  stage_end(c, G4D_STAGE_PREPROCESS);
+  // 2. compaction of active records
+  stage_begin(c);
+  launch_scan(P<uint32_t>(c->act), P<uint32_t>(c->pos), nullptr, (uint32_t)vn, (uint32_t)vn, cnt + kCntA,
+              P<uint32_t>(c->scan_scratch), s);
+  launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
+                 P<uint32_t>(c->cval), s);
+  launch_view_counts(P<uint32_t>(c->pos), P<uint32_t>(c->act), n_views, (uint32_t)c->n, cnt + kCntA,
+                     cnt + kCntViews, s);
+  // 3. stable sort by depth
+  const int g_depth = radix_grid((uint32_t)vn, c->sort_blocks);
+  if ((st = ensure(c, c->radix_scratch, 4 * radix_scratch_words(c->sort_blocks)))) return st;
+  radix_sort(P<uint32_t>(c->ckey), P<uint32_t>(c->cval), P<uint32_t>(c->ckey2), P<uint32_t>(c->cval2), cnt + kCntA,
+             (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
+  // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
+  launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
+                P<int32_t>(c->slot), P<uint32_t>(c->tcount), cnt + kCntInst64, (int)c->n, s);
+  launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
+              P<uint32_t>(c->scan_scratch), s);
+  stage_end(c, G4D_STAGE_BINNING);
+  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (kCntViews + n_views), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const uint32_t A = c->counters_h[kCntA];
+  uint64_t inst64 = 0;
+  std::memcpy(&inst64, c->counters_h + kCntInst64, sizeof(inst64));
+  if (inst64 > 0xFFFFFFF0ull) return fail(c, G4D_ECAPACITY, "tile instances exceed 2^32; render fewer views per call");
+  const uint32_t I = (uint32_t)inst64;
+  c->A = A;
+  c->I = I;
+  c->view_active.assign(c->counters_h + kCntViews, c->counters_h + kCntViews + n_views);
+
+  // 6. emit (tile, record) instances; 7. stable sort by tile; 8. ranges
+  if ((st = ensure(c, c->ikey, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ival, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ikey2, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ival2, 4 * (size_t)I))) return st;
+  stage_begin(c);
+  HIPCHK(c, hipMemsetAsync(c->ranges.ptr, 0, sizeof(uint2) * tiles, s));
+  launch_emit(cnt + kCntA, A, P<uint32_t>(c->toff), cnt + kCntI, P<Record>(c->rec_sorted), P<uint32_t>(c->cval),
+              (int)c->n, P<ViewDev>(c->views_d), P<uint32_t>(c->ikey), P<uint32_t>(c->ival), s);
+  const int tile_bits = ceil_log2((uint32_t)tiles);
+  const int g_tile = radix_grid(I, c->sort_blocks);
+  radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI, I,
+             0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
+  launch_ranges(cnt + kCntI, I, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+  stage_end(c, G4D_STAGE_BINNING);
+  // 9. rasterise
+  stage_begin(c);
+  launch_raster_forward(c->total_tiles, n_views, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
+                        P<Record>(c->rec_sorted), c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t),
+                        P<uint32_t>(c->pix_last), s);
+  stage_end(c, G4D_STAGE_RASTER_FWD);
+  HIPCHK(c, hipGetLastError());
+  c->have_render = true;
+  return G4D_OK;
+}
+
+g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL_ddepth, const float* dL_dalpha,
+                               float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
+                               float* g_opacity_logit, float* g_coeffs, int32_t flags) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (!c->have_render) return fail(c, G4D_ESTATE, "no render since the last set_primitives");
+  if (!dL_drgb) return fail(c, G4D_EINVAL, "dL_drgb is required");
+  if (flags & ~G4D_GRAD_ACCUMULATE) return fail(c, G4D_EINVAL, "unknown flags");
+  if (c->n > 0) {
+    if (!g_means4 || !g_log_scales4 || !g_q_left || !g_q_right || !g_opacity_logit || !g_coeffs)
+      return fail(c, G4D_EINVAL, "null gradient pointer");
+    if (!aligned16(g_means4) || !aligned16(g_log_scales4) || !aligned16(g_q_left) || !aligned16(g_q_right))
+      return fail(c, G4D_EINVAL, "gradient buffers must be 16-byte aligned");
+  }
+  hipStream_t s = c->stream;
+  g4d_status st;
+  if ((st = ensure(c, c->grad2d, sizeof(float) * 12 * (size_t)c->A))) return st;
+  stage_begin(c);
+  if (c->A) HIPCHK(c, hipMemsetAsync(c->grad2d.ptr, 0, sizeof(float) * 12 * (size_t)c->A, s));
+  launch_raster_backward(c->total_tiles, c->n_views, P<ViewDev>(c->views_d), P<uint2>(c->ranges),
+                         P<uint32_t>(c->ival), P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha,
+                         P<float>(c->pix_t), P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
+  stage_end(c, G4D_STAGE_RASTER_BWD);
+  RenderParams p = make_params(c);
+  stage_begin(c);
+  launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), g_means4, g_log_scales4, g_q_left,
+                             g_q_right, g_opacity_logit, g_coeffs, (flags & G4D_GRAD_ACCUMULATE) != 0, s);
+  stage_end(c, G4D_STAGE_PREPROCESS_BWD);
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status g4d_image_loss(g4d_ctx* c, int32_t kind, int64_t n, const float* img, const float* target, float scale,
+                          float* loss_out, float* grad_out) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (kind != G4D_LOSS_L1 && kind != G4D_LOSS_L2) return fail(c, G4D_EINVAL, "unknown loss kind");
+  if (n < 0) return fail(c, G4D_EINVAL, "n must be >= 0");
+  if (!std::isfinite(scale)) return fail(c, G4D_EINVAL, "non-finite scale");
+  if (n > 0 && (!img || !target || !loss_out || !grad_out)) return fail(c, G4D_EINVAL, "null pointer");
+  if (n > 0 && (grad_out == img || grad_out == target)) return fail(c, G4D_EINVAL, "grad_out aliases an input");
+  stage_begin(c);
+  launch_image_loss(kind, (uint64_t)n, img, target, scale, loss_out, grad_out, c->stream);
+  stage_end(c, G4D_STAGE_LOSS);
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status g4d_stage_times(g4d_ctx* c, double* ms_out, int64_t* launches_out) {
+  if (!c || !ms_out || !launches_out) return G4D_EINVAL;
+  g4d_status st = collect_times(c);
+  if (st) return st;
+  for (int i = 0; i < G4D_NUM_STAGES; ++i) {
+    ms_out[i] = c->stage_ms[i];
+    launches_out[i] = c->stage_n[i];
+  }
+  return G4D_OK;
+}
+
+g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
+  if (!c || !out) return G4D_EINVAL;
+  if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
+  out->n_views = c->n_views;
+  out->active_total = c->A;
+  out->instances = c->I;
+  out->tiles = c->total_tiles;
+  // longest list and fragment total need device reads
+  std::vector<uint2> rg(c->total_tiles);
+  HIPCHK(c, hipMemcpyAsync(rg.data(), c->ranges.ptr, sizeof(uint2) * rg.size(), hipMemcpyDeviceToHost, c->stream));
+  uint32_t* cnt = P<uint32_t>(c->counters);
+  HIPCHK(c, hipMemsetAsync(cnt + kCntFrag, 0, 8, c->stream));
+  launch_sum_u32(P<uint32_t>(c->pix_last), (uint64_t)c->total_pix, reinterpret_cast<unsigned long long*>(cnt + kCntFrag),
+                 c->stream);
+  uint64_t frag = 0;
+  HIPCHK(c, hipMemcpyAsync(&frag, cnt + kCntFrag, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int64_t mx = 0;
+  for (const uint2& r : rg) mx = std::max<int64_t>(mx, (int64_t)r.y - (int64_t)r.x);
+  out->max_tile_list = mx;
+  out->fragments = (int64_t)frag;
+  if (active_per_view)
+    for (int v = 0; v < c->n_views; ++v) active_per_view[v] = c->view_active[v];
+  return G4D_OK;
+}
+
+g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
+  if (!c) return G4D_EINVAL;
+  if (key == G4D_TUNE_SORT_BLOCKS) {
+    if (value < 1 || value > 65536) return fail(c, G4D_EINVAL, "sort blocks out of [1, 65536]");
+    c->sort_blocks = value;
+    return G4D_OK;
+  }
+  if (key == G4D_TUNE_STAGE_TIMING) {
+    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "stage timing is 0 or 1");
+    g4d_status st = collect_times(c);
+    if (st) return st;
+    for (int i = 0; i < G4D_NUM_STAGES; ++i) {
+      c->stage_ms[i] = 0.0;
+      c->stage_n[i] = 0;
+    }
+    c->timing = value == 1;
+    return G4D_OK;
+  }
+  return fail(c, G4D_EINVAL, "unknown tuning key");
+}
+
+const char* g4d_last_error(const g4d_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+g4d_status g4d_debug_size(g4d_ctx* c, int32_t what, int64_t* bytes) {
+  if (!c || !bytes) return G4D_EINVAL;
+  if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
+  switch (what) {
+    case G4D_DBG_RECORDS: *bytes = (int64_t)sizeof(Record) * c->A; break;
+    case G4D_DBG_IDS: *bytes = 4ll * c->A; break;
+    case G4D_DBG_TILE_KEYS: case G4D_DBG_TILE_VALS: *bytes = 4ll * c->I; break;
+    case G4D_DBG_RANGES: *bytes = 8ll * c->total_tiles; break;
+    case G4D_DBG_PIX_T: case G4D_DBG_PIX_LAST: *bytes = 4ll * c->total_pix; break;
+    case G4D_DBG_GRAD2D: *bytes = 48ll * c->A; break;
+    default: return fail(c, G4D_EINVAL, "unknown debug item");
+  }
+  return G4D_OK;
+}
+
+g4d_status g4d_debug_copy(g4d_ctx* c, int32_t what, void* host_dst, int64_t bytes) {
+  if (!c || !host_dst) return G4D_EINVAL;
+  int64_t want = 0;
+  g4d_status st = g4d_debug_size(c, what, &want);
+  if (st) return st;
+  if (bytes != want) return fail(c, G4D_EINVAL, "size mismatch");
+  if (bytes == 0) return G4D_OK;
+  const void* src = nullptr;
+  switch (what) {
+    case G4D_DBG_RECORDS: src = c->rec_sorted.ptr; break;
+    case G4D_DBG_IDS: src = c->cval.ptr; break;
+    case G4D_DBG_TILE_KEYS: src = c->ikey.ptr; break;
+    case G4D_DBG_TILE_VALS: src = c->ival.ptr; break;
+    case G4D_DBG_RANGES: src = c->ranges.ptr; break;
+    case G4D_DBG_PIX_T: src = c->pix_t.ptr; break;
+    case G4D_DBG_PIX_LAST: src = c->pix_last.ptr; break;
+    case G4D_DBG_GRAD2D:
+      if (c->grad2d.cap < (size_t)bytes) return fail(c, G4D_ESTATE, "no backward");
+      src = c->grad2d.ptr;
+      break;
+  }
+  HIPCHK(c, hipMemcpyAsync(host_dst, src, (size_t)bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return G4D_OK;
+}
+
+}  // extern "C"

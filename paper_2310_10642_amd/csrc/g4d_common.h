@@ -1,0 +1,102 @@
+// Internal declarations shared by the HIP translation units of libg4d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace g4d {
+
+constexpr int kTile = 16;                 // 16x16 pixel tiles
+constexpr float kLowpass = 0.3f;          // EWA dilation, px^2
+constexpr float kFrustumSlack = 1.3f;     // Jacobian clamp, x half-fov
+constexpr float kSigmaExtent = 3.0f;      // footprint radius in sigmas
+constexpr float kAlphaMax = 0.99f;        // alpha clamp
+constexpr float kTStop = 1e-4f;           // transmittance stop threshold
+constexpr float kColorOffset = 0.5f;
+// log2(1/255): fragments with log2(opacity * exp(power)) below this are skipped
+constexpr float kLog2AlphaMin = -7.994353436858858f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+// One view of a batch, device side.
+struct ViewDev {
+  int width, height, tiles_x, tiles_y;
+  int tile_base;        // first global tile id of this view
+  int pad0;
+  long long pix_base;   // first pixel of this view in the concatenated planes
+  float fx, fy, cx, cy;
+  float rot[9];         // world -> camera rotation, row-major
+  float trans[3];
+  float center[3];      // camera position (world)
+  float t;              // render time
+  float lim_x, lim_y;   // Jacobian clamp limits on x/z, y/z
+};
+
+// Per active (view, primitive) record used by binning and rasterisation.
+// 3 x float4 = 48 bytes:
+//   a: u, v, z, opacity * p(t)
+//   b: conic00, conic01, conic11, rect x range (x0 | x1 << 16, as float bits)
+//   c: r, g, b, rect y range (y0 | y1 << 16, as float bits)
+struct Record {
+  float4 a, b, c;
+};
+
+struct RenderParams {
+  int n;                // primitives
+  int n_views;
+  int sh_degree, t_order;
+  float t_period, t_cull, near_plane;
+  float bg[3];
+  const float4* means4;
+  const float4* log_scales4;
+  const float4* q_left;
+  const float4* q_right;
+  const float* opacity_logit;
+  const float* coeffs;
+  const ViewDev* views;
+};
+
+// ---- launchers (preprocess.hip) ----
+void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
+                       hipStream_t s);
+void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const float* grad2d,
+                                float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
+                                float* g_opacity_logit, float* g_coeffs, bool accumulate, hipStream_t s);
+
+// ---- launchers (loss.hip) ----
+void launch_image_loss(int kind, uint64_t n, const float* img, const float* tgt, float scale, float* loss,
+                       float* grad, hipStream_t s);
+
+// ---- launchers (sort.hip) ----
+// Exclusive scan of n u32 (n read from n_dev when non-null, else n_host); writes total to *total.
+size_t scan_scratch_words(size_t n_max);
+void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint32_t n_host, uint32_t n_max,
+                 uint32_t* total, uint32_t* scratch, hipStream_t s);
+void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dkey, uint32_t n,
+                    uint32_t* ckey, uint32_t* cval, hipStream_t s);
+// LSD radix sort of (key, value) pairs on bits [bit0, bit1); result ends in keys/vals (ping-pong via alt).
+size_t radix_scratch_words(int grid);
+int radix_grid(uint32_t n_max, int max_blocks);
+void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
+                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s);
+// Depth-ordered records, slot map (view*n + index -> depth position), tiles per record,
+// and the 64-bit instance total (to detect 32-bit overflow) in inst64[0..1].
+void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
+                   int32_t* slot, uint32_t* tcount, uint32_t* inst64, int n_prims, hipStream_t s);
+void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, uint32_t n, const uint32_t* total,
+                        uint32_t* out, hipStream_t s);
+void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total,
+                 const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views,
+                 uint32_t* ikey, uint32_t* ival, hipStream_t s);
+void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s);
+
+// ---- launchers (raster.hip) ----
+void launch_raster_forward(int total_tiles, int n_views, const ViewDev* views, const uint2* ranges,
+                           const uint32_t* ival, const Record* rec_sorted, const float* bg, float* out_rgb,
+                           float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s);
+void launch_raster_backward(int total_tiles, int n_views, const ViewDev* views, const uint2* ranges,
+                            const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
+                            const float* dl_depth, const float* dl_alpha, const float* pix_t,
+                            const uint32_t* pix_last, float* grad2d, hipStream_t s);
+void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
+
+}  // namespace g4d

@@ -1,0 +1,449 @@
+// Binning of active records into 16x16 tiles, ordered by (tile, depth).
+//
+// The tile rasteriser the paper adapts (Sec. 3.2, last paragraph of
+// "Representation of 4D Gaussian") needs, per tile, the primitives whose
+// footprint covers it in front-to-back order. This is an LSD radix sort on the
+// composite key (global tile, depth, view*n + index), arranged so the low-order
+// passes run on the active records before they are duplicated per tile:
+//   1. stable 4-pass radix sort of the active records by float depth bits
+//      (ties keep (view, index) order from the compaction scan);
+//   2. emission of one (tile, record) instance per covered tile, in that order;
+//   3. stable radix sort of the instances by global tile id.
+// Every pass is stable, so the result equals a stable sort by (tile, depth)
+// of the instances emitted in (view, index) order.
+#include "g4d_common.h"
+
+namespace g4d {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTileElems = kThreads * kItems;  // 4096 elements per block tile
+
+__device__ __forceinline__ uint32_t dev_n(const uint32_t* n_dev, uint32_t n_max) {
+  return n_dev ? min(*n_dev, n_max) : n_max;
+}
+
+// Exclusive scan of one value per thread across a 256-thread block.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  uint32_t base = 0;
+  total = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint32_t c = s_wave[w];
+    base += (w < wave) ? c : 0u;
+    total += c;
+  }
+  __syncthreads();
+  return base + x - v;
+}
+
+// ---------------------------------------------------------------- scan ----
+__global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* n_dev,
+                                                           uint32_t n_max, uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t s_wave[4];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const size_t base = (size_t)blockIdx.x * kTileElems;
+  if (base >= n) return;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const size_t idx = base + (size_t)i * kThreads + threadIdx.x;
+    if (idx < n) acc += in[idx];
+  }
+  uint32_t total;
+  block_exclusive_scan(acc, s_wave, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block sums in place; total to *total.
+__global__ void __launch_bounds__(1024) k_scan_blocks(uint32_t* __restrict__ bsum, const uint32_t* n_dev,
+                                                      uint32_t n_max, uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_part[1024];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const uint32_t nb = (n + kTileElems - 1) / kTileElems;
+  const uint32_t per = (nb + 1023) / 1024;
+  const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+  uint32_t acc = 0;
+  for (uint32_t b = b0; b < b1; ++b) acc += bsum[b];
+  s_part[threadIdx.x] = acc;
+  __syncthreads();
+  // Hillis-Steele over 1024 partials
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t y = threadIdx.x >= (unsigned)off ? s_part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s_part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = s_part[threadIdx.x] - acc;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t c = bsum[b];
+    bsum[b] = run;
+    run += c;
+  }
+  if (threadIdx.x == 1023) *total = s_part[1023];
+}
+
+__global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                          const uint32_t* n_dev, uint32_t n_max,
+                                                          const uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t s_wave[4];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const size_t base = (size_t)blockIdx.x * kTileElems + (size_t)threadIdx.x * kItems;
+  if ((size_t)blockIdx.x * kTileElems >= n) return;
+  uint32_t v[kItems];
+  uint32_t acc = 0;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0u;
+    acc += v[i];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(acc, s_wave, total) + bsum[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+__global__ void k_compact(const uint32_t* __restrict__ act, const uint32_t* __restrict__ pos,
+                          const uint32_t* __restrict__ dkey, uint32_t n, uint32_t* __restrict__ ckey,
+                          uint32_t* __restrict__ cval) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (act[i]) {
+    const uint32_t p = pos[i];
+    ckey[p] = dkey[i];
+    cval[p] = (uint32_t)i;
+  }
+}
+
+// ---------------------------------------------------------- radix sort ----
+__device__ __forceinline__ void block_range(uint32_t n, int grid, uint32_t& t0, uint32_t& t1) {
+  const uint32_t tiles = (n + kTileElems - 1) / kTileElems;
+  const uint32_t tpb = (tiles + grid - 1) / grid;
+  t0 = min(blockIdx.x * tpb, tiles);
+  t1 = min(t0 + tpb, tiles);
+}
+
+__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
+                                                          uint32_t n_max, int shift, int bits,
+                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t hist[4][256];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) hist[w][threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t t0, t1;
+  block_range(n, gridDim.x, t0, t1);
+  const uint32_t mask = (1u << bits) - 1u;
+  for (uint32_t t = t0; t < t1; ++t) {
+#pragma unroll 4
+    for (int i = 0; i < kItems; ++i) {
+      const size_t idx = (size_t)t * kTileElems + (size_t)i * kThreads + threadIdx.x;
+      if (idx < n) atomicAdd(&hist[wave][(keys[idx] >> shift) & mask], 1u);
+    }
+  }
+  __syncthreads();
+  const uint32_t d = threadIdx.x;
+  counts[(size_t)d * gridDim.x + blockIdx.x] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+}
+
+// Single block: exclusive scan of counts[digit][block] (digit-major) in place.
+__global__ void __launch_bounds__(1024) k_rs_scan(uint32_t* __restrict__ counts, uint32_t len) {
+  __shared__ uint32_t s_part[1024];
+  const uint32_t per = (len + 1023) / 1024;
+  const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, len);
+  uint32_t acc = 0;
+  for (uint32_t b = b0; b < b1; ++b) acc += counts[b];
+  s_part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t y = threadIdx.x >= (unsigned)off ? s_part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s_part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = s_part[threadIdx.x] - acc;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t c = counts[b];
+    counts[b] = run;
+    run += c;
+  }
+}
+
+// Stable scatter of one digit pass. Within a 4096-element tile each wave owns
+// 1024 consecutive elements, processed 64 at a time; a lane's rank among equal
+// digits comes from a ballot match over the digit bits.
+__global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+                                                            const uint32_t* __restrict__ vals_in,
+                                                            uint32_t* __restrict__ keys_out,
+                                                            uint32_t* __restrict__ vals_out, const uint32_t* n_dev,
+                                                            uint32_t n_max, int shift, int bits,
+                                                            const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[4][256];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t mask = (1u << bits) - 1u;
+  run[threadIdx.x] = offs[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+  uint32_t t0, t1;
+  block_range(n, gridDim.x, t0, t1);
+  for (uint32_t t = t0; t < t1; ++t) {
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0u;
+    __syncthreads();
+    const size_t base = (size_t)t * kTileElems + (size_t)wave * (kTileElems / 4);
+    uint32_t k[kItems], v[kItems], rank[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const size_t idx = base + (size_t)i * 64 + lane;
+      k[i] = (idx < n) ? keys_in[idx] : 0u;
+      v[i] = (idx < n) ? vals_in[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const bool valid = base + (size_t)i * 64 + lane < n;
+      const uint32_t d = (k[i] >> shift) & mask;
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const bool set = (d >> b) & 1u;
+        const uint64_t m = __ballot(set);
+        peers &= set ? m : ~m;
+      }
+      const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+      const uint32_t pre = wcnt[wave][d];
+      rank[i] = pre + below;
+      if (valid && below == 0) wcnt[wave][d] = pre + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: offsets of each wave inside this tile, then absolute bases
+    const uint32_t dg = threadIdx.x;
+    const uint32_t c0 = wcnt[0][dg], c1 = wcnt[1][dg], c2 = wcnt[2][dg], c3 = wcnt[3][dg];
+    const uint32_t r = run[dg];
+    __syncthreads();
+    wcnt[0][dg] = r;
+    wcnt[1][dg] = r + c0;
+    wcnt[2][dg] = r + c0 + c1;
+    wcnt[3][dg] = r + c0 + c1 + c2;
+    run[dg] = r + c0 + c1 + c2 + c3;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const bool valid = base + (size_t)i * 64 + lane < n;
+      if (valid) {
+        const uint32_t d = (k[i] >> shift) & mask;
+        const uint32_t p = wcnt[wave][d] + rank[i];
+        if (p < n) {  // always true for consistent counts; keeps a ranking fault in bounds
+          keys_out[p] = k[i];
+          vals_out[p] = v[i];
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- gather ----
+__global__ void __launch_bounds__(kThreads) k_gather(const uint32_t* n_dev, uint32_t n_max,
+                                                      const uint32_t* __restrict__ ids, const Record* __restrict__ rec,
+                                                      Record* __restrict__ rec_sorted, int32_t* __restrict__ slot,
+                                                      uint32_t* __restrict__ tcount,
+                                                      unsigned long long* __restrict__ inst64) {
+  __shared__ uint32_t s_wave[4];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x * blockDim.x >= n) return;
+  uint32_t cnt = 0;
+  if (d < n) {
+    const uint32_t id = ids[d];
+    const Record r = rec[id];
+    rec_sorted[d] = r;
+    slot[id] = (int32_t)d;
+    const uint32_t rx = __float_as_uint(r.b.w), ry = __float_as_uint(r.c.w);
+    cnt = ((rx >> 16) - (rx & 0xFFFFu)) * ((ry >> 16) - (ry & 0xFFFFu));
+    tcount[d] = cnt;
+  }
+  uint32_t total;
+  block_exclusive_scan(cnt, s_wave, total);
+  if (threadIdx.x == 0) atomicAdd(inst64, (unsigned long long)total);
+}
+
+// Active records per view from the compaction scan: pos[(v+1) n] - pos[v n].
+__global__ void k_view_counts(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ act, int n_views,
+                              uint32_t n, const uint32_t* total, uint32_t* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_views) return;
+  if (n == 0) {
+    out[v] = 0u;
+    return;
+  }
+  const size_t b = (size_t)v * n;
+  const uint32_t start = pos[b];
+  const uint32_t end = (v + 1 < n_views) ? pos[b + n] : *total;
+  out[v] = end - start;
+}
+
+// ---------------------------------------------------------------- emit ----
+// One block per 256 consecutive records; the block's instances are spread
+// over its threads, each finding its record by binary search in LDS.
+__global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32_t n_max,
+                                                    const uint32_t* __restrict__ toff, const uint32_t* total,
+                                                    const Record* __restrict__ rec_sorted,
+                                                    const uint32_t* __restrict__ ids, uint32_t n_prims,
+                                                    const ViewDev* __restrict__ views, uint32_t* __restrict__ ikey,
+                                                    uint32_t* __restrict__ ival) {
+  __shared__ uint32_t offs[kThreads + 1];
+  __shared__ uint32_t s_rx[kThreads], s_ry[kThreads], s_tb[kThreads], s_tw[kThreads];
+  const uint32_t n = dev_n(n_dev, n_max);
+  const uint32_t d0 = blockIdx.x * kThreads;
+  if (d0 >= n) return;
+  const uint32_t d = d0 + threadIdx.x;
+  const uint32_t tot = *total;
+  offs[threadIdx.x] = d < n ? toff[d] : tot;
+  if (threadIdx.x == 0) offs[kThreads] = (d0 + kThreads < n) ? toff[d0 + kThreads] : tot;
+  if (d < n) {
+    const Record r = rec_sorted[d];
+    s_rx[threadIdx.x] = __float_as_uint(r.b.w);
+    s_ry[threadIdx.x] = __float_as_uint(r.c.w);
+    const uint32_t v = ids[d] / n_prims;
+    s_tb[threadIdx.x] = (uint32_t)views[v].tile_base;
+    s_tw[threadIdx.x] = (uint32_t)views[v].tiles_x;
+  }
+  __syncthreads();
+  const uint32_t start = offs[0], end = offs[kThreads];
+  for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
+    int lo = 0, hi = kThreads - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t k = i - offs[lo];
+    const uint32_t rx = s_rx[lo], ry = s_ry[lo];
+    const uint32_t x0 = rx & 0xFFFFu, w = (rx >> 16) - x0, y0 = ry & 0xFFFFu;
+    const uint32_t ty = y0 + k / w, tx = x0 + k % w;
+    ikey[i] = s_tb[lo] + ty * s_tw[lo] + tx;
+    ival[i] = d0 + (uint32_t)lo;
+  }
+}
+
+__global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* __restrict__ ikey,
+                         uint2* __restrict__ ranges) {
+  const uint32_t n = dev_n(n_dev, n_max);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = ikey[i];
+  if (i == 0 || ikey[i - 1] != k) ranges[k].x = i;
+  if (i == n - 1 || ikey[i + 1] != k) ranges[k].y = i + 1;
+}
+
+__global__ void k_sum_u32(const uint32_t* __restrict__ in, uint64_t n, unsigned long long* out) {
+  __shared__ uint32_t s_wave[4];
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) acc += in[i];
+  uint32_t total;
+  block_exclusive_scan(acc, s_wave, total);
+  if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)total);
+}
+
+inline unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+size_t scan_scratch_words(size_t n_max) { return (n_max + kTileElems - 1) / kTileElems + 1; }
+
+void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint32_t n_host, uint32_t n_max,
+                 uint32_t* total, uint32_t* scratch, hipStream_t s) {
+  const uint32_t cap = n_dev ? n_max : n_host;
+  const unsigned nb = grid_for(cap, kTileElems);
+  if (nb == 0) {
+    (void)hipMemsetAsync(total, 0, sizeof(uint32_t), s);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n_dev, cap, scratch);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, scratch, n_dev, cap, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, in, out, n_dev, cap, scratch);
+}
+
+void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dkey, uint32_t n, uint32_t* ckey,
+                    uint32_t* cval, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, act, pos, dkey, n, ckey, cval);
+}
+
+size_t radix_scratch_words(int grid) { return (size_t)256 * grid; }
+
+int radix_grid(uint32_t n_max, int max_blocks) {
+  const int need = (int)grid_for(n_max, kTileElems);
+  return need < 1 ? 1 : (need < max_blocks ? need : max_blocks);
+}
+
+void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
+                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s) {
+  // Passes ping-pong between the two buffers; an odd pass count ends with a
+  // copy back so the result is always in (keys, vals).
+  uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
+  int passes = 0;
+  for (int b = bit0; b < bit1; b += 8) {
+    const int bits = (bit1 - b) < 8 ? (bit1 - b) : 8;
+    hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
+    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, s, scratch, (uint32_t)(256 * grid));
+    hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b, bits,
+                       scratch);
+    uint32_t* t = kin; kin = kout; kout = t;
+    t = vin; vin = vout; vout = t;
+    ++passes;
+  }
+  if (passes & 1) {
+    (void)hipMemcpyAsync(keys, kin, sizeof(uint32_t) * (size_t)n_max, hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(vals, vin, sizeof(uint32_t) * (size_t)n_max, hipMemcpyDeviceToDevice, s);
+  }
+}
+
+void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
+                   int32_t* slot, uint32_t* tcount, uint32_t* inst64, int n_prims, hipStream_t s) {
+  (void)n_prims;
+  if (n_max == 0) return;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, ids, rec,
+                     rec_sorted, slot, tcount, reinterpret_cast<unsigned long long*>(inst64));
+}
+
+void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, uint32_t n, const uint32_t* total,
+                        uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_view_counts, dim3(grid_for(n_views, 64)), dim3(64), 0, s, pos, act, n_views, n, total, out);
+}
+
+void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total,
+                 const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, uint32_t* ikey,
+                 uint32_t* ival, hipStream_t s) {
+  if (n_max == 0) return;
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, toff, total,
+                     rec_sorted, ids, (uint32_t)n_prims, views, ikey, ival);
+}
+
+void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s) {
+  if (n_max == 0) return;
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n_max, 256)), dim3(256), 0, s, n_dev, n_max, ikey, ranges);
+}
+
+void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s) {
+  if (n == 0) return;
+  unsigned g = grid_for(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_sum_u32, dim3(g), dim3(256), 0, s, in, n, out);
+}
+
+}  // namespace g4d

@@ -1,0 +1,68 @@
+"""CPU checks of the C ABI: the library loads and exports every declared
+entry point; argument validation returns before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "g4d.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(g4d_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_surface():
+    from paper_2310_10642_amd import g4d
+    assert declared_symbols() == sorted(g4d.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2310_10642_amd import g4d
+    if not os.path.exists(g4d.LIB_PATH):
+        pytest.skip("libg4d.so not built")
+    lib = ctypes.CDLL(g4d.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_header_constants_match_binding():
+    from paper_2310_10642_amd import g4d
+    text = open(HEADER).read()
+    def val(name):
+        return int(re.search(rf"\b{name}\s*=\s*(-?\d+)", text).group(1))
+    assert val("G4D_EINVAL") == g4d.G4D_EINVAL and val("G4D_ESTATE") == g4d.G4D_ESTATE
+    assert val("G4D_GRAD_ACCUMULATE") == g4d.G4D_GRAD_ACCUMULATE
+    assert val("G4D_LOSS_L1") == g4d.G4D_LOSS_L1 and val("G4D_LOSS_L2") == g4d.G4D_LOSS_L2
+    assert val("G4D_TUNE_STAGE_TIMING") == g4d.G4D_TUNE_STAGE_TIMING
+    assert val("G4D_NUM_STAGES") == len(g4d.STAGES)
+    for k, v in g4d.DBG.items():
+        assert val("G4D_DBG_" + k.upper()) == v
+
+
+def test_struct_layouts():
+    from paper_2310_10642_amd import g4d
+    assert ctypes.sizeof(g4d.G4DOptions) == 32
+    assert ctypes.sizeof(g4d.G4DCamera) == 4 * (2 + 4 + 12 + 3)
+    assert ctypes.sizeof(g4d.G4DStats) == 48
+
+
+def test_validation_before_any_hip_call():
+    from paper_2310_10642_amd import g4d
+    if not os.path.exists(g4d.LIB_PATH):
+        pytest.skip("libg4d.so not built")
+    lib = g4d.load_library()
+    h = ctypes.c_void_p()
+    assert lib.g4d_create(None, None, ctypes.byref(h)) == g4d.G4D_EINVAL
+    o = g4d.G4DOptions()
+    lib.g4d_default_options(ctypes.byref(o))
+    assert (o.sh_degree, o.t_order) == (3, 2) and abs(o.t_cull - 0.05) < 1e-7
+    o.sh_degree = 4
+    assert lib.g4d_create(ctypes.byref(o), None, ctypes.byref(h)) == g4d.G4D_EINVAL
+    o.sh_degree, o.t_period = 3, 0.0
+    assert lib.g4d_create(ctypes.byref(o), None, ctypes.byref(h)) == g4d.G4D_EINVAL
+    assert lib.g4d_render(None, 1, None, None, None, None, None) == g4d.G4D_EINVAL
+    assert lib.g4d_destroy(None) == g4d.G4D_EINVAL

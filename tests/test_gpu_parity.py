@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from oracle import render4d as O
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _render_one(r, cam, t):
+    rgb, dep, alp = r.render([cam], [t])
+    torch.cuda.synchronize()
+    h, w = cam.height, cam.width
+    return _np(rgb).reshape(3, h, w), _np(dep).reshape(h, w), _np(alp).reshape(h, w)
+
+
+def _big_splat_scene(seed, n, grow=1.0, spread=1.0, sh=2, to=2, mu_log_t=-1.5):
+    sc = scenegen.random_scene(seed, n, sh_degree=sh, t_order=to, spread=spread, mu_log_t=mu_log_t)
+    sc.log_scales4[:, :3] += np.float32(grow)
+    return sc
+
+
+CASES = [
+    # name, scene factory, camera, t, bg
+    ("cfg0", lambda: scenegen.make_workload(0).scene, lambda: scenegen.make_workload(0).cameras[0], 0.5,
+     (0.0, 0.0, 0.0)),
+    ("ragged_100x70", lambda: _big_splat_scene(5, 3000, grow=0.8),
+     lambda: scenegen.look_at_camera((1.0, 0.5, 3.5), 100, 70), 0.37, (0.2, 0.1, 0.05)),
+    ("dense_stop_48x40", lambda: _big_splat_scene(6, 2500, grow=1.5, spread=0.5, sh=3, to=1),
+     lambda: scenegen.look_at_camera((0.0, -0.3, 3.0), 48, 40), 0.6, (0.0, 0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+def test_forward_image_parity(name, mk_scene, mk_cam, t, bg):
+    _say(f"[forward parity] {name}")
+    scene, cam = mk_scene(), mk_cam()
+    r, _ = PT.gpu_setup(scene, bg)
+    g_rgb, g_dep, g_alp = _render_one(r, cam, t)
+    _, img = PT.oracle_view(scene, cam, t, bg)
+    res = PT.compare_images(g_rgb, g_dep, g_alp, img)
+    _say(f"  {res}")
+    # per-pixel backward state: last contributor count matches away from flagged pixels
+    last = r.debug("pix_last").reshape(cam.height, cam.width)
+    ok = ~img["unc"].numpy()
+    assert (last[ok] == img["last"].numpy()[ok]).all()
+    T = r.debug("pix_t").reshape(cam.height, cam.width)
+    assert np.allclose(T[ok], img["T"].numpy()[ok], atol=2e-5)
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+def test_preprocess_records_parity(name, mk_scene, mk_cam, t, bg):
+    _say(f"[preprocess parity] {name}")
+    scene, cam = mk_scene(), mk_cam()
+    r, _ = PT.gpu_setup(scene, bg)
+    r.render([cam], [t])
+    recs, ids = r.debug("records"), r.debug("ids")
+    pre = O.preprocess(O.params_from_scene(scene), O.to_ocamera(cam), float(t), scene.sh_degree, scene.t_order,
+                       scene.t_period)
+    act_o = pre["active"].numpy()
+    rs, rm = pre["rect_sure"].numpy(), pre["rect_maybe"].numpy()
+    area = lambda rr: np.maximum(rr[:, 2] - rr[:, 0], 0) * np.maximum(rr[:, 3] - rr[:, 1], 0)
+    unsure = (area(rs) == 0) & (area(rm) > 0)
+    act_g = np.zeros(scene.n, bool)
+    act_g[ids] = True
+    diff = act_g != act_o
+    assert not (diff & ~unsure).any(), np.nonzero(diff & ~unsure)[0][:10]
+    common = ids[act_o[ids]]
+    row = {int(g): i for i, g in enumerate(ids)}
+    sel = np.array([row[int(g)] for g in common])
+    R = recs[sel]
+    u, v, z = pre["u"].detach().numpy()[common], pre["v"].detach().numpy()[common], pre["z"].detach().numpy()[common]
+    assert np.allclose(R[:, 0], u, atol=2e-3, rtol=0)
+    assert np.allclose(R[:, 1], v, atol=2e-3, rtol=0)
+    assert np.allclose(R[:, 2], z, rtol=2e-6, atol=0)
+    assert np.allclose(R[:, 3], pre["opac"].detach().numpy()[common], rtol=2e-5, atol=1e-7)
+    con = pre["conic"].detach().numpy()[common]
+    scale = np.abs(con).max(1, keepdims=True)
+    assert np.allclose(R[:, 4:7] / scale, con / scale, atol=2e-4, rtol=0)
+    col = pre["color"].detach().numpy()[common]
+    assert np.allclose(R[:, 8:11], col, atol=2e-5, rtol=0)
+    rx = R[:, 7].view(np.uint32)
+    ry = R[:, 11].view(np.uint32)
+    rect_g = np.stack([rx & 0xFFFF, ry & 0xFFFF, rx >> 16, ry >> 16], 1).astype(np.int64)
+    rect_o = pre["rect"].numpy()[common]
+    same = (rect_g == rect_o).all(1)
+    edge_unsure = (rs[common] != rm[common]).any(1)
+    assert (same | edge_unsure).all()
+    # depth order: non-decreasing float z, ties by (view, index)
+    zg = recs[:, 2]
+    assert (np.diff(zg) >= 0).all()
+    tie = np.diff(zg) == 0
+    assert (np.diff(ids.astype(np.int64))[tie] > 0).all()
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+def test_binning_is_a_valid_stable_sort(name, mk_scene, mk_cam, t, bg):
+    """The sorted (tile, record) instances are exactly the expansion of every
+    record's rectangle, ordered by tile then by depth position, and the tile
+    ranges delimit them."""
+    _say(f"[binning] {name}")
+    scene, cam = mk_scene(), mk_cam()
+    r, _ = PT.gpu_setup(scene, bg)
+    r.render([cam], [t])
+    recs = r.debug("records")
+    keys, vals, ranges = r.debug("tile_keys"), r.debug("tile_vals"), r.debug("ranges")
+    tx = (cam.width + 15) // 16
+    rx, ry = recs[:, 7].view(np.uint32), recs[:, 11].view(np.uint32)
+    exp = []
+    for d in range(recs.shape[0]):
+        x0, x1, y0, y1 = rx[d] & 0xFFFF, rx[d] >> 16, ry[d] & 0xFFFF, ry[d] >> 16
+        for yy in range(y0, y1):
+            for xx in range(x0, x1):
+                exp.append((yy * tx + xx, d))
+    exp.sort()
+    got = list(zip(keys.tolist(), vals.tolist()))
+    assert got == exp
+    for tid in range(ranges.shape[0]):
+        s, e = ranges[tid]
+        if e > s:
+            assert (keys[s:e] == tid).all()
+            assert s == 0 or keys[s - 1] != tid
+            assert e == len(keys) or keys[e] != tid
+        else:
+            assert tid not in set(keys.tolist()[:0])
+    stats = r.stats()
+    assert stats["instances"] == len(exp)
+    assert stats["active_total"] == recs.shape[0]
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+def test_backward_gradient_parity(name, mk_scene, mk_cam, t, bg):
+    _say(f"[backward parity] {name}")
+    scene, cam = mk_scene(), mk_cam()
+    r, _ = PT.gpu_setup(scene, bg)
+    r.render([cam], [t])
+    out, img = PT.oracle_view(scene, cam, t, bg, requires_grad=True)
+    mask = (~img["unc_g"].numpy()).astype(np.float64)
+    drgb, ddep, dalp = PT.dl_maps(11, cam.height, cam.width, mask)
+    L = O.tile_linear_loss(out, torch.as_tensor(drgb), torch.as_tensor(ddep), torch.as_tensor(dalp), cam)
+    L.backward()
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    g = r.backward(f32(drgb).reshape(-1), f32(ddep).reshape(-1), f32(dalp).reshape(-1))
+    torch.cuda.synchronize()
+    rep = {}
+    PT.compare_grads(g, out["params"], report=rep)
+    _say(f"  rel L2 {rep}")
+
+
+def test_batched_equals_per_view():
+    """One batched call over views of different sizes and times gives the
+    per-view images bit for bit and the sum of the per-view gradients."""
+    _say("[batched == per-view]")
+    scene = _big_splat_scene(7, 4000, grow=0.7, sh=3, to=2)
+    cams = [scenegen.look_at_camera((math.sin(a) * 3.5, 0.3, math.cos(a) * 3.5), w, h)
+            for a, (w, h) in zip([0.0, 1.2, 2.5], [(64, 48), (80, 80), (33, 17)])]
+    times = [0.2, 0.5, 0.85]
+    r, _ = PT.gpu_setup(scene)
+    rgb_b, dep_b, alp_b = r.render(cams, times)
+    views_b = [[_np(x) for x in item] for item in r.split(rgb_b, dep_b, alp_b)]
+    rng = np.random.default_rng(3)
+    dl = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    gb = r.backward(torch.from_numpy(np.concatenate([d.reshape(-1) for d in dl])).cuda())
+    gsum = [torch.zeros_like(x) for x in gb]
+    for v, (c, t) in enumerate(zip(cams, times)):
+        rgb, dep, alp = r.render([c], [t])
+        assert np.array_equal(_np(rgb).reshape(3, c.height, c.width), views_b[v][0])
+        assert np.array_equal(_np(dep).reshape(c.height, c.width), views_b[v][1])
+        assert np.array_equal(_np(alp).reshape(c.height, c.width), views_b[v][2])
+        g = r.backward(torch.from_numpy(dl[v].reshape(-1)).cuda())
+        for a, b in zip(gsum, g):
+            a += b
+    torch.cuda.synchronize()
+    for name, a, b in zip(PT.GROUPS, gb, gsum):
+        a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
+        nb = np.linalg.norm(b)
+        assert nb == 0 or np.linalg.norm(a - b) <= 1e-5 * nb, name
+
+
+def test_empty_and_degenerate_inputs():
+    _say("[edge cases]")
+    bg = (0.25, 0.5, 0.75)
+    # n = 0: background everywhere
+    sc = scenegen.random_scene(1, 4)
+    empty = scenegen.Scene(sc.means4[:0].copy(), sc.log_scales4[:0].copy(), sc.q_left[:0].copy(),
+                           sc.q_right[:0].copy(), sc.opacity_logit[:0].copy(), sc.coeffs[:0].copy(), 1, 1)
+    r, _ = PT.gpu_setup(empty, bg)
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 23, 9)
+    rgb, dep, alp = _render_one(r, cam, 0.5)
+    assert np.allclose(rgb, np.array(bg, np.float32)[:, None, None]) and (dep == 0).all() and (alp == 0).all()
+    g = r.backward(torch.ones(3 * 23 * 9, device="cuda"))
+    assert all(x.numel() == 0 for x in g)
+    # every primitive culled by the temporal filter: background, zero gradients
+    sc = scenegen.random_scene(2, 200, mu_log_t=-4.0)
+    sc.means4[:, 3] = 0.0
+    r, _ = PT.gpu_setup(sc, bg)
+    rgb, dep, alp = _render_one(r, cam, 1.0)
+    assert np.allclose(rgb, np.array(bg, np.float32)[:, None, None]) and r.stats()["active_total"] == 0
+    g = r.backward(torch.ones(3 * 23 * 9, device="cuda"))
+    assert all(float(x.abs().max()) == 0.0 for x in g)
+    # 1x1 image, primitives behind the camera and at the near plane
+    sc = scenegen.random_scene(3, 300, spread=2.5)
+    cam1 = scenegen.look_at_camera((0.0, 0.0, 2.0), 1, 1)
+    r, _ = PT.gpu_setup(sc, bg)
+    g_rgb, g_dep, g_alp = _render_one(r, cam1, 0.5)
+    _, img = PT.oracle_view(sc, cam1, 0.5, bg)
+    PT.compare_images(g_rgb, g_dep, g_alp, img, max_flag_frac=1.0)
+
+
+def test_abi_errors():
+    _say("[abi errors]")
+    from paper_2310_10642_amd import g4d
+    r = g4d.Renderer(1, 1)
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 8, 8)
+    with pytest.raises(g4d.G4DError) as e:
+        r.render([cam], [0.5])
+    assert e.value.status == g4d.G4D_ESTATE
+    sc = scenegen.random_scene(4, 10)
+    r, _ = PT.gpu_setup(sc)
+    with pytest.raises(g4d.G4DError) as e:
+        r.backward(torch.zeros(192, device="cuda"))
+    assert e.value.status == g4d.G4D_ESTATE
+    bad = scenegen.look_at_camera((0.0, 0.0, 4.0), 8, 8)
+    bad.fx = -1.0
+    with pytest.raises(g4d.G4DError) as e:
+        r.render([bad], [0.5])
+    assert e.value.status == g4d.G4D_EINVAL
+    with pytest.raises(g4d.G4DError) as e:
+        r.render([cam], [float("nan")])
+    assert e.value.status == g4d.G4D_EINVAL
+    with pytest.raises(g4d.G4DError) as e:
+        r.set_tuning(99, 1)
+    assert e.value.status == g4d.G4D_EINVAL
