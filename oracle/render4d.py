@@ -322,7 +322,9 @@ def preprocess(params: Dict[str, torch.Tensor], cam: OCamera, t: float,
 class Margins:
     """Relative/absolute thresholds below which a decision counts as one that
     FP32 arithmetic may legitimately take the other way."""
-    rel: float = MARGIN_REL  # alpha vs floor, T vs stop (fragment level)
+    rel: float = 3e-5        # alpha vs the 1/255 floor (FP32 error of alpha is ~1e-6 |power|)
+    stop_rel: float = 3e-4   # T(1-a) vs the stop threshold: FP32 T after hundreds of fragments,
+                             # with (1-a) of alphas near the clamp, drifts up to ~1e-4 relative
     depth_rel: float = 5e-7  # relative depth gap within which FP32 may order two primitives either way
     clamp_rel: float = 1e-4  # alpha clamp / colour clamp / Jacobian clamp (gradients only)
 
@@ -400,9 +402,13 @@ def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
 
 def _tile_flags(pre, cam, tx, ty, pxc, pyc, ids, mg: Margins, h, w):
     """Pixels whose result depends on a decision within FP32 reach of its
-    threshold (value flags), or whose gradient does (grad flags)."""
+    threshold. A value flag is raised when taking such a decision the other
+    way can move an output (rgb, depth or alpha) by more than a tenth of the
+    image tolerance; a gradient flag whenever the decision touches a fragment
+    that contributes (the tests zero dL/dI there on both sides)."""
     C = CONVENTIONS
     P = pxc.shape[0]
+    tol_v = 0.1 * IMG_TOL
     with torch.no_grad():
         rs, rm = pre["rect_sure"], pre["rect_maybe"]
         in_maybe = (rm[:, 0] <= tx) & (tx < rm[:, 2]) & (rm[:, 1] <= ty) & (ty < rm[:, 3])
@@ -410,50 +416,83 @@ def _tile_flags(pre, cam, tx, ty, pxc, pyc, ids, mg: Margins, h, w):
         cand = torch.nonzero(in_maybe & ~in_sure).reshape(-1)
         flag_v = torch.zeros(P, dtype=torch.bool)
         flag_g = torch.zeros(P, dtype=torch.bool)
+        flag_o = torch.zeros(P, dtype=torch.bool)   # some valid pair may be ordered either way
         if cand.numel() > 0:
             gv = _gval(pre, cand, pxc, pyc)
             flag_v |= (gv >= C["alpha_min"] * (1 - mg.rel)).any(1)
         if ids.numel() > 0:
             gv = _gval(pre, ids, pxc, pyc)
-            near_floor = ((gv - C["alpha_min"]).abs() < mg.rel * C["alpha_min"])
-            flag_v |= near_floor.any(1)
+            z = pre["z"].detach()[ids]
+            col = pre["color"].detach()[ids]
+            # largest change one fragment can make to any output, per unit weight a*T
+            reach = (col.abs().amax(-1) + z.abs() + 1.0)[None, :]
             valid = gv >= C["alpha_min"]
             a = torch.clamp(gv, max=C["alpha_max"])
             a_v = torch.where(valid, a, torch.zeros_like(a))
             t_incl = torch.cumprod(1.0 - a_v, dim=1)
-            near_stop = ((t_incl - C["t_stop"]).abs() < mg.rel * C["t_stop"]) & valid
-            flag_v |= near_stop.any(1)
-            alive = t_incl >= C["t_stop"] * (1 - mg.rel)
+            t_ex_v = torch.cat([torch.ones_like(t_incl[:, :1]), t_incl[:, :-1]], 1)
+            alive = t_incl >= C["t_stop"] * (1 - mg.stop_rel)
+            # alpha floor: a fragment within reach of 1/255 may be skipped or not
+            near_floor = (gv - C["alpha_min"]).abs() < mg.rel * C["alpha_min"]
+            nf = near_floor & (t_ex_v >= C["t_stop"] * (1 - mg.stop_rel))
+            flag_v |= (nf & (C["alpha_min"] * t_ex_v * reach > tol_v)).any(1)
+            flag_g |= nf.any(1)
+            # stop threshold: fragments whose T after them lies in the FP32 band
+            # around the threshold may or may not be blended
+            maybe = valid & (t_incl >= C["t_stop"] * (1 - mg.stop_rel)) & (t_incl < C["t_stop"] * (1 + mg.stop_rel))
+            eff = torch.where(maybe, (t_ex_v - t_incl) * reach, torch.zeros_like(t_incl)).sum(1)
+            flag_v |= eff > tol_v
+            flag_g |= maybe.any(1)
             contrib = valid & alive
-            # Depth near-ties: two consecutive contributors of a pixel whose
-            # depths are within FP32 reach may be blended in either order.
-            # Swapping adjacent contributors i, j changes the pixel by exactly
-            # a_i a_j T_i (c_i - c_j); flag the value when that can exceed a
-            # tenth of the image tolerance, the gradient when a_i a_j T_i does.
-            z = pre["z"].detach()[ids]
+            # Depth near-ties: two consecutive fragments of a pixel whose depths
+            # are within FP32 reach may be blended in either order.
             if ids.numel() > 1:
-                zc = torch.where(contrib, z[None, :], torch.full_like(a, float("inf")))
-                nz, nidx = torch.cummin(torch.flip(zc, [1]), dim=1)
-                nz, nidx = torch.flip(nz, [1]), (zc.shape[1] - 1) - torch.flip(nidx, [1])
-                nxt_z = torch.cat([nz[:, 1:], torch.full_like(nz[:, :1], float("inf"))], 1)
-                nxt_i = torch.cat([nidx[:, 1:], torch.zeros_like(nidx[:, :1])], 1)
-                tie = contrib & ((nxt_z - z[None, :]) < mg.depth_rel * z[None, :])
+                nxt_z, nxt_i = _next_of(valid, z)
+                tie = valid & ((nxt_z - z[None, :]) < mg.depth_rel * z[None, :])
+                flag_o |= tie.any(1)
                 if tie.any():
+                    # (a) the stop can fall inside the pair in one order and not
+                    # the other: T before the pair >= stop > T after both;
+                    # either fragment may then be blended or not
+                    a_nv = torch.gather(a_v, 1, nxt_i)
+                    t_after = t_ex_v * (1.0 - a_v) * (1.0 - a_nv)
+                    straddle = tie & (t_ex_v >= C["t_stop"] * (1 - mg.stop_rel)) & \
+                        (t_after < C["t_stop"] * (1 + mg.stop_rel))
+                    eff_s = (a_v + a_nv) * t_ex_v * torch.maximum(reach, torch.gather(reach.expand_as(a_v), 1, nxt_i))
+                    flag_v |= (straddle & (eff_s > tol_v)).any(1)
+                    flag_g |= straddle.any(1)
+                    # (b) both blended: swapping adjacent contributors i, j changes
+                    # the pixel by exactly a_i a_j T_i (c_i - c_j); flag the value
+                    # when that can exceed a tenth of the image tolerance, the
+                    # gradient when a_i a_j T_i does
+                    nxt_zc, nxt_ic = _next_of(contrib, z)
+                    tie_c = contrib & ((nxt_zc - z[None, :]) < mg.depth_rel * z[None, :])
                     a_c = torch.where(contrib, a, torch.zeros_like(a))
                     t_ex = torch.cat([torch.ones_like(a_c[:, :1]), torch.cumprod(1.0 - a_c, 1)[:, :-1]], 1)
-                    a_n = torch.gather(a_c, 1, nxt_i)
-                    col = pre["color"].detach()[ids]
-                    dc = (col[None, :, :] - col[nxt_i]).abs().amax(-1)
+                    a_n = torch.gather(a_c, 1, nxt_ic)
+                    dc = (col[None, :, :] - col[nxt_ic]).abs().amax(-1)
                     w2 = a_c * a_n * t_ex
-                    flag_v |= (tie & (w2 * dc > 0.1 * IMG_TOL)).any(1)
-                    flag_g |= (tie & (w2 > 0.01 * IMG_TOL)).any(1)
+                    flag_v |= (tie_c & (w2 * dc > tol_v)).any(1)
+                    flag_g |= (tie_c & (w2 > 0.1 * tol_v)).any(1)
             # gradient-only: alpha clamp, colour clamp, Jacobian clamp
             near_clamp = ((gv - C["alpha_max"]).abs() < mg.clamp_rel) & contrib
             col_m = (pre["color_raw"][ids].abs() < mg.clamp_rel).any(1)
             jac_m = pre["m_jac"][ids] < mg.clamp_rel
             flag_g |= near_clamp.any(1) | (contrib & (col_m | jac_m)[None, :]).any(1)
         flag_g |= flag_v
-    return dict(uncertain=flag_v.reshape(h, w), uncertain_grad=flag_g.reshape(h, w))
+    return dict(uncertain=flag_v.reshape(h, w), uncertain_grad=flag_g.reshape(h, w),
+                uncertain_order=(flag_o | flag_v).reshape(h, w))
+
+
+def _next_of(mask: torch.Tensor, z: torch.Tensor):
+    """Per pixel and list position k: depth and position of the next masked
+    entry after k (inf / 0 when none). z is ascending along the list."""
+    zm = torch.where(mask, z[None, :], torch.full(mask.shape, float("inf"), dtype=z.dtype))
+    nz, nidx = torch.cummin(torch.flip(zm, [1]), dim=1)
+    nz, nidx = torch.flip(nz, [1]), (zm.shape[1] - 1) - torch.flip(nidx, [1])
+    nxt_z = torch.cat([nz[:, 1:], torch.full_like(nz[:, :1], float("inf"))], 1)
+    nxt_i = torch.cat([nidx[:, 1:], torch.zeros_like(nidx[:, :1])], 1)
+    return nxt_z, nxt_i
 
 
 def _gval(pre, ids, pxc, pyc):
@@ -487,7 +526,7 @@ def assemble(out, cam, key: str, channels: int = 0) -> torch.Tensor:
     H, W = ocam.height, ocam.width
     shape = (channels, H, W) if channels else (H, W)
     img = torch.full(shape, float("nan"), dtype=F64)
-    if key in ("uncertain", "uncertain_grad"):
+    if key in ("uncertain", "uncertain_grad", "uncertain_order"):
         img = torch.zeros(shape, dtype=torch.bool)
     if key == "last":
         img = torch.zeros(shape, dtype=torch.long)

@@ -160,45 +160,72 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restr
   counts[(size_t)d * gridDim.x + blockIdx.x] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
 }
 
-// Single block: exclusive scan of counts[digit][block] (digit-major) in place.
-__global__ void __launch_bounds__(1024) k_rs_scan(uint32_t* __restrict__ counts, uint32_t len) {
-  __shared__ uint32_t s_part[1024];
-  const uint32_t per = (len + 1023) / 1024;
-  const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, len);
-  uint32_t acc = 0;
-  for (uint32_t b = b0; b < b1; ++b) acc += counts[b];
-  s_part[threadIdx.x] = acc;
+// Exclusive scan across a block of any multiple of 64 threads (<= 1024).
+__device__ __forceinline__ uint32_t block_exclusive_scan_any(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t y = threadIdx.x >= (unsigned)off ? s_part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    s_part[threadIdx.x] += y;
-    __syncthreads();
+  uint32_t base = 0;
+  total = 0;
+  for (int w = 0; w < nw; ++w) {
+    const uint32_t c = s_wave[w];
+    base += (w < wave) ? c : 0u;
+    total += c;
   }
-  uint32_t run = s_part[threadIdx.x] - acc;
-  for (uint32_t b = b0; b < b1; ++b) {
-    const uint32_t c = counts[b];
-    counts[b] = run;
-    run += c;
+  __syncthreads();
+  return base + x - v;
+}
+
+// One block per digit: exclusive scan of counts[digit][0..grid) in place and
+// the digit's total into digit_tot[digit].
+__global__ void __launch_bounds__(1024) k_rs_rowscan(uint32_t* __restrict__ counts, int grid,
+                                                     uint32_t* __restrict__ digit_tot) {
+  __shared__ uint32_t s_wave[16];
+  uint32_t* row = counts + (size_t)blockIdx.x * grid;
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < grid; b0 += blockDim.x) {
+    const int b = b0 + threadIdx.x;
+    const uint32_t v = b < grid ? row[b] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan_any(v, s_wave, tot);
+    if (b < grid) row[b] = carry + ex;
+    carry += tot;
   }
+  if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
 // Stable scatter of one digit pass. Within a 4096-element tile each wave owns
 // 1024 consecutive elements, processed 64 at a time; a lane's rank among equal
-// digits comes from a ballot match over the digit bits.
+// digits comes from a ballot match over the digit bits. The tile is reordered
+// by digit in LDS first, so the global writes of each digit run are contiguous.
 __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in,
                                                             uint32_t* __restrict__ keys_out,
                                                             uint32_t* __restrict__ vals_out, const uint32_t* n_dev,
                                                             uint32_t n_max, int shift, int bits,
-                                                            const uint32_t* __restrict__ offs) {
-  __shared__ uint32_t run[256];
+                                                            const uint32_t* __restrict__ counts,
+                                                            const uint32_t* __restrict__ digit_tot) {
+  __shared__ uint32_t s_k[kTileElems], s_v[kTileElems];
   __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t tstart[256];
+  __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t mask = (1u << bits) - 1u;
-  run[threadIdx.x] = offs[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+  const uint32_t dg = threadIdx.x;
+  {
+    uint32_t tot;
+    const uint32_t base = block_exclusive_scan(digit_tot[dg], s_wave, tot);
+    run[dg] = base + counts[(size_t)dg * gridDim.x + blockIdx.x];
+  }
   uint32_t t0, t1;
   block_range(n, gridDim.x, t0, t1);
   for (uint32_t t = t0; t < t1; ++t) {
@@ -230,29 +257,47 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
       if (valid && below == 0) wcnt[wave][d] = pre + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit: offsets of each wave inside this tile, then absolute bases
-    const uint32_t dg = threadIdx.x;
+    // per digit: tile-local start, then each wave's start inside it
     const uint32_t c0 = wcnt[0][dg], c1 = wcnt[1][dg], c2 = wcnt[2][dg], c3 = wcnt[3][dg];
-    const uint32_t r = run[dg];
-    __syncthreads();
-    wcnt[0][dg] = r;
-    wcnt[1][dg] = r + c0;
-    wcnt[2][dg] = r + c0 + c1;
-    wcnt[3][dg] = r + c0 + c1 + c2;
-    run[dg] = r + c0 + c1 + c2 + c3;
+    const uint32_t ctot = c0 + c1 + c2 + c3;
+    uint32_t all;
+    const uint32_t ts = block_exclusive_scan(ctot, s_wave, all);  // contains barriers
+    wcnt[0][dg] = ts;
+    wcnt[1][dg] = ts + c0;
+    wcnt[2][dg] = ts + c0 + c1;
+    wcnt[3][dg] = ts + c0 + c1 + c2;
+    tstart[dg] = ts;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const bool valid = base + (size_t)i * 64 + lane < n;
       if (valid) {
         const uint32_t d = (k[i] >> shift) & mask;
-        const uint32_t p = wcnt[wave][d] + rank[i];
-        if (p < n) {  // always true for consistent counts; keeps a ranking fault in bounds
-          keys_out[p] = k[i];
-          vals_out[p] = v[i];
+        const uint32_t lp = wcnt[wave][d] + rank[i];
+        if (lp < (uint32_t)kTileElems) {
+          s_k[lp] = k[i];
+          s_v[lp] = v[i];
         }
       }
     }
+    __syncthreads();
+    const size_t tbase = (size_t)t * kTileElems;
+    const uint32_t nvalid = (uint32_t)min((size_t)kTileElems, (size_t)n - tbase);
+#pragma unroll 4
+    for (int i = 0; i < kItems; ++i) {
+      const uint32_t lp = (uint32_t)i * kThreads + threadIdx.x;
+      if (lp < nvalid) {
+        const uint32_t key = s_k[lp];
+        const uint32_t d = (key >> shift) & mask;
+        const uint32_t p = run[d] + lp - tstart[d];
+        if (p < n) {  // always true for consistent counts; keeps a ranking fault in bounds
+          keys_out[p] = key;
+          vals_out[p] = s_v[lp];
+        }
+      }
+    }
+    __syncthreads();
+    run[dg] += ctot;
   }
 }
 
@@ -384,7 +429,7 @@ void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dk
   hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, act, pos, dkey, n, ckey, cval);
 }
 
-size_t radix_scratch_words(int grid) { return (size_t)256 * grid; }
+size_t radix_scratch_words(int grid) { return (size_t)256 * grid + 256; }
 
 int radix_grid(uint32_t n_max, int max_blocks) {
   const int need = (int)grid_for(n_max, kTileElems);
@@ -400,9 +445,9 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
   for (int b = bit0; b < bit1; b += 8) {
     const int bits = (bit1 - b) < 8 ? (bit1 - b) : 8;
     hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
-    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, s, scratch, (uint32_t)(256 * grid));
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, scratch, grid, scratch + (size_t)256 * grid);
     hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b, bits,
-                       scratch);
+                       scratch, scratch + (size_t)256 * grid);
     uint32_t* t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;
     ++passes;

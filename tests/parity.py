@@ -34,11 +34,12 @@ def oracle_view(scene, cam, t, bg=(0.0, 0.0, 0.0), tiles=None, requires_grad=Fal
     out = O.render_full(scene, cam, float(t), bg=bg, requires_grad=requires_grad, tiles=tiles)
     img = dict(rgb=O.assemble(out, cam, "rgb", 3), depth=O.assemble(out, cam, "depth"),
                alpha=O.assemble(out, cam, "alpha"), T=O.assemble(out, cam, "T"), last=O.assemble(out, cam, "last"),
-               unc=O.assemble(out, cam, "uncertain"), unc_g=O.assemble(out, cam, "uncertain_grad"))
+               unc=O.assemble(out, cam, "uncertain"), unc_g=O.assemble(out, cam, "uncertain_grad"),
+               unc_o=O.assemble(out, cam, "uncertain_order"))
     return out, img
 
 
-def compare_images(gpu_rgb, gpu_depth, gpu_alpha, img, max_flag_frac=2e-3, atol=IMG_ATOL):
+def compare_images(gpu_rgb, gpu_depth, gpu_alpha, img, max_flag_frac=1e-2, atol=IMG_ATOL):
     """gpu_*: numpy [3,H,W] / [H,W]; img from oracle_view. NaN in the oracle
     marks pixels not rendered there (sampled tiles)."""
     rgb = img["rgb"].detach().numpy()

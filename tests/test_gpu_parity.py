@@ -58,7 +58,8 @@ def test_forward_image_parity(name, mk_scene, mk_cam, t, bg):
     # per-pixel backward state: last contributor count matches away from flagged pixels
     last = r.debug("pix_last").reshape(cam.height, cam.width)
     ok = ~img["unc"].numpy()
-    assert (last[ok] == img["last"].numpy()[ok]).all()
+    ok_order = ok & ~img["unc_o"].numpy()        # list positions shift under an FP32 depth tie
+    assert (last[ok_order] == img["last"].numpy()[ok_order]).all()
     T = r.debug("pix_t").reshape(cam.height, cam.width)
     assert np.allclose(T[ok], img["T"].numpy()[ok], atol=2e-5)
 
@@ -246,3 +247,80 @@ def test_abi_errors():
     with pytest.raises(g4d.G4DError) as e:
         r.set_tuning(99, 1)
     assert e.value.status == g4d.G4D_EINVAL
+
+
+def _sampled_parity(wl, view, n_tiles, seed, dl_seed):
+    """Full-size render on the GPU; the oracle renders `n_tiles` random tiles
+    of one view; images compared there, gradients for dL/dI supported there."""
+    cam, t = wl.cameras[view], float(wl.times[view])
+    tiles = scenegen.sample_pixels_dlddi(seed, [cam], n_tiles)[0].tolist()
+    _say(f"  oracle on tiles {tiles}")
+    out, img = PT.oracle_view(wl.scene, cam, t, tiles=tiles, requires_grad=True)
+    r, _ = PT.gpu_setup(wl.scene)
+    V = len(wl.cameras)
+    rgb, dep, alp = r.render(wl.cameras, [float(x) for x in wl.times])
+    item = r.split(rgb, dep, alp)[view]
+    g_rgb, g_dep, g_alp = (_np(x) for x in item)
+    res = PT.compare_images(g_rgb, g_dep, g_alp, img)
+    _say(f"  image {res}")
+    rendered = ~np.isnan(img["depth"].detach().numpy())
+    mask = (rendered & ~img["unc_g"].numpy()).astype(np.float64)
+    drgb, ddep, dalp = PT.dl_maps(dl_seed, cam.height, cam.width, mask)
+    L = O.tile_linear_loss(out, torch.as_tensor(drgb), torch.as_tensor(ddep), torch.as_tensor(dalp), cam)
+    L.backward()
+    full_rgb = [np.zeros((3, c.height, c.width), np.float32) for c in wl.cameras]
+    full_dep = [np.zeros((c.height, c.width), np.float32) for c in wl.cameras]
+    full_alp = [np.zeros((c.height, c.width), np.float32) for c in wl.cameras]
+    full_rgb[view], full_dep[view], full_alp[view] = drgb, ddep, dalp
+    cat = lambda xs: torch.from_numpy(np.concatenate([x.reshape(-1) for x in xs]).astype(np.float32)).cuda()
+    g = r.backward(cat(full_rgb), cat(full_dep), cat(full_alp))
+    torch.cuda.synchronize()
+    rep = {}
+    PT.compare_grads(g, out["params"], report=rep)
+    _say(f"  grads rel L2 {rep}")
+
+
+def test_training_config_full_size_sampled():
+    """300k primitives, SH degree 3 x order 2, 1352x1014, random time."""
+    _say("[300k @ 1352x1014, sampled tiles]")
+    _sampled_parity(scenegen.make_workload(1), 0, 10, seed=1, dl_seed=12)
+
+
+def test_image_loss_kernel():
+    _say("[image loss]")
+    from paper_2310_10642_amd import g4d
+    r = g4d.Renderer(1, 1)
+    rng = np.random.default_rng(9)
+    n = 3 * 1000 + 7
+    img, tgt = rng.uniform(size=n).astype(np.float32), rng.uniform(size=n).astype(np.float32)
+    tgt[:5] = img[:5]                      # exact ties: zero L1 gradient
+    I, Tg = torch.from_numpy(img).cuda(), torch.from_numpy(tgt).cuda()
+    for kind, ref_l, ref_g in [(g4d.G4D_LOSS_L1, np.abs(img - tgt.astype(np.float64)).sum(),
+                                np.sign(img.astype(np.float64) - tgt)),
+                               (g4d.G4D_LOSS_L2, ((img.astype(np.float64) - tgt) ** 2).sum(),
+                                2 * (img.astype(np.float64) - tgt))]:
+        loss = torch.zeros(1, device="cuda")
+        grad = torch.empty(n, device="cuda")
+        r.image_loss(kind, I, Tg, 0.5, loss, grad)
+        torch.cuda.synchronize()
+        assert abs(float(loss) - 0.5 * ref_l) <= 1e-5 * 0.5 * ref_l
+        assert np.allclose(_np(grad), 0.5 * ref_g, rtol=1e-6, atol=1e-7)
+
+
+def test_stage_timing_and_stats():
+    _say("[stage timing]")
+    sc = _big_splat_scene(8, 2000)
+    cam = scenegen.look_at_camera((0.0, 0.0, 3.5), 64, 64)
+    r, _ = PT.gpu_setup(sc)
+    r.stage_timing(True)
+    r.render([cam, cam], [0.4, 0.6])
+    r.backward(torch.ones(2 * 3 * 64 * 64, device="cuda"))
+    st = r.stage_times()
+    r.stage_timing(False)
+    assert st["preprocess"][1] == 1 and st["binning"][1] == 2 and st["raster_fwd"][1] == 1
+    assert st["raster_bwd"][1] == 1 and st["preprocess_bwd"][1] == 1
+    assert all(ms >= 0 for ms, _ in st.values())
+    s = r.stats()
+    assert s["n_views"] == 2 and sum(s["active_per_view"]) == s["active_total"] > 0
+    last = r.debug("pix_last").astype(np.int64)
+    assert s["fragments"] == int(last.sum())
