@@ -206,7 +206,10 @@ __device__ __forceinline__ bool view_geometry(const float4 mu, const Shape4& sh,
   g.a2 = s00 + kLowpass;
   g.b2 = s01;
   g.c2 = s11 + kLowpass;
-  g.det = g.a2 * g.c2 - g.b2 * g.b2;
+  {  // a2 c2 - b2^2 without cancellation error (the b2^2 rounding error is recovered by an FMA)
+    const float p = g.b2 * g.b2;
+    g.det = fmaf(g.a2, g.c2, -p) - fmaf(g.b2, g.b2, -p);
+  }
   const float idet = 1.f / g.det;
   g.conic[0] = g.c2 * idet;
   g.conic[1] = -g.b2 * idet;
@@ -258,6 +261,22 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
       x1 = (int)fminf(fmaxf(floorf((g.u + rad) * ft) + 1.f, 0.f), (float)vw.tiles_x);
       y0 = (int)fminf(fmaxf(floorf((g.v - rad) * ft), 0.f), (float)vw.tiles_y);
       y1 = (int)fminf(fmaxf(floorf((g.v + rad) * ft) + 1.f, 0.f), (float)vw.tiles_y);
+      // Binning footprint: only tiles that can hold a pixel with
+      // opacity * exp(power) >= 1/255, i.e. inside the ellipse
+      // 1/2 d^T conic d <= ln(255 opacity); its bounding box has half-widths
+      // sqrt(2 K Sigma2d_00), sqrt(2 K Sigma2d_11). Every other tile of the
+      // 3-sigma rectangle would skip this primitive at every pixel, so the
+      // blend is unchanged. The slack keeps the box conservative under FP32.
+      const float K = __logf(255.f * opa * g.pt);
+      ok = ok && K > -1e-4f;
+      const float Kc = fmaxf(K, 0.f);
+      const float hx = sqrtf(2.f * Kc * g.a2) * 1.001f + 0.05f;
+      const float hy = sqrtf(2.f * Kc * g.c2) * 1.001f + 0.05f;
+      const float bx = (float)vw.tiles_x + 1.f, by = (float)vw.tiles_y + 1.f;
+      x0 = max(x0, (int)fminf(fmaxf(floorf((g.u - hx) * ft), -1.f), bx));
+      x1 = min(x1, (int)fminf(fmaxf(floorf((g.u + hx) * ft) + 1.f, -1.f), bx));
+      y0 = max(y0, (int)fminf(fmaxf(floorf((g.v - hy) * ft), -1.f), by));
+      y1 = min(y1, (int)fminf(fmaxf(floorf((g.v + hy) * ft) + 1.f, -1.f), by));
       ok = ok && (x1 > x0) && (y1 > y0) && isfinite(g.u) && isfinite(g.v);
     }
     if (!ok) {

@@ -1,19 +1,24 @@
 // Tile rasteriser: front-to-back alpha blending of Eq. (6) with p_i(t) folded
 // into each primitive's opacity (Sec. 3.2), and its backward pass.
 //
-// One workgroup per 16x16 tile (4 waves, one pixel per lane). The tile's
-// primitive list is staged through LDS in batches; every lane evaluates each
-// staged primitive for its own pixel, so LDS reads are broadcasts.
+// One workgroup per 16x16 tile; each of its 4 waves owns an 8x8 quadrant, one
+// pixel per lane. The tile's primitive list is staged through LDS in batches.
+// While staging, each entry's alpha-floor ellipse (the pixels where
+// opacity * exp(power) can reach 1/255) is bounded by a box and tested against
+// the four quadrants; every wave then walks only the entries that can touch
+// its quadrant. A skipped entry would have failed the 1/255 test at every
+// pixel of the quadrant, so the blend is unchanged. The per-fragment body is
+// branch-free: skipped and post-stop fragments get alpha 0.
 //
 // The forward pass keeps only the final transmittance and the number of list
 // entries up to the last contributor per pixel. The backward pass walks the
 // list back to front from there, recovering T_i = T_{i+1} / (1 - a_i), and
 // works in two phases per batch of 16 primitives: (1) each lane (pixel)
-// writes dL/dpower and a_i T_i for the 16 primitives into LDS; (2) the lanes
-// regroup as 16 primitives x 16 pixel columns and accumulate the per-primitive
-// sums over the tile's pixels from LDS. No cross-lane reduction is needed per
-// fragment; one 16-lane reduction per batch combines the columns, and one
-// atomic per value and (tile, primitive) adds the tile's share.
+// writes dL/dpower and a_i T_i for the batch into LDS; (2) the lanes regroup
+// as 16 primitives x 16 pixel columns and accumulate the per-primitive sums
+// over the tile's pixels (only over quadrants the primitive can touch). One
+// 16-lane reduction per batch combines the columns, and one atomic per value
+// and (tile, primitive) adds the tile's share.
 #include "g4d_common.h"
 
 namespace g4d {
@@ -22,6 +27,7 @@ namespace {
 constexpr int kFwdBatch = 256;
 constexpr int kBwdBatch = 16;
 constexpr int kGwStride = 256 + 16;  // padded LDS row per primitive (pixels)
+constexpr float kLn2 = 0.69314718055994531f;
 
 // log2 of opacity * exp(power) at offset (dx, dy) from the mean.
 // sa = (u, v, A, B), sb = (C, log2 opacity, ., .) with
@@ -34,6 +40,30 @@ __device__ __forceinline__ void stage_record(const Record& r, float4& sa, float4
   sa = make_float4(r.a.x, r.a.y, -0.5f * kLog2e * r.b.x, -kLog2e * r.b.y);
   sb = make_float4(-0.5f * kLog2e * r.b.z, __log2f(r.a.w), r.a.z, 0.f);
   sc = make_float4(r.c.x, r.c.y, r.c.z, 0.f);
+}
+
+// Bit q set when the alpha-floor box of the record can overlap quadrant q of
+// the tile (quadrant q covers pixel centres x0 + 8 (q & 1) + [0.5, 7.5],
+// y0 + 8 (q >> 1) + [0.5, 7.5]).
+__device__ __forceinline__ uint32_t quadrant_mask(const Record& r, float log2_opacity, float tile_x0, float tile_y0) {
+  const float K = (log2_opacity - kLog2AlphaMin) * kLn2;  // ln(255 opacity)
+  if (!(K > -1e-4f)) return 0u;
+  const float c0 = r.b.x, c1 = r.b.y, c2 = r.b.z;
+  // c0 c2 - c1^2 without cancellation error (the c1^2 rounding error is recovered by an FMA)
+  const float p = c1 * c1;
+  const float idet = 1.f / (fmaf(c0, c2, -p) - fmaf(c1, c1, -p));
+  const float Kc = fmaxf(K, 0.f);
+  const float hx = sqrtf(2.f * Kc * c2 * idet) * 1.001f + 0.05f;
+  const float hy = sqrtf(2.f * Kc * c0 * idet) * 1.001f + 0.05f;
+  const float u = r.a.x, v = r.a.y;
+  uint32_t m = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float xa = tile_x0 + 8.f * (q & 1) + 0.5f, ya = tile_y0 + 8.f * (q >> 1) + 0.5f;
+    const bool hit = (u + hx >= xa) && (u - hx <= xa + 7.f) && (v + hy >= ya) && (v - hy <= ya + 7.f);
+    m |= hit ? (1u << q) : 0u;
+  }
+  return m;
 }
 
 __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int tile) {
@@ -53,14 +83,19 @@ __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewD
                                                          float* __restrict__ out_depth, float* __restrict__ out_alpha,
                                                          float* __restrict__ pix_t, uint32_t* __restrict__ pix_last) {
   __shared__ float4 s_a[kFwdBatch], s_b[kFwdBatch], s_c[kFwdBatch];
+  __shared__ __align__(16) uint8_t s_mask[kFwdBatch];
+  __shared__ uint8_t s_list[4][kFwdBatch];
   const int tile = blockIdx.x;
   const int vi = find_view(views, n_views, tile);
   const ViewDev& vw = views[vi];
   const int lt = tile - vw.tile_base;
   const int tx = lt % vw.tiles_x, ty = lt / vw.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
   const bool inside = px < vw.width && py < vw.height;
   const float fx = px + 0.5f, fy = py + 0.5f;
+  const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
   const uint2 rg = ranges[tile];
   const int count = (int)(rg.y - rg.x);
 
@@ -70,6 +105,7 @@ __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewD
   for (int b0 = 0; b0 < count; b0 += kFwdBatch) {
     if (__syncthreads_count(done) == 256) break;
     const int e = b0 + threadIdx.x;
+    uint32_t mask = 0u;
     if (e < count) {
       const Record r = recs[ival[rg.x + e]];
       float4 sa, sb, sc;
@@ -77,30 +113,50 @@ __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewD
       s_a[threadIdx.x] = sa;
       s_b[threadIdx.x] = sb;
       s_c[threadIdx.x] = sc;
+      mask = quadrant_mask(r, sb.y, tile_x0, tile_y0);
     }
+    s_mask[threadIdx.x] = (uint8_t)mask;
     __syncthreads();
-    const int nb = min(kFwdBatch, count - b0);
-    if (!done) {
-      for (int j = 0; j < nb; ++j) {
-        const float4 sa = s_a[j];
-        const float4 sb = s_b[j];
-        const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
-        if (p2 < kLog2AlphaMin) continue;
-        const float a = fminf(__builtin_amdgcn_exp2f(p2), kAlphaMax);
-        const float Tn = fmaf(-a, T, T);
-        if (Tn < kTStop) {
-          done = true;
-          break;
-        }
-        const float4 sc = s_c[j];
-        const float w = a * T;
-        C0 = fmaf(w, sc.x, C0);
-        C1 = fmaf(w, sc.y, C1);
-        C2 = fmaf(w, sc.z, C2);
-        D = fmaf(w, sb.z, D);
-        T = Tn;
-        last = (uint32_t)(b0 + j + 1);
-      }
+    // per-wave list of the batch entries that can touch this wave's quadrant,
+    // in list order: lane l owns entries 4l .. 4l+3
+    const uint32_t m4 = *reinterpret_cast<const uint32_t*>(&s_mask[4 * lane]);
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bits |= ((m4 >> (8 * k + wave)) & 1u) << k;
+    const uint32_t cnt = (uint32_t)__popc(bits);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    const int nw = __shfl(incl, 63, 64);
+    uint32_t o = incl - cnt;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if ((bits >> k) & 1u) s_list[wave][o++] = (uint8_t)(4 * lane + k);
+    __syncthreads();
+    if (__all(done)) continue;
+    for (int k = 0; k < nw; ++k) {
+      const int j = s_list[wave][k];
+      const float4 sa = s_a[j];
+      const float4 sb = s_b[j];
+      const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
+      float a = fminf(__builtin_amdgcn_exp2f(p2), kAlphaMax);
+      a = (p2 >= kLog2AlphaMin && !done) ? a : 0.f;
+      const float Tn = fmaf(-a, T, T);
+      const bool stop = Tn < kTStop;  // T >= kTStop always, so stop implies a > 0
+      done = done || stop;
+      a = stop ? 0.f : a;
+      const float4 sc = s_c[j];
+      const float w = a * T;
+      C0 = fmaf(w, sc.x, C0);
+      C1 = fmaf(w, sc.y, C1);
+      C2 = fmaf(w, sc.z, C2);
+      D = fmaf(w, sb.z, D);
+      T = stop ? T : Tn;
+      last = (a > 0.f) ? (uint32_t)(b0 + j + 1) : last;
+      if ((k & 15) == 15 && __all(done)) break;
     }
   }
   if (!inside) return;
@@ -124,6 +180,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d) {
   __shared__ float4 s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch];
   __shared__ uint32_t s_d[kBwdBatch];
+  __shared__ uint32_t s_qm[kBwdBatch];
   __shared__ float2 s_gw[kBwdBatch * kGwStride];
   __shared__ float4 s_pix[256];
   __shared__ uint32_t s_max;
@@ -133,9 +190,13 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   const ViewDev& vw = views[vi];
   const int lt = tile - vw.tile_base;
   const int tx = lt % vw.tiles_x, ty = lt / vw.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
+  const int p_self = ly * 16 + lx;  // row-major pixel slot within the tile
+  const int px = tx * kTile + lx, py = ty * kTile + ly;
   const bool inside = px < vw.width && py < vw.height;
   const float fx = px + 0.5f, fy = py + 0.5f;
+  const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
   const uint2 rg = ranges[tile];
   const int count = (int)(rg.y - rg.x);
 
@@ -155,7 +216,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     T = pix_t[pix];
     last = pix_last[pix];
   }
-  s_pix[threadIdx.x] = make_float4(gC0, gC1, gC2, gD);
+  s_pix[p_self] = make_float4(gC0, gC1, gC2, gD);
   __syncthreads();
   if (last) atomicMax(&s_max, last);
   // "behind" accumulators: colour, depth and alpha of everything after the
@@ -170,66 +231,71 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     __syncthreads();
     if (threadIdx.x < kBwdBatch) {
       const int e = b0 + threadIdx.x;
+      uint32_t qm = 0u;
       if (e < count) {
         const uint32_t d = ival[rg.x + e];
+        const Record r = recs[d];
         float4 sa, sb, sc;
-        stage_record(recs[d], sa, sb, sc);
+        stage_record(r, sa, sb, sc);
         s_a[threadIdx.x] = sa;
         s_b[threadIdx.x] = sb;
         s_c[threadIdx.x] = sc;
         s_d[threadIdx.x] = d;
+        qm = quadrant_mask(r, sb.y, tile_x0, tile_y0);
       }
+      s_qm[threadIdx.x] = qm;
     }
     __syncthreads();
     // ---- phase 1: this lane's pixel, back to front over the batch ----
-#pragma unroll 4
     for (int j = kBwdBatch - 1; j >= 0; --j) {
-      float g = 0.f, w = 0.f;
-      if ((uint32_t)(b0 + j) < last) {
-        const float4 sa = s_a[j];
-        const float4 sb = s_b[j];
-        const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
-        if (p2 >= kLog2AlphaMin) {
-          const float G = __builtin_amdgcn_exp2f(p2);
-          const float a = fminf(G, kAlphaMax);
-          const float4 sc = s_c[j];
-          T = T / (1.f - a);
-          w = a * T;
-          const float dLda = T * (gC0 * (sc.x - B0) + gC1 * (sc.y - B1) + gC2 * (sc.z - B2) + gD * (sb.z - Bd) +
-                                  gA * (1.f - Ba));
-          B0 = fmaf(a, sc.x - B0, B0);
-          B1 = fmaf(a, sc.y - B1, B1);
-          B2 = fmaf(a, sc.z - B2, B2);
-          Bd = fmaf(a, sb.z - Bd, Bd);
-          Ba = fmaf(a, 1.f - Ba, Ba);
-          g = (G < kAlphaMax) ? dLda * G : 0.f;  // dL/dpower
-        }
-      }
-      s_gw[j * kGwStride + threadIdx.x] = make_float2(g, w);
+      if (!((s_qm[j] >> wave) & 1u)) continue;  // wave-uniform: no pixel of this quadrant
+      const float4 sa = s_a[j];
+      const float4 sb = s_b[j];
+      const float4 sc = s_c[j];
+      const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
+      const bool valid = ((uint32_t)(b0 + j) < last) && (p2 >= kLog2AlphaMin);
+      const float G = __builtin_amdgcn_exp2f(p2);
+      const float a = valid ? fminf(G, kAlphaMax) : 0.f;
+      T = T * __builtin_amdgcn_rcpf(1.f - a);
+      const float w = a * T;
+      const float dLda = T * (gC0 * (sc.x - B0) + gC1 * (sc.y - B1) + gC2 * (sc.z - B2) + gD * (sb.z - Bd) +
+                              gA * (1.f - Ba));
+      B0 = fmaf(a, sc.x - B0, B0);
+      B1 = fmaf(a, sc.y - B1, B1);
+      B2 = fmaf(a, sc.z - B2, B2);
+      Bd = fmaf(a, sb.z - Bd, Bd);
+      Ba = fmaf(a, 1.f - Ba, Ba);
+      const float g = (valid && G < kAlphaMax) ? dLda * G : 0.f;  // dL/dpower
+      s_gw[j * kGwStride + p_self] = make_float2(g, w);
     }
     __syncthreads();
-    // ---- phase 2: primitive j2, pixel column c2, rows 0..15 ----
+    // ---- phase 2: primitive j2, pixel column c2, rows of touched quadrants ----
     const int e2 = b0 + j2;
     float Sg = 0.f, Sgy = 0.f, Sgyy = 0.f, Sr = 0.f, Sgc = 0.f, Sb = 0.f, Sd = 0.f;
     float dx = 0.f;
     if (e2 < count) {
       const float4 sa = s_a[j2];
+      const uint32_t qm = s_qm[j2];
       dx = (float)(tx * kTile + c2) + 0.5f - sa.x;
       const float dy0 = (float)(ty * kTile) + 0.5f - sa.y;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int p = k * 16 + c2;
-        const float2 gw = s_gw[j2 * kGwStride + p];
-        const float4 pd = s_pix[p];
-        const float dy = dy0 + (float)k;
-        Sg += gw.x;
-        const float gdy = gw.x * dy;
-        Sgy += gdy;
-        Sgyy = fmaf(gdy, dy, Sgyy);
-        Sr = fmaf(gw.y, pd.x, Sr);
-        Sgc = fmaf(gw.y, pd.y, Sgc);
-        Sb = fmaf(gw.y, pd.z, Sb);
-        Sd = fmaf(gw.y, pd.w, Sd);
+      for (int half = 0; half < 2; ++half) {
+        if (!((qm >> ((c2 >> 3) + 2 * half)) & 1u)) continue;
+#pragma unroll
+        for (int k = 8 * half; k < 8 * half + 8; ++k) {
+          const int p = k * 16 + c2;
+          const float2 gw = s_gw[j2 * kGwStride + p];
+          const float4 pd = s_pix[p];
+          const float dy = dy0 + (float)k;
+          Sg += gw.x;
+          const float gdy = gw.x * dy;
+          Sgy += gdy;
+          Sgyy = fmaf(gdy, dy, Sgyy);
+          Sr = fmaf(gw.y, pd.x, Sr);
+          Sgc = fmaf(gw.y, pd.y, Sgc);
+          Sb = fmaf(gw.y, pd.z, Sb);
+          Sd = fmaf(gw.y, pd.w, Sd);
+        }
       }
     }
     float v[10] = {Sg, dx * Sg, Sgy, dx * dx * Sg, dx * Sgy, Sgyy, Sr, Sgc, Sb, Sd};

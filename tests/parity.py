@@ -80,6 +80,57 @@ def compare_grads(gpu_grads, oracle_params, rel=GRAD_REL, report=None):
     return out
 
 
+def alpha_floor_box(pre, cam, shrink_px=0.01):
+    """Per primitive, the tile range that can hold a pixel with
+    opacity * exp(power) >= 1/255 (FP64, slightly shrunk), intersected with
+    the 3-sigma rectangle, and whether any such tile exists. A binning
+    footprint must contain this range to leave the blend unchanged."""
+    u, v = pre["u"].detach().numpy(), pre["v"].detach().numpy()
+    cov2 = pre["cov2"].detach().numpy()
+    op = pre["opac"].detach().numpy()
+    rect = pre["rect"].numpy()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        K = np.log(255.0 * op)
+        hx = np.sqrt(np.maximum(2 * K * cov2[:, 0], 0)) - shrink_px
+        hy = np.sqrt(np.maximum(2 * K * cov2[:, 2], 0)) - shrink_px
+        box = np.stack([np.floor((u - hx) / 16), np.floor((v - hy) / 16),
+                        np.floor((u + hx) / 16) + 1, np.floor((v + hy) / 16) + 1], 1)
+    box = np.nan_to_num(box, nan=0.0, posinf=1e9, neginf=-1e9)
+    lo = np.maximum(box[:, :2], rect[:, :2])
+    hi = np.minimum(box[:, 2:], rect[:, 2:])
+    tight = np.concatenate([lo, hi], 1).astype(np.int64)
+    nonempty = (K > 0) & (hx > 0) & (hy > 0) & (tight[:, 2] > tight[:, 0]) & (tight[:, 3] > tight[:, 1])
+    return tight, nonempty
+
+
+def last_contributor_ids(r, cam, ids_gpu):
+    """Per pixel, the primitive id of the last contributor on the GPU (-1 if
+    none), from its per-pixel list count and its sorted tile lists."""
+    last = r.debug("pix_last").astype(np.int64).reshape(cam.height, cam.width)
+    vals = r.debug("tile_vals")
+    ranges = r.debug("ranges")
+    tx = (cam.width + 15) // 16
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    tile = (ys // 16) * tx + (xs // 16)
+    start = ranges[tile, 0].astype(np.int64)
+    pos = np.clip(start + last - 1, 0, max(len(vals) - 1, 0))
+    out = np.where(last > 0, ids_gpu[vals[pos]] if len(vals) else -1, -1)
+    return out
+
+
+def oracle_last_ids(out, cam):
+    H, W = cam.height, cam.width
+    res = np.full((H, W), -1, dtype=np.int64)
+    tx = (W + 15) // 16
+    for tid, part in out["parts"].items():
+        x0, y0 = (tid % tx) * 16, (tid // tx) * 16
+        last = part["last"].numpy()
+        ids = part["ids"].numpy()
+        h, w = last.shape
+        res[y0:y0 + h, x0:x0 + w] = np.where(last > 0, ids[np.maximum(last - 1, 0)] if len(ids) else -1, -1)
+    return res
+
+
 def dl_maps(seed, h, w, mask=None, scale_depth=0.1):
     rng = np.random.default_rng(seed)
     drgb = rng.normal(size=(3, h, w))
