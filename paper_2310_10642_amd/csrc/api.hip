@@ -45,6 +45,7 @@ struct g4d_ctx {
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
+  DevBuf bwd_scratch;
   uint32_t* counters_h = nullptr;  // pinned
 
   // stage timing (HIP events on the context's stream)
@@ -225,7 +226,7 @@ g4d_status g4d_destroy(g4d_ctx* c) {
   DevBuf* bufs[] = {&c->views_d, &c->act, &c->pos, &c->dkey, &c->rec, &c->slot, &c->ckey, &c->cval, &c->ckey2,
                     &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
                     &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
-                    &c->counters};
+                    &c->counters, &c->bwd_scratch};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->counters_h) (void)hipHostFree(c->counters_h);
@@ -433,9 +434,12 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
                          P<float>(c->pix_t), P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
   stage_end(c, G4D_STAGE_RASTER_BWD);
   RenderParams p = make_params(c);
+  if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(c->A)))) return st;
   stage_begin(c);
-  launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), g_means4, g_log_scales4, g_q_left,
-                             g_q_right, g_opacity_logit, g_coeffs, (flags & G4D_GRAD_ACCUMULATE) != 0, s);
+  launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), P<uint32_t>(c->counters) + kCntA, c->A,
+                             P<uint32_t>(c->cval), P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4,
+                             g_log_scales4, g_q_left, g_q_right, g_opacity_logit, g_coeffs,
+                             (flags & G4D_GRAD_ACCUMULATE) != 0, s);
   stage_end(c, G4D_STAGE_PREPROCESS_BWD);
   HIPCHK(c, hipGetLastError());
   return G4D_OK;

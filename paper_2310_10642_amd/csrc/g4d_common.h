@@ -58,9 +58,13 @@ struct RenderParams {
 // ---- launchers (preprocess.hip) ----
 void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
                        hipStream_t s);
+// ---- launchers (preprocess_bwd.hip) ----
+size_t preprocess_backward_scratch_floats(size_t n_records);
 void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const float* grad2d,
-                                float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
-                                float* g_opacity_logit, float* g_coeffs, bool accumulate, hipStream_t s);
+                                const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
+                                const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,
+                                float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
+                                bool accumulate, hipStream_t s);
 
 // ---- launchers (loss.hip) ----
 void launch_image_loss(int kind, uint64_t n, const float* img, const float* tgt, float scale, float* loss,

@@ -1,0 +1,391 @@
+// Backward of the per-primitive stages: from the per-record 2D gradients
+// (dL/du, dL/dv, dL/dconic, dL/d(opacity p), dL/drgb, dL/dz) to every 4D
+// parameter, summed over the views of a batch.
+//
+// Three kernels, so that each one reads or writes memory in the order it is
+// laid out:
+//   pairs:   one thread per active (view, primitive) record: the EWA
+//            projection, camera, opacity, temporal-marginal and slice chain
+//            (Sec. 3.2, Eqs. 3-4) up to dL/dSigma, dL/dmu and dL/dlogit of
+//            that view; the colour gradient is passed on (clamp decided from
+//            the record's colour).
+//   colour:  16 lanes per primitive, one per SH basis function: 4D
+//            spherindrical-harmonic coefficients (Sec. 3.2), read and written
+//            once and coalesced; per view the gradient to the view direction
+//            and to t - mu_t is reduced over the lanes and passed on.
+//   prims:   one thread per primitive: sums the views, adds the colour part
+//            through the slice, then Sigma = M M^T, M = R S, R = L(q_l) R(q_r)
+//            and the quaternion normalisation.
+#include "shade.h"
+
+namespace g4d {
+namespace {
+
+using namespace shade;
+
+// pair scratch layout (floats per active record)
+constexpr int kGeoFloats = 16;  // G4 upper triangle (10), dL/dmu (4), dL/dlogit, pad
+constexpr int kColFloats = 8;   // dL/draw (3), t - mu_t, view direction (3), 1/|mu_c - c|
+constexpr int kCgFloats = 4;    // dL/dmu_c and dL/d(t - mu_t) through the colour
+
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xF, 0xF, false));  // row_ror:2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xF, 0xF, false));  // row_ror:1
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_t* n_dev, uint32_t n_max,
+                                                    const uint32_t* __restrict__ ids, const Record* __restrict__ recs,
+                                                    const float* __restrict__ grad2d, float4* __restrict__ geo,
+                                                    float4* __restrict__ colbuf) {
+  const uint32_t n = min(*n_dev, n_max);
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n) return;
+  const uint32_t id = ids[d];
+  const int vi = (int)(id / (uint32_t)p.n);
+  const int gidx = (int)(id - (uint32_t)vi * (uint32_t)p.n);
+  const float4 mu = p.means4[gidx];
+  const float4 ls = p.log_scales4[gidx];
+  float inl, inr;
+  const float4 ql = normalize4(p.q_left[gidx], inl);
+  const float4 qr = normalize4(p.q_right[gidx], inr);
+  const float opa = 1.f / (1.f + __expf(-p.opacity_logit[gidx]));
+  Shape4 sh;
+  build_shape(ql, qr, ls, sh);
+  const ViewDev& vw = p.views[vi];
+  ViewGeom g;
+  view_geometry(mu, sh, vw, p.t_cull, p.near_plane, g);
+  const float4 q0 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * 12);
+  const float4 q1 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * 12 + 4);
+  const float4 q2 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * 12 + 8);
+  const float gu = q0.x, gv = q0.y, gC0 = q0.z, gC1 = q0.w, gC2 = q1.x, go = q1.y;
+  const float gdepth = q2.y;
+  // colour = max(0, raw + 0.5): the clamp passes the gradient where the blended colour is positive
+  const float4 rc = recs[d].c;
+  const float graw0 = rc.x > 0.f ? q1.z : 0.f;
+  const float graw1 = rc.y > 0.f ? q1.w : 0.f;
+  const float graw2 = rc.z > 0.f ? q2.x : 0.f;
+  colbuf[2 * (size_t)d] = make_float4(graw0, graw1, graw2, g.dt);
+  colbuf[2 * (size_t)d + 1] = make_float4(g.dir[0], g.dir[1], g.dir[2], g.rinv);
+
+  // ---- opacity * p(t) ----
+  const float gpt = go * opa;
+  const float glogit = go * g.pt * opa * (1.f - opa);
+  // ---- conic -> Sigma_2d: G_S = -Q G_Q Q ----
+  const float C0 = g.conic[0], C1 = g.conic[1], C2 = g.conic[2];
+  const float h1 = 0.5f * gC1;
+  const float X00 = C0 * gC0 + C1 * h1, X01 = C0 * h1 + C1 * gC2;
+  const float X10 = C1 * gC0 + C2 * h1, X11 = C1 * h1 + C2 * gC2;
+  const float G00 = -(X00 * C0 + X01 * C1);
+  const float G01 = -(X00 * C1 + X01 * C2);
+  const float G11 = -(X10 * C1 + X11 * C2);
+  // ---- Sigma_2d = T Sc T^T:  g_Sc = T^T G T,  g_T = 2 G T Sc ----
+  float GT[2][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    GT[0][k] = G00 * g.T[0][k] + G01 * g.T[1][k];
+    GT[1][k] = G01 * g.T[0][k] + G11 * g.T[1][k];
+  }
+  float gSc[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gSc[i][j] = g.T[0][i] * GT[0][j] + g.T[1][i] * GT[1][j];
+  float gT[2][3];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      gT[r][k] = 2.f * (GT[r][0] * g.Sc[0][k] + GT[r][1] * g.Sc[1][k] + GT[r][2] * g.Sc[2][k]);
+  // ---- T = J W:  g_J = g_T W^T ----
+  const float* W = vw.rot;
+  const float gJ00 = gT[0][0] * W[0] + gT[0][1] * W[1] + gT[0][2] * W[2];
+  const float gJ02 = gT[0][0] * W[6] + gT[0][1] * W[7] + gT[0][2] * W[8];
+  const float gJ11 = gT[1][0] * W[3] + gT[1][1] * W[4] + gT[1][2] * W[5];
+  const float gJ12 = gT[1][0] * W[6] + gT[1][1] * W[7] + gT[1][2] * W[8];
+  // ---- camera-space point (x, y, z) ----
+  const float x = g.pc[0], y = g.pc[1], iz = g.iz, iz2 = iz * iz;
+  float gx = gu * vw.fx * iz;
+  float gy = gv * vw.fy * iz;
+  float gz = gdepth - gu * vw.fx * x * iz2 - gv * vw.fy * y * iz2;
+  gz += -gJ00 * vw.fx * iz2 - gJ11 * vw.fy * iz2;
+  if (g.clx) {
+    gz += gJ02 * vw.fx * g.xi * iz2;
+  } else {
+    gx += -gJ02 * vw.fx * iz2;
+    gz += 2.f * gJ02 * vw.fx * g.xi * iz2;
+  }
+  if (g.cly) {
+    gz += gJ12 * vw.fy * g.eta * iz2;
+  } else {
+    gy += -gJ12 * vw.fy * iz2;
+    gz += 2.f * gJ12 * vw.fy * g.eta * iz2;
+  }
+  // p_cam = W mu_c + w
+  float gmuc[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) gmuc[i] = W[i] * gx + W[3 + i] * gy + W[6 + i] * gz;
+  // ---- slice: Sc = Sxyz - v v^T / S44, mu_c = mu_xyz + v lam ----
+  const float inv44 = 1.f / g.s44;
+  float Gv[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Gv[i] = gSc[i][0] * g.v3[0] + gSc[i][1] * g.v3[1] + gSc[i][2] * g.v3[2];
+  const float vGv = g.v3[0] * Gv[0] + g.v3[1] * Gv[1] + g.v3[2] * Gv[2];
+  float gv3[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) gv3[i] = -2.f * Gv[i] * inv44 + gmuc[i] * g.lam;
+  float gs44 = vGv * inv44 * inv44;
+  const float glam = gmuc[0] * g.v3[0] + gmuc[1] * g.v3[1] + gmuc[2] * g.v3[2];
+  float gdt = glam * inv44;
+  gs44 += -glam * g.lam * inv44;
+  // p(t) = exp(-dt^2 / (2 S44))
+  gdt += -gpt * g.pt * g.lam;
+  gs44 += gpt * g.pt * 0.5f * g.lam * g.lam;
+  // upper triangle of the symmetric dL/dSigma: (00 01 02 03 | 11 12 13 22 | 23 33)
+  float4* o = geo + 4 * (size_t)d;
+  o[0] = make_float4(gSc[0][0], 0.5f * (gSc[0][1] + gSc[1][0]), 0.5f * (gSc[0][2] + gSc[2][0]), 0.5f * gv3[0]);
+  o[1] = make_float4(gSc[1][1], 0.5f * (gSc[1][2] + gSc[2][1]), 0.5f * gv3[1], gSc[2][2]);
+  o[2] = make_float4(0.5f * gv3[2], gs44, gmuc[0], gmuc[1]);
+  o[3] = make_float4(gmuc[2], -gdt, glogit, 0.f);
+}
+
+// 16 lanes per primitive (lane = SH basis index lm); lanes with lm >= (L+1)^2 idle.
+__global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
+                                                     const float4* __restrict__ colbuf, float4* __restrict__ cgbuf,
+                                                     float* __restrict__ g_coeffs, bool accumulate) {
+  const int gidx = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
+  const int lm = threadIdx.x & 15;
+  if (gidx >= p.n) return;  // uniform per 16-lane group
+  const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
+  const int nt = p.t_order + 1;
+  const int K = nt * nb;
+  const bool lane_on = lm < nb;
+  const float* kc = p.coeffs + (size_t)gidx * K * 3;
+  float k[3][3], gk[3][3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      k[n][c] = (lane_on && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+      gk[n][c] = 0.f;
+    }
+  bool any = false;
+  for (int vi = 0; vi < p.n_views; ++vi) {
+    const int d = slot[(size_t)vi * p.n + gidx];
+    if (d < 0) continue;
+    any = true;
+    const float4 c0 = colbuf[2 * (size_t)d];
+    const float4 c1 = colbuf[2 * (size_t)d + 1];
+    const float graw[3] = {c0.x, c0.y, c0.z};
+    const float dt = c0.w;
+    float Y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Y[i] = 0.f;
+    sh_eval(p.sh_degree, c1.x, c1.y, c1.z, Y);
+    float ylm = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ylm = (i == lm) ? Y[i] : ylm;
+    if (!lane_on) ylm = 0.f;
+    float cs[3], sn[3];
+    const float ph = 2.f * dt / p.t_period;
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      cs[n] = (n == 0) ? 1.f : (n < nt ? cospif(n * ph) : 0.f);
+      sn[n] = (n == 0) ? 0.f : (n < nt ? sinpif(n * ph) : 0.f);
+    }
+    // kd_n = sum_ch graw_ch k[n][lm][ch]
+    float kd[3], gy = 0.f;
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      kd[n] = fmaf(graw[0], k[n][0], fmaf(graw[1], k[n][1], graw[2] * k[n][2]));
+      gy = fmaf(cs[n], kd[n], gy);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gk[n][c] = fmaf(cs[n] * ylm, graw[c], gk[n][c]);
+    }
+    // gradient of this lane's basis function in the view direction
+    float gY[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) gY[i] = (i == lm && lane_on) ? gy : 0.f;
+    float gdx, gdy, gdz;
+    sh_grad(p.sh_degree, c1.x, c1.y, c1.z, gY, gdx, gdy, gdz);
+    gdx = row16_sum(gdx);
+    gdy = row16_sum(gdy);
+    gdz = row16_sum(gdz);
+    // d/d(dt) cos(2 pi n dt / T) = -(2 pi n / T) sin(2 pi n dt / T)
+    float gdt = 0.f;
+#pragma unroll
+    for (int n = 1; n < 3; ++n) {
+      const float gcos = row16_sum(ylm * kd[n]);
+      gdt = fmaf(gcos, -2.f * kPi * n / p.t_period * sn[n], gdt);
+    }
+    if (lm == 0) {
+      const float dd = gdx * c1.x + gdy * c1.y + gdz * c1.z;
+      cgbuf[d] = make_float4((gdx - c1.x * dd) * c1.w, (gdy - c1.y * dd) * c1.w, (gdz - c1.z * dd) * c1.w, gdt);
+    }
+  }
+  if (!lane_on || (accumulate && !any)) return;
+  float* out = g_coeffs + (size_t)gidx * K * 3;
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    if (n >= nt) break;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float* q = out + (n * nb + lm) * 3 + c;
+      *q = accumulate ? *q + gk[n][c] : gk[n][c];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t* __restrict__ slot,
+                                                   const float4* __restrict__ geo, const float4* __restrict__ cgbuf,
+                                                   float4* __restrict__ g_means4, float4* __restrict__ g_log_scales4,
+                                                   float4* __restrict__ g_q_left, float4* __restrict__ g_q_right,
+                                                   float* __restrict__ g_logit, bool accumulate) {
+  const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gidx >= p.n) return;
+  bool any = false;
+  for (int vi = 0; vi < p.n_views; ++vi) any |= slot[(size_t)vi * p.n + gidx] >= 0;
+  if (!any) {
+    if (accumulate) return;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    g_means4[gidx] = z;
+    g_log_scales4[gidx] = z;
+    g_q_left[gidx] = z;
+    g_q_right[gidx] = z;
+    g_logit[gidx] = 0.f;
+    return;
+  }
+  const float4 mu = p.means4[gidx];
+  const float4 ls = p.log_scales4[gidx];
+  float inl, inr;
+  const float4 ql = normalize4(p.q_left[gidx], inl);
+  const float4 qr = normalize4(p.q_right[gidx], inr);
+  Shape4 sh;
+  build_shape(ql, qr, ls, sh);
+  const float s44 = sh.S[3][3], inv44 = 1.f / s44;
+  const float v3[3] = {sh.S[0][3], sh.S[1][3], sh.S[2][3]};
+
+  float G4[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) G4[i][j] = 0.f;
+  float gmu[4] = {0.f, 0.f, 0.f, 0.f};
+  float glogit = 0.f;
+  for (int vi = 0; vi < p.n_views; ++vi) {
+    const int d = slot[(size_t)vi * p.n + gidx];
+    if (d < 0) continue;
+    const float4 a = geo[4 * (size_t)d], b = geo[4 * (size_t)d + 1], c = geo[4 * (size_t)d + 2];
+    const float4 e = geo[4 * (size_t)d + 3];
+    G4[0][0] += a.x; G4[0][1] += a.y; G4[0][2] += a.z; G4[0][3] += a.w;
+    G4[1][1] += b.x; G4[1][2] += b.y; G4[1][3] += b.z; G4[2][2] += b.w;
+    G4[2][3] += c.x; G4[3][3] += c.y;
+    gmu[0] += c.z; gmu[1] += c.w; gmu[2] += e.x; gmu[3] += e.y;
+    glogit += e.z;
+    // colour part through the slice: mu_c = mu_xyz + v lam, lam = (t - mu_t) / S44
+    const float4 cg = cgbuf[d];
+    const float lam = (p.views[vi].t - mu.w) * inv44;
+    const float glam = cg.x * v3[0] + cg.y * v3[1] + cg.z * v3[2];
+    gmu[0] += cg.x; gmu[1] += cg.y; gmu[2] += cg.z;
+    G4[0][3] += 0.5f * cg.x * lam;
+    G4[1][3] += 0.5f * cg.y * lam;
+    G4[2][3] += 0.5f * cg.z * lam;
+    G4[3][3] += -glam * lam * inv44;
+    gmu[3] += -(glam * inv44 + cg.w);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j) G4[i][j] = G4[j][i];
+
+  // ---- Sigma = M M^T, M = R S:  g_M = 2 G4 M ----
+  float gR[4][4], gs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float gm = 2.f * (G4[i][0] * sh.M[0][k] + G4[i][1] * sh.M[1][k] + G4[i][2] * sh.M[2][k] +
+                              G4[i][3] * sh.M[3][k]);
+      gR[i][k] = gm * sh.s[k];
+      gs[k] = fmaf(gm, sh.R[i][k], gs[k]);
+    }
+  // ---- R = L Rr:  g_L = g_R Rr^T,  g_Rr = L^T g_R ----
+  float L[4][4], Rr[4][4], gL[4][4], gRr[4][4];
+  isoclinic_left(ql, L);
+  isoclinic_right(qr, Rr);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float a = 0.f, b = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a = fmaf(gR[i][k], Rr[j][k], a);
+        b = fmaf(L[k][i], gR[k][j], b);
+      }
+      gL[i][j] = a;
+      gRr[i][j] = b;
+    }
+  // matrix-entry gradients to quaternion components (sign patterns of the two matrices)
+  float4 gql, gqr;
+  gql.x = gL[0][0] + gL[1][1] + gL[2][2] + gL[3][3];
+  gql.y = -gL[0][1] + gL[1][0] - gL[2][3] + gL[3][2];
+  gql.z = -gL[0][2] + gL[1][3] + gL[2][0] - gL[3][1];
+  gql.w = -gL[0][3] - gL[1][2] + gL[2][1] + gL[3][0];
+  gqr.x = gRr[0][0] + gRr[1][1] + gRr[2][2] + gRr[3][3];
+  gqr.y = -gRr[0][1] + gRr[1][0] + gRr[2][3] - gRr[3][2];
+  gqr.z = -gRr[0][2] - gRr[1][3] + gRr[2][0] + gRr[3][1];
+  gqr.w = -gRr[0][3] + gRr[1][2] - gRr[2][1] + gRr[3][0];
+  // normalisation q_hat = q / |q|
+  const float dl = gql.x * ql.x + gql.y * ql.y + gql.z * ql.z + gql.w * ql.w;
+  const float dr = gqr.x * qr.x + gqr.y * qr.y + gqr.z * qr.z + gqr.w * qr.w;
+  float4 o_ql = make_float4((gql.x - ql.x * dl) * inl, (gql.y - ql.y * dl) * inl, (gql.z - ql.z * dl) * inl,
+                            (gql.w - ql.w * dl) * inl);
+  float4 o_qr = make_float4((gqr.x - qr.x * dr) * inr, (gqr.y - qr.y * dr) * inr, (gqr.z - qr.z * dr) * inr,
+                            (gqr.w - qr.w * dr) * inr);
+  float4 o_ls = make_float4(gs[0] * sh.s[0], gs[1] * sh.s[1], gs[2] * sh.s[2], gs[3] * sh.s[3]);
+  float4 o_mu = make_float4(gmu[0], gmu[1], gmu[2], gmu[3]);
+  if (accumulate) {
+    const float4 a = g_q_left[gidx], b = g_q_right[gidx], c = g_log_scales4[gidx], d = g_means4[gidx];
+    o_ql = make_float4(o_ql.x + a.x, o_ql.y + a.y, o_ql.z + a.z, o_ql.w + a.w);
+    o_qr = make_float4(o_qr.x + b.x, o_qr.y + b.y, o_qr.z + b.z, o_qr.w + b.w);
+    o_ls = make_float4(o_ls.x + c.x, o_ls.y + c.y, o_ls.z + c.z, o_ls.w + c.w);
+    o_mu = make_float4(o_mu.x + d.x, o_mu.y + d.y, o_mu.z + d.z, o_mu.w + d.w);
+    glogit += g_logit[gidx];
+  }
+  g_q_left[gidx] = o_ql;
+  g_q_right[gidx] = o_qr;
+  g_log_scales4[gidx] = o_ls;
+  g_means4[gidx] = o_mu;
+  g_logit[gidx] = glogit;
+}
+
+}  // namespace
+
+size_t preprocess_backward_scratch_floats(size_t n_records) {
+  return n_records * (kGeoFloats + kColFloats + kCgFloats);
+}
+
+void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const float* grad2d,
+                                const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
+                                const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,
+                                float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
+                                bool accumulate, hipStream_t s) {
+  if (p.n == 0) return;
+  float4* geo = reinterpret_cast<float4*>(scratch);
+  float4* col = reinterpret_cast<float4*>(scratch + (size_t)n_records_max * kGeoFloats);
+  float4* cg = reinterpret_cast<float4*>(scratch + (size_t)n_records_max * (kGeoFloats + kColFloats));
+  if (n_records_max > 0)
+    hipLaunchKernelGGL(k_bwd_pairs, dim3((n_records_max + 255) / 256), dim3(256), 0, s, p, n_records_dev,
+                       n_records_max, ids, recs, grad2d, geo, col);
+  hipLaunchKernelGGL(k_bwd_colour, dim3((unsigned)(((size_t)p.n * 16 + 255) / 256)), dim3(256), 0, s, p, slot, col,
+                     cg, g_coeffs, accumulate);
+  hipLaunchKernelGGL(k_bwd_prims, dim3((p.n + 127) / 128), dim3(128), 0, s, p, slot, geo, cg,
+                     reinterpret_cast<float4*>(g_means4), reinterpret_cast<float4*>(g_log_scales4),
+                     reinterpret_cast<float4*>(g_q_left), reinterpret_cast<float4*>(g_q_right), g_opacity_logit,
+                     accumulate);
+}
+
+}  // namespace g4d

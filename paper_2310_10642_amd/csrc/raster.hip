@@ -16,9 +16,9 @@
 // works in two phases per batch of 16 primitives: (1) each lane (pixel)
 // writes dL/dpower and a_i T_i for the batch into LDS; (2) the lanes regroup
 // as 16 primitives x 16 pixel columns and accumulate the per-primitive sums
-// over the tile's pixels (only over quadrants the primitive can touch). One
-// 16-lane reduction per batch combines the columns, and one atomic per value
-// and (tile, primitive) adds the tile's share.
+// over the tile's pixels (only over quadrants where the primitive blended).
+// One 16-lane DPP reduction per batch combines the columns, and one atomic
+// per value and (tile, primitive) adds the tile's share.
 #include "g4d_common.h"
 
 namespace g4d {
@@ -26,7 +26,14 @@ namespace {
 
 constexpr int kFwdBatch = 256;
 constexpr int kBwdBatch = 16;
-constexpr int kGwStride = 256 + 16;  // padded LDS row per primitive (pixels)
+// Backward LDS slots of one primitive's per-pixel values: pixel (row, col) of
+// the tile sits at 16 row + (col ^ 8 [(row >> 1) & 1]); the x-halves of rows
+// 2-3 of every four are swapped so that a wave's 8x8 quadrant (4 rows per
+// half-wave) hits 32 distinct banks when writing, and 16 columns x 2
+// primitives (stride 272 = 16 mod 32) do when reading. Unpadded rows keep the
+// workgroup at <= 40 KB of LDS, i.e. 4 workgroups per CU.
+constexpr int kGwStride = 256 + 16;
+__device__ __forceinline__ int gw_slot(int row, int col) { return 16 * row + (col ^ (((row >> 1) & 1) << 3)); }
 constexpr float kLn2 = 0.69314718055994531f;
 
 // log2 of opacity * exp(power) at offset (dx, dy) from the mean.
@@ -73,6 +80,21 @@ __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int 
     if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// Sum over each 16-lane row with DPP row rotations (every lane gets the sum).
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xF, 0xF, false));  // row_ror:2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xF, 0xF, false));  // row_ror:1
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+  return v;
 }
 
 __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewDev* __restrict__ views,
@@ -173,6 +195,9 @@ __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewD
   pix_last[pix] = last;
 }
 
+// HAS_D / HAS_A: whether dL/d(depth) and dL/d(alpha) are given (otherwise
+// their terms are compiled out).
+template <bool HAS_D, bool HAS_A>
 __global__ void __launch_bounds__(256) k_raster_backward(
     int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
@@ -181,7 +206,9 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   __shared__ float4 s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch];
   __shared__ uint32_t s_d[kBwdBatch];
   __shared__ uint32_t s_qm[kBwdBatch];
-  __shared__ float2 s_gw[kBwdBatch * kGwStride];
+  __shared__ uint8_t s_act[4][kBwdBatch];  // entry blended somewhere in quadrant
+  __shared__ float s_g[kBwdBatch * kGwStride];   // dL/dpower per (primitive, pixel)
+  __shared__ float s_w[kBwdBatch * kGwStride];   // a_i T_i per (primitive, pixel)
   __shared__ float4 s_pix[256];
   __shared__ uint32_t s_max;
 
@@ -192,7 +219,8 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   const int tx = lt % vw.tiles_x, ty = lt / vw.tiles_x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
-  const int p_self = ly * 16 + lx;  // row-major pixel slot within the tile
+  const int p_self = ly * 16 + lx;                  // row-major pixel index within the tile
+  const int q_self = gw_slot(ly, lx);               // this pixel's slot in s_g / s_w
   const int px = tx * kTile + lx, py = ty * kTile + ly;
   const bool inside = px < vw.width && py < vw.height;
   const float fx = px + 0.5f, fy = py + 0.5f;
@@ -211,14 +239,15 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     gC0 = g[0];
     gC1 = g[hw];
     gC2 = g[2 * hw];
-    if (dl_depth) gD = dl_depth[pix];
-    if (dl_alpha) gA = dl_alpha[pix];
+    if (HAS_D) gD = dl_depth[pix];
+    if (HAS_A) gA = dl_alpha[pix];
     T = pix_t[pix];
     last = pix_last[pix];
   }
   s_pix[p_self] = make_float4(gC0, gC1, gC2, gD);
+  const uint32_t wave_last = wave_max_u32(last);
   __syncthreads();
-  if (last) atomicMax(&s_max, last);
+  if (lane == 0 && wave_last) atomicMax(&s_max, wave_last);
   // "behind" accumulators: colour, depth and alpha of everything after the
   // current primitive, normalised by the transmittance after it
   float B0 = bg0, B1 = bg1, B2 = bg2, Bd = 0.f, Ba = 0.f;
@@ -227,64 +256,82 @@ __global__ void __launch_bounds__(256) k_raster_backward(
 
   const int j2 = threadIdx.x >> 4;  // phase 2: primitive within the batch
   const int c2 = threadIdx.x & 15;  // phase 2: pixel column
-  for (int b0 = ((max_last + kBwdBatch - 1) / kBwdBatch - 1) * kBwdBatch; b0 >= 0; b0 -= kBwdBatch) {
+  const int b_first = ((max_last + kBwdBatch - 1) / kBwdBatch - 1) * kBwdBatch;
+  // records of the next batch are loaded one batch ahead (threads < 16)
+  Record nxt;
+  uint32_t nxt_d = 0;
+  if (threadIdx.x < kBwdBatch && b_first >= 0 && b_first + (int)threadIdx.x < count) {
+    nxt_d = ival[rg.x + b_first + threadIdx.x];
+    nxt = recs[nxt_d];
+  }
+  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch) {
     __syncthreads();
     if (threadIdx.x < kBwdBatch) {
-      const int e = b0 + threadIdx.x;
       uint32_t qm = 0u;
-      if (e < count) {
-        const uint32_t d = ival[rg.x + e];
-        const Record r = recs[d];
+      if (b0 + (int)threadIdx.x < count) {
         float4 sa, sb, sc;
-        stage_record(r, sa, sb, sc);
+        stage_record(nxt, sa, sb, sc);
         s_a[threadIdx.x] = sa;
         s_b[threadIdx.x] = sb;
         s_c[threadIdx.x] = sc;
-        s_d[threadIdx.x] = d;
-        qm = quadrant_mask(r, sb.y, tile_x0, tile_y0);
+        s_d[threadIdx.x] = nxt_d;
+        qm = quadrant_mask(nxt, sb.y, tile_x0, tile_y0);
       }
       s_qm[threadIdx.x] = qm;
+      const int en = b0 - kBwdBatch + (int)threadIdx.x;
+      if (en >= 0) {  // prefetch the next (earlier) batch
+        nxt_d = ival[rg.x + en];
+        nxt = recs[nxt_d];
+      }
     }
+    if (lane < kBwdBatch) s_act[wave][lane] = 0;
     __syncthreads();
     // ---- phase 1: this lane's pixel, back to front over the batch ----
     for (int j = kBwdBatch - 1; j >= 0; --j) {
-      if (!((s_qm[j] >> wave) & 1u)) continue;  // wave-uniform: no pixel of this quadrant
+      // wave-uniform skips: no pixel of this quadrant reaches the entry
+      if (!((s_qm[j] >> wave) & 1u) || (uint32_t)(b0 + j) >= wave_last) continue;
       const float4 sa = s_a[j];
       const float4 sb = s_b[j];
-      const float4 sc = s_c[j];
       const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
       const bool valid = ((uint32_t)(b0 + j) < last) && (p2 >= kLog2AlphaMin);
+      if (!__any(valid)) continue;
+      const float4 sc = s_c[j];
       const float G = __builtin_amdgcn_exp2f(p2);
       const float a = valid ? fminf(G, kAlphaMax) : 0.f;
       T = T * __builtin_amdgcn_rcpf(1.f - a);
       const float w = a * T;
-      const float dLda = T * (gC0 * (sc.x - B0) + gC1 * (sc.y - B1) + gC2 * (sc.z - B2) + gD * (sb.z - Bd) +
-                              gA * (1.f - Ba));
+      float s = gC0 * (sc.x - B0) + gC1 * (sc.y - B1) + gC2 * (sc.z - B2);
+      if (HAS_D) s = fmaf(gD, sb.z - Bd, s);
+      if (HAS_A) s = fmaf(gA, 1.f - Ba, s);
+      const float dLda = T * s;
       B0 = fmaf(a, sc.x - B0, B0);
       B1 = fmaf(a, sc.y - B1, B1);
       B2 = fmaf(a, sc.z - B2, B2);
-      Bd = fmaf(a, sb.z - Bd, Bd);
-      Ba = fmaf(a, 1.f - Ba, Ba);
+      if (HAS_D) Bd = fmaf(a, sb.z - Bd, Bd);
+      if (HAS_A) Ba = fmaf(a, 1.f - Ba, Ba);
       const float g = (valid && G < kAlphaMax) ? dLda * G : 0.f;  // dL/dpower
-      s_gw[j * kGwStride + p_self] = make_float2(g, w);
+      s_g[j * kGwStride + q_self] = g;
+      s_w[j * kGwStride + q_self] = w;
+      if (lane == 0) s_act[wave][j] = 1;
     }
     __syncthreads();
-    // ---- phase 2: primitive j2, pixel column c2, rows of touched quadrants ----
+    // ---- phase 2: primitive j2, pixel column c2, rows of active quadrants ----
     const int e2 = b0 + j2;
     float Sg = 0.f, Sgy = 0.f, Sgyy = 0.f, Sr = 0.f, Sgc = 0.f, Sb = 0.f, Sd = 0.f;
     float dx = 0.f;
     if (e2 < count) {
       const float4 sa = s_a[j2];
-      const uint32_t qm = s_qm[j2];
       dx = (float)(tx * kTile + c2) + 0.5f - sa.x;
       const float dy0 = (float)(ty * kTile) + 0.5f - sa.y;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        if (!((qm >> ((c2 >> 3) + 2 * half)) & 1u)) continue;
+        const int q = (c2 >> 3) + 2 * half;
+        if (!s_act[q][j2]) continue;
 #pragma unroll
         for (int k = 8 * half; k < 8 * half + 8; ++k) {
           const int p = k * 16 + c2;
-          const float2 gw = s_gw[j2 * kGwStride + p];
+          const int slot = j2 * kGwStride + gw_slot(k, c2);
+          const float2 gw = make_float2(s_g[slot], s_w[slot]);
           const float4 pd = s_pix[p];
           const float dy = dy0 + (float)k;
           Sg += gw.x;
@@ -294,35 +341,37 @@ __global__ void __launch_bounds__(256) k_raster_backward(
           Sr = fmaf(gw.y, pd.x, Sr);
           Sgc = fmaf(gw.y, pd.y, Sgc);
           Sb = fmaf(gw.y, pd.z, Sb);
-          Sd = fmaf(gw.y, pd.w, Sd);
+          if (HAS_D) Sd = fmaf(gw.y, pd.w, Sd);
         }
       }
     }
+    // v: Sg, Sgx, Sgy, Sgxx, Sgxy, Sgyy, w*dL/dr, w*dL/dg, w*dL/db, w*dL/dD
     float v[10] = {Sg, dx * Sg, Sgy, dx * dx * Sg, dx * Sgy, Sgyy, Sr, Sgc, Sb, Sd};
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1)
-#pragma unroll
-      for (int q = 0; q < 10; ++q) v[q] += __shfl_xor(v[q], off, 16);
+    for (int q = 0; q < 10; ++q) {
+      if (!HAS_D && q == 9) continue;
+      v[q] = row16_sum(v[q]);
+    }
     if (c2 == 0 && e2 < count) {
       bool nz = false;
 #pragma unroll
       for (int q = 0; q < 10; ++q) nz |= (v[q] != 0.f);
       if (nz) {
         const uint32_t d = s_d[j2];
-        const Record r = recs[d];
-        const float k0 = r.b.x, k1 = r.b.y, k2 = r.b.z;
-        // v: Sg, Sgx, Sgy, Sgxx, Sgxy, Sgyy, w*dL/dr, w*dL/dg, w*dL/db, w*dL/dD
+        const float k0 = s_a[j2].z * (-2.f / kLog2e), k1 = s_a[j2].w * (-1.f / kLog2e);
+        const float k2 = s_b[j2].x * (-2.f / kLog2e);
+        const float opac = __builtin_amdgcn_exp2f(s_b[j2].y);
         float* o = grad2d + (size_t)d * 12;
         unsafeAtomicAdd(o + 0, k0 * v[1] + k1 * v[2]);   // dL/du
         unsafeAtomicAdd(o + 1, k1 * v[1] + k2 * v[2]);   // dL/dv
         unsafeAtomicAdd(o + 2, -0.5f * v[3]);            // dL/dconic00
         unsafeAtomicAdd(o + 3, -v[4]);                   // dL/dconic01
         unsafeAtomicAdd(o + 4, -0.5f * v[5]);            // dL/dconic11
-        unsafeAtomicAdd(o + 5, v[0] / r.a.w);            // dL/d(opacity p)
+        unsafeAtomicAdd(o + 5, v[0] / opac);             // dL/d(opacity p)
         unsafeAtomicAdd(o + 6, v[6]);
         unsafeAtomicAdd(o + 7, v[7]);
         unsafeAtomicAdd(o + 8, v[8]);
-        unsafeAtomicAdd(o + 9, v[9]);                    // dL/dz
+        if (HAS_D) unsafeAtomicAdd(o + 9, v[9]);         // dL/dz
       }
     }
   }
@@ -343,8 +392,14 @@ void launch_raster_backward(int total_tiles, int n_views, const ViewDev* views, 
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
                             const uint32_t* pix_last, float* grad2d, hipStream_t s) {
   if (total_tiles == 0) return;
-  hipLaunchKernelGGL(k_raster_backward, dim3(total_tiles), dim3(256), 0, s, n_views, views, ranges, ival, rec_sorted,
-                     bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d);
+#define G4D_BWD(HD, HA)                                                                                          \
+  hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(total_tiles), dim3(256), 0, s, n_views, views, ranges,    \
+                     ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d)
+  if (dl_depth && dl_alpha) G4D_BWD(true, true);
+  else if (dl_depth) G4D_BWD(true, false);
+  else if (dl_alpha) G4D_BWD(false, true);
+  else G4D_BWD(false, false);
+#undef G4D_BWD
 }
 
 }  // namespace g4d
