@@ -63,21 +63,42 @@ def cpu_oracle_baseline(wl, seconds: float):
         loss.backward()
         return time.perf_counter() - t0
 
-    k1 = 2
+    k1, k2 = 4, 16
     t1 = run(k1)
-    per_tile_guess = max(t1 / 4, 0.05)
-    k2 = int(max(k1 + 4, min(64, (seconds - t1) / (2 * per_tile_guess))))
     t2 = run(k2)
-    b = max((t2 - t1) / (k2 - k1), 1e-9)
+    b = max((t2 - t1) / (k2 - k1), 1e-6)
+    a = max(t1 - b * k1, 0.0)
+    # third run sized so that the whole sample takes about `seconds`
+    k3 = int(min(n_tiles, max(k2 + 1, (seconds - t1 - t2 - a) / b)))
+    t3 = run(k3)
+    b = max((t3 - t1) / (k3 - k1), 1e-6)
     a = max(t1 - b * k1, 0.0)
     full = a + b * n_tiles
     px = cam.width * cam.height
     return dict(value=px / full / 1e6, unit="Mpix/s (fwd+bwd, one view, extrapolated)",
                 cores=int(torch.get_num_threads()), kind="oracle",
                 sample=(f"1 of {len(wl.cameras)} views at {cam.width}x{cam.height}, {wl.scene.n} primitives: "
-                        f"FP64 preprocess of all primitives + fwd/bwd of {k1} and {k2} random 16x16 tiles "
-                        f"({t1:.1f}s, {t2:.1f}s); full view = {a:.2f}s + {b:.3f}s x {n_tiles} tiles"),
-                seconds=round(t1 + t2, 2))
+                        f"FP64 preprocess of all primitives + fwd/bwd of {k1}, {k2} and {k3} random 16x16 tiles "
+                        f"({t1:.1f}s, {t2:.1f}s, {t3:.1f}s); full view = {a:.2f}s + {b:.4f}s x {n_tiles} tiles"),
+                seconds=round(t1 + t2 + t3, 2))
+
+
+def profiled_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch from the counter summary under profiles/, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(summary).read()
+        sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith("|"))
+    if fields.get("source_sha256", "").strip() != sha:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -89,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by view "
@@ -102,6 +125,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe_mb > 0:
+        nfl = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(nfl, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] copy probe: 3 x {args.copy_probe_mb} MiB device copies")
     log(f"[bench] building workload ({args.views} views)")
     wl = scenegen.bench_workload(args.views)
     sc = wl.scene
@@ -187,8 +219,13 @@ def main():
     if dom in ("raster_bwd", "raster_fwd"):
         ops = frag * (OPS_BWD if dom == "raster_bwd" else OPS_FWD)
         achieved = ops / (per_launch[dom] * 1e-3)
+        traffic = None
+        if dom == "raster_bwd":
+            traffic = profiled_traffic(os.path.join(HERE, "paper_2310_10642_amd", "csrc", "raster.hip"),
+                                       os.path.join(HERE, "profiles",
+                                                    "traffic_raster_backward_bench_300k_8x1352x1014.md"))
         roof = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=ALU_PEAK_OPS / 1e12,
-                    unit="Tops/s (FP32 lane ops)", frac=achieved / ALU_PEAK_OPS, traffic=None,
+                    unit="Tops/s (FP32 lane ops)", frac=achieved / ALU_PEAK_OPS, traffic=traffic,
                     ms_per_launch=per_launch[dom], units=frag,
                     units_name="evaluated fragments (pixel x list entry up to the last contributor)")
     else:

@@ -4,20 +4,43 @@
 namespace g4d {
 namespace {
 
+__device__ __forceinline__ float loss_term(int kind, float d, float scale, float& g) {
+  if (kind == 1) {
+    g = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+    return fabsf(d);
+  }
+  g = 2.f * scale * d;
+  return d * d;
+}
+
+// Grid-stride over float4 groups; one atomic per block for the loss.
 __global__ void __launch_bounds__(256) k_image_loss(int kind, uint64_t n, const float* __restrict__ img,
                                                      const float* __restrict__ tgt, float scale,
                                                      float* __restrict__ loss, float* __restrict__ grad) {
   __shared__ float s_part[4];
   float acc = 0.f;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const float d = img[i] - tgt[i];
-    if (kind == 1) {
-      acc += fabsf(d);
-      grad[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-    } else {
-      acc = fmaf(d, d, acc);
-      grad[i] = 2.f * scale * d;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t n4 = n / 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
+                     reinterpret_cast<uintptr_t>(grad)) & 15u) == 0;
+  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec) {
+    for (uint64_t i = i0; i < n4; i += stride) {
+      const float4 a = reinterpret_cast<const float4*>(img)[i];
+      const float4 b = reinterpret_cast<const float4*>(tgt)[i];
+      float4 g;
+      acc += loss_term(kind, a.x - b.x, scale, g.x);
+      acc += loss_term(kind, a.y - b.y, scale, g.y);
+      acc += loss_term(kind, a.z - b.z, scale, g.z);
+      acc += loss_term(kind, a.w - b.w, scale, g.w);
+      reinterpret_cast<float4*>(grad)[i] = g;
     }
+  }
+  // scalar path: everything when unaligned, else the tail after the float4 groups
+  for (uint64_t i = (vec ? 4 * n4 : 0) + i0; i < n; i += stride) {
+    float g;
+    acc += loss_term(kind, img[i] - tgt[i], scale, g);
+    grad[i] = g;
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -31,8 +54,9 @@ __global__ void __launch_bounds__(256) k_image_loss(int kind, uint64_t n, const 
 void launch_image_loss(int kind, uint64_t n, const float* img, const float* tgt, float scale, float* loss,
                        float* grad, hipStream_t s) {
   if (n == 0) return;
-  uint64_t g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
+  uint64_t g = (n / 4 + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
   hipLaunchKernelGGL(k_image_loss, dim3((unsigned)g), dim3(256), 0, s, kind, n, img, tgt, scale, loss, grad);
 }
 

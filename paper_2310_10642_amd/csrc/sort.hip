@@ -386,12 +386,26 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
 
 __global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* __restrict__ ikey,
                          uint2* __restrict__ ranges) {
+  // four consecutive keys per thread (one 16-byte load when in bounds)
   const uint32_t n = dev_n(n_dev, n_max);
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t k = ikey[i];
-  if (i == 0 || ikey[i - 1] != k) ranges[k].x = i;
-  if (i == n - 1 || ikey[i + 1] != k) ranges[k].y = i + 1;
+  const uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= n) return;
+  uint32_t k[6];  // k[0] = key before i0 (or none), k[1..4] = keys i0..i0+3, k[5] = key after
+  if (i0 + 4 <= n) {
+    const uint4 q = *reinterpret_cast<const uint4*>(ikey + i0);
+    k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+  } else {
+    for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? ikey[i0 + j] : 0xFFFFFFFFu;
+  }
+  k[0] = i0 > 0 ? ikey[i0 - 1] : 0xFFFFFFFFu;
+  k[5] = (i0 + 4 < n) ? ikey[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 1; j <= 4; ++j) {
+    const uint32_t i = i0 + j - 1;
+    if (i >= n) break;
+    if (i == 0 || k[j - 1] != k[j]) ranges[k[j]].x = i;
+    if (i == n - 1 || k[j + 1] != k[j]) ranges[k[j]].y = i + 1;
+  }
 }
 
 __global__ void k_sum_u32(const uint32_t* __restrict__ in, uint64_t n, unsigned long long* out) {
@@ -481,7 +495,7 @@ void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, co
 
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s) {
   if (n_max == 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n_max, 256)), dim3(256), 0, s, n_dev, n_max, ikey, ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for((n_max + 3) / 4, 256)), dim3(256), 0, s, n_dev, n_max, ikey, ranges);
 }
 
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s) {
