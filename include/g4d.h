@@ -84,6 +84,7 @@ typedef struct {
   int64_t tiles;          /* 16x16 tiles over all views */
   int64_t max_tile_list;  /* longest per-tile list */
   int64_t fragments;      /* list entries visited per pixel up to its last contributor, summed */
+  int64_t rounds;         /* view groups the render was binned and rasterised in */
 } g4d_stats;
 
 /* Fills the defaults: L=3, N_t=2, T=1, t_cull=0.05, near=0.2, black background. */
@@ -118,7 +119,12 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
  *   out_depth  device [sum_v H_v*W_v] or NULL: sum_i a_i T_i z_i (not normalised)
  *   out_alpha  device [sum_v H_v*W_v] or NULL: 1 - final transmittance
  * Keeps per-pixel final transmittance and last-contributor count for backward.
- * Synchronises the stream once, mid-call, to size the tile-instance arena. */
+ * Views are processed in rounds of consecutive views: a round holds at most
+ * G4D_TUNE_ROUND_PAIRS (view, primitive) pairs (but at least one view) and at
+ * most G4D_TUNE_ROUND_INSTANCES tile instances; a round over the instance cap
+ * is shrunk and binned again. Each view's result does not depend on the
+ * grouping. Synchronises the stream once per binning attempt, to size the
+ * tile-instance arena. G4D_ECAPACITY if one view alone exceeds the cap. */
 g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
                       float* out_rgb, float* out_depth, float* out_alpha);
 
@@ -126,7 +132,9 @@ g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, con
  * be NULL (treated as zero). Layouts match render's outputs. The gradient
  * buffers (layouts as set_primitives) receive the sum over the views of the
  * last render: overwritten (primitives active in no view get zeros), or added
- * to their contents when flags has G4D_GRAD_ACCUMULATE.
+ * to their contents when flags has G4D_GRAD_ACCUMULATE. When the render took
+ * more than one round, every round except the last is binned again (the
+ * same bins as in the render) before its backward passes.
  * Returns G4D_ESTATE if no render happened since the last set_primitives. */
 enum { G4D_GRAD_ACCUMULATE = 1 };
 g4d_status g4d_render_backward(g4d_ctx* ctx, const float* dL_drgb, const float* dL_ddepth,
@@ -144,15 +152,20 @@ enum { G4D_LOSS_L1 = 1, G4D_LOSS_L2 = 2 };
 g4d_status g4d_image_loss(g4d_ctx* ctx, int32_t kind, int64_t n, const float* img, const float* target,
                           float scale, float* loss_out, float* grad_out);
 
-/* Counters of the last render; active_per_view (host [n_views]) may be NULL.
- * `fragments` is computed on demand and synchronises the stream. */
+/* Counters of the last render, summed over its rounds; active_per_view
+ * (host [n_views]) may be NULL. `fragments` is computed on demand and
+ * synchronises the stream. */
 g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view);
 
 /* Tuning knobs (key, value); unknown keys give G4D_EINVAL.
  *   G4D_TUNE_SORT_BLOCKS   max workgroups of each radix-sort pass (>= 1)
  *   G4D_TUNE_STAGE_TIMING  1: bracket every stage with HIP events on the
- *                          context's stream (resets the totals); 0: off     */
-enum { G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2 };
+ *                          context's stream (resets the totals); 0: off
+ *   G4D_TUNE_ROUND_PAIRS     max (view, primitive) pairs per round (>= 1;
+ *                            default 2^28, about 37 GB of per-pair scratch)
+ *   G4D_TUNE_ROUND_INSTANCES max tile instances per round (>= 1; default
+ *                            2^30, 16 GB of key/value arena)              */
+enum { G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2, G4D_TUNE_ROUND_PAIRS = 3, G4D_TUNE_ROUND_INSTANCES = 4 };
 g4d_status g4d_set_tuning(g4d_ctx* ctx, int32_t key, int32_t value);
 
 /* Per-stage GPU time accumulated since stage timing was switched on
@@ -173,7 +186,9 @@ const char* g4d_last_error(const g4d_ctx* ctx);
 
 /* Copies an intermediate of the last render to host memory, for inspection
  * by tests. Synchronises the stream. `bytes` must equal the size reported by
- * g4d_debug_size for the same `what`.
+ * g4d_debug_size for the same `what`. Per-pair, per-instance and per-tile
+ * items belong to the round binned last (tile ids and view indices relative
+ * to it); per-pixel items cover all views.
  *   G4D_DBG_RECORDS   per active pair in depth order, 12 x float32:
  *                     u, v, z, opacity*p(t), conic00, conic01, conic11, rect x (x0 | x1<<16 as bits),
  *                     r, g, b, rect y (y0 | y1<<16 as bits)

@@ -34,14 +34,23 @@ struct g4d_ctx {
   const float *opacity_logit = nullptr, *coeffs = nullptr;
 
   // last render
+  struct Round {
+    int v0, v1;    // views [v0, v1)
+    int tiles;     // tiles of those views
+    uint32_t A, I; // active records and tile instances
+  };
   bool have_render = false;
   int n_views = 0;
-  std::vector<ViewDev> views_h;
-  int total_tiles = 0;
+  std::vector<ViewDev> views_h;  // every view; tile_base is set per round
+  int64_t total_tiles = 0;
   int64_t total_pix = 0;
-  uint32_t A = 0, I = 0;
+  std::vector<Round> rounds;
+  int bound = -1;                // round whose records and bins are resident
+  uint64_t A_total = 0, I_total = 0;
   std::vector<uint32_t> view_active;
   int sort_blocks = 1024;
+  int64_t round_pairs = int64_t(1) << 28;
+  int64_t round_instances = int64_t(1) << 30;
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
@@ -68,6 +77,7 @@ constexpr int kCntA = 0;          // active records
 constexpr int kCntI = 1;          // instances
 constexpr int kCntInst64 = 2;     // 64-bit instance total (words 2, 3)
 constexpr int kCntFrag = 4;       // 64-bit fragment sum (words 4, 5)
+constexpr int kCntMaxList = 6;    // longest tile list over the rounds of a render
 constexpr int kCntViews = 8;      // per-view active counts follow
 constexpr int kMaxViews = 4096;
 
@@ -162,10 +172,10 @@ g4d_status collect_times(g4d_ctx* c) {
   return G4D_OK;
 }
 
-RenderParams make_params(g4d_ctx* c) {
+RenderParams make_params(g4d_ctx* c, int n_views) {
   RenderParams p{};
   p.n = (int)c->n;
-  p.n_views = c->n_views;
+  p.n_views = n_views;
   p.sh_degree = c->opts.sh_degree;
   p.t_order = c->opts.t_order;
   p.t_period = c->opts.t_period;
@@ -180,6 +190,104 @@ RenderParams make_params(g4d_ctx* c) {
   p.coeffs = c->coeffs;
   p.views = P<ViewDev>(c->views_d);
   return p;
+}
+
+int round_tiles(const g4d_ctx* c, int v0, int v1) {
+  int64_t t = 0;
+  for (int v = v0; v < v1; ++v) t += (int64_t)c->views_h[v].tiles_x * c->views_h[v].tiles_y;
+  return (int)t;
+}
+
+// Per-pair stage of one round, views [v0, v1): preprocess every (view,
+// primitive) pair, compact the active ones, sort them by depth, gather the
+// records in that order and scan their tile counts. Synchronises once and
+// returns the active count and the instance total.
+g4d_status bin_pairs(g4d_ctx* c, int v0, int v1, uint32_t& A, uint64_t& inst64) {
+  c->bound = -1;
+  hipStream_t s = c->stream;
+  const int nv = v1 - v0;
+  std::vector<ViewDev> vr(c->views_h.begin() + v0, c->views_h.begin() + v1);
+  int tile_base = 0;
+  for (ViewDev& d : vr) {
+    d.tile_base = tile_base;
+    tile_base += d.tiles_x * d.tiles_y;
+  }
+  const uint64_t vn = (uint64_t)c->n * nv;
+  g4d_status st;
+  if ((st = ensure(c, c->views_d, sizeof(ViewDev) * nv))) return st;
+  if ((st = ensure(c, c->act, 4 * vn))) return st;
+  if ((st = ensure(c, c->pos, 4 * vn))) return st;
+  if ((st = ensure(c, c->dkey, 4 * vn))) return st;
+  if ((st = ensure(c, c->slot, 4 * vn))) return st;
+  if ((st = ensure(c, c->rec, sizeof(Record) * vn))) return st;
+  if ((st = ensure(c, c->ckey, 4 * vn))) return st;
+  if ((st = ensure(c, c->cval, 4 * vn))) return st;
+  if ((st = ensure(c, c->ckey2, 4 * vn))) return st;
+  if ((st = ensure(c, c->cval2, 4 * vn))) return st;
+  if ((st = ensure(c, c->rec_sorted, sizeof(Record) * vn))) return st;
+  if ((st = ensure(c, c->tcount, 4 * vn))) return st;
+  if ((st = ensure(c, c->toff, 4 * vn))) return st;
+  if ((st = ensure(c, c->scan_scratch, 4 * scan_scratch_words(vn)))) return st;
+  if ((st = ensure(c, c->radix_scratch, 4 * radix_scratch_words(c->sort_blocks)))) return st;
+  RenderParams p = make_params(c, nv);
+  uint32_t* cnt = P<uint32_t>(c->counters);
+
+  HIPCHK(c, hipMemcpyAsync(c->views_d.ptr, vr.data(), sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * 4, s));
+  // 1. per (view, primitive): cull, slice, project, colour
+  stage_begin(c);
+  launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot), s);
+  stage_end(c, G4D_STAGE_PREPROCESS);
+  // 2. compaction of active records
+  stage_begin(c);
+  launch_scan(P<uint32_t>(c->act), P<uint32_t>(c->pos), nullptr, (uint32_t)vn, (uint32_t)vn, cnt + kCntA,
+              P<uint32_t>(c->scan_scratch), s);
+  launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
+                 P<uint32_t>(c->cval), s);
+  launch_view_counts(P<uint32_t>(c->pos), P<uint32_t>(c->act), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews, s);
+  // 3. stable sort by depth
+  const int g_depth = radix_grid((uint32_t)vn, c->sort_blocks);
+  radix_sort(P<uint32_t>(c->ckey), P<uint32_t>(c->cval), P<uint32_t>(c->ckey2), P<uint32_t>(c->cval2), cnt + kCntA,
+             (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
+  // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
+  launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
+                P<int32_t>(c->slot), P<uint32_t>(c->tcount), cnt + kCntInst64, (int)c->n, s);
+  launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
+              P<uint32_t>(c->scan_scratch), s);
+  stage_end(c, G4D_STAGE_BINNING);
+  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (kCntViews + nv), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  A = c->counters_h[kCntA];
+  std::memcpy(&inst64, c->counters_h + kCntInst64, sizeof(inst64));
+  std::copy(c->counters_h + kCntViews, c->counters_h + kCntViews + nv, c->view_active.begin() + v0);
+  return G4D_OK;
+}
+
+// Per-instance stage of a round whose pairs are binned: emit the (tile,
+// record) instances, sort them stably by tile and find each tile's range.
+g4d_status bin_tiles(g4d_ctx* c, const g4d_ctx::Round& r) {
+  hipStream_t s = c->stream;
+  g4d_status st;
+  const uint32_t I = r.I;
+  if ((st = ensure(c, c->ikey, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ival, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ikey2, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ival2, 4 * (size_t)I))) return st;
+  if ((st = ensure(c, c->ranges, sizeof(uint2) * (size_t)r.tiles))) return st;
+  uint32_t* cnt = P<uint32_t>(c->counters);
+  // 6. emit (tile, record) instances; 7. stable sort by tile; 8. ranges
+  stage_begin(c);
+  HIPCHK(c, hipMemsetAsync(c->ranges.ptr, 0, sizeof(uint2) * (size_t)r.tiles, s));
+  launch_emit(cnt + kCntA, r.A, P<uint32_t>(c->toff), cnt + kCntI, P<Record>(c->rec_sorted), P<uint32_t>(c->cval),
+              (int)c->n, P<ViewDev>(c->views_d), P<uint32_t>(c->ikey), P<uint32_t>(c->ival), s);
+  const int tile_bits = ceil_log2((uint32_t)r.tiles);
+  const int g_tile = radix_grid(I, c->sort_blocks);
+  radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI, I,
+             0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
+  launch_ranges(cnt + kCntI, I, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+  stage_end(c, G4D_STAGE_BINNING);
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
 }
 
 }  // namespace
@@ -277,8 +385,6 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
   if (c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
   if (n_views < 1 || n_views > kMaxViews) return fail(c, G4D_EINVAL, "n_views must be in [1, 4096]");
   if (!cams || !times || !out_rgb) return fail(c, G4D_EINVAL, "null cams/times/out_rgb");
-  if ((uint64_t)c->n * (uint64_t)n_views > 0xFFFFFFF0ull)
-    return fail(c, G4D_ECAPACITY, "n * n_views exceeds 2^32");
 
   // ---- views (host) ----
   std::vector<ViewDev> vh(n_views);
@@ -300,7 +406,7 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
     d.height = cm.height;
     d.tiles_x = (cm.width + kTile - 1) / kTile;
     d.tiles_y = (cm.height + kTile - 1) / kTile;
-    d.tile_base = (int)tiles;
+    d.tile_base = 0;
     d.pad0 = 0;
     d.pix_base = pix;
     d.fx = cm.fx; d.fy = cm.fy; d.cx = cm.cx; d.cy = cm.cy;
@@ -318,94 +424,58 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
   if (tiles > (int64_t)0x7FFFFFFF) return fail(c, G4D_ECAPACITY, "too many tiles");
 
   hipStream_t s = c->stream;
-  const uint64_t vn = (uint64_t)c->n * n_views;
   g4d_status st;
-  // ---- scratch ----
-  if ((st = ensure(c, c->views_d, sizeof(ViewDev) * n_views))) return st;
   if ((st = ensure(c, c->counters, sizeof(uint32_t) * (kCntViews + kMaxViews)))) return st;
-  if ((st = ensure(c, c->act, 4 * vn))) return st;
-  if ((st = ensure(c, c->pos, 4 * vn))) return st;
-  if ((st = ensure(c, c->dkey, 4 * vn))) return st;
-  if ((st = ensure(c, c->slot, 4 * vn))) return st;
-  if ((st = ensure(c, c->rec, sizeof(Record) * vn))) return st;
-  if ((st = ensure(c, c->ckey, 4 * vn))) return st;
-  if ((st = ensure(c, c->cval, 4 * vn))) return st;
-  if ((st = ensure(c, c->ckey2, 4 * vn))) return st;
-  if ((st = ensure(c, c->cval2, 4 * vn))) return st;
-  if ((st = ensure(c, c->rec_sorted, sizeof(Record) * vn))) return st;
-  if ((st = ensure(c, c->tcount, 4 * vn))) return st;
-  if ((st = ensure(c, c->toff, 4 * vn))) return st;
-  if ((st = ensure(c, c->scan_scratch, 4 * scan_scratch_words(vn)))) return st;
-  if ((st = ensure(c, c->ranges, sizeof(uint2) * tiles))) return st;
   if ((st = ensure(c, c->pix_t, 4 * pix))) return st;
   if ((st = ensure(c, c->pix_last, 4 * pix))) return st;
 
   c->have_render = false;
   c->n_views = n_views;
   c->views_h = vh;
-  c->total_tiles = (int)tiles;
+  c->total_tiles = tiles;
   c->total_pix = pix;
-  RenderParams p = make_params(c);
+  c->rounds.clear();
+  c->A_total = c->I_total = 0;
+  c->view_active.assign(n_views, 0);
   uint32_t* cnt = P<uint32_t>(c->counters);
+  HIPCHK(c, hipMemsetAsync(cnt + kCntMaxList, 0, sizeof(uint32_t), s));
 
-  HIPCHK(c, hipMemcpyAsync(c->views_d.ptr, c->views_h.data(), sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * kCntViews, s));
-  // 1. per (view, primitive): cull, slice, project, colour
-  stage_begin(c);
-  launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot), s);
-  stage_end(c, G4D_STAGE_PREPROCESS);
-  // 2. compaction of active records
-  stage_begin(c);
-  launch_scan(P<uint32_t>(c->act), P<uint32_t>(c->pos), nullptr, (uint32_t)vn, (uint32_t)vn, cnt + kCntA,
-              P<uint32_t>(c->scan_scratch), s);
-  launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
-                 P<uint32_t>(c->cval), s);
-  launch_view_counts(P<uint32_t>(c->pos), P<uint32_t>(c->act), n_views, (uint32_t)c->n, cnt + kCntA,
-                     cnt + kCntViews, s);
-  // 3. stable sort by depth
-  const int g_depth = radix_grid((uint32_t)vn, c->sort_blocks);
-  if ((st = ensure(c, c->radix_scratch, 4 * radix_scratch_words(c->sort_blocks)))) return st;
-  radix_sort(P<uint32_t>(c->ckey), P<uint32_t>(c->cval), P<uint32_t>(c->ckey2), P<uint32_t>(c->cval2), cnt + kCntA,
-             (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
-  // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
-  launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
-                P<int32_t>(c->slot), P<uint32_t>(c->tcount), cnt + kCntInst64, (int)c->n, s);
-  launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
-              P<uint32_t>(c->scan_scratch), s);
-  stage_end(c, G4D_STAGE_BINNING);
-  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (kCntViews + n_views), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  const uint32_t A = c->counters_h[kCntA];
-  uint64_t inst64 = 0;
-  std::memcpy(&inst64, c->counters_h + kCntInst64, sizeof(inst64));
-  if (inst64 > 0xFFFFFFF0ull) return fail(c, G4D_ECAPACITY, "tile instances exceed 2^32; render fewer views per call");
-  const uint32_t I = (uint32_t)inst64;
-  c->A = A;
-  c->I = I;
-  c->view_active.assign(c->counters_h + kCntViews, c->counters_h + kCntViews + n_views);
-
-  // 6. emit (tile, record) instances; 7. stable sort by tile; 8. ranges
-  if ((st = ensure(c, c->ikey, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ival, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ikey2, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ival2, 4 * (size_t)I))) return st;
-  stage_begin(c);
-  HIPCHK(c, hipMemsetAsync(c->ranges.ptr, 0, sizeof(uint2) * tiles, s));
-  launch_emit(cnt + kCntA, A, P<uint32_t>(c->toff), cnt + kCntI, P<Record>(c->rec_sorted), P<uint32_t>(c->cval),
-              (int)c->n, P<ViewDev>(c->views_d), P<uint32_t>(c->ikey), P<uint32_t>(c->ival), s);
-  const int tile_bits = ceil_log2((uint32_t)tiles);
-  const int g_tile = radix_grid(I, c->sort_blocks);
-  radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI, I,
-             0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
-  launch_ranges(cnt + kCntI, I, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
-  stage_end(c, G4D_STAGE_BINNING);
-  // 9. rasterise
-  stage_begin(c);
-  launch_raster_forward(c->total_tiles, n_views, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
-                        P<Record>(c->rec_sorted), c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t),
-                        P<uint32_t>(c->pix_last), s);
-  stage_end(c, G4D_STAGE_RASTER_FWD);
-  HIPCHK(c, hipGetLastError());
+  // Rounds of consecutive views under the pair and instance caps. The next
+  // round's size is predicted from the last one's instances per view; a round
+  // over the instance cap is shrunk in proportion and binned again.
+  const uint64_t inst_cap = (uint64_t)c->round_instances;
+  const int by_pairs = (int)std::min<int64_t>(n_views, std::max<int64_t>(1, c->round_pairs / std::max<int64_t>(c->n, 1)));
+  int k_next = by_pairs;
+  for (int v0 = 0; v0 < n_views;) {
+    int k = std::min(k_next, n_views - v0);
+    uint32_t A = 0;
+    uint64_t inst = 0;
+    for (;;) {
+      if ((st = bin_pairs(c, v0, v0 + k, A, inst))) return st;
+      if (inst <= inst_cap) break;
+      if (k == 1)
+        return fail(c, G4D_ECAPACITY, "view " + std::to_string(v0) + " alone needs " + std::to_string(inst) +
+                                          " tile instances, over the round cap " + std::to_string(inst_cap));
+      k = std::max(1, std::min(k - 1, (int)(0.9 * (double)k * (double)inst_cap / (double)inst)));
+    }
+    g4d_ctx::Round r{v0, v0 + k, round_tiles(c, v0, v0 + k), A, (uint32_t)inst};
+    if ((st = bin_tiles(c, r))) return st;
+    c->rounds.push_back(r);
+    c->bound = (int)c->rounds.size() - 1;
+    launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, cnt + kCntMaxList, s);
+    // 9. rasterise the round's views into their places in the outputs
+    stage_begin(c);
+    launch_raster_forward(r.tiles, k, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
+                          P<Record>(c->rec_sorted), c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t),
+                          P<uint32_t>(c->pix_last), s);
+    stage_end(c, G4D_STAGE_RASTER_FWD);
+    HIPCHK(c, hipGetLastError());
+    c->A_total += A;
+    c->I_total += inst;
+    k_next = inst ? (int)std::min<double>(by_pairs, std::max(1.0, 0.9 * (double)k * (double)inst_cap / (double)inst))
+                  : by_pairs;
+    v0 += k;
+  }
   c->have_render = true;
   return G4D_OK;
 }
@@ -426,22 +496,37 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
   }
   hipStream_t s = c->stream;
   g4d_status st;
-  if ((st = ensure(c, c->grad2d, sizeof(float) * 12 * (size_t)c->A))) return st;
-  stage_begin(c);
-  if (c->A) HIPCHK(c, hipMemsetAsync(c->grad2d.ptr, 0, sizeof(float) * 12 * (size_t)c->A, s));
-  launch_raster_backward(c->total_tiles, c->n_views, P<ViewDev>(c->views_d), P<uint2>(c->ranges),
-                         P<uint32_t>(c->ival), P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha,
-                         P<float>(c->pix_t), P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
-  stage_end(c, G4D_STAGE_RASTER_BWD);
-  RenderParams p = make_params(c);
-  if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(c->A)))) return st;
-  stage_begin(c);
-  launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), P<uint32_t>(c->counters) + kCntA, c->A,
-                             P<uint32_t>(c->cval), P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4,
-                             g_log_scales4, g_q_left, g_q_right, g_opacity_logit, g_coeffs,
-                             (flags & G4D_GRAD_ACCUMULATE) != 0, s);
-  stage_end(c, G4D_STAGE_PREPROCESS_BWD);
-  HIPCHK(c, hipGetLastError());
+  // Rounds last to first: the last one is still binned after the render.
+  bool accumulate = (flags & G4D_GRAD_ACCUMULATE) != 0;
+  for (int ri = (int)c->rounds.size() - 1; ri >= 0; --ri) {
+    const g4d_ctx::Round r = c->rounds[ri];
+    const int nv = r.v1 - r.v0;
+    if (c->bound != ri) {
+      uint32_t A = 0;
+      uint64_t inst = 0;
+      if ((st = bin_pairs(c, r.v0, r.v1, A, inst))) return st;
+      if (A != r.A || inst != r.I)
+        return fail(c, G4D_ESTATE, "binning a round again gave other counts; primitives changed since render");
+      if ((st = bin_tiles(c, r))) return st;
+      c->bound = ri;
+    }
+    if ((st = ensure(c, c->grad2d, sizeof(float) * 12 * (size_t)r.A))) return st;
+    stage_begin(c);
+    if (r.A) HIPCHK(c, hipMemsetAsync(c->grad2d.ptr, 0, sizeof(float) * 12 * (size_t)r.A, s));
+    launch_raster_backward(r.tiles, nv, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
+                           P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
+                           P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
+    stage_end(c, G4D_STAGE_RASTER_BWD);
+    RenderParams p = make_params(c, nv);
+    if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(r.A)))) return st;
+    stage_begin(c);
+    launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), P<uint32_t>(c->counters) + kCntA, r.A,
+                               P<uint32_t>(c->cval), P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4,
+                               g_log_scales4, g_q_left, g_q_right, g_opacity_logit, g_coeffs, accumulate, s);
+    stage_end(c, G4D_STAGE_PREPROCESS_BWD);
+    HIPCHK(c, hipGetLastError());
+    accumulate = true;
+  }
   return G4D_OK;
 }
 
@@ -476,22 +561,21 @@ g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
   if (!c || !out) return G4D_EINVAL;
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
   out->n_views = c->n_views;
-  out->active_total = c->A;
-  out->instances = c->I;
+  out->active_total = (int64_t)c->A_total;
+  out->instances = (int64_t)c->I_total;
   out->tiles = c->total_tiles;
+  out->rounds = (int64_t)c->rounds.size();
   // longest list and fragment total need device reads
-  std::vector<uint2> rg(c->total_tiles);
-  HIPCHK(c, hipMemcpyAsync(rg.data(), c->ranges.ptr, sizeof(uint2) * rg.size(), hipMemcpyDeviceToHost, c->stream));
   uint32_t* cnt = P<uint32_t>(c->counters);
   HIPCHK(c, hipMemsetAsync(cnt + kCntFrag, 0, 8, c->stream));
   launch_sum_u32(P<uint32_t>(c->pix_last), (uint64_t)c->total_pix, reinterpret_cast<unsigned long long*>(cnt + kCntFrag),
                  c->stream);
-  uint64_t frag = 0;
-  HIPCHK(c, hipMemcpyAsync(&frag, cnt + kCntFrag, 8, hipMemcpyDeviceToHost, c->stream));
+  uint32_t words[3] = {0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(words, cnt + kCntFrag, sizeof(words), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  int64_t mx = 0;
-  for (const uint2& r : rg) mx = std::max<int64_t>(mx, (int64_t)r.y - (int64_t)r.x);
-  out->max_tile_list = mx;
+  uint64_t frag = 0;
+  std::memcpy(&frag, words, sizeof(frag));
+  out->max_tile_list = words[kCntMaxList - kCntFrag];
   out->fragments = (int64_t)frag;
   if (active_per_view)
     for (int v = 0; v < c->n_views; ++v) active_per_view[v] = c->view_active[v];
@@ -516,6 +600,11 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     c->timing = value == 1;
     return G4D_OK;
   }
+  if (key == G4D_TUNE_ROUND_PAIRS || key == G4D_TUNE_ROUND_INSTANCES) {
+    if (value < 1) return fail(c, G4D_EINVAL, "round caps must be >= 1");
+    (key == G4D_TUNE_ROUND_PAIRS ? c->round_pairs : c->round_instances) = value;
+    return G4D_OK;
+  }
   return fail(c, G4D_EINVAL, "unknown tuning key");
 }
 
@@ -524,13 +613,15 @@ const char* g4d_last_error(const g4d_ctx* c) { return c ? c->err.c_str() : "null
 g4d_status g4d_debug_size(g4d_ctx* c, int32_t what, int64_t* bytes) {
   if (!c || !bytes) return G4D_EINVAL;
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
+  if (c->bound < 0) return fail(c, G4D_ESTATE, "no round is binned");
+  const g4d_ctx::Round& r = c->rounds[c->bound];
   switch (what) {
-    case G4D_DBG_RECORDS: *bytes = (int64_t)sizeof(Record) * c->A; break;
-    case G4D_DBG_IDS: *bytes = 4ll * c->A; break;
-    case G4D_DBG_TILE_KEYS: case G4D_DBG_TILE_VALS: *bytes = 4ll * c->I; break;
-    case G4D_DBG_RANGES: *bytes = 8ll * c->total_tiles; break;
+    case G4D_DBG_RECORDS: *bytes = (int64_t)sizeof(Record) * r.A; break;
+    case G4D_DBG_IDS: *bytes = 4ll * r.A; break;
+    case G4D_DBG_TILE_KEYS: case G4D_DBG_TILE_VALS: *bytes = 4ll * r.I; break;
+    case G4D_DBG_RANGES: *bytes = 8ll * r.tiles; break;
     case G4D_DBG_PIX_T: case G4D_DBG_PIX_LAST: *bytes = 4ll * c->total_pix; break;
-    case G4D_DBG_GRAD2D: *bytes = 48ll * c->A; break;
+    case G4D_DBG_GRAD2D: *bytes = 48ll * r.A; break;
     default: return fail(c, G4D_EINVAL, "unknown debug item");
   }
   return G4D_OK;

@@ -102,5 +102,6 @@ void launch_raster_backward(int total_tiles, int n_views, const ViewDev* views, 
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
                             const uint32_t* pix_last, float* grad2d, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
+void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
 
 }  // namespace g4d

@@ -409,13 +409,25 @@ __global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* 
 }
 
 __global__ void k_sum_u32(const uint32_t* __restrict__ in, uint64_t n, unsigned long long* out) {
-  __shared__ uint32_t s_wave[4];
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t acc = 0;
+  unsigned long long acc = 0;
   for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) acc += in[i];
-  uint32_t total;
-  block_exclusive_scan(acc, s_wave, total);
-  if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)total);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
+// Longest tile list: max over tiles of end - start, one atomic per wave.
+__global__ void k_range_max(const uint2* __restrict__ ranges, uint32_t tiles, uint32_t* out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t len = 0;
+  if (t < tiles) {
+    const uint2 r = ranges[t];
+    len = r.y - r.x;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) len = max(len, (uint32_t)__shfl_xor((int)len, off, 64));
+  if ((threadIdx.x & 63) == 0 && len) atomicMax(out, len);
 }
 
 inline unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -503,6 +515,11 @@ void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hip
   unsigned g = grid_for(n, 256);
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_sum_u32, dim3(g), dim3(256), 0, s, in, n, out);
+}
+
+void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s) {
+  if (tiles == 0) return;
+  hipLaunchKernelGGL(k_range_max, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles, out);
 }
 
 }  // namespace g4d

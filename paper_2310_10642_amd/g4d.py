@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libg4d.so")
 
 G4D_OK, G4D_EINVAL, G4D_ENOMEM, G4D_EHIP, G4D_ESTATE, G4D_ECAPACITY = 0, -1, -2, -3, -4, -5
 G4D_TUNE_SORT_BLOCKS, G4D_TUNE_STAGE_TIMING = 1, 2
+G4D_TUNE_ROUND_PAIRS, G4D_TUNE_ROUND_INSTANCES = 3, 4
 G4D_GRAD_ACCUMULATE = 1
 G4D_LOSS_L1, G4D_LOSS_L2 = 1, 2
 STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss"]
@@ -41,7 +42,8 @@ class G4DCamera(ctypes.Structure):
 
 class G4DStats(ctypes.Structure):
     _fields_ = [("n_views", ctypes.c_int64), ("active_total", ctypes.c_int64), ("instances", ctypes.c_int64),
-                ("tiles", ctypes.c_int64), ("max_tile_list", ctypes.c_int64), ("fragments", ctypes.c_int64)]
+                ("tiles", ctypes.c_int64), ("max_tile_list", ctypes.c_int64), ("fragments", ctypes.c_int64),
+                ("rounds", ctypes.c_int64)]
 
 
 class G4DError(RuntimeError):

@@ -38,6 +38,8 @@ def test_header_constants_match_binding():
     assert val("G4D_GRAD_ACCUMULATE") == g4d.G4D_GRAD_ACCUMULATE
     assert val("G4D_LOSS_L1") == g4d.G4D_LOSS_L1 and val("G4D_LOSS_L2") == g4d.G4D_LOSS_L2
     assert val("G4D_TUNE_STAGE_TIMING") == g4d.G4D_TUNE_STAGE_TIMING
+    assert val("G4D_TUNE_ROUND_PAIRS") == g4d.G4D_TUNE_ROUND_PAIRS
+    assert val("G4D_TUNE_ROUND_INSTANCES") == g4d.G4D_TUNE_ROUND_INSTANCES
     assert val("G4D_NUM_STAGES") == len(g4d.STAGES)
     for k, v in g4d.DBG.items():
         assert val("G4D_DBG_" + k.upper()) == v
@@ -47,7 +49,7 @@ def test_struct_layouts():
     from paper_2310_10642_amd import g4d
     assert ctypes.sizeof(g4d.G4DOptions) == 32
     assert ctypes.sizeof(g4d.G4DCamera) == 4 * (2 + 4 + 12 + 3)
-    assert ctypes.sizeof(g4d.G4DStats) == 48
+    assert ctypes.sizeof(g4d.G4DStats) == 56
 
 
 def test_validation_before_any_hip_call():

@@ -298,6 +298,149 @@ def test_training_config_full_size_sampled():
     _sampled_parity(scenegen.make_workload(1), 0, 10, seed=1, dl_seed=12)
 
 
+def _sampled_forward(wl, views, n_tiles, seed):
+    r, _ = PT.gpu_setup(wl.scene)
+    rgb, dep, alp = r.render(wl.cameras, [float(x) for x in wl.times])
+    items = r.split(rgb, dep, alp)
+    stats = r.stats()
+    _say(f"  active per view {stats['active_per_view']}, instances {stats['instances']}")
+    for v in views:
+        cam, t = wl.cameras[v], float(wl.times[v])
+        tiles = scenegen.sample_pixels_dlddi(seed + v, [cam], n_tiles)[0].tolist()
+        _, img = PT.oracle_view(wl.scene, cam, t, tiles=tiles)
+        res = PT.compare_images(*(_np(x) for x in items[v]), img)
+        _say(f"  view {v} ({cam.width}x{cam.height}) {res}")
+    return r
+
+
+def test_batched_forward_1m_16_mixed_views_sampled():
+    """1M primitives with short lifetimes, 16 views at 800x800 and 1352x1014,
+    one batched call; sampled tiles of one view of each size."""
+    _say("[1M, 16 mixed views, sampled tiles]")
+    _sampled_forward(scenegen.make_workload(2), [0, 1], 6, seed=20)
+
+
+def test_batched_fwd_bwd_500k_8_views():
+    """500k primitives, 8 views at 1352x1014, L2 loss: the batched gradient
+    equals the sum of per-view gradients, and sampled tiles of two views
+    match the oracle in value and gradient."""
+    _say("[500k, 8 views, fwd+bwd]")
+    wl = scenegen.make_workload(3)
+    r, params = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    rgb, _, _ = r.render(wl.cameras, times, depth=False, alpha=False)
+    target = torch.from_numpy(np.concatenate([x.reshape(-1) for x in wl.targets])).cuda()
+    loss = torch.zeros(1, device="cuda")
+    dl = torch.empty_like(rgb)
+    scale = 1.0 / (3 * wl.cameras[0].width * wl.cameras[0].height)
+    r.image_loss(2, rgb, target, scale, loss, dl)          # L2, per-view mean, summed over views
+    gb = r.backward(dl)
+    gsum = r.grad_buffers()
+    o = 0
+    for v, (c, t) in enumerate(zip(wl.cameras, times)):
+        n3 = 3 * c.width * c.height
+        r.render([c], [t], depth=False, alpha=False)
+        r.backward(dl[o:o + n3], out=gsum, accumulate=v > 0)
+        o += n3
+    torch.cuda.synchronize()
+    for name, a, b in zip(PT.GROUPS, gb, gsum):
+        a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
+        nb = np.linalg.norm(b)
+        assert nb == 0 or np.linalg.norm(a - b) <= 1e-5 * nb, name
+    # oracle on sampled tiles of views 0 and 5
+    sel = [0, 5]
+    outs = []
+    dls = []
+    total = torch.zeros((), dtype=torch.float64)
+    params_o = O.params_from_scene(wl.scene, requires_grad=True)
+    for v in sel:
+        cam, t = wl.cameras[v], times[v]
+        tiles = scenegen.sample_pixels_dlddi(30 + v, [cam], 5)[0].tolist()
+        out = O.render_view(params_o, cam, t, wl.scene.sh_degree, wl.scene.t_order, wl.scene.t_period, tiles=tiles)
+        img = dict(rgb=O.assemble(out, cam, "rgb", 3), depth=O.assemble(out, cam, "depth"),
+                   alpha=O.assemble(out, cam, "alpha"), unc=O.assemble(out, cam, "uncertain"),
+                   unc_g=O.assemble(out, cam, "uncertain_grad"))
+        rendered = ~np.isnan(img["depth"].detach().numpy())
+        mask = (rendered & ~img["unc_g"].numpy()).astype(np.float64)
+        drgb, _, _ = PT.dl_maps(40 + v, cam.height, cam.width, mask)
+        total = total + O.tile_linear_loss(out, torch.as_tensor(drgb), cam=cam)
+        outs.append((v, img))
+        dls.append((v, drgb))
+    total.backward()
+    rgb, dep, alp = r.render(wl.cameras, times)
+    items = r.split(rgb, dep, alp)
+    for v, img in outs:
+        res = PT.compare_images(*(_np(x) for x in items[v]), img)
+        _say(f"  view {v} {res}")
+    full = [np.zeros((3, c.height, c.width), np.float32) for c in wl.cameras]
+    for v, d in dls:
+        full[v] = d.astype(np.float32)
+    g = r.backward(torch.from_numpy(np.concatenate([x.reshape(-1) for x in full])).cuda())
+    torch.cuda.synchronize()
+    rep = {}
+    PT.compare_grads(g, params_o, report=rep)
+    _say(f"  grads rel L2 {rep}")
+
+
+def test_rounds_match_one_round():
+    """Caps that split 8 views into rounds (including a round that is over the
+    instance cap and binned again) change nothing per view: images and
+    per-pixel state bit for bit, counters exactly, gradients up to the order
+    of the sums. One view over the cap is a capacity error."""
+    _say("[rounds vs one round, 300k x 8 views]")
+    from paper_2310_10642_amd import g4d
+    wl = scenegen.bench_workload(8)
+    r, _ = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    n = wl.scene.means4.shape[0]
+    one = r.render(wl.cameras, times)
+    s1 = r.stats()
+    pt1, pl1 = r.debug("pix_t"), r.debug("pix_last")
+    assert s1["rounds"] == 1
+    assert s1["max_tile_list"] == int(np.diff(r.debug("ranges").reshape(-1, 2), axis=1).max())
+    dl = torch.from_numpy(np.random.default_rng(55).uniform(-1, 1, one[0].numel()).astype(np.float32)).cuda()
+    g1 = [x.clone() for x in r.backward(dl)]
+    r.set_tuning(g4d.G4D_TUNE_ROUND_INSTANCES, s1["instances"] // 3)
+    r.set_tuning(g4d.G4D_TUNE_ROUND_PAIRS, 3 * n)
+    many = r.render(wl.cameras, times)
+    s2 = r.stats()
+    _say(f"  rounds {s2['rounds']}, instances {s1['instances']}")
+    assert s2["rounds"] >= 3
+    for a, b in zip(one, many):
+        assert torch.equal(a, b)
+    assert np.array_equal(pt1, r.debug("pix_t")) and np.array_equal(pl1, r.debug("pix_last"))
+    for k in ("active_total", "instances", "fragments", "max_tile_list", "active_per_view", "tiles"):
+        assert s1[k] == s2[k], k
+    g2 = r.backward(dl)
+    torch.cuda.synchronize()
+    for name, a, b in zip(PT.GROUPS, g1, g2):
+        a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
+        nb = np.linalg.norm(b)
+        assert nb == 0 or np.linalg.norm(a - b) <= 1e-5 * nb, name
+    r.set_tuning(g4d.G4D_TUNE_ROUND_INSTANCES, 10)
+    with pytest.raises(g4d.G4DError) as ei:
+        r.render(wl.cameras[:1], times[:1])
+    assert ei.value.status == g4d.G4D_ECAPACITY
+    r.set_tuning(g4d.G4D_TUNE_ROUND_INSTANCES, 1 << 30)
+    r.set_tuning(g4d.G4D_TUNE_ROUND_PAIRS, 1 << 28)
+    again = r.render(wl.cameras, times)
+    assert r.stats()["rounds"] == 1 and torch.equal(again[0], one[0])
+
+
+@pytest.mark.timeout(400)
+def test_long_sequence_3m_240_views_sampled():
+    """3M short-lived primitives over 60 frames x 4 cameras at 1920x1080 in one
+    call (several rounds under the default caps); sampled tiles of two views
+    against the oracle."""
+    _say("[3M, 240 views 1080p, sampled tiles]")
+    wl = scenegen.make_workload(4)
+    _say("  scene drawn")
+    r = _sampled_forward(wl, [0, 237], 4, seed=70)
+    s = r.stats()
+    _say(f"  rounds {s['rounds']}, max list {s['max_tile_list']}, fragments {s['fragments']}")
+    assert s["rounds"] >= 2 and s["n_views"] == 240
+
+
 def test_image_loss_kernel():
     _say("[image loss]")
     from paper_2310_10642_amd import g4d
