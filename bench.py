@@ -157,9 +157,12 @@ def main():
     dl = torch.empty(3 * P_total, device=dev)
     dl_v = [torch.empty(3 * h * w, device=dev) for h, w in hw]
 
+    rgb_b = torch.empty(3 * P_total, device=dev)
+
     def step_batched():
-        rgb, _, _ = r.render(cams, times, depth=False, alpha=False)
-        r.image_loss(g4d.G4D_LOSS_L1, rgb, target, scale, loss, dl)
+        r.render(cams, times, depth=False, alpha=False, out=(rgb_b, None, None))
+        loss.zero_()
+        r.image_loss(g4d.G4D_LOSS_L1, rgb_b, target, scale, loss, dl)
         r.backward(dl, out=grads)
 
     def step_per_view():
@@ -201,6 +204,25 @@ def main():
     stats = r.stats()
     log(f"[bench] batched step {sec * 1e3:.3f} ms; stages {stages}; stats {stats}")
 
+    # the same step, sync-free, captured once into a HIP graph and replayed
+    graph_sec = None
+    try:
+        r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+        step_batched()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step_batched()
+        graph_sec = timed(graph.replay, args.steps, args.warmup)
+        r.stats()  # raises if a replay overflowed the instance arena
+        log(f"[bench] graph replay step {graph_sec * 1e3:.3f} ms")
+    except Exception as e:  # capture unsupported: the eager figure stands
+        log(f"[bench] graph replay unavailable: {e}")
+        graph_sec = None
+    finally:
+        r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
+    best = min(sec, graph_sec) if graph_sec else sec
+
     fwd_b = timed(forward_batched, max(3, args.steps // 2), 2)
     extra = {}
     if not args.no_per_view:
@@ -210,7 +232,7 @@ def main():
         extra = dict(per_view_fwd_bwd_mpix_per_s=P_total / step_pv / 1e6,
                      per_view_fwd_bwd_steps_per_s=1.0 / step_pv,
                      per_view_forward_mpix_per_s=P_total / fwd_pv / 1e6,
-                     batched_over_per_view_fwd_bwd=step_pv / sec)
+                     batched_over_per_view_fwd_bwd=step_pv / best)
 
     # roofline of the dominant stage
     per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
@@ -250,15 +272,18 @@ def main():
 
     out = {
         "metric": "Mpix/s render and fwd+bwd steps/s, 300k 4D Gaussians, batched vs per-view",
-        "value": P_total / sec / 1e6,
+        "value": P_total / best / 1e6,
         "unit": "Mpix/s (fwd+bwd training step, batched)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": best * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "primitives": sc.n, "views": V, "resolution": f"{hw[0][1]}x{hw[0][0]}",
                    "sh_degree": sc.sh_degree, "t_order": sc.t_order, "loss": "l1", "batched": True},
-        "fwd_bwd_steps_per_s": 1.0 / sec,
+        "fwd_bwd_steps_per_s": 1.0 / best,
+        "batched_step_mode": "graph replay" if best != sec else "eager",
+        "eager_ms_per_step": sec * 1e3,
+        "graph_ms_per_step": graph_sec * 1e3 if graph_sec else None,
         "forward_mpix_per_s": P_total / fwd_b / 1e6,
         **extra,
         "stage_ms_per_step": {k: ms / args.steps for k, (ms, n) in stages.items()},

@@ -124,7 +124,9 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
  * most G4D_TUNE_ROUND_INSTANCES tile instances; a round over the instance cap
  * is shrunk and binned again. Each view's result does not depend on the
  * grouping. Synchronises the stream once per binning attempt, to size the
- * tile-instance arena. G4D_ECAPACITY if one view alone exceeds the cap. */
+ * tile-instance arena (see G4D_TUNE_SYNC_FREE for the mode that does not).
+ * G4D_ECAPACITY if one view alone exceeds the cap. Views reach the device as
+ * kernel arguments: cams and times may be reused as soon as this returns. */
 g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
                       float* out_rgb, float* out_depth, float* out_alpha);
 
@@ -153,8 +155,9 @@ g4d_status g4d_image_loss(g4d_ctx* ctx, int32_t kind, int64_t n, const float* im
                           float scale, float* loss_out, float* grad_out);
 
 /* Counters of the last render, summed over its rounds; active_per_view
- * (host [n_views]) may be NULL. `fragments` is computed on demand and
- * synchronises the stream. */
+ * (host [n_views]) may be NULL. Synchronises the stream. Returns
+ * G4D_ECAPACITY (after filling `out`) when a sync-free render since the last
+ * call overflowed the instance arena. */
 g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view);
 
 /* Tuning knobs (key, value); unknown keys give G4D_EINVAL.
@@ -164,8 +167,27 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *   G4D_TUNE_ROUND_PAIRS     max (view, primitive) pairs per round (>= 1;
  *                            default 2^28, about 37 GB of per-pair scratch)
  *   G4D_TUNE_ROUND_INSTANCES max tile instances per round (>= 1; default
- *                            2^30, 16 GB of key/value arena)              */
-enum { G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2, G4D_TUNE_ROUND_PAIRS = 3, G4D_TUNE_ROUND_INSTANCES = 4 };
+ *                            2^30, 16 GB of key/value arena)
+ *   G4D_TUNE_SYNC_FREE     1: render and render_backward read no device
+ *                          count on the host and never synchronise, so a
+ *                          caller may capture them (with image_loss) into a
+ *                          HIP graph. The batch is one round (n * n_views
+ *                          within G4D_TUNE_ROUND_PAIRS) and the tile-instance
+ *                          arena keeps the capacity that earlier synchronous
+ *                          renders or G4D_TUNE_ARENA_INSTANCES gave it. A
+ *                          render that needs more raises a sticky device
+ *                          flag and outputs background only; get_stats
+ *                          reports it as G4D_ECAPACITY and clears it.
+ *                          Scratch that must grow grows (synchronising) when
+ *                          the stream is not capturing; during capture that
+ *                          is G4D_ECAPACITY, so make one uncaptured call of
+ *                          the same shape first. 0 (default): off.
+ *   G4D_TUNE_ARENA_INSTANCES  grow the tile-instance arena now to hold at
+ *                          least this many instances (>= 0)               */
+enum {
+  G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2, G4D_TUNE_ROUND_PAIRS = 3, G4D_TUNE_ROUND_INSTANCES = 4,
+  G4D_TUNE_SYNC_FREE = 5, G4D_TUNE_ARENA_INSTANCES = 6
+};
 g4d_status g4d_set_tuning(g4d_ctx* ctx, int32_t key, int32_t value);
 
 /* Per-stage GPU time accumulated since stage timing was switched on

@@ -51,6 +51,7 @@ struct g4d_ctx {
   int sort_blocks = 1024;
   int64_t round_pairs = int64_t(1) << 28;
   int64_t round_instances = int64_t(1) << 30;
+  bool sync_free = false;          // no host read of device counts inside render/backward
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
@@ -78,8 +79,10 @@ constexpr int kCntI = 1;          // instances
 constexpr int kCntInst64 = 2;     // 64-bit instance total (words 2, 3)
 constexpr int kCntFrag = 4;       // 64-bit fragment sum (words 4, 5)
 constexpr int kCntMaxList = 6;    // longest tile list over the rounds of a render
+constexpr int kCntOverflow = 7;   // sticky: a sync-free render exceeded the instance arena
 constexpr int kCntViews = 8;      // per-view active counts follow
 constexpr int kMaxViews = 4096;
+constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the device
 
 g4d_status fail(g4d_ctx* c, g4d_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -99,9 +102,23 @@ g4d_status check_hip(g4d_ctx* c, hipError_t e, const char* what) {
     if (_s != G4D_OK) return _s;                          \
   } while (0)
 
+bool capturing(g4d_ctx* c) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Grows a scratch buffer (25% headroom). Growth synchronises the stream and
+// allocates, so it is refused while the stream is being captured.
 g4d_status ensure(g4d_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return G4D_OK;
+  if (capturing(c))
+    return fail(c, G4D_ECAPACITY, "a scratch buffer would grow during stream capture; make the same call "
+                                  "uncaptured first");
   if (b.ptr) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipFree(b.ptr));
@@ -143,13 +160,13 @@ hipEvent_t take_event(g4d_ctx* c) {
 }
 
 void stage_begin(g4d_ctx* c) {
-  if (!c->timing) return;
+  if (!c->timing || capturing(c)) return;
   c->open_ev = take_event(c);
   if (c->open_ev) (void)hipEventRecord(c->open_ev, c->stream);
 }
 
 void stage_end(g4d_ctx* c, int stage) {
-  if (!c->timing || !c->open_ev) return;
+  if (!c->timing || !c->open_ev || capturing(c)) return;
   hipEvent_t e = take_event(c);
   if (!e) return;
   (void)hipEventRecord(e, c->stream);
@@ -200,9 +217,8 @@ int round_tiles(const g4d_ctx* c, int v0, int v1) {
 
 // Per-pair stage of one round, views [v0, v1): preprocess every (view,
 // primitive) pair, compact the active ones, sort them by depth, gather the
-// records in that order and scan their tile counts. Synchronises once and
-// returns the active count and the instance total.
-g4d_status bin_pairs(g4d_ctx* c, int v0, int v1, uint32_t& A, uint64_t& inst64) {
+// records in that order and scan their tile counts. Counts stay on the device.
+g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
   c->bound = -1;
   hipStream_t s = c->stream;
   const int nv = v1 - v0;
@@ -232,8 +248,8 @@ g4d_status bin_pairs(g4d_ctx* c, int v0, int v1, uint32_t& A, uint64_t& inst64) 
   RenderParams p = make_params(c, nv);
   uint32_t* cnt = P<uint32_t>(c->counters);
 
-  HIPCHK(c, hipMemcpyAsync(c->views_d.ptr, vr.data(), sizeof(ViewDev) * nv, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * 4, s));
+  launch_set_views(vr.data(), nv, P<ViewDev>(c->views_d), s);
+  launch_fill_u32(cnt, 4, 0u, s);
   // 1. per (view, primitive): cull, slice, project, colour
   stage_begin(c);
   launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot), s);
@@ -255,38 +271,79 @@ g4d_status bin_pairs(g4d_ctx* c, int v0, int v1, uint32_t& A, uint64_t& inst64) 
   launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
               P<uint32_t>(c->scan_scratch), s);
   stage_end(c, G4D_STAGE_BINNING);
-  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (kCntViews + nv), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
+// Reads a round's active count, instance total and per-view counts
+// (synchronises the stream).
+g4d_status read_pairs(g4d_ctx* c, int v0, int nv, uint32_t& A, uint64_t& inst64) {
+  uint32_t* cnt = P<uint32_t>(c->counters);
+  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (kCntViews + nv), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   A = c->counters_h[kCntA];
   std::memcpy(&inst64, c->counters_h + kCntInst64, sizeof(inst64));
   std::copy(c->counters_h + kCntViews, c->counters_h + kCntViews + nv, c->view_active.begin() + v0);
   return G4D_OK;
 }
 
+uint64_t arena_instances(const g4d_ctx* c) {
+  return std::min(std::min(c->ikey.cap, c->ival.cap), std::min(c->ikey2.cap, c->ival2.cap)) / 4;
+}
+
 // Per-instance stage of a round whose pairs are binned: emit the (tile,
 // record) instances, sort them stably by tile and find each tile's range.
-g4d_status bin_tiles(g4d_ctx* c, const g4d_ctx::Round& r) {
+// a_max bounds the active records and cap the instances (the device counts
+// decide within those bounds).
+g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   hipStream_t s = c->stream;
   g4d_status st;
-  const uint32_t I = r.I;
-  if ((st = ensure(c, c->ikey, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ival, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ikey2, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ival2, 4 * (size_t)I))) return st;
-  if ((st = ensure(c, c->ranges, sizeof(uint2) * (size_t)r.tiles))) return st;
+  if ((st = ensure(c, c->ikey, 4 * (size_t)cap))) return st;
+  if ((st = ensure(c, c->ival, 4 * (size_t)cap))) return st;
+  if ((st = ensure(c, c->ikey2, 4 * (size_t)cap))) return st;
+  if ((st = ensure(c, c->ival2, 4 * (size_t)cap))) return st;
+  if ((st = ensure(c, c->ranges, sizeof(uint2) * (size_t)tiles))) return st;
   uint32_t* cnt = P<uint32_t>(c->counters);
   // 6. emit (tile, record) instances; 7. stable sort by tile; 8. ranges
   stage_begin(c);
-  HIPCHK(c, hipMemsetAsync(c->ranges.ptr, 0, sizeof(uint2) * (size_t)r.tiles, s));
-  launch_emit(cnt + kCntA, r.A, P<uint32_t>(c->toff), cnt + kCntI, P<Record>(c->rec_sorted), P<uint32_t>(c->cval),
-              (int)c->n, P<ViewDev>(c->views_d), P<uint32_t>(c->ikey), P<uint32_t>(c->ival), s);
-  const int tile_bits = ceil_log2((uint32_t)r.tiles);
-  const int g_tile = radix_grid(I, c->sort_blocks);
-  radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI, I,
-             0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
-  launch_ranges(cnt + kCntI, I, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+  launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
+  launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, P<Record>(c->rec_sorted),
+              P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), P<uint32_t>(c->ikey), P<uint32_t>(c->ival), s);
+  const int tile_bits = ceil_log2((uint32_t)tiles);
+  const int g_tile = radix_grid(cap, c->sort_blocks);
+  radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI,
+             cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
+  launch_ranges(cnt + kCntI, cap, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
   stage_end(c, G4D_STAGE_BINNING);
   HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, float* out_depth, float* out_alpha) {
+  hipStream_t s = c->stream;
+  launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, P<uint32_t>(c->counters) + kCntMaxList, s);
+  // 9. rasterise the round's views into their places in the outputs
+  stage_begin(c);
+  launch_raster_forward(r.tiles, r.v1 - r.v0, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
+                        P<Record>(c->rec_sorted), c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t),
+                        P<uint32_t>(c->pix_last), s);
+  stage_end(c, G4D_STAGE_RASTER_FWD);
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
+// Fills a sync-free round's counts from the device (synchronises).
+g4d_status resolve_round(g4d_ctx* c, g4d_ctx::Round& r) {
+  if (r.A != kOnDevice) return G4D_OK;
+  uint32_t A = 0;
+  uint64_t inst = 0;
+  g4d_status st = read_pairs(c, r.v0, r.v1 - r.v0, A, inst);
+  if (st) return st;
+  r.A = A;
+  r.I = c->counters_h[kCntI];  // zero after an overflow
+  c->A_total = A;
+  c->I_total = r.I;
   return G4D_OK;
 }
 
@@ -425,7 +482,9 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
 
   hipStream_t s = c->stream;
   g4d_status st;
+  const bool fresh_counters = c->counters.ptr == nullptr;
   if ((st = ensure(c, c->counters, sizeof(uint32_t) * (kCntViews + kMaxViews)))) return st;
+  if (fresh_counters) launch_fill_u32(P<uint32_t>(c->counters), kCntViews, 0u, s);  // the overflow flag starts clear
   if ((st = ensure(c, c->pix_t, 4 * pix))) return st;
   if ((st = ensure(c, c->pix_last, 4 * pix))) return st;
 
@@ -438,7 +497,23 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
   c->A_total = c->I_total = 0;
   c->view_active.assign(n_views, 0);
   uint32_t* cnt = P<uint32_t>(c->counters);
-  HIPCHK(c, hipMemsetAsync(cnt + kCntMaxList, 0, sizeof(uint32_t), s));
+  launch_fill_u32(cnt + kCntMaxList, 1, 0u, s);
+
+  if (c->sync_free) {
+    // One round; counts stay on the device and the arena keeps its capacity.
+    if ((uint64_t)c->n * n_views > (uint64_t)c->round_pairs)
+      return fail(c, G4D_ECAPACITY, "a sync-free render is one round: n * n_views exceeds the pair cap");
+    g4d_ctx::Round r{0, n_views, (int)tiles, kOnDevice, kOnDevice};
+    if ((st = enqueue_pairs(c, 0, n_views))) return st;
+    const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(arena_instances(c), 1), 0xFFFFFFF0ull);
+    launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
+    if ((st = bin_tiles(c, r.tiles, (uint32_t)((uint64_t)c->n * n_views), (uint32_t)cap))) return st;
+    c->rounds.push_back(r);
+    c->bound = 0;
+    if ((st = rasterise_round(c, r, out_rgb, out_depth, out_alpha))) return st;
+    c->have_render = true;
+    return G4D_OK;
+  }
 
   // Rounds of consecutive views under the pair and instance caps. The next
   // round's size is predicted from the last one's instances per view; a round
@@ -451,7 +526,8 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
     uint32_t A = 0;
     uint64_t inst = 0;
     for (;;) {
-      if ((st = bin_pairs(c, v0, v0 + k, A, inst))) return st;
+      if ((st = enqueue_pairs(c, v0, v0 + k))) return st;
+      if ((st = read_pairs(c, v0, k, A, inst))) return st;
       if (inst <= inst_cap) break;
       if (k == 1)
         return fail(c, G4D_ECAPACITY, "view " + std::to_string(v0) + " alone needs " + std::to_string(inst) +
@@ -459,17 +535,10 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
       k = std::max(1, std::min(k - 1, (int)(0.9 * (double)k * (double)inst_cap / (double)inst)));
     }
     g4d_ctx::Round r{v0, v0 + k, round_tiles(c, v0, v0 + k), A, (uint32_t)inst};
-    if ((st = bin_tiles(c, r))) return st;
+    if ((st = bin_tiles(c, r.tiles, r.A, r.I))) return st;
     c->rounds.push_back(r);
     c->bound = (int)c->rounds.size() - 1;
-    launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, cnt + kCntMaxList, s);
-    // 9. rasterise the round's views into their places in the outputs
-    stage_begin(c);
-    launch_raster_forward(r.tiles, k, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
-                          P<Record>(c->rec_sorted), c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t),
-                          P<uint32_t>(c->pix_last), s);
-    stage_end(c, G4D_STAGE_RASTER_FWD);
-    HIPCHK(c, hipGetLastError());
+    if ((st = rasterise_round(c, r, out_rgb, out_depth, out_alpha))) return st;
     c->A_total += A;
     c->I_total += inst;
     k_next = inst ? (int)std::min<double>(by_pairs, std::max(1.0, 0.9 * (double)k * (double)inst_cap / (double)inst))
@@ -498,31 +567,35 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
   g4d_status st;
   // Rounds last to first: the last one is still binned after the render.
   bool accumulate = (flags & G4D_GRAD_ACCUMULATE) != 0;
+  uint32_t* cnt = P<uint32_t>(c->counters);
   for (int ri = (int)c->rounds.size() - 1; ri >= 0; --ri) {
     const g4d_ctx::Round r = c->rounds[ri];
     const int nv = r.v1 - r.v0;
     if (c->bound != ri) {
       uint32_t A = 0;
       uint64_t inst = 0;
-      if ((st = bin_pairs(c, r.v0, r.v1, A, inst))) return st;
+      if ((st = enqueue_pairs(c, r.v0, r.v1))) return st;
+      if ((st = read_pairs(c, r.v0, nv, A, inst))) return st;
       if (A != r.A || inst != r.I)
         return fail(c, G4D_ESTATE, "binning a round again gave other counts; primitives changed since render");
-      if ((st = bin_tiles(c, r))) return st;
+      if ((st = bin_tiles(c, r.tiles, r.A, r.I))) return st;
       c->bound = ri;
     }
-    if ((st = ensure(c, c->grad2d, sizeof(float) * 12 * (size_t)r.A))) return st;
+    // records bound: exact for a synchronous round, every pair for a sync-free one
+    const uint32_t a_max = r.A == kOnDevice ? (uint32_t)((uint64_t)c->n * nv) : r.A;
+    if ((st = ensure(c, c->grad2d, sizeof(float) * 12 * (size_t)a_max))) return st;
+    if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(a_max)))) return st;
     stage_begin(c);
-    if (r.A) HIPCHK(c, hipMemsetAsync(c->grad2d.ptr, 0, sizeof(float) * 12 * (size_t)r.A, s));
+    launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, 12, a_max, s);
     launch_raster_backward(r.tiles, nv, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
                            P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
     RenderParams p = make_params(c, nv);
-    if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(r.A)))) return st;
     stage_begin(c);
-    launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), P<uint32_t>(c->counters) + kCntA, r.A,
-                               P<uint32_t>(c->cval), P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4,
-                               g_log_scales4, g_q_left, g_q_right, g_opacity_logit, g_coeffs, accumulate, s);
+    launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), cnt + kCntA, a_max, P<uint32_t>(c->cval),
+                               P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4, g_log_scales4, g_q_left,
+                               g_q_right, g_opacity_logit, g_coeffs, accumulate, s);
     stage_end(c, G4D_STAGE_PREPROCESS_BWD);
     HIPCHK(c, hipGetLastError());
     accumulate = true;
@@ -559,19 +632,25 @@ g4d_status g4d_stage_times(g4d_ctx* c, double* ms_out, int64_t* launches_out) {
 
 g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
   if (!c || !out) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
+  g4d_status st;
+  for (auto& r : c->rounds)
+    if ((st = resolve_round(c, r))) return st;
   out->n_views = c->n_views;
   out->active_total = (int64_t)c->A_total;
   out->instances = (int64_t)c->I_total;
   out->tiles = c->total_tiles;
   out->rounds = (int64_t)c->rounds.size();
-  // longest list and fragment total need device reads
+  // longest list, overflow flag and fragment total need device reads
   uint32_t* cnt = P<uint32_t>(c->counters);
-  HIPCHK(c, hipMemsetAsync(cnt + kCntFrag, 0, 8, c->stream));
+  launch_fill_u32(cnt + kCntFrag, 2, 0u, c->stream);
   launch_sum_u32(P<uint32_t>(c->pix_last), (uint64_t)c->total_pix, reinterpret_cast<unsigned long long*>(cnt + kCntFrag),
                  c->stream);
-  uint32_t words[3] = {0, 0, 0};
+  uint32_t words[4] = {0, 0, 0, 0};
+  uint64_t need = 0;
   HIPCHK(c, hipMemcpyAsync(words, cnt + kCntFrag, sizeof(words), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&need, cnt + kCntInst64, sizeof(need), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   uint64_t frag = 0;
   std::memcpy(&frag, words, sizeof(frag));
@@ -579,6 +658,13 @@ g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
   out->fragments = (int64_t)frag;
   if (active_per_view)
     for (int v = 0; v < c->n_views; ++v) active_per_view[v] = c->view_active[v];
+  if (words[kCntOverflow - kCntFrag]) {
+    launch_fill_u32(cnt + kCntOverflow, 1, 0u, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return fail(c, G4D_ECAPACITY, "a sync-free render since the last get_stats exceeded the instance arena of " +
+                                      std::to_string(arena_instances(c)) + " (last render needs " +
+                                      std::to_string(need) + "); its outputs are background only");
+  }
   return G4D_OK;
 }
 
@@ -600,6 +686,18 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     c->timing = value == 1;
     return G4D_OK;
   }
+  if (key == G4D_TUNE_SYNC_FREE) {
+    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "sync-free is 0 or 1");
+    c->sync_free = value == 1;
+    return G4D_OK;
+  }
+  if (key == G4D_TUNE_ARENA_INSTANCES) {
+    if (value < 0) return fail(c, G4D_EINVAL, "arena size must be >= 0");
+    g4d_status st;
+    for (DevBuf* b : {&c->ikey, &c->ival, &c->ikey2, &c->ival2})
+      if ((st = ensure(c, *b, 4 * (size_t)value))) return st;
+    return G4D_OK;
+  }
   if (key == G4D_TUNE_ROUND_PAIRS || key == G4D_TUNE_ROUND_INSTANCES) {
     if (value < 1) return fail(c, G4D_EINVAL, "round caps must be >= 1");
     (key == G4D_TUNE_ROUND_PAIRS ? c->round_pairs : c->round_instances) = value;
@@ -614,7 +712,9 @@ g4d_status g4d_debug_size(g4d_ctx* c, int32_t what, int64_t* bytes) {
   if (!c || !bytes) return G4D_EINVAL;
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
   if (c->bound < 0) return fail(c, G4D_ESTATE, "no round is binned");
-  const g4d_ctx::Round& r = c->rounds[c->bound];
+  g4d_ctx::Round& r = c->rounds[c->bound];
+  g4d_status st = resolve_round(c, r);
+  if (st) return st;
   switch (what) {
     case G4D_DBG_RECORDS: *bytes = (int64_t)sizeof(Record) * r.A; break;
     case G4D_DBG_IDS: *bytes = 4ll * r.A; break;

@@ -88,7 +88,8 @@ void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, c
                    int32_t* slot, uint32_t* tcount, uint32_t* inst64, int n_prims, hipStream_t s);
 void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, uint32_t n, const uint32_t* total,
                         uint32_t* out, hipStream_t s);
-void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total,
+// Instances beyond min(*total, cap) are not written.
+void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views,
                  uint32_t* ikey, uint32_t* ival, hipStream_t s);
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s);
@@ -103,5 +104,17 @@ void launch_raster_backward(int total_tiles, int n_views, const ViewDev* views, 
                             const uint32_t* pix_last, float* grad2d, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
+
+// ---- launchers (util.hip) ----
+// Views reach the device through kernel arguments, never a host copy.
+void launch_set_views(const ViewDev* host, int n, ViewDev* dev, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t s);
+// Zeroes floats_per_item (a multiple of 4) floats per item for min(*n_dev, max_items) items.
+void launch_zero_counted(float* p, const uint32_t* n_dev, uint32_t floats_per_item, uint64_t max_items,
+                         hipStream_t s);
+// If the 64-bit instance total at inst64 exceeds cap: *overflow = 1 and *n_inst = 0.
+void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s);
+void launch_copy_pairs(const uint32_t* ka, const uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
+                       uint32_t n_max, hipStream_t s);
 
 }  // namespace g4d

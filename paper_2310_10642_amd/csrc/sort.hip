@@ -346,7 +346,7 @@ __global__ void k_view_counts(const uint32_t* __restrict__ pos, const uint32_t* 
 // over its threads, each finding its record by binary search in LDS.
 __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32_t n_max,
                                                     const uint32_t* __restrict__ toff, const uint32_t* total,
-                                                    const Record* __restrict__ rec_sorted,
+                                                    uint32_t cap, const Record* __restrict__ rec_sorted,
                                                     const uint32_t* __restrict__ ids, uint32_t n_prims,
                                                     const ViewDev* __restrict__ views, uint32_t* __restrict__ ikey,
                                                     uint32_t* __restrict__ ival) {
@@ -368,7 +368,8 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
     s_tw[threadIdx.x] = (uint32_t)views[v].tiles_x;
   }
   __syncthreads();
-  const uint32_t start = offs[0], end = offs[kThreads];
+  const uint32_t lim = min(tot, cap);
+  const uint32_t start = offs[0], end = min(offs[kThreads], lim);
   for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
     int lo = 0, hi = kThreads - 1;
     while (lo < hi) {
@@ -441,7 +442,7 @@ void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint3
   const uint32_t cap = n_dev ? n_max : n_host;
   const unsigned nb = grid_for(cap, kTileElems);
   if (nb == 0) {
-    (void)hipMemsetAsync(total, 0, sizeof(uint32_t), s);
+    launch_fill_u32(total, 1, 0u, s);
     return;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n_dev, cap, scratch);
@@ -478,10 +479,7 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
     t = vin; vin = vout; vout = t;
     ++passes;
   }
-  if (passes & 1) {
-    (void)hipMemcpyAsync(keys, kin, sizeof(uint32_t) * (size_t)n_max, hipMemcpyDeviceToDevice, s);
-    (void)hipMemcpyAsync(vals, vin, sizeof(uint32_t) * (size_t)n_max, hipMemcpyDeviceToDevice, s);
-  }
+  if (passes & 1) launch_copy_pairs(kin, vin, keys, vals, n_dev, n_max, s);
 }
 
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
@@ -497,11 +495,11 @@ void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, u
   hipLaunchKernelGGL(k_view_counts, dim3(grid_for(n_views, 64)), dim3(64), 0, s, pos, act, n_views, n, total, out);
 }
 
-void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total,
+void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, uint32_t* ikey,
                  uint32_t* ival, hipStream_t s) {
   if (n_max == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, toff, total,
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, toff, total, cap,
                      rec_sorted, ids, (uint32_t)n_prims, views, ikey, ival);
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libg4d.so")
 G4D_OK, G4D_EINVAL, G4D_ENOMEM, G4D_EHIP, G4D_ESTATE, G4D_ECAPACITY = 0, -1, -2, -3, -4, -5
 G4D_TUNE_SORT_BLOCKS, G4D_TUNE_STAGE_TIMING = 1, 2
 G4D_TUNE_ROUND_PAIRS, G4D_TUNE_ROUND_INSTANCES = 3, 4
+G4D_TUNE_SYNC_FREE, G4D_TUNE_ARENA_INSTANCES = 5, 6
 G4D_GRAD_ACCUMULATE = 1
 G4D_LOSS_L1, G4D_LOSS_L2 = 1, 2
 STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss"]
@@ -162,17 +163,26 @@ class Renderer:
         self._check(self.lib.g4d_set_primitives(self.ctx, n, *[_ptr(t) for t in ts]))
         self.n = n
 
-    def render(self, cameras: Sequence, times: Sequence[float], depth: bool = True, alpha: bool = True):
-        """Returns flat (rgb, depth, alpha) tensors over the concatenated views."""
+    def render(self, cameras: Sequence, times: Sequence[float], depth: bool = True, alpha: bool = True,
+               out: Optional[Sequence[Optional[torch.Tensor]]] = None):
+        """Returns flat (rgb, depth, alpha) tensors over the concatenated views,
+        written into `out` = (rgb, depth or None, alpha or None) when given."""
         self._stream()
         V = len(cameras)
         cams = (G4DCamera * V)(*[to_camera(c) for c in cameras])
         tarr = (ctypes.c_float * V)(*[float(t) for t in times])
         npix = sum(int(c.width) * int(c.height) for c in cameras)
         dev = torch.device("cuda", torch.cuda.current_device())
-        rgb = torch.empty(3 * npix, device=dev, dtype=torch.float32)
-        dep = torch.empty(npix, device=dev, dtype=torch.float32) if depth else None
-        alp = torch.empty(npix, device=dev, dtype=torch.float32) if alpha else None
+        if out is not None:
+            rgb, dep, alp = out
+            for t, k in ((rgb, 3), (dep, 1), (alp, 1)):
+                if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                                          and t.numel() == k * npix):
+                    raise ValueError("render outputs must be contiguous float32 GPU tensors of the batch's size")
+        else:
+            rgb = torch.empty(3 * npix, device=dev, dtype=torch.float32)
+            dep = torch.empty(npix, device=dev, dtype=torch.float32) if depth else None
+            alp = torch.empty(npix, device=dev, dtype=torch.float32) if alpha else None
         self._check(self.lib.g4d_render(self.ctx, V, cams, tarr, _ptr(rgb), _ptr(dep), _ptr(alp)))
         self.generation += 1
         self._views = [(int(c.height), int(c.width)) for c in cameras]

@@ -40,6 +40,8 @@ def test_header_constants_match_binding():
     assert val("G4D_TUNE_STAGE_TIMING") == g4d.G4D_TUNE_STAGE_TIMING
     assert val("G4D_TUNE_ROUND_PAIRS") == g4d.G4D_TUNE_ROUND_PAIRS
     assert val("G4D_TUNE_ROUND_INSTANCES") == g4d.G4D_TUNE_ROUND_INSTANCES
+    assert val("G4D_TUNE_SYNC_FREE") == g4d.G4D_TUNE_SYNC_FREE
+    assert val("G4D_TUNE_ARENA_INSTANCES") == g4d.G4D_TUNE_ARENA_INSTANCES
     assert val("G4D_NUM_STAGES") == len(g4d.STAGES)
     for k, v in g4d.DBG.items():
         assert val("G4D_DBG_" + k.upper()) == v

@@ -427,6 +427,107 @@ def test_rounds_match_one_round():
     assert r.stats()["rounds"] == 1 and torch.equal(again[0], one[0])
 
 
+def _close_grads(ga, gb, rel=1e-5):
+    for name, a, b in zip(PT.GROUPS, ga, gb):
+        a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
+        assert np.isfinite(a).all(), name
+        nb = np.linalg.norm(b)
+        assert nb == 0 or np.linalg.norm(a - b) <= rel * nb, name
+
+
+def test_sync_free_and_graph_replay():
+    """The sync-free mode reproduces the synchronous training step (images bit
+    for bit, loss and gradients up to summation order); a HIP graph captured
+    around render + loss + backward replays it, three times, with eager work
+    and synchronisation between the replays."""
+    _say("[sync-free and graph replay, 300k x 2 views]")
+    from paper_2310_10642_amd import g4d
+    wl = scenegen.bench_workload(2)
+    r, _ = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    tgt = torch.from_numpy(np.concatenate([x.reshape(-1) for x in wl.targets])).cuda()
+    scale = 1.0 / (3 * wl.cameras[0].width * wl.cameras[0].height)
+
+    def buffers():
+        return (torch.empty_like(tgt), torch.empty(tgt.numel() // 3, device="cuda"),
+                torch.empty(tgt.numel() // 3, device="cuda"), torch.zeros(1, device="cuda"), torch.empty_like(tgt))
+
+    def step(grads, bufs):
+        rgb, dep, alp, loss, dl = bufs
+        r.render(wl.cameras, times, out=(rgb, dep, alp))
+        loss.zero_()
+        r.image_loss(g4d.G4D_LOSS_L1, rgb, tgt, scale, loss, dl)
+        r.backward(dl, out=grads)
+        return rgb, dep, alp, loss
+
+    g_ref = r.grad_buffers()
+    ref = step(g_ref, buffers())
+    s_ref = r.stats()
+    r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+    g_sf = r.grad_buffers()
+    sf = step(g_sf, buffers())
+    s_sf = r.stats()
+    for a, b in zip(ref[:3], sf[:3]):
+        assert torch.equal(a, b)
+    assert abs(float(sf[3]) - float(ref[3])) <= 1e-6 * abs(float(ref[3]))
+    _close_grads(g_sf, g_ref)
+    for k in ("active_total", "instances", "fragments", "max_tile_list", "active_per_view", "rounds"):
+        assert s_ref[k] == s_sf[k], k
+
+    g_gr = r.grad_buffers()
+    bufs = buffers()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step(g_gr, bufs)
+    for rep in range(3):
+        for t in (*outs, *g_gr):
+            t.fill_(float("nan"))
+        x = torch.randn(512, 512, device="cuda")
+        _ = float((x @ x).sum())               # eager work and a synchronisation
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(ref[:3], outs[:3]):
+            assert torch.equal(a, b), rep
+        assert abs(float(outs[3]) - float(ref[3])) <= 1e-6 * abs(float(ref[3])), rep
+        _close_grads(g_gr, g_ref)
+        _say(f"  replay {rep} ok")
+    del graph
+    r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
+
+
+def test_sync_free_arena_overflow():
+    """A sync-free render that needs more tile instances than the arena holds
+    renders background only, its backward gives zero gradients, and get_stats
+    reports the overflow once; a synchronous render then works."""
+    _say("[sync-free arena overflow]")
+    from paper_2310_10642_amd import g4d
+    wl = scenegen.make_workload(0)
+    cam = wl.cameras[0]
+    r, _ = PT.gpu_setup(wl.scene)
+    ref, _, _ = r.render([cam], [0.5])
+    need = r.stats()["instances"]
+    r2, _ = PT.gpu_setup(wl.scene)
+    r2.render([cam], [50.0])                   # every primitive culled in time: a near-empty arena
+    assert r2.stats()["instances"] == 0 < need
+    r2.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+    rgb, _, alp = r2.render([cam], [0.5])
+    g = r2.backward(torch.ones_like(rgb))
+    torch.cuda.synchronize()
+    assert float(rgb.abs().max()) == 0.0 and float(alp.abs().max()) == 0.0
+    assert all(float(x.abs().max()) == 0.0 for x in g)
+    with pytest.raises(g4d.G4DError) as ei:
+        r2.stats()
+    assert ei.value.status == g4d.G4D_ECAPACITY and str(need) in str(ei.value)
+    assert r2.stats()["instances"] == 0       # reported once
+    r2.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
+    again, _, _ = r2.render([cam], [0.5])
+    assert torch.equal(again, ref)
+    r2.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+    again2, _, _ = r2.render([cam], [0.5])     # the arena now fits
+    assert torch.equal(again2, ref) and r2.stats()["instances"] == need
+
+
 @pytest.mark.timeout(400)
 def test_long_sequence_3m_240_views_sampled():
     """3M short-lived primitives over 60 frames x 4 cameras at 1920x1080 in one
