@@ -220,8 +220,8 @@ const char* g4d_last_error(const g4d_ctx* ctx);
  *   G4D_DBG_RANGES    per global tile, uint32 [start, end)
  *   G4D_DBG_PIX_T     per pixel (views concatenated), float32 final transmittance
  *   G4D_DBG_PIX_LAST  per pixel, uint32 list entries up to the last contributor
- *   G4D_DBG_GRAD2D    after a backward: per active pair, 12 x float32
- *                     dL/du, dL/dv, dL/dconic00, 01, 11, dL/d(opacity*p), dL/dr, g, b, dL/dz, 0, 0 */
+ *   G4D_DBG_GRAD2D    after a backward: per active pair, 16 x float32
+ *                     dL/du, dL/dv, dL/dconic00, 01, 11, dL/d(opacity*p), dL/dr, g, b, dL/dz, 0 x 6 */
 enum {
   G4D_DBG_RECORDS = 1, G4D_DBG_IDS = 2, G4D_DBG_TILE_KEYS = 3, G4D_DBG_TILE_VALS = 4,
   G4D_DBG_RANGES = 5, G4D_DBG_PIX_T = 6, G4D_DBG_PIX_LAST = 7, G4D_DBG_GRAD2D = 8

@@ -583,10 +583,10 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     }
     // records bound: exact for a synchronous round, every pair for a sync-free one
     const uint32_t a_max = r.A == kOnDevice ? (uint32_t)((uint64_t)c->n * nv) : r.A;
-    if ((st = ensure(c, c->grad2d, sizeof(float) * 12 * (size_t)a_max))) return st;
+    if ((st = ensure(c, c->grad2d, sizeof(float) * kGrad2dStride * (size_t)a_max))) return st;
     if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(a_max)))) return st;
     stage_begin(c);
-    launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, 12, a_max, s);
+    launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, kGrad2dStride, a_max, s);
     launch_raster_backward(r.tiles, nv, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
                            P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
@@ -721,7 +721,7 @@ g4d_status g4d_debug_size(g4d_ctx* c, int32_t what, int64_t* bytes) {
     case G4D_DBG_TILE_KEYS: case G4D_DBG_TILE_VALS: *bytes = 4ll * r.I; break;
     case G4D_DBG_RANGES: *bytes = 8ll * r.tiles; break;
     case G4D_DBG_PIX_T: case G4D_DBG_PIX_LAST: *bytes = 4ll * c->total_pix; break;
-    case G4D_DBG_GRAD2D: *bytes = 48ll * r.A; break;
+    case G4D_DBG_GRAD2D: *bytes = 4ll * kGrad2dStride * r.A; break;
     default: return fail(c, G4D_EINVAL, "unknown debug item");
   }
   return G4D_OK;

@@ -31,6 +31,11 @@ struct ViewDev {
   float lim_x, lim_y;   // Jacobian clamp limits on x/z, y/z
 };
 
+// Floats per active record in the screen-space gradient buffer: one 64-byte
+// line holding dL/du, dL/dv, dL/dconic (3), dL/d(opacity p), dL/drgb (3),
+// dL/dz and padding.
+constexpr int kGrad2dStride = 16;
+
 // Per active (view, primitive) record used by binning and rasterisation.
 // 3 x float4 = 48 bytes:
 //   a: u, v, z, opacity * p(t)

@@ -57,9 +57,9 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
   const ViewDev& vw = p.views[vi];
   ViewGeom g;
   view_geometry(mu, sh, vw, p.t_cull, p.near_plane, g);
-  const float4 q0 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * 12);
-  const float4 q1 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * 12 + 4);
-  const float4 q2 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * 12 + 8);
+  const float4 q0 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride);
+  const float4 q1 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride + 4);
+  const float4 q2 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride + 8);
   const float gu = q0.x, gv = q0.y, gC0 = q0.z, gC1 = q0.w, gC2 = q1.x, go = q1.y;
   const float gdepth = q2.y;
   // colour = max(0, raw + 0.5): the clamp passes the gradient where the blended colour is positive

@@ -18,7 +18,8 @@
 // as 16 primitives x 16 pixel columns and accumulate the per-primitive sums
 // over the tile's pixels (only over quadrants where the primitive blended).
 // One 16-lane DPP reduction per batch combines the columns, and one atomic
-// per value and (tile, primitive) adds the tile's share.
+// per value and (tile, primitive) adds the tile's share; the lanes of a
+// primitive's row issue its values together into one 64-byte line.
 #include "g4d_common.h"
 
 namespace g4d {
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   __shared__ float4 s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch];
   __shared__ uint32_t s_d[kBwdBatch];
   __shared__ uint32_t s_qm[kBwdBatch];
-  __shared__ uint8_t s_act[4][kBwdBatch];  // entry blended somewhere in quadrant
+  __shared__ uint32_t s_act[4];  // per quadrant: bit j when entry j blended somewhere in it
   __shared__ float s_g[kBwdBatch * kGwStride];   // dL/dpower per (primitive, pixel)
   __shared__ float s_w[kBwdBatch * kGwStride];   // a_i T_i per (primitive, pixel)
   __shared__ float4 s_pix[256];
@@ -248,9 +249,10 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   const uint32_t wave_last = wave_max_u32(last);
   __syncthreads();
   if (lane == 0 && wave_last) atomicMax(&s_max, wave_last);
-  // "behind" accumulators: colour, depth and alpha of everything after the
-  // current primitive, normalised by the transmittance after it
-  float B0 = bg0, B1 = bg1, B2 = bg2, Bd = 0.f, Ba = 0.f;
+  // Only the dot product of this pixel's output gradient with the colour,
+  // depth and alpha of everything behind the current primitive (normalised by
+  // the transmittance after it) enters dL/da; it starts at the background.
+  float beta = fmaf(gC0, bg0, fmaf(gC1, bg1, gC2 * bg2));
   __syncthreads();
   const int max_last = (int)s_max;
 
@@ -284,60 +286,75 @@ __global__ void __launch_bounds__(256) k_raster_backward(
         nxt = recs[nxt_d];
       }
     }
-    if (lane < kBwdBatch) s_act[wave][lane] = 0;
     __syncthreads();
     // ---- phase 1: this lane's pixel, back to front over the batch ----
-    for (int j = kBwdBatch - 1; j >= 0; --j) {
-      // wave-uniform skips: no pixel of this quadrant reaches the entry
-      if (!((s_qm[j] >> wave) & 1u) || (uint32_t)(b0 + j) >= wave_last) continue;
-      const float4 sa = s_a[j];
-      const float4 sb = s_b[j];
+    // entries that can reach this wave's quadrant before its last contributor
+    uint32_t todo;
+    {
+      const uint32_t qm = lane < kBwdBatch ? s_qm[lane] : 0u;
+      todo = (uint32_t)__ballot(((qm >> wave) & 1u) && (uint32_t)(b0 + lane) < wave_last);
+    }
+    uint32_t blended = 0u;
+    auto entry = [&](int j, const float4& sa, const float4& sb, const float4& sc) {
       const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
       const bool valid = ((uint32_t)(b0 + j) < last) && (p2 >= kLog2AlphaMin);
-      if (!__any(valid)) continue;
-      const float4 sc = s_c[j];
+      if (!__any(valid)) return;
       const float G = __builtin_amdgcn_exp2f(p2);
-      const float a = valid ? fminf(G, kAlphaMax) : 0.f;
+      const float a = valid ? __builtin_amdgcn_fmed3f(G, 0.f, kAlphaMax) : 0.f;
       T = T * __builtin_amdgcn_rcpf(1.f - a);
-      const float w = a * T;
-      float s = gC0 * (sc.x - B0) + gC1 * (sc.y - B1) + gC2 * (sc.z - B2);
-      if (HAS_D) s = fmaf(gD, sb.z - Bd, s);
-      if (HAS_A) s = fmaf(gA, 1.f - Ba, s);
-      const float dLda = T * s;
-      B0 = fmaf(a, sc.x - B0, B0);
-      B1 = fmaf(a, sc.y - B1, B1);
-      B2 = fmaf(a, sc.z - B2, B2);
-      if (HAS_D) Bd = fmaf(a, sb.z - Bd, Bd);
-      if (HAS_A) Ba = fmaf(a, 1.f - Ba, Ba);
-      const float g = (valid && G < kAlphaMax) ? dLda * G : 0.f;  // dL/dpower
+      float dot = fmaf(gC0, sc.x, fmaf(gC1, sc.y, gC2 * sc.z));
+      if (HAS_D) dot = fmaf(gD, sb.z, dot);
+      if (HAS_A) dot += gA;
+      const float s = dot - beta;
+      beta = fmaf(a, s, beta);
+      const float g = (valid && G < kAlphaMax) ? (T * s) * G : 0.f;  // dL/dpower
       s_g[j * kGwStride + q_self] = g;
-      s_w[j * kGwStride + q_self] = w;
-      if (lane == 0) s_act[wave][j] = 1;
+      s_w[j * kGwStride + q_self] = a * T;
+      blended |= 1u << j;
+    };
+    // back to front over the set entries, the next one's values loaded ahead
+    if (todo) {
+      int j = 31 - __clz(todo);
+      float4 sa = s_a[j], sb = s_b[j], sc = s_c[j];
+      for (;;) {
+        todo &= ~(1u << j);
+        const int jn = todo ? 31 - __clz(todo) : j;
+        const float4 na = s_a[jn], nb = s_b[jn], nc = s_c[jn];
+        entry(j, sa, sb, sc);
+        if (!todo) break;
+        j = jn;
+        sa = na;
+        sb = nb;
+        sc = nc;
+      }
     }
+    if (lane == 0) s_act[wave] = blended;
     __syncthreads();
     // ---- phase 2: primitive j2, pixel column c2, rows of active quadrants ----
+    // Row moments are taken about the tile's middle row (offset m = k - 7.5)
+    // and moved to the primitive's centre afterwards: with dy = dc + m,
+    // sum g dy = dc Sg + Sgm and sum g dy^2 = dc^2 Sg + 2 dc Sgm + Sgmm.
     const int e2 = b0 + j2;
-    float Sg = 0.f, Sgy = 0.f, Sgyy = 0.f, Sr = 0.f, Sgc = 0.f, Sb = 0.f, Sd = 0.f;
-    float dx = 0.f;
+    float Sg = 0.f, Sgm = 0.f, Sgmm = 0.f, Sr = 0.f, Sgc = 0.f, Sb = 0.f, Sd = 0.f;
+    float dx = 0.f, dc = 0.f;
     if (e2 < count) {
       const float4 sa = s_a[j2];
       dx = (float)(tx * kTile + c2) + 0.5f - sa.x;
-      const float dy0 = (float)(ty * kTile) + 0.5f - sa.y;
+      dc = (float)(ty * kTile) + 8.f - sa.y;
+      const uint32_t act = (s_act[c2 >> 3] | (s_act[2 + (c2 >> 3)] << 16)) >> j2;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        const int q = (c2 >> 3) + 2 * half;
-        if (!s_act[q][j2]) continue;
+        if (!((act >> (16 * half)) & 1u)) continue;
 #pragma unroll
         for (int k = 8 * half; k < 8 * half + 8; ++k) {
           const int p = k * 16 + c2;
           const int slot = j2 * kGwStride + gw_slot(k, c2);
           const float2 gw = make_float2(s_g[slot], s_w[slot]);
           const float4 pd = s_pix[p];
-          const float dy = dy0 + (float)k;
+          const float m = (float)k - 7.5f;
           Sg += gw.x;
-          const float gdy = gw.x * dy;
-          Sgy += gdy;
-          Sgyy = fmaf(gdy, dy, Sgyy);
+          Sgm = fmaf(gw.x, m, Sgm);
+          Sgmm = fmaf(gw.x, m * m, Sgmm);
           Sr = fmaf(gw.y, pd.x, Sr);
           Sgc = fmaf(gw.y, pd.y, Sgc);
           Sb = fmaf(gw.y, pd.z, Sb);
@@ -345,6 +362,8 @@ __global__ void __launch_bounds__(256) k_raster_backward(
         }
       }
     }
+    const float Sgy = fmaf(dc, Sg, Sgm);
+    const float Sgyy = fmaf(dc, fmaf(dc, Sg, 2.f * Sgm), Sgmm);
     // v: Sg, Sgx, Sgy, Sgxx, Sgxy, Sgyy, w*dL/dr, w*dL/dg, w*dL/db, w*dL/dD
     float v[10] = {Sg, dx * Sg, Sgy, dx * dx * Sg, dx * Sgy, Sgyy, Sr, Sgc, Sb, Sd};
 #pragma unroll
@@ -352,26 +371,29 @@ __global__ void __launch_bounds__(256) k_raster_backward(
       if (!HAS_D && q == 9) continue;
       v[q] = row16_sum(v[q]);
     }
-    if (c2 == 0 && e2 < count) {
+    // lanes c2 < 10 of the primitive's row each add one value of its
+    // gradient line, so a wave's atomics for a primitive share one line
+    if (e2 < count) {
       bool nz = false;
 #pragma unroll
       for (int q = 0; q < 10; ++q) nz |= (v[q] != 0.f);
-      if (nz) {
+      const int nvals = HAS_D ? 10 : 9;
+      if (nz && c2 < nvals) {
         const uint32_t d = s_d[j2];
         const float k0 = s_a[j2].z * (-2.f / kLog2e), k1 = s_a[j2].w * (-1.f / kLog2e);
         const float k2 = s_b[j2].x * (-2.f / kLog2e);
         const float opac = __builtin_amdgcn_exp2f(s_b[j2].y);
-        float* o = grad2d + (size_t)d * 12;
-        unsafeAtomicAdd(o + 0, k0 * v[1] + k1 * v[2]);   // dL/du
-        unsafeAtomicAdd(o + 1, k1 * v[1] + k2 * v[2]);   // dL/dv
-        unsafeAtomicAdd(o + 2, -0.5f * v[3]);            // dL/dconic00
-        unsafeAtomicAdd(o + 3, -v[4]);                   // dL/dconic01
-        unsafeAtomicAdd(o + 4, -0.5f * v[5]);            // dL/dconic11
-        unsafeAtomicAdd(o + 5, v[0] / opac);             // dL/d(opacity p)
-        unsafeAtomicAdd(o + 6, v[6]);
-        unsafeAtomicAdd(o + 7, v[7]);
-        unsafeAtomicAdd(o + 8, v[8]);
-        if (HAS_D) unsafeAtomicAdd(o + 9, v[9]);         // dL/dz
+        float val = k0 * v[1] + k1 * v[2];
+        val = c2 == 1 ? k1 * v[1] + k2 * v[2] : val;
+        val = c2 == 2 ? -0.5f * v[3] : val;
+        val = c2 == 3 ? -v[4] : val;
+        val = c2 == 4 ? -0.5f * v[5] : val;
+        val = c2 == 5 ? v[0] / opac : val;
+        val = c2 == 6 ? v[6] : val;
+        val = c2 == 7 ? v[7] : val;
+        val = c2 == 8 ? v[8] : val;
+        if (HAS_D) val = c2 == 9 ? v[9] : val;
+        unsafeAtomicAdd(grad2d + (size_t)d * kGrad2dStride + c2, val);
       }
     }
   }

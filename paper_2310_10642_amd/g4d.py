@@ -255,8 +255,10 @@ class Renderer:
         arr = np.empty(int(nb.value) // 4, dtype=dt)
         if arr.size:
             self._check(self.lib.g4d_debug_copy(self.ctx, code, arr.ctypes.data_as(ctypes.c_void_p), nb.value))
-        if what in ("records", "grad2d"):
+        if what == "records":
             arr = arr.reshape(-1, 12)
+        if what == "grad2d":
+            arr = arr.reshape(-1, 16)
         if what == "ranges":
             arr = arr.reshape(-1, 2)
         return arr
