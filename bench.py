@@ -40,7 +40,7 @@ def log(*a):
 
 def cpu_oracle_baseline(wl, seconds: float):
     """Times the FP64 oracle (forward + autograd backward) on one view of the
-    workload for two tile-sample sizes; a linear fit over the sample size
+    workload for growing tile samples; a linear fit over the sample size
     extrapolates to the full view (fixed cost: preprocessing all primitives)."""
     import numpy as np
     import torch
@@ -63,24 +63,30 @@ def cpu_oracle_baseline(wl, seconds: float):
         loss.backward()
         return time.perf_counter() - t0
 
-    k1, k2 = 4, 16
-    t1 = run(k1)
-    t2 = run(k2)
-    b = max((t2 - t1) / (k2 - k1), 1e-6)
-    a = max(t1 - b * k1, 0.0)
-    # third run sized so that the whole sample takes about `seconds`
-    k3 = int(min(n_tiles, max(k2 + 1, (seconds - t1 - t2 - a) / b)))
-    t3 = run(k3)
-    b = max((t3 - t1) / (k3 - k1), 1e-6)
-    a = max(t1 - b * k1, 0.0)
+    # samples of 4, 8, 16, ... tiles until the next one would overrun `seconds`;
+    # the last two fix the per-tile slope and the fixed cost
+    ks, ts = [], []
+    k = 4
+    while True:
+        ks.append(k)
+        ts.append(run(k))
+        if k >= n_tiles or (len(ks) >= 2 and sum(ts) + 2.2 * ts[-1] > seconds):
+            break
+        k = min(2 * k, n_tiles)
+    if len(ks) == 1:  # the sample was the whole view
+        b, a = ts[0] / ks[0], 0.0
+    else:
+        b = max((ts[-1] - ts[-2]) / (ks[-1] - ks[-2]), 1e-9)
+        a = max(ts[-1] - b * ks[-1], 0.0)
     full = a + b * n_tiles
     px = cam.width * cam.height
     return dict(value=px / full / 1e6, unit="Mpix/s (fwd+bwd, one view, extrapolated)",
                 cores=int(torch.get_num_threads()), kind="oracle",
                 sample=(f"1 of {len(wl.cameras)} views at {cam.width}x{cam.height}, {wl.scene.n} primitives: "
-                        f"FP64 preprocess of all primitives + fwd/bwd of {k1}, {k2} and {k3} random 16x16 tiles "
-                        f"({t1:.1f}s, {t2:.1f}s, {t3:.1f}s); full view = {a:.2f}s + {b:.4f}s x {n_tiles} tiles"),
-                seconds=round(t1 + t2 + t3, 2))
+                        f"FP64 preprocess of all primitives + fwd/bwd of random 16x16 tiles, samples of "
+                        f"{ks} tiles took {[round(x, 2) for x in ts]} s; full view = {a:.2f}s + {b:.4f}s x "
+                        f"{n_tiles} tiles"),
+                seconds=round(sum(ts), 2))
 
 
 def profiled_traffic(kernel_source: str, summary: str):

@@ -149,10 +149,25 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restr
   block_range(n, gridDim.x, t0, t1);
   const uint32_t mask = (1u << bits) - 1u;
   for (uint32_t t = t0; t < t1; ++t) {
-#pragma unroll 4
-    for (int i = 0; i < kItems; ++i) {
-      const size_t idx = (size_t)t * kTileElems + (size_t)i * kThreads + threadIdx.x;
-      if (idx < n) atomicAdd(&hist[wave][(keys[idx] >> shift) & mask], 1u);
+    const size_t tb = (size_t)t * kTileElems;
+    if (tb + kTileElems <= n) {
+      // full tile: four 16-byte loads per thread, all in flight together
+      uint4 q[kItems / 4];
+#pragma unroll
+      for (int i = 0; i < kItems / 4; ++i)
+        q[i] = reinterpret_cast<const uint4*>(keys + tb)[i * kThreads + threadIdx.x];
+#pragma unroll
+      for (int i = 0; i < kItems / 4; ++i) {
+        atomicAdd(&hist[wave][(q[i].x >> shift) & mask], 1u);
+        atomicAdd(&hist[wave][(q[i].y >> shift) & mask], 1u);
+        atomicAdd(&hist[wave][(q[i].z >> shift) & mask], 1u);
+        atomicAdd(&hist[wave][(q[i].w >> shift) & mask], 1u);
+      }
+    } else {
+      for (int i = 0; i < kItems; ++i) {
+        const size_t idx = tb + (size_t)i * kThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&hist[wave][(keys[idx] >> shift) & mask], 1u);
+      }
     }
   }
   __syncthreads();
@@ -246,7 +261,9 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
       const bool valid = base + (size_t)i * 64 + lane < n;
       const uint32_t d = (k[i] >> shift) & mask;
       uint64_t peers = __ballot(valid);
-      for (int b = 0; b < bits; ++b) {
+      // digits have at most 8 bits; bits above `bits` are zero in every lane
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
         const bool set = (d >> b) & 1u;
         const uint64_t m = __ballot(set);
         peers &= set ? m : ~m;
@@ -409,26 +426,39 @@ __global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* 
   }
 }
 
-__global__ void k_sum_u32(const uint32_t* __restrict__ in, uint64_t n, unsigned long long* out) {
+// Block sums (64-bit per thread), one atomic per block.
+__global__ void __launch_bounds__(256) k_sum_u32(const uint32_t* __restrict__ in, uint64_t n,
+                                                 unsigned long long* out) {
+  __shared__ unsigned long long s_part[4];
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long acc = 0;
   for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) acc += in[i];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long tot = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    if (tot) atomicAdd(out, tot);
+  }
 }
 
-// Longest tile list: max over tiles of end - start, one atomic per wave.
-__global__ void k_range_max(const uint2* __restrict__ ranges, uint32_t tiles, uint32_t* out) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+// Longest tile list: max over tiles of end - start, one atomic per block.
+__global__ void __launch_bounds__(256) k_range_max(const uint2* __restrict__ ranges, uint32_t tiles, uint32_t* out) {
+  __shared__ uint32_t s_part[4];
   uint32_t len = 0;
-  if (t < tiles) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
     const uint2 r = ranges[t];
-    len = r.y - r.x;
+    len = max(len, r.y - r.x);
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) len = max(len, (uint32_t)__shfl_xor((int)len, off, 64));
-  if ((threadIdx.x & 63) == 0 && len) atomicMax(out, len);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t m = max(max(s_part[0], s_part[1]), max(s_part[2], s_part[3]));
+    if (m) atomicMax(out, m);
+  }
 }
 
 inline unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -517,7 +547,8 @@ void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hip
 
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s) {
   if (tiles == 0) return;
-  hipLaunchKernelGGL(k_range_max, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles, out);
+  unsigned g = grid_for(tiles, 1024);
+  hipLaunchKernelGGL(k_range_max, dim3(g > 256 ? 256 : g), dim3(256), 0, s, ranges, tiles, out);
 }
 
 }  // namespace g4d

@@ -469,7 +469,9 @@ def test_sync_free_and_graph_replay():
     s_sf = r.stats()
     for a, b in zip(ref[:3], sf[:3]):
         assert torch.equal(a, b)
-    assert abs(float(sf[3]) - float(ref[3])) <= 1e-6 * abs(float(ref[3]))
+    # the loss sums ~1e3 block partials with float atomics in any order
+    loss_tol = 1e-5 * abs(float(ref[3]))
+    assert abs(float(sf[3]) - float(ref[3])) <= loss_tol
     _close_grads(g_sf, g_ref)
     for k in ("active_total", "instances", "fragments", "max_tile_list", "active_per_view", "rounds"):
         assert s_ref[k] == s_sf[k], k
@@ -489,7 +491,7 @@ def test_sync_free_and_graph_replay():
         torch.cuda.synchronize()
         for a, b in zip(ref[:3], outs[:3]):
             assert torch.equal(a, b), rep
-        assert abs(float(outs[3]) - float(ref[3])) <= 1e-6 * abs(float(ref[3])), rep
+        assert abs(float(outs[3]) - float(ref[3])) <= loss_tol, rep
         _close_grads(g_gr, g_ref)
         _say(f"  replay {rep} ok")
     del graph
