@@ -183,12 +183,25 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *                          is G4D_ECAPACITY, so make one uncaptured call of
  *                          the same shape first. 0 (default): off.
  *   G4D_TUNE_ARENA_INSTANCES  grow the tile-instance arena now to hold at
- *                          least this many instances (>= 0)               */
+ *                          least this many instances (>= 0)
+ *   G4D_TUNE_TILE_ORDER    1 (default): the rasterisers take tiles in order
+ *                          of decreasing list length; 0: in tile-id order.
+ *                          Results are identical; changing it invalidates
+ *                          the state kept for render_backward.
+ *   G4D_TUNE_AUTOTUNE      1: the next render that is not being captured
+ *                          first renders its batch under every combination
+ *                          of G4D_TUNE_SORT_BLOCKS in {256, 512, 1024, 2048}
+ *                          and G4D_TUNE_TILE_ORDER in {0, 1} (once, then
+ *                          twice timed with HIP events), keeps the fastest,
+ *                          then renders normally. One-shot.              */
 enum {
   G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2, G4D_TUNE_ROUND_PAIRS = 3, G4D_TUNE_ROUND_INSTANCES = 4,
-  G4D_TUNE_SYNC_FREE = 5, G4D_TUNE_ARENA_INSTANCES = 6
+  G4D_TUNE_SYNC_FREE = 5, G4D_TUNE_ARENA_INSTANCES = 6, G4D_TUNE_TILE_ORDER = 7, G4D_TUNE_AUTOTUNE = 8
 };
 g4d_status g4d_set_tuning(g4d_ctx* ctx, int32_t key, int32_t value);
+/* Current value of a tuning key (G4D_TUNE_ARENA_INSTANCES: the arena's
+ * capacity; counts above 2^31 - 1 read as 2^31 - 1). */
+g4d_status g4d_get_tuning(g4d_ctx* ctx, int32_t key, int32_t* value);
 
 /* Per-stage GPU time accumulated since stage timing was switched on
  * (synchronises the stream). ms_out and launches_out: host [G4D_NUM_STAGES]. */

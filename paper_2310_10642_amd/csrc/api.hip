@@ -52,10 +52,12 @@ struct g4d_ctx {
   int64_t round_pairs = int64_t(1) << 28;
   int64_t round_instances = int64_t(1) << 30;
   bool sync_free = false;          // no host read of device counts inside render/backward
+  bool heavy_first = true;         // rasterise tiles by decreasing list length
+  bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
-  DevBuf bwd_scratch;
+  DevBuf bwd_scratch, okey, oval, okey2, oval2;
   uint32_t* counters_h = nullptr;  // pinned
 
   // stage timing (HIP events on the context's stream)
@@ -315,6 +317,14 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI,
              cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
   launch_ranges(cnt + kCntI, cap, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+  if (c->heavy_first) {
+    // workgroups take the tiles with the longest lists first, so the launch
+    // does not end on a few heavy tiles
+    for (DevBuf* b : {&c->okey, &c->oval, &c->okey2, &c->oval2})
+      if ((st = ensure(c, *b, 4 * (size_t)tiles))) return st;
+    launch_tile_order(P<uint2>(c->ranges), (uint32_t)tiles, P<uint32_t>(c->okey), P<uint32_t>(c->oval),
+                      P<uint32_t>(c->okey2), P<uint32_t>(c->oval2), c->sort_blocks, P<uint32_t>(c->radix_scratch), s);
+  }
   stage_end(c, G4D_STAGE_BINNING);
   HIPCHK(c, hipGetLastError());
   return G4D_OK;
@@ -325,9 +335,9 @@ g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, 
   launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, P<uint32_t>(c->counters) + kCntMaxList, s);
   // 9. rasterise the round's views into their places in the outputs
   stage_begin(c);
-  launch_raster_forward(r.tiles, r.v1 - r.v0, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
-                        P<Record>(c->rec_sorted), c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t),
-                        P<uint32_t>(c->pix_last), s);
+  launch_raster_forward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, r.v1 - r.v0,
+                        P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival), P<Record>(c->rec_sorted),
+                        c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t), P<uint32_t>(c->pix_last), s);
   stage_end(c, G4D_STAGE_RASTER_FWD);
   HIPCHK(c, hipGetLastError());
   return G4D_OK;
@@ -345,6 +355,49 @@ g4d_status resolve_round(g4d_ctx* c, g4d_ctx::Round& r) {
   c->A_total = A;
   c->I_total = r.I;
   return G4D_OK;
+}
+
+// Times the render of this batch under every combination of the knobs that
+// do not change results (radix-sort workgroups, tile order) and keeps the
+// fastest. Each candidate renders once to size its scratch, then twice timed.
+g4d_status autotune(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times, float* rgb, float* dep,
+                    float* alp) {
+  const bool timing = c->timing;
+  c->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  g4d_status st = check_hip(c, hipEventCreate(&e0), "hipEventCreate");
+  if (!st) st = check_hip(c, hipEventCreate(&e1), "hipEventCreate");
+  const int blocks[] = {256, 512, 1024, 2048};
+  float best = 0.f;
+  int best_blocks = c->sort_blocks;
+  bool best_order = c->heavy_first;
+  bool first = true;
+  for (int order = 0; order < 2 && !st; ++order) {
+    for (int b : blocks) {
+      c->sort_blocks = b;
+      c->heavy_first = order == 1;
+      if ((st = g4d_render(c, n_views, cams, times, rgb, dep, alp))) break;
+      if ((st = check_hip(c, hipEventRecord(e0, c->stream), "hipEventRecord"))) break;
+      for (int k = 0; k < 2 && !st; ++k) st = g4d_render(c, n_views, cams, times, rgb, dep, alp);
+      if (st) break;
+      if ((st = check_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord"))) break;
+      if ((st = check_hip(c, hipEventSynchronize(e1), "hipEventSynchronize"))) break;
+      float ms = 0.f;
+      if ((st = check_hip(c, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime"))) break;
+      if (first || ms < best) {
+        best = ms;
+        best_blocks = b;
+        best_order = order == 1;
+        first = false;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->timing = timing;
+  c->sort_blocks = best_blocks;
+  c->heavy_first = best_order;
+  return st;
 }
 
 }  // namespace
@@ -391,7 +444,7 @@ g4d_status g4d_destroy(g4d_ctx* c) {
   DevBuf* bufs[] = {&c->views_d, &c->act, &c->pos, &c->dkey, &c->rec, &c->slot, &c->ckey, &c->cval, &c->ckey2,
                     &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
                     &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
-                    &c->counters, &c->bwd_scratch};
+                    &c->counters, &c->bwd_scratch, &c->okey, &c->oval, &c->okey2, &c->oval2};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->counters_h) (void)hipHostFree(c->counters_h);
@@ -442,6 +495,11 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
   if (c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
   if (n_views < 1 || n_views > kMaxViews) return fail(c, G4D_EINVAL, "n_views must be in [1, 4096]");
   if (!cams || !times || !out_rgb) return fail(c, G4D_EINVAL, "null cams/times/out_rgb");
+  if (c->autotune_pending && !capturing(c)) {
+    c->autotune_pending = false;
+    g4d_status st = autotune(c, n_views, cams, times, out_rgb, out_depth, out_alpha);
+    if (st) return st;
+  }
 
   // ---- views (host) ----
   std::vector<ViewDev> vh(n_views);
@@ -587,7 +645,8 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(a_max)))) return st;
     stage_begin(c);
     launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, kGrad2dStride, a_max, s);
-    launch_raster_backward(r.tiles, nv, P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival),
+    launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
+                           P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
                            P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
@@ -686,6 +745,17 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     c->timing = value == 1;
     return G4D_OK;
   }
+  if (key == G4D_TUNE_AUTOTUNE) {
+    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "autotune is 0 or 1");
+    c->autotune_pending = value == 1;
+    return G4D_OK;
+  }
+  if (key == G4D_TUNE_TILE_ORDER) {
+    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "tile order is 0 or 1");
+    c->heavy_first = value == 1;
+    c->have_render = false;  // the order of the last render's tiles may be missing
+    return G4D_OK;
+  }
   if (key == G4D_TUNE_SYNC_FREE) {
     if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "sync-free is 0 or 1");
     c->sync_free = value == 1;
@@ -704,6 +774,23 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     return G4D_OK;
   }
   return fail(c, G4D_EINVAL, "unknown tuning key");
+}
+
+g4d_status g4d_get_tuning(g4d_ctx* c, int32_t key, int32_t* value) {
+  if (!c || !value) return G4D_EINVAL;
+  const auto clamp32 = [](int64_t v) { return (int32_t)std::min<int64_t>(v, 0x7FFFFFFF); };
+  switch (key) {
+    case G4D_TUNE_SORT_BLOCKS: *value = c->sort_blocks; break;
+    case G4D_TUNE_STAGE_TIMING: *value = c->timing ? 1 : 0; break;
+    case G4D_TUNE_ROUND_PAIRS: *value = clamp32(c->round_pairs); break;
+    case G4D_TUNE_ROUND_INSTANCES: *value = clamp32(c->round_instances); break;
+    case G4D_TUNE_SYNC_FREE: *value = c->sync_free ? 1 : 0; break;
+    case G4D_TUNE_ARENA_INSTANCES: *value = clamp32((int64_t)arena_instances(c)); break;
+    case G4D_TUNE_TILE_ORDER: *value = c->heavy_first ? 1 : 0; break;
+    case G4D_TUNE_AUTOTUNE: *value = c->autotune_pending ? 1 : 0; break;
+    default: return fail(c, G4D_EINVAL, "unknown tuning key");
+  }
+  return G4D_OK;
 }
 
 const char* g4d_last_error(const g4d_ctx* c) { return c ? c->err.c_str() : "null context"; }

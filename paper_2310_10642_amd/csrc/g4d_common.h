@@ -100,15 +100,21 @@ void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, co
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s);
 
 // ---- launchers (raster.hip) ----
-void launch_raster_forward(int total_tiles, int n_views, const ViewDev* views, const uint2* ranges,
-                           const uint32_t* ival, const Record* rec_sorted, const float* bg, float* out_rgb,
+// order (nullable): the tile each workgroup takes, e.g. heaviest lists first.
+void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
+                           const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
+                           float* out_rgb,
                            float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s);
-void launch_raster_backward(int total_tiles, int n_views, const ViewDev* views, const uint2* ranges,
+void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
+                            const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
                             const uint32_t* pix_last, float* grad2d, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
+// Tile ids by decreasing list length (stable within ~4.4 % length bins) into vals.
+void launch_tile_order(const uint2* ranges, uint32_t tiles, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                       uint32_t* vals_alt, int sort_blocks, uint32_t* scratch, hipStream_t s);
 
 // ---- launchers (util.hip) ----
 // Views reach the device through kernel arguments, never a host copy.

@@ -98,7 +98,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
-__global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewDev* __restrict__ views,
+__global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restrict__ order, int n_views,
+                                                         const ViewDev* __restrict__ views,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ ival,
                                                          const Record* __restrict__ recs, float bg0, float bg1,
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewD
   __shared__ float4 s_a[kFwdBatch], s_b[kFwdBatch], s_c[kFwdBatch];
   __shared__ __align__(16) uint8_t s_mask[kFwdBatch];
   __shared__ uint8_t s_list[4][kFwdBatch];
-  const int tile = blockIdx.x;
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   const int vi = find_view(views, n_views, tile);
   const ViewDev& vw = views[vi];
   const int lt = tile - vw.tile_base;
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(256) k_raster_forward(int n_views, const ViewD
 // their terms are compiled out).
 template <bool HAS_D, bool HAS_A>
 __global__ void __launch_bounds__(256) k_raster_backward(
-    int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
+    const uint32_t* __restrict__ order, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
     const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d) {
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   __shared__ float4 s_pix[256];
   __shared__ uint32_t s_max;
 
-  const int tile = blockIdx.x;
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   const int vi = find_view(views, n_views, tile);
   const ViewDev& vw = views[vi];
   const int lt = tile - vw.tile_base;
@@ -401,21 +402,25 @@ __global__ void __launch_bounds__(256) k_raster_backward(
 
 }  // namespace
 
-void launch_raster_forward(int total_tiles, int n_views, const ViewDev* views, const uint2* ranges,
-                           const uint32_t* ival, const Record* rec_sorted, const float* bg, float* out_rgb,
-                           float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s) {
+void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
+                           const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
+                           float* out_rgb, float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last,
+                           hipStream_t s) {
   if (total_tiles == 0) return;
-  hipLaunchKernelGGL(k_raster_forward, dim3(total_tiles), dim3(256), 0, s, n_views, views, ranges, ival, rec_sorted,
+  hipLaunchKernelGGL(k_raster_forward, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges, ival,
+                     rec_sorted,
                      bg[0], bg[1], bg[2], out_rgb, out_depth, out_alpha, pix_t, pix_last);
 }
 
-void launch_raster_backward(int total_tiles, int n_views, const ViewDev* views, const uint2* ranges,
+void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
+                            const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
                             const uint32_t* pix_last, float* grad2d, hipStream_t s) {
   if (total_tiles == 0) return;
 #define G4D_BWD(HD, HA)                                                                                          \
-  hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(total_tiles), dim3(256), 0, s, n_views, views, ranges,    \
+  hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(total_tiles), dim3(256), 0, s, order, n_views, views,     \
+                     ranges,                                                                                      \
                      ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d)
   if (dl_depth && dl_alpha) G4D_BWD(true, true);
   else if (dl_depth) G4D_BWD(true, false);

@@ -461,6 +461,20 @@ __global__ void __launch_bounds__(256) k_range_max(const uint2* __restrict__ ran
   }
 }
 
+// Heavy-first tile order: key 255 - floor(16 log2(len + 1)), so that a
+// stable sort of the keys lists tiles by decreasing list length in bins of
+// ~4.4 %, keeping the natural order within a bin.
+__global__ void k_order_keys(const uint2* __restrict__ ranges, uint32_t tiles, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const uint2 r = ranges[t];
+  const uint32_t len = r.y - r.x;
+  const uint32_t b = (uint32_t)(16.f * __log2f((float)len + 1.f));
+  keys[t] = 255u - min(b, 255u);
+  vals[t] = t;
+}
+
 inline unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -543,6 +557,13 @@ void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hip
   unsigned g = grid_for(n, 256);
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_sum_u32, dim3(g), dim3(256), 0, s, in, n, out);
+}
+
+void launch_tile_order(const uint2* ranges, uint32_t tiles, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                       uint32_t* vals_alt, int sort_blocks, uint32_t* scratch, hipStream_t s) {
+  if (tiles == 0) return;
+  hipLaunchKernelGGL(k_order_keys, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles, keys, vals);
+  radix_sort(keys, vals, keys_alt, vals_alt, nullptr, tiles, 0, 8, radix_grid(tiles, sort_blocks), scratch, s);
 }
 
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s) {

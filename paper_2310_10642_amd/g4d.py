@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libg4d.so")
 G4D_OK, G4D_EINVAL, G4D_ENOMEM, G4D_EHIP, G4D_ESTATE, G4D_ECAPACITY = 0, -1, -2, -3, -4, -5
 G4D_TUNE_SORT_BLOCKS, G4D_TUNE_STAGE_TIMING = 1, 2
 G4D_TUNE_ROUND_PAIRS, G4D_TUNE_ROUND_INSTANCES = 3, 4
-G4D_TUNE_SYNC_FREE, G4D_TUNE_ARENA_INSTANCES = 5, 6
+G4D_TUNE_SYNC_FREE, G4D_TUNE_ARENA_INSTANCES, G4D_TUNE_TILE_ORDER, G4D_TUNE_AUTOTUNE = 5, 6, 7, 8
 G4D_GRAD_ACCUMULATE = 1
 G4D_LOSS_L1, G4D_LOSS_L2 = 1, 2
 STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss"]
@@ -27,7 +27,7 @@ DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_la
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
             "g4d_render", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
-            "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
+            "g4d_get_tuning", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
 
 
 class G4DOptions(ctypes.Structure):
@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH):
     lib.g4d_image_loss.argtypes = [vp, i32, i64, fp, fp, ctypes.c_float, fp, fp]
     lib.g4d_get_stats.argtypes = [vp, ctypes.POINTER(G4DStats), ctypes.POINTER(ctypes.c_int64)]
     lib.g4d_set_tuning.argtypes = [vp, i32, i32]
+    lib.g4d_get_tuning.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.g4d_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.g4d_last_error.argtypes = [vp]
     lib.g4d_last_error.restype = ctypes.c_char_p
@@ -148,6 +149,11 @@ class Renderer:
 
     def set_tuning(self, key: int, value: int):
         self._check(self.lib.g4d_set_tuning(self.ctx, key, value))
+
+    def get_tuning(self, key: int) -> int:
+        v = ctypes.c_int32()
+        self._check(self.lib.g4d_get_tuning(self.ctx, key, ctypes.byref(v)))
+        return int(v.value)
 
     def set_primitives(self, means4, log_scales4, q_left, q_right, opacity_logit, coeffs):
         ts = [means4, log_scales4, q_left, q_right, opacity_logit, coeffs]

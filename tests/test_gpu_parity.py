@@ -498,6 +498,37 @@ def test_sync_free_and_graph_replay():
     r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
 
 
+def test_tile_order_and_autotune():
+    """Heavy-first tile order and the autotuner's knobs change no result:
+    images bit for bit, gradients up to the order of the atomic sums."""
+    _say("[tile order and autotune, 300k x 2 views]")
+    from paper_2310_10642_amd import g4d
+    wl = scenegen.bench_workload(2)
+    r, _ = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    r.set_tuning(g4d.G4D_TUNE_TILE_ORDER, 0)
+    ref = r.render(wl.cameras, times)
+    dl = torch.from_numpy(np.random.default_rng(56).uniform(-1, 1, ref[0].numel()).astype(np.float32)).cuda()
+    g_ref = [x.clone() for x in r.backward(dl)]
+    r.set_tuning(g4d.G4D_TUNE_TILE_ORDER, 1)
+    with pytest.raises(g4d.G4DError):             # the order change invalidated the kept state
+        r.backward(dl)
+    out = r.render(wl.cameras, times)
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
+    _close_grads(r.backward(dl), g_ref)
+    r.set_tuning(g4d.G4D_TUNE_AUTOTUNE, 1)
+    assert r.get_tuning(g4d.G4D_TUNE_AUTOTUNE) == 1
+    out = r.render(wl.cameras, times)
+    assert r.get_tuning(g4d.G4D_TUNE_AUTOTUNE) == 0
+    blocks, order = r.get_tuning(g4d.G4D_TUNE_SORT_BLOCKS), r.get_tuning(g4d.G4D_TUNE_TILE_ORDER)
+    _say(f"  autotune chose sort blocks {blocks}, tile order {order}")
+    assert blocks in (256, 512, 1024, 2048) and order in (0, 1)
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
+    _close_grads(r.backward(dl), g_ref)
+
+
 def test_sync_free_arena_overflow():
     """A sync-free render that needs more tile instances than the arena holds
     renders background only, its backward gives zero gradients, and get_stats
