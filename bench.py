@@ -25,10 +25,12 @@ sys.path.insert(0, HERE)
 # pixel's last contributor), counted in FP32 lane operations (an FMA is one):
 #   forward:  offset 2, quadratic form 5, floor test 1, exp 1, clamp 1,
 #             transmittance 1, weight 1, colour+depth accumulation 4      = 16
-#   backward: recompute 10, T recovery 1, weight 1, dL/dalpha 11,
-#             behind-accumulators 5, dL/dpower 2, per-primitive sums 9    = 39
+#   backward: offset 2, quadratic form 5, floor test 1, exp 1, clamp 1,
+#             transmittance recovery 3 (1 - a, reciprocal, product),
+#             colour dot 3, behind term 2, dL/da 1, dL/dpower 1, weight 1,
+#             per-primitive tile sums 6 (g, g m, g m^2, w dL/dC x 3)      = 27
 OPS_FWD = 16
-OPS_BWD = 39
+OPS_BWD = 27
 # FP32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
@@ -89,6 +91,64 @@ def cpu_oracle_baseline(wl, seconds: float):
                 seconds=round(sum(ts), 2))
 
 
+def other_workloads(log_fn, steps: int):
+    """The other seeded workloads in their own right (not the headline):
+    batched forward of 1M primitives over 16 mixed views, batched fwd+bwd of
+    500k over 8 views with an L2 loss, and one call rendering 3M primitives
+    over 60 frames x 4 cameras at 1920x1080 (several rounds)."""
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2310_10642_amd import g4d
+
+    dev = torch.device("cuda", 0)
+    res = {}
+    for cfg in (2, 3, 4):
+        t0 = time.perf_counter()
+        wl = scenegen.make_workload(cfg)
+        sc = wl.scene
+        r = g4d.Renderer(sc.sh_degree, sc.t_order, sc.t_period)
+        params = [torch.from_numpy(a).to(dev) for a in (sc.means4, sc.log_scales4, sc.q_left, sc.q_right,
+                                                           sc.opacity_logit, sc.coeffs)]
+        r.set_primitives(*params)
+        cams, times = wl.cameras, [float(x) for x in wl.times]
+        P = sum(c.width * c.height for c in cams)
+        rgb = torch.empty(3 * P, device=dev)
+        if wl.loss is None:
+            def step():
+                r.render(cams, times, depth=False, alpha=False, out=(rgb, None, None))
+            kind = "forward"
+        else:
+            target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).to(dev)
+            loss = torch.zeros(1, device=dev)
+            dl = torch.empty_like(rgb)
+            grads = r.grad_buffers(dev)
+            scale = 1.0 / (3 * cams[0].width * cams[0].height)
+
+            def step():
+                r.render(cams, times, depth=False, alpha=False, out=(rgb, None, None))
+                r.image_loss(g4d.G4D_LOSS_L2 if wl.loss == "l2" else g4d.G4D_LOSS_L1, rgb, target, scale, loss, dl)
+                r.backward(dl, out=grads)
+            kind = "fwd+bwd"
+        n = steps if cfg != 4 else max(2, steps // 5)
+        step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(n):
+            step()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t1) / n
+        st = r.stats()
+        res[wl.name] = dict(kind=kind, ms_per_call=sec * 1e3, mpix_per_s=P / sec / 1e6, views=len(cams),
+                            primitives=sc.n, rounds=st["rounds"], instances=st["instances"],
+                            active_mean=float(np.mean(st["active_per_view"])), calls_timed=n)
+        log_fn(f"[bench] {wl.name}: {kind} {sec * 1e3:.2f} ms per call, {P / sec / 1e6:.0f} Mpix/s, "
+               f"{st['rounds']} round(s) ({time.perf_counter() - t0:.1f} s with setup)")
+        del r, params, rgb
+        torch.cuda.empty_cache()
+    return res
+
+
 def profiled_traffic(kernel_source: str, summary: str):
     """HBM bytes per launch from the counter summary under profiles/, or
     None when the kernel source changed since the counters were taken."""
@@ -116,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the 1M x 16-view, 500k x 8-view and 3M x 240-view figures")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -269,6 +331,10 @@ def main():
         achieved = byts / (per_launch[dom] * 1e-3)
         roof = dict(kernel=dom, bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=achieved / HBM_PEAK, traffic=None, ms_per_launch=per_launch[dom])
+    others = None
+    if not args.no_other_workloads:
+        log("[bench] other workloads")
+        others = other_workloads(log, max(3, args.steps // 2))
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -296,6 +362,7 @@ def main():
         "active_per_view": stats["active_per_view"], "instances": stats["instances"],
         "fragments": frag, "max_tile_list": stats["max_tile_list"],
         "roofline": roof,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -121,9 +121,10 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
  * Keeps per-pixel final transmittance and last-contributor count for backward.
  * Views are processed in rounds of consecutive views: a round holds at most
  * G4D_TUNE_ROUND_PAIRS (view, primitive) pairs (but at least one view) and at
- * most G4D_TUNE_ROUND_INSTANCES tile instances; a round over the instance cap
- * is shrunk and binned again. Each view's result does not depend on the
- * grouping. Synchronises the stream once per binning attempt, to size the
+ * most G4D_TUNE_ROUND_INSTANCES tile instances; the first round takes at most
+ * 16 views, later ones are sized from the instances per view seen so far, and
+ * a round over the instance cap is shrunk and binned again. Each view's
+ * result does not depend on the grouping. Synchronises the stream once per binning attempt, to size the
  * tile-instance arena (see G4D_TUNE_SYNC_FREE for the mode that does not).
  * G4D_ECAPACITY if one view alone exceeds the cap. Views reach the device as
  * kernel arguments: cams and times may be reused as soon as this returns. */

@@ -573,12 +573,14 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
     return G4D_OK;
   }
 
-  // Rounds of consecutive views under the pair and instance caps. The next
-  // round's size is predicted from the last one's instances per view; a round
-  // over the instance cap is shrunk in proportion and binned again.
+  // Rounds of consecutive views under the pair and instance caps. The first
+  // round takes at most 16 views; each next round's size is predicted from
+  // the last one's instances per view; a round over the instance cap is
+  // shrunk in proportion and binned again.
   const uint64_t inst_cap = (uint64_t)c->round_instances;
   const int by_pairs = (int)std::min<int64_t>(n_views, std::max<int64_t>(1, c->round_pairs / std::max<int64_t>(c->n, 1)));
-  int k_next = by_pairs;
+  // the first round is kept modest: an over-full attempt costs a preprocess
+  int k_next = std::min(by_pairs, 16);
   for (int v0 = 0; v0 < n_views;) {
     int k = std::min(k_next, n_views - v0);
     uint32_t A = 0;
