@@ -366,7 +366,7 @@ def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
         zeros = torch.zeros(P, dtype=F64)
         out = dict(rgb=rgb.reshape(3, h, w), depth=zeros.reshape(h, w), alpha=zeros.reshape(h, w),
                    T=torch.ones(P, dtype=F64).reshape(h, w), last=torch.zeros(P, dtype=torch.long).reshape(h, w),
-                   n_list=0, ids=ids)
+                   n_list=0, ids=ids, blended=torch.zeros(0, dtype=torch.bool))
     else:
         u, v = pre["u"][ids], pre["v"][ids]
         conic = pre["conic"][ids]
@@ -394,7 +394,8 @@ def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
             pos = torch.arange(1, G + 1).expand(P, G)
             last = torch.where(contrib, pos, torch.zeros_like(pos)).max(1).values
         out = dict(rgb=rgb.T.reshape(3, h, w), depth=depth.reshape(h, w), alpha=(1.0 - t_fin).reshape(h, w),
-                   T=t_fin.reshape(h, w), last=last.reshape(h, w), n_list=G, ids=ids)
+                   T=t_fin.reshape(h, w), last=last.reshape(h, w), n_list=G, ids=ids,
+                   blended=contrib.any(0))
     if with_flags:
         out.update(_tile_flags(pre, cam, tx, ty, pxc, pyc, ids, mg, h, w))
     return out
@@ -554,6 +555,43 @@ def tile_linear_loss(out, dl_rgb=None, dl_depth=None, dl_alpha=None, cam=None) -
         if dl_alpha is not None:
             total = total + (part["alpha"] * dl_alpha[sl[0], sl[1]]).sum()
     return total
+
+
+def densify_stats(scene, cams, times, dl_rgb, dl_depth=None, dl_alpha=None, bg=(0.0, 0.0, 0.0)):
+    """Densification statistics of Sec. 3.3 ("Densification in spacetime"):
+    the view-space position gradient magnitude and the mu_t gradient
+    magnitude, accumulated per primitive over the views in which it blended
+    at least one pixel, with the number of such views.
+
+    For view v with loss L_v = <dL/dI_v, I_v> (the vector-Jacobian product the
+    backward computes): uv[i] += |(dL_v/du_i, dL_v/dv_i)| (pixel units),
+    t[i] += |dL_v/dmu_t,i|, count[i] += 1, for every primitive i that has a
+    blended fragment (alpha >= 1/255 before the stop) in view v.
+    Returns float64 uv [N], t [N] and int64 count [N]."""
+    n = scene.means4.shape[0]
+    uv = torch.zeros(n, dtype=F64)
+    tg = torch.zeros(n, dtype=F64)
+    cnt = torch.zeros(n, dtype=torch.long)
+    for v, (cam, t) in enumerate(zip(cams, times)):
+        params = params_from_scene(scene, requires_grad=True)
+        out = render_view(params, cam, float(t), scene.sh_degree, scene.t_order, scene.t_period, bg,
+                          with_flags=False)
+        pre = out["pre"]
+        blended = torch.zeros(n, dtype=torch.bool)
+        for part in out["parts"].values():
+            if part["n_list"]:
+                blended[part["ids"][part["blended"]]] = True
+        loss = tile_linear_loss(out, torch.as_tensor(dl_rgb[v]),
+                                None if dl_depth is None else torch.as_tensor(dl_depth[v]),
+                                None if dl_alpha is None else torch.as_tensor(dl_alpha[v]), cam)
+        gu, gv, gm = torch.autograd.grad(loss, [pre["u"], pre["v"], params["means4"]], allow_unused=True)
+        gu = torch.zeros(n, dtype=F64) if gu is None else gu
+        gv = torch.zeros(n, dtype=F64) if gv is None else gv
+        gm = torch.zeros(n, 4, dtype=F64) if gm is None else gm
+        uv = uv + torch.where(blended, torch.sqrt(gu * gu + gv * gv), torch.zeros_like(uv))
+        tg = tg + torch.where(blended, gm[:, 3].abs(), torch.zeros_like(tg))
+        cnt = cnt + blended.long()
+    return uv.detach(), tg.detach(), cnt
 
 
 def render_full(scene, cam, t, bg=(0.0, 0.0, 0.0), requires_grad=False, with_flags=True,

@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: closed
 forms, invariants stated in the paper, a library routine, an independent
 sequential loop, or finite differences.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -422,3 +423,103 @@ def test_config0_renders_with_no_uncertain_pixels():
     out = O.render_full(wl.scene, wl.cameras[0], float(wl.times[0]))
     assert int(out["pre"]["active"].sum()) > 0
     assert not bool(O.assemble(out, wl.cameras[0], "uncertain").any())
+
+
+# --- Sec. 3.3 "Densification in spacetime": statistics --------------------------------
+def _blend_sets_by_sequential_loop(sc, cam, t):
+    """Primitives blended at some pixel of the view, from the independent
+    per-pixel loop (which pixel decides nothing beyond alpha >= 1/255 before
+    the stop)."""
+    out = O.render_full(sc, cam, t, with_flags=False)
+    pre = out["pre"]
+    n = sc.means4.shape[0]
+    blended = set()
+    for py in range(cam.height):
+        for px in range(cam.width):
+            tx, ty = px // 16, py // 16
+            T = 1.0
+            cand = []
+            for i in range(n):
+                r = pre["rect"][i]
+                if bool(pre["active"][i]) and r[0] <= tx < r[2] and r[1] <= ty < r[3]:
+                    cand.append((float(pre["z"][i]), i))
+            for _, i in sorted(cand):
+                dx, dy = px + 0.5 - float(pre["u"][i]), py + 0.5 - float(pre["v"][i])
+                a_, b_, c_ = [float(c) for c in pre["conic"][i]]
+                G = float(pre["opac"][i]) * math.exp(-0.5 * (a_ * dx * dx + c_ * dy * dy) - b_ * dx * dy)
+                if G < 1.0 / 255.0:
+                    continue
+                alpha = min(0.99, G)
+                if T * (1.0 - alpha) < 1e-4:
+                    break
+                blended.add(i)
+                T *= 1.0 - alpha
+    return blended
+
+
+def test_densify_count_matches_sequential_loop():
+    sc = scenegen.random_scene(23, 30, spread=0.4, mu_log_t=-1.0)
+    sc.log_scales4[:, :3] += 1.2
+    sc.opacity_logit[:] += 2.0
+    sc.means4[:3, 3] = 0.95                    # three short-lived primitives, culled at both times
+    sc.log_scales4[:3, 3] = math.log(0.02)
+    cams = [scenegen.look_at_camera((0.0, 0.0, 3.5), 32, 32), scenegen.look_at_camera((1.5, 0.3, 3.0), 32, 32)]
+    times = [0.35, 0.6]
+    rng = np.random.default_rng(24)
+    dl = [rng.normal(size=(3, 32, 32)) for _ in cams]
+    _, _, cnt = O.densify_stats(sc, cams, times, dl)
+    ref = np.zeros(sc.means4.shape[0], np.int64)
+    for cam, t in zip(cams, times):
+        for i in _blend_sets_by_sequential_loop(sc, cam, t):
+            ref[i] += 1
+    assert np.array_equal(cnt.numpy(), ref)
+    assert ref.max() == 2 and (ref == 0).any()   # seen in both views by some, in none by others
+
+
+def test_densify_uv_gradient_is_principal_point_derivative():
+    """With one primitive, moving the principal point by h moves its projected
+    mean by h and nothing else, so dL/du = dL/dc_x and dL/dv = dL/dc_y."""
+    sc = scenegen.random_scene(25, 1, sh_degree=1, t_order=1)
+    sc.means4[:] = [[0.1, -0.05, 0.0, 0.5]]
+    sc.log_scales4[:] = [[math.log(0.25), math.log(0.15), math.log(0.2), math.log(0.3)]]
+    sc.opacity_logit[:] = [1.5]
+    cam = scenegen.look_at_camera((0.0, 0.0, 3.0), 32, 32)
+    t = 0.5
+    dl = np.random.default_rng(26).normal(size=(3, 32, 32))
+    uv, _, cnt = O.densify_stats(sc, [cam], [t], [dl])
+    assert int(cnt[0]) == 1
+
+    def loss(c):
+        out = O.render_full(sc, c, t, with_flags=False)
+        return float(O.tile_linear_loss(out, torch.as_tensor(dl), cam=c))
+    h = 1e-6
+    du = (loss(dataclasses.replace(cam, cx=cam.cx + h)) - loss(dataclasses.replace(cam, cx=cam.cx - h))) / (2 * h)
+    dv = (loss(dataclasses.replace(cam, cy=cam.cy + h)) - loss(dataclasses.replace(cam, cy=cam.cy - h))) / (2 * h)
+    assert abs(float(uv[0]) - math.hypot(du, dv)) <= 1e-6 * (1 + math.hypot(du, dv))
+
+
+def test_densify_t_gradient_sums_per_view_magnitudes():
+    """|dL_v/dmu_t| is taken per view before summing: with two views whose
+    time derivatives differ in sign the statistic is the sum of magnitudes."""
+    sc = scenegen.random_scene(27, 1, sh_degree=1, t_order=2)
+    sc.means4[:] = [[0.0, 0.05, 0.0, 0.5]]
+    sc.log_scales4[:] = [[math.log(0.3), math.log(0.2), math.log(0.25), math.log(0.2)]]
+    sc.opacity_logit[:] = [1.0]
+    cam = scenegen.look_at_camera((0.0, 0.0, 3.0), 32, 32)
+    times = [0.4, 0.62]
+    ones = np.ones((3, 32, 32))
+    _, tg, cnt = O.densify_stats(sc, [cam, cam], times, [ones, ones])
+    assert int(cnt[0]) == 2
+    h = 1e-6
+    fd = []
+    for t in times:
+        vals = []
+        for sgn in (1.0, -1.0):
+            params = O.params_from_scene(sc)          # float64: the step is not rounded away
+            params["means4"][0, 3] += sgn * h
+            out = O.render_view(params, cam, t, sc.sh_degree, sc.t_order, sc.t_period, with_flags=False)
+            vals.append(float(O.tile_linear_loss(out, torch.as_tensor(ones), cam=cam)))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    assert fd[0] * fd[1] < 0                    # the two views pull mu_t in opposite directions
+    ref = abs(fd[0]) + abs(fd[1])
+    assert abs(float(tg[0]) - ref) <= 1e-5 * (1 + ref)
