@@ -145,6 +145,20 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const float* dL_drgb, const float* 
                                float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
                                int32_t flags);
 
+/* Densification statistics (Sec. 3.3, "Densification in spacetime"): every
+ * later render_backward adds, for each primitive and each view of the render
+ * in which it blended at least one pixel (a fragment with alpha >= 1/255
+ * before the stop):
+ *   uv_grad_norm_sum[i] += |(dL/du_i, dL/dv_i)|   (that view's share, pixels)
+ *   t_grad_abs_sum[i]   += |dL/dmu_t,i|           (that view's share)
+ *   blend_count[i]      += 1
+ * so that sum / count are the average gradient magnitudes the paper uses as
+ * density-control indicators. Device arrays [n] of the current primitives,
+ * borrowed, never cleared by the library (zero them to start an interval).
+ * All three NULL switches the statistics off; set_primitives also does. */
+g4d_status g4d_set_densify_stats(g4d_ctx* ctx, float* uv_grad_norm_sum, float* t_grad_abs_sum,
+                                 int32_t* blend_count);
+
 /* Image loss and its gradient dL/dI (Sec. 3.3: optimisation is supervised by
  * a rendering loss only), on the context's stream: over n values,
  *   G4D_LOSS_L1: loss += scale * sum |img - target|,  grad = scale * sign(img - target)

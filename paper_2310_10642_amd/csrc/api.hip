@@ -32,6 +32,7 @@ struct g4d_ctx {
   int64_t n = -1;
   const float *means4 = nullptr, *log_scales4 = nullptr, *q_left = nullptr, *q_right = nullptr;
   const float *opacity_logit = nullptr, *coeffs = nullptr;
+  DensifyStats densify{nullptr, nullptr, nullptr};  // borrowed accumulators
 
   // last render
   struct Round {
@@ -484,6 +485,7 @@ g4d_status g4d_set_primitives(g4d_ctx* c, int64_t n, const float* means4, const 
   c->q_right = q_right;
   c->opacity_logit = opacity_logit;
   c->coeffs = coeffs;
+  c->densify = DensifyStats{nullptr, nullptr, nullptr};
   c->have_render = false;
   return G4D_OK;
 }
@@ -650,17 +652,29 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
-                           P<uint32_t>(c->pix_last), P<float>(c->grad2d), s);
+                           P<uint32_t>(c->pix_last), P<float>(c->grad2d), c->densify.blend_count != nullptr, s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
     RenderParams p = make_params(c, nv);
     stage_begin(c);
     launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), cnt + kCntA, a_max, P<uint32_t>(c->cval),
                                P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4, g_log_scales4, g_q_left,
-                               g_q_right, g_opacity_logit, g_coeffs, accumulate, s);
+                               g_q_right, g_opacity_logit, g_coeffs, accumulate, c->densify, s);
     stage_end(c, G4D_STAGE_PREPROCESS_BWD);
     HIPCHK(c, hipGetLastError());
     accumulate = true;
   }
+  return G4D_OK;
+}
+
+g4d_status g4d_set_densify_stats(g4d_ctx* c, float* uv_grad_norm_sum, float* t_grad_abs_sum,
+                                 int32_t* blend_count) {
+  if (!c) return G4D_EINVAL;
+  const int nn = (uv_grad_norm_sum != nullptr) + (t_grad_abs_sum != nullptr) + (blend_count != nullptr);
+  if (nn != 0 && nn != 3) return fail(c, G4D_EINVAL, "give all three accumulators or none");
+  if (nn == 3 && c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
+  if (nn == 3 && (!aligned4(uv_grad_norm_sum) || !aligned4(t_grad_abs_sum) || !aligned4(blend_count)))
+    return fail(c, G4D_EINVAL, "misaligned accumulator");
+  c->densify = DensifyStats{uv_grad_norm_sum, t_grad_abs_sum, blend_count};
   return G4D_OK;
 }
 

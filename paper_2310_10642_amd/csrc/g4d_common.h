@@ -60,6 +60,13 @@ struct RenderParams {
   const ViewDev* views;
 };
 
+// Per-primitive densification accumulators (all null: off).
+struct DensifyStats {
+  float* uv_grad_norm_sum;
+  float* t_grad_abs_sum;
+  int32_t* blend_count;
+};
+
 // ---- launchers (preprocess.hip) ----
 void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
                        hipStream_t s);
@@ -69,7 +76,7 @@ void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, cons
                                 const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
                                 const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,
                                 float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
-                                bool accumulate, hipStream_t s);
+                                bool accumulate, const DensifyStats& stats, hipStream_t s);
 
 // ---- launchers (loss.hip) ----
 void launch_image_loss(int kind, uint64_t n, const float* img, const float* tgt, float scale, float* loss,
@@ -109,7 +116,7 @@ void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views,
                             const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, float* grad2d, hipStream_t s);
+                            const uint32_t* pix_last, float* grad2d, bool mark_blended, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
 // Tile ids by decreasing list length (stable within ~4.4 % length bins) into vals.

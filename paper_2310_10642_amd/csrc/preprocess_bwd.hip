@@ -24,7 +24,7 @@ namespace {
 using namespace shade;
 
 // pair scratch layout (floats per active record)
-constexpr int kGeoFloats = 16;  // G4 upper triangle (10), dL/dmu (4), dL/dlogit, pad
+constexpr int kGeoFloats = 16;  // G4 upper triangle (10), dL/dmu (4), dL/dlogit, |dL/d(u,v)| (-1: not blended)
 constexpr int kColFloats = 8;   // dL/draw (3), t - mu_t, view direction (3), 1/|mu_c - c|
 constexpr int kCgFloats = 4;    // dL/dmu_c and dL/d(t - mu_t) through the colour
 
@@ -62,6 +62,9 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
   const float4 q2 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride + 8);
   const float gu = q0.x, gv = q0.y, gC0 = q0.z, gC1 = q0.w, gC2 = q1.x, go = q1.y;
   const float gdepth = q2.y;
+  // last float of the line: 1 when the record blended some pixel (set by the
+  // rasteriser's backward when statistics are on)
+  const bool blended = grad2d[(size_t)d * kGrad2dStride + 15] > 0.5f;
   // colour = max(0, raw + 0.5): the clamp passes the gradient where the blended colour is positive
   const float4 rc = recs[d].c;
   const float graw0 = rc.x > 0.f ? q1.z : 0.f;
@@ -148,7 +151,7 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
   o[0] = make_float4(gSc[0][0], 0.5f * (gSc[0][1] + gSc[1][0]), 0.5f * (gSc[0][2] + gSc[2][0]), 0.5f * gv3[0]);
   o[1] = make_float4(gSc[1][1], 0.5f * (gSc[1][2] + gSc[2][1]), 0.5f * gv3[1], gSc[2][2]);
   o[2] = make_float4(0.5f * gv3[2], gs44, gmuc[0], gmuc[1]);
-  o[3] = make_float4(gmuc[2], -gdt, glogit, 0.f);
+  o[3] = make_float4(gmuc[2], -gdt, glogit, blended ? sqrtf(gu * gu + gv * gv) : -1.f);
 }
 
 // 16 lanes per primitive (lane = SH basis index lm); lanes with lm >= (L+1)^2 idle.
@@ -242,7 +245,8 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
                                                    const float4* __restrict__ geo, const float4* __restrict__ cgbuf,
                                                    float4* __restrict__ g_means4, float4* __restrict__ g_log_scales4,
                                                    float4* __restrict__ g_q_left, float4* __restrict__ g_q_right,
-                                                   float* __restrict__ g_logit, bool accumulate) {
+                                                   float* __restrict__ g_logit, bool accumulate,
+                                                   DensifyStats st) {
   const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (gidx >= p.n) return;
   bool any = false;
@@ -274,6 +278,8 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
     for (int j = 0; j < 4; ++j) G4[i][j] = 0.f;
   float gmu[4] = {0.f, 0.f, 0.f, 0.f};
   float glogit = 0.f;
+  float st_uv = 0.f, st_t = 0.f;
+  int st_n = 0;
   for (int vi = 0; vi < p.n_views; ++vi) {
     const int d = slot[(size_t)vi * p.n + gidx];
     if (d < 0) continue;
@@ -293,7 +299,18 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
     G4[1][3] += 0.5f * cg.y * lam;
     G4[2][3] += 0.5f * cg.z * lam;
     G4[3][3] += -glam * lam * inv44;
-    gmu[3] += -(glam * inv44 + cg.w);
+    const float gmt_col = -(glam * inv44 + cg.w);
+    gmu[3] += gmt_col;
+    if (e.w >= 0.f) {  // blended in this view: densification statistics (Sec. 3.3)
+      st_uv += e.w;
+      st_t += fabsf(e.y + gmt_col);
+      ++st_n;
+    }
+  }
+  if (st.blend_count && st_n) {
+    st.uv_grad_norm_sum[gidx] += st_uv;
+    st.t_grad_abs_sum[gidx] += st_t;
+    st.blend_count[gidx] += st_n;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -372,7 +389,7 @@ void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, cons
                                 const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
                                 const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,
                                 float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
-                                bool accumulate, hipStream_t s) {
+                                bool accumulate, const DensifyStats& stats, hipStream_t s) {
   if (p.n == 0) return;
   float4* geo = reinterpret_cast<float4*>(scratch);
   float4* col = reinterpret_cast<float4*>(scratch + (size_t)n_records_max * kGeoFloats);
@@ -385,7 +402,7 @@ void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, cons
   hipLaunchKernelGGL(k_bwd_prims, dim3((p.n + 127) / 128), dim3(128), 0, s, p, slot, geo, cg,
                      reinterpret_cast<float4*>(g_means4), reinterpret_cast<float4*>(g_log_scales4),
                      reinterpret_cast<float4*>(g_q_left), reinterpret_cast<float4*>(g_q_right), g_opacity_logit,
-                     accumulate);
+                     accumulate, stats);
 }
 
 }  // namespace g4d

@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const uint32_t* __restrict__ order, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
-    const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d) {
+    const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d, bool mark_blended) {
   __shared__ float4 s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch];
   __shared__ uint32_t s_d[kBwdBatch];
   __shared__ uint32_t s_qm[kBwdBatch];
@@ -372,6 +372,11 @@ __global__ void __launch_bounds__(256) k_raster_backward(
       if (!HAS_D && q == 9) continue;
       v[q] = row16_sum(v[q]);
     }
+    // the record blended in this tile: flag it in the gradient line's last
+    // float (the same 1 from every tile, so plain stores suffice)
+    if (mark_blended && c2 == 15 && e2 < count &&
+        (((s_act[0] | s_act[1] | s_act[2] | s_act[3]) >> j2) & 1u))
+      grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.f;
     // lanes c2 < 10 of the primitive's row each add one value of its
     // gradient line, so a wave's atomics for a primitive share one line
     if (e2 < count) {
@@ -416,12 +421,13 @@ void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views,
                             const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, float* grad2d, hipStream_t s) {
+                            const uint32_t* pix_last, float* grad2d, bool mark_blended, hipStream_t s) {
   if (total_tiles == 0) return;
 #define G4D_BWD(HD, HA)                                                                                          \
   hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(total_tiles), dim3(256), 0, s, order, n_views, views,     \
                      ranges,                                                                                      \
-                     ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d)
+                     ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d,      \
+                     mark_blended)
   if (dl_depth && dl_alpha) G4D_BWD(true, true);
   else if (dl_depth) G4D_BWD(true, false);
   else if (dl_alpha) G4D_BWD(false, true);

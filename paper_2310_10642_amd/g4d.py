@@ -27,7 +27,7 @@ DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_la
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
             "g4d_render", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
-            "g4d_get_tuning", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
+            "g4d_get_tuning", "g4d_set_densify_stats", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
 
 
 class G4DOptions(ctypes.Structure):
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     lib.g4d_get_stats.argtypes = [vp, ctypes.POINTER(G4DStats), ctypes.POINTER(ctypes.c_int64)]
     lib.g4d_set_tuning.argtypes = [vp, i32, i32]
     lib.g4d_get_tuning.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.g4d_set_densify_stats.argtypes = [vp, fp, fp, vp]
     lib.g4d_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.g4d_last_error.argtypes = [vp]
     lib.g4d_last_error.restype = ctypes.c_char_p
@@ -227,6 +228,22 @@ class Renderer:
         self._check(self.lib.g4d_render_backward(self.ctx, *[_ptr(a) for a in args], *[_ptr(t) for t in g], flags))
         self._keep = args
         return g
+
+    def set_densify_stats(self, uv_grad_norm_sum: Optional[torch.Tensor], t_grad_abs_sum: Optional[torch.Tensor],
+                          blend_count: Optional[torch.Tensor]):
+        """Registers per-primitive accumulators (float32, float32, int32 [n] on
+        the GPU) that every later backward adds the densification statistics
+        to; None for all three switches them off."""
+        ts = (uv_grad_norm_sum, t_grad_abs_sum, blend_count)
+        if all(t is None for t in ts):
+            self._densify = None
+            self._check(self.lib.g4d_set_densify_stats(self.ctx, None, None, None))
+            return
+        for t, dt in zip(ts, (torch.float32, torch.float32, torch.int32)):
+            if t is None or not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == self.n):
+                raise ValueError("densify accumulators: contiguous GPU float32, float32, int32 tensors of n values")
+        self._densify = ts  # keep alive
+        self._check(self.lib.g4d_set_densify_stats(self.ctx, *[_ptr(t) for t in ts]))
 
     def image_loss(self, kind: int, img: torch.Tensor, target: torch.Tensor, scale: float,
                    loss_out: torch.Tensor, grad_out: torch.Tensor):

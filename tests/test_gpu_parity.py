@@ -498,6 +498,51 @@ def test_sync_free_and_graph_replay():
     r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
 
 
+def test_densify_stats_parity():
+    """Densification statistics of two views in one batch against the
+    oracle's: per-view |dL/d(u,v)|, |dL/dmu_t| and the blended-view count;
+    then the same batch split into two rounds accumulates the same values."""
+    _say("[densification statistics, 3000 primitives x 2 views]")
+    from paper_2310_10642_amd import g4d
+    scene = _big_splat_scene(5, 3000, grow=0.8)
+    cams = [scenegen.look_at_camera((1.0, 0.5, 3.5), 100, 70), scenegen.look_at_camera((-1.2, -0.2, 3.2), 96, 64)]
+    times = [0.37, 0.52]
+    dls = []
+    for v, (cam, t) in enumerate(zip(cams, times)):
+        _, img = PT.oracle_view(scene, cam, t)
+        mask = (~img["unc_g"].numpy()).astype(np.float64)
+        dls.append(PT.dl_maps(60 + v, cam.height, cam.width, mask)[0])
+    uv_o, t_o, cnt_o = (x.numpy() for x in O.densify_stats(scene, cams, times, dls))
+    r, _ = PT.gpu_setup(scene)
+    n = scene.n
+    dl = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dls]).astype(np.float32)).cuda()
+    runs = []
+    for pairs in (1 << 28, n):                       # one round, then one view per round
+        acc = (torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"),
+               torch.zeros(n, dtype=torch.int32, device="cuda"))
+        r.set_tuning(g4d.G4D_TUNE_ROUND_PAIRS, pairs)
+        r.set_densify_stats(*acc)
+        r.render(cams, times)
+        r.backward(dl)
+        torch.cuda.synchronize()
+        assert r.stats()["rounds"] == (1 if pairs > n else 2)
+        runs.append([_np(x) for x in acc])
+    uv_g, t_g, cnt_g = runs[0]
+    same = cnt_g == cnt_o
+    _say(f"  blended-view counts equal for {same.mean():.4%} of primitives; "
+         f"{int((cnt_o > 0).sum())} blended somewhere")
+    assert (cnt_o > 0).sum() > 100 and same.mean() >= 0.995
+    for name, a, b in (("uv", uv_g, uv_o), ("t", t_g, t_o)):
+        a, b = a[same].astype(np.float64), b[same]
+        assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), name
+        rms = np.sqrt(np.mean(b * b))
+        assert (np.abs(a - b) <= 1e-3 * (np.abs(b) + rms)).all(), name
+    assert np.array_equal(runs[1][2], cnt_g)
+    for a, b in zip(runs[1][:2], runs[0][:2]):
+        assert np.allclose(a, b, rtol=1e-5, atol=1e-7 * float(np.abs(b).max()))
+    r.set_densify_stats(None, None, None)
+
+
 def test_tile_order_and_autotune():
     """Heavy-first tile order and the autotuner's knobs change no result:
     images bit for bit, gradients up to the order of the atomic sums."""
