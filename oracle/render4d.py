@@ -594,6 +594,43 @@ def densify_stats(scene, cams, times, dl_rgb, dl_depth=None, dl_alpha=None, bg=(
     return uv.detach(), tg.detach(), cnt
 
 
+def flow_displacement(params: Dict[str, torch.Tensor], cam: OCamera, t: float, dt: float) -> torch.Tensor:
+    """Sec. 4.3 ("Render Flow"): the image-plane displacement of each
+    primitive's conditional mean mu_xyz|t between t and t + dt, both points
+    projected by the view's pinhole camera; zero when the later point is not in
+    front of the near plane. Returns [N, 2] (du, dv) in pixels."""
+    cov4 = covariance_4d(params["log_scales4"], params["q_left"], params["q_right"])
+    mean4 = params["means4"]
+    mu0, _ = slice_at(mean4, cov4, t)
+    mu1, _ = slice_at(mean4, cov4, t + dt)
+
+    def project(mu):
+        p = mu @ cam.rot.T + cam.trans
+        return cam.fx * p[:, 0] / p[:, 2] + cam.cx, cam.fy * p[:, 1] / p[:, 2] + cam.cy, p[:, 2]
+    u0, v0, _ = project(mu0)
+    u1, v1, z1 = project(mu1)
+    ok = z1 > CONVENTIONS["near"]
+    zero = torch.zeros_like(u0)
+    return torch.stack([torch.where(ok, u1 - u0, zero), torch.where(ok, v1 - v0, zero)], -1)
+
+
+def render_flow(scene, cam, t: float, dt: float, tiles=None, margins=None, with_flags=True):
+    """Optical flow of one view (Sec. 4.3): each primitive's displacement
+    (flow_displacement) blended with the render's weights of Eq. (6) over a
+    zero background. Same primitives, footprints and order as the render.
+    Returns render_view's structure whose "rgb" planes 0-1 hold the flow."""
+    ocam = cam if isinstance(cam, OCamera) else to_ocamera(cam)
+    params = params_from_scene(scene)
+    pre = preprocess(params, ocam, float(t), scene.sh_degree, scene.t_order, scene.t_period)
+    f = flow_displacement(params, ocam, float(t), float(dt))
+    pre = dict(pre, color=torch.cat([f, torch.zeros_like(f[:, :1])], -1))
+    tile_list = range(ocam.tiles_x * ocam.tiles_y) if tiles is None else tiles
+    out = dict(pre=pre, tiles=list(tile_list), parts={})
+    for tid in tile_list:
+        out["parts"][int(tid)] = composite_tile(pre, ocam, int(tid), (0.0, 0.0, 0.0), margins, with_flags)
+    return out
+
+
 def render_full(scene, cam, t, bg=(0.0, 0.0, 0.0), requires_grad=False, with_flags=True,
                 tiles=None, margins=None):
     """Convenience: render a whole view from a scenegen Scene."""

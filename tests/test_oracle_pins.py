@@ -523,3 +523,60 @@ def test_densify_t_gradient_sums_per_view_magnitudes():
     assert fd[0] * fd[1] < 0                    # the two views pull mu_t in opposite directions
     ref = abs(fd[0]) + abs(fd[1])
     assert abs(float(tg[0]) - ref) <= 1e-5 * (1 + ref)
+
+
+# --- Sec. 4.3: rendered optical flow -------------------------------------------------
+def _xt_rotation_scene(theta, sx=0.3, st=0.1):
+    """One primitive at the origin rotated by theta in the (x, t) plane:
+    q_l = q_r = (cos theta/2, 0, 0, sin theta/2) (x <-> 1, t <-> k)."""
+    sc = scenegen.random_scene(28, 1, sh_degree=0, t_order=0)
+    q = [math.cos(theta / 2), 0.0, 0.0, math.sin(theta / 2)]
+    sc.q_left[:] = q
+    sc.q_right[:] = q
+    sc.means4[:] = [[0.0, 0.0, 0.0, 0.5]]
+    sc.log_scales4[:] = [[math.log(sx), math.log(0.3), math.log(0.3), math.log(st)]]
+    sc.opacity_logit[:] = [2.0]
+    return sc
+
+
+def test_static_primitives_have_no_flow():
+    """q_l = (cos a, 0, 0, sin a), q_r = (cos a, 0, 0, -sin a) fixes the x and t
+    axes and rotates the (y, z) plane: Sigma_xyz,t = 0, the slice mean does
+    not move and no primitive has flow."""
+    sc = scenegen.random_scene(29, 40, spread=0.6)
+    ang = np.random.default_rng(30).uniform(0, math.pi, 40)
+    sc.q_left[:] = np.stack([np.cos(ang), 0 * ang, 0 * ang, np.sin(ang)], 1)
+    sc.q_right[:] = np.stack([np.cos(ang), 0 * ang, 0 * ang, -np.sin(ang)], 1)
+    cam = scenegen.look_at_camera((0.4, 0.2, 3.5), 32, 32)
+    out = O.render_flow(sc, cam, 0.5, 0.05, with_flags=False)
+    flow = O.assemble(out, cam, "rgb", 3)
+    assert float(flow.abs().max()) < 1e-12
+    alpha = O.assemble(O.render_full(sc, cam, 0.5, with_flags=False), cam, "alpha")
+    assert float(alpha.max()) > 0.5               # the primitives are on screen
+
+
+def test_flow_of_xt_rotated_primitive_closed_form():
+    """A rotation by theta in the (x, t) plane gives the slice mean the velocity
+    Sigma_xt / Sigma_tt = (s_x^2 - s_t^2) sin cos / (s_x^2 sin^2 + s_t^2 cos^2)
+    along world x (sign aside), which the camera on the z axis sees as a
+    horizontal image velocity f_x v / z; the centre pixel holds its alpha times
+    the displacement."""
+    cam = scenegen.look_at_camera((0.0, 0.0, 4.0), 32, 32)
+    sx, st, dt = 0.3, 0.1, 0.02
+    flows = []
+    for theta in (0.4, -0.4):
+        sc = _xt_rotation_scene(theta, sx, st)
+        out = O.render_flow(sc, cam, 0.5, dt, with_flags=False)
+        flow = O.assemble(out, cam, "rgb", 3)
+        alpha = O.assemble(O.render_full(sc, cam, 0.5, with_flags=False), cam, "alpha").detach()
+        # the stored (float32) parameters, exactly
+        qs = [float(x) for x in sc.q_left[0]]
+        th = 2.0 * math.atan2(qs[3], qs[0])
+        ax, at = math.exp(float(sc.log_scales4[0, 0])), math.exp(float(sc.log_scales4[0, 3]))
+        vel = (ax * ax - at * at) * math.sin(th) * math.cos(th) / (
+            ax * ax * math.sin(th) ** 2 + at * at * math.cos(th) ** 2)
+        expect = float(alpha[15, 15]) * cam.fx * abs(vel) * dt / 4.0
+        assert abs(abs(float(flow[0, 15, 15])) - expect) <= 1e-9 * (1 + expect)
+        assert abs(float(flow[1, 15, 15])) < 1e-12 and float(flow[2].abs().max()) == 0.0
+        flows.append(float(flow[0, 15, 15]))
+    assert flows[0] != 0.0 and abs(flows[0] + flows[1]) <= 1e-12   # opposite rotations, opposite ways
