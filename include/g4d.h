@@ -131,6 +131,18 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
 g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
                       float* out_rgb, float* out_depth, float* out_alpha);
 
+/* Rendered optical flow (Sec. 4.3): for each view, the alpha blend of Eq. (6)
+ * (the render's weights, zero background) of every primitive's image-plane
+ * displacement between t and t + frame_dt of its conditional mean
+ * mu_xyz|t: f_i = pi(mu_c(t + frame_dt)) - pi(mu_c(t)) with pi the view's
+ * pinhole projection, or 0 when mu_c(t + frame_dt) is not in front of the near
+ * plane. Primitives, footprints and order are exactly those of g4d_render.
+ *   out_flow  device [sum_v 2*H_v*W_v], per view planar [2][H][W] (du, dv, px)
+ * There is no gradient of the flow: the call invalidates the state kept for
+ * render_backward. */
+g4d_status g4d_render_flow(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
+                           float frame_dt, float* out_flow);
+
 /* Gradient of the last render. dL_drgb is required; dL_ddepth and dL_dalpha may
  * be NULL (treated as zero). Layouts match render's outputs. The gradient
  * buffers (layouts as set_primitives) receive the sum over the views of the

@@ -55,6 +55,8 @@ struct g4d_ctx {
   bool sync_free = false;          // no host read of device counts inside render/backward
   bool heavy_first = true;         // rasterise tiles by decreasing list length
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
+  bool flow_mode = false;          // the render in progress blends flow (Sec. 4.3), not colour
+  float flow_dt = 0.f;
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
@@ -209,6 +211,8 @@ RenderParams make_params(g4d_ctx* c, int n_views) {
   p.opacity_logit = c->opacity_logit;
   p.coeffs = c->coeffs;
   p.views = P<ViewDev>(c->views_d);
+  p.flow = c->flow_mode ? 1 : 0;
+  p.flow_dt = c->flow_dt;
   return p;
 }
 
@@ -336,9 +340,11 @@ g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, 
   launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, P<uint32_t>(c->counters) + kCntMaxList, s);
   // 9. rasterise the round's views into their places in the outputs
   stage_begin(c);
+  static const float kZero3[3] = {0.f, 0.f, 0.f};
   launch_raster_forward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, r.v1 - r.v0,
                         P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival), P<Record>(c->rec_sorted),
-                        c->opts.bg, out_rgb, out_depth, out_alpha, P<float>(c->pix_t), P<uint32_t>(c->pix_last), s);
+                        c->flow_mode ? kZero3 : c->opts.bg, c->flow_mode ? 2 : 3, out_rgb, out_depth, out_alpha,
+                        P<float>(c->pix_t), P<uint32_t>(c->pix_last), s);
   stage_end(c, G4D_STAGE_RASTER_FWD);
   HIPCHK(c, hipGetLastError());
   return G4D_OK;
@@ -490,6 +496,9 @@ g4d_status g4d_set_primitives(g4d_ctx* c, int64_t n, const float* means4, const 
   return G4D_OK;
 }
 
+static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times,
+                              float* out_rgb, float* out_depth, float* out_alpha);
+
 g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times, float* out_rgb,
                       float* out_depth, float* out_alpha) {
   if (!c) return G4D_EINVAL;
@@ -502,7 +511,28 @@ g4d_status g4d_render(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const
     g4d_status st = autotune(c, n_views, cams, times, out_rgb, out_depth, out_alpha);
     if (st) return st;
   }
+  c->flow_mode = false;
+  return render_impl(c, n_views, cams, times, out_rgb, out_depth, out_alpha);
+}
 
+g4d_status g4d_render_flow(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times, float frame_dt,
+                           float* out_flow) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
+  if (n_views < 1 || n_views > kMaxViews) return fail(c, G4D_EINVAL, "n_views must be in [1, 4096]");
+  if (!cams || !times || !out_flow) return fail(c, G4D_EINVAL, "null cams/times/out_flow");
+  if (!std::isfinite(frame_dt)) return fail(c, G4D_EINVAL, "non-finite frame_dt");
+  c->flow_mode = true;
+  c->flow_dt = frame_dt;
+  const g4d_status st = render_impl(c, n_views, cams, times, out_flow, nullptr, nullptr);
+  c->flow_mode = false;
+  c->have_render = false;  // the kept records hold flow, not colour: no backward
+  return st;
+}
+
+static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times,
+                              float* out_rgb, float* out_depth, float* out_alpha) {
   // ---- views (host) ----
   std::vector<ViewDev> vh(n_views);
   int64_t tiles = 0, pix = 0;

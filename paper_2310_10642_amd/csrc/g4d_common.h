@@ -58,6 +58,8 @@ struct RenderParams {
   const float* opacity_logit;
   const float* coeffs;
   const ViewDev* views;
+  int flow;             // 1: records carry the image-plane flow over flow_dt instead of the colour
+  float flow_dt;
 };
 
 // Per-primitive densification accumulators (all null: off).
@@ -108,9 +110,10 @@ void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, 
 
 // ---- launchers (raster.hip) ----
 // order (nullable): the tile each workgroup takes, e.g. heaviest lists first.
+// channels: 3 (rgb planes) or 2 (the first two record colour values, e.g. flow).
 void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                            const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
-                           float* out_rgb,
+                           int channels, float* out_rgb,
                            float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s);
 void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                             const uint2* ranges,

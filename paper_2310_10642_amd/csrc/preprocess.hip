@@ -1,12 +1,11 @@
-// Per-primitive stages of the 4D Gaussian render, forward and backward.
-//
-// Forward (one thread per primitive, looping over the views of a batch so the
-// parameters are read once): 4D covariance Sigma = R S S^T R^T with
-// R = L(q_l) R(q_r) (Sec. 3.2, "Representation of 4D Gaussian"), temporal
-// marginal and filter (Sec. 3.2 and Sec. 4.2), conditional 3D Gaussian at t
-// (Sec. 3.2), EWA projection (Eqs. 3-4), footprint and tile rectangle, and the
-// 4D spherindrical-harmonic colour (Sec. 3.2). Backward: the chain rule of
-// the same steps from the per-record 2D gradients to every parameter.
+// Per-primitive stage of the 4D Gaussian render (one thread per primitive,
+// looping over the views of a batch so the parameters are read once):
+// 4D covariance Sigma = R S S^T R^T with R = L(q_l) R(q_r) (Sec. 3.2,
+// "Representation of 4D Gaussian"), temporal marginal and filter (Sec. 3.2
+// and Sec. 4.2), conditional 3D Gaussian at t (Sec. 3.2), EWA projection
+// (Eqs. 3-4), footprint and tile rectangle, and the 4D spherindrical-harmonic
+// colour (Sec. 3.2) -- or, for a flow render, the image-plane displacement of
+// the conditional mean (Sec. 4.3). The backward is in preprocess_bwd.hip.
 #include "shade.h"
 
 namespace g4d {
@@ -70,6 +69,29 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
       slot[idx] = -1;
       continue;
     }
+    Record r;
+    r.a = make_float4(g.u, g.v, g.pc[2], opa * g.pt);
+    r.b = make_float4(g.conic[0], g.conic[1], g.conic[2], __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)));
+    if (p.flow) {
+      // Sec. 4.3: the conditional mean moves by v3 dt / S44 (it is linear in
+      // t); its projection moves by f (x' z - x z') / (z z') per axis
+      const float s = p.flow_dt / g.s44;
+      float dp[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        dp[i] = s * (vw.rot[3 * i] * g.v3[0] + vw.rot[3 * i + 1] * g.v3[1] + vw.rot[3 * i + 2] * g.v3[2]);
+      const float x = g.pc[0], y = g.pc[1], z = g.pc[2], z1 = z + dp[2];
+      const bool front = z1 > p.near_plane;
+      const float q = front ? 1.f / (z * z1) : 0.f;
+      const float fu = vw.fx * (dp[0] * z - x * dp[2]) * q;
+      const float fv = vw.fy * (dp[1] * z - y * dp[2]) * q;
+      r.c = make_float4(fu, fv, 0.f, __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
+      rec[idx] = r;
+      act[idx] = 1u;
+      dkey[idx] = __float_as_uint(g.pc[2]);
+      slot[idx] = -1;
+      continue;
+    }
     // 4D spherindrical harmonics colour
     float Y[16], cs[3];
     sh_eval(p.sh_degree, g.dir[0], g.dir[1], g.dir[2], Y);
@@ -87,9 +109,6 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
       col[1] = fmaf(cs[n], acc[1], col[1]);
       col[2] = fmaf(cs[n], acc[2], col[2]);
     }
-    Record r;
-    r.a = make_float4(g.u, g.v, g.pc[2], opa * g.pt);
-    r.b = make_float4(g.conic[0], g.conic[1], g.conic[2], __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)));
     r.c = make_float4(fmaxf(col[0] + kColorOffset, 0.f), fmaxf(col[1] + kColorOffset, 0.f),
                       fmaxf(col[2] + kColorOffset, 0.f), __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
     rec[idx] = r;

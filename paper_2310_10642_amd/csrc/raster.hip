@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ ival,
                                                          const Record* __restrict__ recs, float bg0, float bg1,
-                                                         float bg2, float* __restrict__ out_rgb,
+                                                         float bg2, int channels, float* __restrict__ out_rgb,
                                                          float* __restrict__ out_depth, float* __restrict__ out_alpha,
                                                          float* __restrict__ pix_t, uint32_t* __restrict__ pix_last) {
   __shared__ float4 s_a[kFwdBatch], s_b[kFwdBatch], s_c[kFwdBatch];
@@ -187,10 +187,10 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
   const long long hw = (long long)vw.width * vw.height;
   const long long pl = (long long)py * vw.width + px;
   const long long pix = vw.pix_base + pl;
-  float* rgb = out_rgb + 3 * vw.pix_base + pl;
+  float* rgb = out_rgb + channels * vw.pix_base + pl;
   rgb[0] = fmaf(T, bg0, C0);
   rgb[hw] = fmaf(T, bg1, C1);
-  rgb[2 * hw] = fmaf(T, bg2, C2);
+  if (channels == 3) rgb[2 * hw] = fmaf(T, bg2, C2);
   if (out_depth) out_depth[pix] = D;
   if (out_alpha) out_alpha[pix] = 1.f - T;
   pix_t[pix] = T;
@@ -409,12 +409,11 @@ __global__ void __launch_bounds__(256) k_raster_backward(
 
 void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                            const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
-                           float* out_rgb, float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last,
-                           hipStream_t s) {
+                           int channels, float* out_rgb, float* out_depth, float* out_alpha, float* pix_t,
+                           uint32_t* pix_last, hipStream_t s) {
   if (total_tiles == 0) return;
   hipLaunchKernelGGL(k_raster_forward, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges, ival,
-                     rec_sorted,
-                     bg[0], bg[1], bg[2], out_rgb, out_depth, out_alpha, pix_t, pix_last);
+                     rec_sorted, bg[0], bg[1], bg[2], channels, out_rgb, out_depth, out_alpha, pix_t, pix_last);
 }
 
 void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,

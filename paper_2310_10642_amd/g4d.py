@@ -26,7 +26,7 @@ STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd",
 DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_last=7, grad2d=8)
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
-            "g4d_render", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
+            "g4d_render", "g4d_render_flow", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
             "g4d_get_tuning", "g4d_set_densify_stats", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
 
 
@@ -72,6 +72,8 @@ def load_library(path: str = LIB_PATH):
     lib.g4d_set_stream.argtypes = [vp, vp]
     lib.g4d_set_primitives.argtypes = [vp, i64, fp, fp, fp, fp, fp, fp]
     lib.g4d_render.argtypes = [vp, i32, ctypes.POINTER(G4DCamera), ctypes.POINTER(ctypes.c_float), fp, fp, fp]
+    lib.g4d_render_flow.argtypes = [vp, i32, ctypes.POINTER(G4DCamera), ctypes.POINTER(ctypes.c_float), ctypes.c_float,
+                                    fp]
     lib.g4d_render_backward.argtypes = [vp, fp, fp, fp, fp, fp, fp, fp, fp, fp, i32]
     lib.g4d_image_loss.argtypes = [vp, i32, i64, fp, fp, ctypes.c_float, fp, fp]
     lib.g4d_get_stats.argtypes = [vp, ctypes.POINTER(G4DStats), ctypes.POINTER(ctypes.c_int64)]
@@ -194,6 +196,23 @@ class Renderer:
         self.generation += 1
         self._views = [(int(c.height), int(c.width)) for c in cameras]
         return rgb, dep, alp
+
+    def render_flow(self, cameras: Sequence, times: Sequence[float], frame_dt: float,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Flat [sum 2 H W] optical flow (du, dv planes per view) over t -> t + frame_dt."""
+        self._stream()
+        V = len(cameras)
+        cams = (G4DCamera * V)(*[to_camera(c) for c in cameras])
+        tarr = (ctypes.c_float * V)(*[float(t) for t in times])
+        npix = sum(int(c.width) * int(c.height) for c in cameras)
+        if out is None:
+            out = torch.empty(2 * npix, device=torch.device("cuda", torch.cuda.current_device()))
+        elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() == 2 * npix):
+            raise ValueError("flow output must be a contiguous float32 GPU tensor of 2 x pixels")
+        self._check(self.lib.g4d_render_flow(self.ctx, V, cams, tarr, float(frame_dt), _ptr(out)))
+        self.generation += 1
+        self._views = [(int(c.height), int(c.width)) for c in cameras]
+        return out
 
     def split(self, rgb, depth=None, alpha=None):
         """Per-view [3,H,W] / [H,W] views of the flat outputs."""

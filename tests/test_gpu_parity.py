@@ -498,6 +498,38 @@ def test_sync_free_and_graph_replay():
     r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
 
 
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+def test_flow_parity(name, mk_scene, mk_cam, t, bg):
+    """Rendered optical flow (two planes) against the oracle's, away from
+    pixels with a decision FP32 may take the other way; the flow render keeps
+    no state for a backward, and a render after it is unaffected."""
+    _say(f"[flow parity] {name}")
+    from paper_2310_10642_amd import g4d
+    scene, cam = mk_scene(), mk_cam()
+    dt = 0.05
+    r, _ = PT.gpu_setup(scene, bg)
+    t2 = t + 0.01                                  # a second view at another time
+    flow = _np(r.render_flow([cam, cam], [t, t2], dt)).reshape(2, 2, cam.height, cam.width)
+    with pytest.raises(g4d.G4DError):
+        r.backward(torch.zeros(3 * cam.width * cam.height, device="cuda"))
+    g_rgb, _, _ = _render_one(r, cam, t)
+    _, img = PT.oracle_view(scene, cam, t, bg)
+    assert np.abs(g_rgb - img["rgb"].numpy())[:, ~img["unc"].numpy()].max() <= PT.IMG_ATOL
+    for v, tv in enumerate((t, t2)):
+        out = O.render_flow(scene, cam, tv, dt)
+        ref = O.assemble(out, cam, "rgb", 3)[:2].detach().numpy()
+        # value flags: a decision FP32 may flip moves the blend weights by at
+        # most 1e-5 at unflagged pixels, i.e. the flow by 1e-5 x a few pixels
+        unc = O.assemble(out, cam, "uncertain").numpy()
+        ok = ~unc
+        err = np.abs(flow[v] - ref)[:, ok]
+        tol = 1e-4 * (1.0 + np.abs(ref)[:, ok])
+        _say(f"  view {v}: max |flow| {np.abs(ref).max():.3g} px, max err {err.max():.3g}, "
+             f"flagged {unc.mean():.3%}")
+        assert unc.mean() <= 1e-2 and (err <= tol).all()
+        assert np.abs(ref).max() > 1e-3           # the scene moves
+
+
 def test_densify_stats_parity():
     """Densification statistics of two views in one batch against the
     oracle's: per-view |dL/d(u,v)|, |dL/dmu_t| and the blended-view count;
