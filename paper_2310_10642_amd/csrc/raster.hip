@@ -313,21 +313,12 @@ __global__ void __launch_bounds__(256) k_raster_backward(
       s_w[j * kGwStride + q_self] = a * T;
       blended |= 1u << j;
     };
-    // back to front over the set entries, the next one's values loaded ahead
-    if (todo) {
-      int j = 31 - __clz(todo);
-      float4 sa = s_a[j], sb = s_b[j], sc = s_c[j];
-      for (;;) {
-        todo &= ~(1u << j);
-        const int jn = todo ? 31 - __clz(todo) : j;
-        const float4 na = s_a[jn], nb = s_b[jn], nc = s_c[jn];
-        entry(j, sa, sb, sc);
-        if (!todo) break;
-        j = jn;
-        sa = na;
-        sb = nb;
-        sc = nc;
-      }
+    // back to front over the set entries; j is a constant in every unrolled
+    // step, so the LDS addresses are immediate offsets
+#pragma unroll
+    for (int j = kBwdBatch - 1; j >= 0; --j) {
+      if (!((todo >> j) & 1u)) continue;
+      entry(j, s_a[j], s_b[j], s_c[j]);
     }
     if (lane == 0) s_act[wave] = blended;
     __syncthreads();
