@@ -6,9 +6,11 @@
 // While staging, each entry's alpha-floor ellipse (the pixels where
 // opacity * exp(power) can reach 1/255) is bounded by a box and tested against
 // the four quadrants; every wave then walks only the entries that can touch
-// its quadrant. A skipped entry would have failed the 1/255 test at every
-// pixel of the quadrant, so the blend is unchanged. The per-fragment body is
-// branch-free: skipped and post-stop fragments get alpha 0.
+// its quadrant, 16 at a time under a wave-uniform bit mask with the entry
+// index a constant in each unrolled step (LDS reads at immediate offsets).
+// A skipped entry would have failed the 1/255 test at every pixel of the
+// quadrant, so the blend is unchanged. The per-fragment body is branch-free:
+// skipped and post-stop fragments get alpha 0.
 //
 // The forward pass keeps only the final transmittance and the number of list
 // entries up to the last contributor per pixel. The backward pass walks the
@@ -108,7 +110,6 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
                                                          float* __restrict__ pix_t, uint32_t* __restrict__ pix_last) {
   __shared__ float4 s_a[kFwdBatch], s_b[kFwdBatch], s_c[kFwdBatch];
   __shared__ __align__(16) uint8_t s_mask[kFwdBatch];
-  __shared__ uint8_t s_list[4][kFwdBatch];
   const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   const int vi = find_view(views, n_views, tile);
   const ViewDev& vw = views[vi];
@@ -141,46 +142,35 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
     }
     s_mask[threadIdx.x] = (uint8_t)mask;
     __syncthreads();
-    // per-wave list of the batch entries that can touch this wave's quadrant,
-    // in list order: lane l owns entries 4l .. 4l+3
-    const uint32_t m4 = *reinterpret_cast<const uint32_t*>(&s_mask[4 * lane]);
-    uint32_t bits = 0u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) bits |= ((m4 >> (8 * k + wave)) & 1u) << k;
-    const uint32_t cnt = (uint32_t)__popc(bits);
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += y;
-    }
-    const int nw = __shfl(incl, 63, 64);
-    uint32_t o = incl - cnt;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if ((bits >> k) & 1u) s_list[wave][o++] = (uint8_t)(4 * lane + k);
-    __syncthreads();
     if (__all(done)) continue;
-    for (int k = 0; k < nw; ++k) {
-      const int j = s_list[wave][k];
-      const float4 sa = s_a[j];
-      const float4 sb = s_b[j];
-      const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
-      float a = fminf(__builtin_amdgcn_exp2f(p2), kAlphaMax);
-      a = (p2 >= kLog2AlphaMin && !done) ? a : 0.f;
-      const float Tn = fmaf(-a, T, T);
-      const bool stop = Tn < kTStop;  // T >= kTStop always, so stop implies a > 0
-      done = done || stop;
-      a = stop ? 0.f : a;
-      const float4 sc = s_c[j];
-      const float w = a * T;
-      C0 = fmaf(w, sc.x, C0);
-      C1 = fmaf(w, sc.y, C1);
-      C2 = fmaf(w, sc.z, C2);
-      D = fmaf(w, sb.z, D);
-      T = stop ? T : Tn;
-      last = (a > 0.f) ? (uint32_t)(b0 + j + 1) : last;
-      if ((k & 15) == 15 && __all(done)) break;
+    // chunks of 16 entries: a wave-uniform mask of those that can touch this
+    // wave's quadrant, walked with constant LDS offsets
+    const int nb = min(kFwdBatch, count - b0);
+    for (int c0 = 0; c0 < nb; c0 += 16) {
+      const uint32_t m = lane < 16 ? (uint32_t)s_mask[c0 + lane] : 0u;
+      const uint32_t todo = (uint32_t)__ballot((m >> wave) & 1u);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (!((todo >> j) & 1u)) continue;
+        const float4 sa = s_a[c0 + j];
+        const float4 sb = s_b[c0 + j];
+        const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
+        float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(p2), 0.f, kAlphaMax);
+        a = (p2 >= kLog2AlphaMin && !done) ? a : 0.f;
+        const float Tn = fmaf(-a, T, T);
+        const bool stop = Tn < kTStop;  // T >= kTStop always, so stop implies a > 0
+        done = done || stop;
+        a = stop ? 0.f : a;
+        const float4 sc = s_c[c0 + j];
+        const float w = a * T;
+        C0 = fmaf(w, sc.x, C0);
+        C1 = fmaf(w, sc.y, C1);
+        C2 = fmaf(w, sc.z, C2);
+        D = fmaf(w, sb.z, D);
+        T = stop ? T : Tn;
+        last = (a > 0.f) ? (uint32_t)(b0 + c0 + j + 1) : last;
+      }
+      if (__all(done)) break;
     }
   }
   if (!inside) return;
