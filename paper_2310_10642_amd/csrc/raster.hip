@@ -19,9 +19,10 @@
 // writes dL/dpower and a_i T_i for the batch into LDS; (2) the lanes regroup
 // as 16 primitives x 16 pixel columns and accumulate the per-primitive sums
 // over the tile's pixels (only over quadrants where the primitive blended).
-// One 16-lane DPP reduction per batch combines the columns, and one atomic
-// per value and (tile, primitive) adds the tile's share; the lanes of a
-// primitive's row issue its values together into one 64-byte line.
+// A 16-lane DPP reduce-scatter per batch combines the columns, leaving each
+// of ten lanes of a primitive's row with one value of its gradient line, and
+// those lanes add the tile's share with one atomic instruction into one
+// 64-byte line.
 #include "g4d_common.h"
 
 namespace g4d {
@@ -85,13 +86,31 @@ __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int 
   return lo;
 }
 
-// Sum over each 16-lane row with DPP row rotations (every lane gets the sum).
-__device__ __forceinline__ float row16_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xF, 0xF, false));  // row_ror:2
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xF, 0xF, false));  // row_ror:1
-  return v;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Reduce-scatter of ten values over each 16-lane row: afterwards lane c holds
+// the row sum of value slot(c), slot = 5 (c >> 3) + 3 ((c >> 2) & 1) +
+// 2 ((c >> 1) & 1) + (c & 1), on lanes 0-2, 4-5, 8-10, 12-13 (slot -1
+// elsewhere). Pairs: row mirror (c <-> 15 - c), half-row mirror, quad
+// (c <-> 3 - c), quad (c <-> c ^ 1); each step keeps half of the values.
+__device__ __forceinline__ float row16_reduce_scatter10(const float (&q)[10], int c, int& slot) {
+  const bool hi = c & 8, b = c & 4, cc = c & 2, d = c & 1;
+  float r[6], s[4], t[2];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r[i] = (hi ? q[i + 5] : q[i]) + dpp<0x140>(hi ? q[i] : q[i + 5]);
+  r[5] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s[i] = (b ? r[i + 3] : r[i]) + dpp<0x141>(b ? r[i] : r[i + 3]);
+  s[3] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) t[i] = (cc ? s[i + 2] : s[i]) + dpp<0x1B>(cc ? s[i] : s[i + 2]);
+  const float out = (d ? t[1] : t[0]) + dpp<0xB1>(d ? t[0] : t[1]);
+  const int e = 2 * (int)cc + (int)d;
+  slot = (e <= (b ? 1 : 2)) ? 5 * (int)hi + 3 * (int)b + e : -1;
+  return out;
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
@@ -347,42 +366,40 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const float Sgy = fmaf(dc, Sg, Sgm);
     const float Sgyy = fmaf(dc, fmaf(dc, Sg, 2.f * Sgm), Sgmm);
     // v: Sg, Sgx, Sgy, Sgxx, Sgxy, Sgyy, w*dL/dr, w*dL/dg, w*dL/db, w*dL/dD
-    float v[10] = {Sg, dx * Sg, Sgy, dx * dx * Sg, dx * Sgy, Sgyy, Sr, Sgc, Sb, Sd};
-#pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      if (!HAS_D && q == 9) continue;
-      v[q] = row16_sum(v[q]);
+    // This column's share of the primitive's gradient line (the 2D-mean,
+    // conic and opacity entries are linear in the moments, so they are formed
+    // before the row sum): dL/du, dL/dv, dL/dconic (3), dL/d(opacity p),
+    // dL/drgb (3), dL/dz.
+    float q[10];
+    {
+      const bool live = e2 < count;
+      const float4 pa = s_a[j2], pb = s_b[j2];
+      const float k0 = live ? pa.z * (-2.f / kLog2e) : 0.f, k1 = live ? pa.w * (-1.f / kLog2e) : 0.f;
+      const float k2 = live ? pb.x * (-2.f / kLog2e) : 0.f;
+      const float iop = live ? __builtin_amdgcn_exp2f(-pb.y) : 0.f;
+      const float Sgx = dx * Sg, Sgxy = dx * Sgy;
+      q[0] = fmaf(k0, Sgx, k1 * Sgy);
+      q[1] = fmaf(k1, Sgx, k2 * Sgy);
+      q[2] = -0.5f * dx * Sgx;
+      q[3] = -Sgxy;
+      q[4] = -0.5f * Sgyy;
+      q[5] = Sg * iop;
+      q[6] = Sr;
+      q[7] = Sgc;
+      q[8] = Sb;
+      q[9] = HAS_D ? Sd : 0.f;
     }
+    int slot_q;
+    const float val = row16_reduce_scatter10(q, c2, slot_q);
     // the record blended in this tile: flag it in the gradient line's last
     // float (the same 1 from every tile, so plain stores suffice)
     if (mark_blended && c2 == 15 && e2 < count &&
         (((s_act[0] | s_act[1] | s_act[2] | s_act[3]) >> j2) & 1u))
       grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.f;
-    // lanes c2 < 10 of the primitive's row each add one value of its
-    // gradient line, so a wave's atomics for a primitive share one line
-    if (e2 < count) {
-      bool nz = false;
-#pragma unroll
-      for (int q = 0; q < 10; ++q) nz |= (v[q] != 0.f);
-      const int nvals = HAS_D ? 10 : 9;
-      if (nz && c2 < nvals) {
-        const uint32_t d = s_d[j2];
-        const float k0 = s_a[j2].z * (-2.f / kLog2e), k1 = s_a[j2].w * (-1.f / kLog2e);
-        const float k2 = s_b[j2].x * (-2.f / kLog2e);
-        const float opac = __builtin_amdgcn_exp2f(s_b[j2].y);
-        float val = k0 * v[1] + k1 * v[2];
-        val = c2 == 1 ? k1 * v[1] + k2 * v[2] : val;
-        val = c2 == 2 ? -0.5f * v[3] : val;
-        val = c2 == 3 ? -v[4] : val;
-        val = c2 == 4 ? -0.5f * v[5] : val;
-        val = c2 == 5 ? v[0] / opac : val;
-        val = c2 == 6 ? v[6] : val;
-        val = c2 == 7 ? v[7] : val;
-        val = c2 == 8 ? v[8] : val;
-        if (HAS_D) val = c2 == 9 ? v[9] : val;
-        unsafeAtomicAdd(grad2d + (size_t)d * kGrad2dStride + c2, val);
-      }
-    }
+    // ten lanes of the primitive's row each add one value of its gradient
+    // line, so a wave's atomics for a primitive share one 64-byte line
+    if (e2 < count && slot_q >= 0 && val != 0.f)
+      unsafeAtomicAdd(grad2d + (size_t)s_d[j2] * kGrad2dStride + slot_q, val);
   }
 }
 
