@@ -60,7 +60,7 @@ struct g4d_ctx {
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
-  DevBuf bwd_scratch, okey, oval, okey2, oval2;
+  DevBuf bwd_scratch, okey, oval, okey2, oval2, cdir;
   uint32_t* counters_h = nullptr;  // pinned
 
   // stage timing (HIP events on the context's stream)
@@ -243,6 +243,7 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
   if ((st = ensure(c, c->dkey, 4 * vn))) return st;
   if ((st = ensure(c, c->slot, 4 * vn))) return st;
   if ((st = ensure(c, c->rec, sizeof(Record) * vn))) return st;
+  if ((st = ensure(c, c->cdir, sizeof(float4) * vn))) return st;
   if ((st = ensure(c, c->ckey, 4 * vn))) return st;
   if ((st = ensure(c, c->cval, 4 * vn))) return st;
   if ((st = ensure(c, c->ckey2, 4 * vn))) return st;
@@ -259,7 +260,8 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
   launch_fill_u32(cnt, 4, 0u, s);
   // 1. per (view, primitive): cull, slice, project, colour
   stage_begin(c);
-  launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot), s);
+  launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot),
+                    P<float4>(c->cdir), s);
   stage_end(c, G4D_STAGE_PREPROCESS);
   // 2. compaction of active records
   stage_begin(c);
@@ -451,7 +453,7 @@ g4d_status g4d_destroy(g4d_ctx* c) {
   DevBuf* bufs[] = {&c->views_d, &c->act, &c->pos, &c->dkey, &c->rec, &c->slot, &c->ckey, &c->cval, &c->ckey2,
                     &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
                     &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
-                    &c->counters, &c->bwd_scratch, &c->okey, &c->oval, &c->okey2, &c->oval2};
+                    &c->counters, &c->bwd_scratch, &c->okey, &c->oval, &c->okey2, &c->oval2, &c->cdir};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->counters_h) (void)hipHostFree(c->counters_h);

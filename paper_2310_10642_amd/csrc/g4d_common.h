@@ -70,8 +70,9 @@ struct DensifyStats {
 };
 
 // ---- launchers (preprocess.hip) ----
+// cdir: per (view, primitive) scratch [n_views * n] of (view direction, t - mu_t).
 void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
-                       hipStream_t s);
+                       float4* cdir, hipStream_t s);
 // ---- launchers (preprocess_bwd.hip) ----
 size_t preprocess_backward_scratch_floats(size_t n_records);
 void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const float* grad2d,

@@ -15,7 +15,7 @@ using namespace shade;
 
 __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __restrict__ act,
                                                     uint32_t* __restrict__ dkey, Record* __restrict__ rec,
-                                                    int32_t* __restrict__ slot) {
+                                                    int32_t* __restrict__ slot, float4* __restrict__ cdir) {
   const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (gidx >= p.n) return;
   const float4 mu = p.means4[gidx];
@@ -26,9 +26,6 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
   const float opa = 1.f / (1.f + __expf(-p.opacity_logit[gidx]));
   Shape4 sh;
   build_shape(ql, qr, ls, sh);
-  const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
-  const int K = (p.t_order + 1) * nb;
-  const float* kc = p.coeffs + (size_t)gidx * K * 3;
 
   for (int vi = 0; vi < p.n_views; ++vi) {
     const size_t idx = (size_t)vi * p.n + gidx;
@@ -92,25 +89,9 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
       slot[idx] = -1;
       continue;
     }
-    // 4D spherindrical harmonics colour
-    float Y[16], cs[3];
-    sh_eval(p.sh_degree, g.dir[0], g.dir[1], g.dir[2], Y);
-    const int nt = fourier_terms(p.t_order, g.dt, p.t_period, cs);
-    float col[3] = {0.f, 0.f, 0.f};
-    for (int n = 0; n < nt; ++n) {
-      float acc[3] = {0.f, 0.f, 0.f};
-      const float* kn = kc + (size_t)n * nb * 3;
-      for (int lm = 0; lm < nb; ++lm) {
-        acc[0] = fmaf(kn[3 * lm + 0], Y[lm], acc[0]);
-        acc[1] = fmaf(kn[3 * lm + 1], Y[lm], acc[1]);
-        acc[2] = fmaf(kn[3 * lm + 2], Y[lm], acc[2]);
-      }
-      col[0] = fmaf(cs[n], acc[0], col[0]);
-      col[1] = fmaf(cs[n], acc[1], col[1]);
-      col[2] = fmaf(cs[n], acc[2], col[2]);
-    }
-    r.c = make_float4(fmaxf(col[0] + kColorOffset, 0.f), fmaxf(col[1] + kColorOffset, 0.f),
-                      fmaxf(col[2] + kColorOffset, 0.f), __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
+    // colour: k_colour fills c.xyz from the view direction and t - mu_t
+    r.c = make_float4(0.f, 0.f, 0.f, __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
+    cdir[idx] = make_float4(g.dir[0], g.dir[1], g.dir[2], g.dt);
     rec[idx] = r;
     act[idx] = 1u;
     dkey[idx] = __float_as_uint(g.pc[2]);  // z > near > 0: bit order = numeric order
@@ -118,13 +99,66 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
   }
 }
 
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xF, 0xF, false));  // row_ror:2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xF, 0xF, false));  // row_ror:1
+  return v;
+}
+
+// 4D spherindrical-harmonic colour (Sec. 3.2): 16 lanes per primitive, one
+// per SH basis function l^2 + l + m, so the coefficients [K][3] are read once
+// and coalesced; per active view each lane weights its basis value by the
+// Fourier terms, and a 16-lane sum gives c = max(0, 0.5 + sum).
+__global__ void __launch_bounds__(256) k_colour(RenderParams p, const uint32_t* __restrict__ act,
+                                                const float4* __restrict__ cdir, Record* __restrict__ rec) {
+  const int gidx = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
+  const int lm = threadIdx.x & 15;
+  if (gidx >= p.n) return;  // uniform per 16-lane group
+  const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
+  const int nt = p.t_order + 1;
+  const bool lane_on = lm < nb;
+  const float* kc = p.coeffs + (size_t)gidx * nt * nb * 3;
+  float k[3][3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k[n][c] = (lane_on && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+  for (int vi = 0; vi < p.n_views; ++vi) {
+    const size_t idx = (size_t)vi * p.n + gidx;
+    if (!act[idx]) continue;  // uniform per group
+    const float4 cd = cdir[idx];
+    float Y[16], cs[3] = {0.f, 0.f, 0.f};
+    sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
+    fourier_terms(p.t_order, cd.w, p.t_period, cs);
+    float ylm = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ylm = (i == lm) ? Y[i] : ylm;
+    if (!lane_on) ylm = 0.f;
+    float col[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      col[c] = row16_sum(ylm * fmaf(cs[0], k[0][c], fmaf(cs[1], k[1][c], cs[2] * k[2][c])));
+    if (lm == 0) {
+      float* o = reinterpret_cast<float*>(&rec[idx].c);
+      o[0] = fmaxf(col[0] + kColorOffset, 0.f);
+      o[1] = fmaxf(col[1] + kColorOffset, 0.f);
+      o[2] = fmaxf(col[2] + kColorOffset, 0.f);
+    }
+  }
+}
+
 }  // namespace
 
 void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
-                       hipStream_t s) {
+                       float4* cdir, hipStream_t s) {
   if (p.n == 0) return;
   const int bs = 256;
-  hipLaunchKernelGGL(k_preprocess, dim3((p.n + bs - 1) / bs), dim3(bs), 0, s, p, act, dkey, rec, slot);
+  hipLaunchKernelGGL(k_preprocess, dim3((p.n + bs - 1) / bs), dim3(bs), 0, s, p, act, dkey, rec, slot, cdir);
+  if (!p.flow)
+    hipLaunchKernelGGL(k_colour, dim3((unsigned)(((size_t)p.n * 16 + 255) / 256)), dim3(256), 0, s, p, act, cdir,
+                       rec);
 }
 
 }  // namespace g4d
