@@ -192,12 +192,7 @@ __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_
     for (int i = 0; i < 16; ++i) ylm = (i == lm) ? Y[i] : ylm;
     if (!lane_on) ylm = 0.f;
     float cs[3], sn[3];
-    const float ph = 2.f * dt / p.t_period;
-#pragma unroll
-    for (int n = 0; n < 3; ++n) {
-      cs[n] = (n == 0) ? 1.f : (n < nt ? cospif(n * ph) : 0.f);
-      sn[n] = (n == 0) ? 0.f : (n < nt ? sinpif(n * ph) : 0.f);
-    }
+    fourier_terms(p.t_order, dt, p.t_period, cs, sn);
     // kd_n = sum_ch graw_ch k[n][lm][ch]
     float kd[3], gy = 0.f;
 #pragma unroll

@@ -217,11 +217,20 @@ __device__ __forceinline__ bool view_geometry(const float4 mu, const Shape4& sh,
   return true;
 }
 
-__device__ __forceinline__ int fourier_terms(int t_order, float dt, float period, float* cs) {
+// cos(2 pi n dt / T) and sin(2 pi n dt / T) for n = 0..t_order (<= 2): one
+// sincospi, the second order by the double-angle identities.
+__device__ __forceinline__ int fourier_terms(int t_order, float dt, float period, float* cs, float* sn = nullptr) {
   const float ph = 2.f * dt / period;  // cos(2 pi n dt / T) = cospi(n * ph)
-#pragma unroll
-  for (int n = 0; n <= 2; ++n)
-    if (n <= t_order) cs[n] = (n == 0) ? 1.f : cospif(n * ph);
+  float s1 = 0.f, c1 = 1.f;
+  if (t_order >= 1) sincospif(ph, &s1, &c1);
+  cs[0] = 1.f;
+  cs[1] = t_order >= 1 ? c1 : 0.f;
+  cs[2] = t_order >= 2 ? fmaf(2.f * c1, c1, -1.f) : 0.f;
+  if (sn) {
+    sn[0] = 0.f;
+    sn[1] = t_order >= 1 ? s1 : 0.f;
+    sn[2] = t_order >= 2 ? 2.f * s1 * c1 : 0.f;
+  }
   return t_order + 1;
 }
 
