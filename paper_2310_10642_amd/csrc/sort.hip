@@ -396,7 +396,11 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
     const uint32_t k = i - offs[lo];
     const uint32_t rx = s_rx[lo], ry = s_ry[lo];
     const uint32_t x0 = rx & 0xFFFFu, w = (rx >> 16) - x0, y0 = ry & 0xFFFFu;
-    const uint32_t ty = y0 + k / w, tx = x0 + k % w;
+    // k / w through a float reciprocal, corrected to the exact quotient
+    uint32_t q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
+    q -= (q * w > k) ? 1u : 0u;
+    q += ((q + 1u) * w <= k) ? 1u : 0u;
+    const uint32_t ty = y0 + q, tx = x0 + (k - q * w);
     ikey[i] = s_tb[lo] + ty * s_tw[lo] + tx;
     ival[i] = d0 + (uint32_t)lo;
   }
