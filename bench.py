@@ -291,6 +291,19 @@ def main():
         r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
     best = min(sec, graph_sec) if graph_sec else sec
 
+    # the fused Adam step over every parameter group (outside the headline step)
+    m_buf = torch.zeros(sc.n * (17 + 3 * sc.coeffs.shape[1]), device=dev)
+    v_buf = torch.zeros_like(m_buf)
+    adam_state = {"step": 0}
+    lr = [1.6e-4, 5e-3, 1e-3, 1e-3, 5e-2, 2.5e-3]
+
+    def adam():
+        adam_state["step"] += 1
+        r.adam_step(params, grads, m_buf, v_buf, adam_state["step"], lr)
+    adam_sec = timed(adam, max(3, args.steps // 2), 2)
+    adam_bytes = 28 * m_buf.numel()           # read p, g, m, v; write p, m, v (4 B each)
+    log(f"[bench] adam step {adam_sec * 1e3:.3f} ms, {adam_bytes / adam_sec / 1e9:.0f} GB/s")
+
     fwd_b = timed(forward_batched, max(3, args.steps // 2), 2)
     extra = {}
     if not args.no_per_view:
@@ -359,6 +372,7 @@ def main():
         "forward_mpix_per_s": P_total / fwd_b / 1e6,
         **extra,
         "stage_ms_per_step": {k: ms / args.steps for k, (ms, n) in stages.items()},
+        "adam_step_ms": adam_sec * 1e3, "adam_step_gb_per_s": adam_bytes / adam_sec / 1e9,
         "active_per_view": stats["active_per_view"], "instances": stats["instances"],
         "fragments": frag, "max_tile_list": stats["max_tile_list"],
         "roofline": roof,

@@ -171,6 +171,34 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const float* dL_drgb, const float* 
 g4d_status g4d_set_densify_stats(g4d_ctx* ctx, float* uv_grad_norm_sum, float* t_grad_abs_sum,
                                  int32_t* blend_count);
 
+/* One Adam step over the six parameter groups, in one launch (Sec. 4.2: the
+ * optimiser settings of 3D Gaussian Splatting, i.e. Adam with a learning rate
+ * per group):
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   p -= lr_g (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ *   params      host [6] of device pointers, updated in place: means4,
+ *               log_scales4, q_left, q_right, opacity_logit, coeffs of n
+ *               primitives (layouts of set_primitives; K from the options)
+ *   grads       host [6] of device pointers, same layouts (render_backward's)
+ *   exp_avg, exp_avg_sq  device [n (17 + 3K)] each: the groups' moments one
+ *               group after the other in that order; zero them before step 1
+ *   step        1, 2, ... (bias correction) */
+typedef struct {
+  float lr[6];
+  float beta1, beta2, eps;
+} g4d_adam_options;
+g4d_status g4d_adam_step(g4d_ctx* ctx, int64_t n, const g4d_adam_options* opts, int64_t step,
+                         float* const* params, const float* const* grads, float* exp_avg, float* exp_avg_sq);
+
+/* New 4D positions for splitting primitives (Sec. 3.3 "Densification in
+ * spacetime", Sec. 4.4: samples of the primitive's complete 4D Gaussian):
+ *   out_means4[k] = mu_i + R_i S_i z[k],  i = idx[k]
+ * over the primitives of set_primitives (R = L(q_l) R(q_r), S = exp(log
+ * scales)); z [count][4] are the caller's standard-normal draws. Device
+ * arrays: idx [count] int32, z and out_means4 [count][4] (16-byte aligned).
+ * An idx outside [0, n) reads nothing and gives a NaN row. */
+g4d_status g4d_split_sample(g4d_ctx* ctx, int64_t count, const int32_t* idx, const float* z, float* out_means4);
+
 /* Image loss and its gradient dL/dI (Sec. 3.3: optimisation is supervised by
  * a rendering loss only), on the context's stream: over n values,
  *   G4D_LOSS_L1: loss += scale * sum |img - target|,  grad = scale * sign(img - target)

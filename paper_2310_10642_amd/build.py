@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libg4d.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "preprocess.hip", "preprocess_bwd.hip", "sort.hip", "raster.hip", "loss.hip", "util.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "preprocess_bwd.hip", "sort.hip", "raster.hip", "loss.hip", "util.hip", "optim.hip"]
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions in device code

@@ -710,6 +710,50 @@ g4d_status g4d_set_densify_stats(g4d_ctx* c, float* uv_grad_norm_sum, float* t_g
   return G4D_OK;
 }
 
+g4d_status g4d_adam_step(g4d_ctx* c, int64_t n, const g4d_adam_options* o, int64_t step, float* const* params,
+                         const float* const* grads, float* exp_avg, float* exp_avg_sq) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (!o || !params || !grads) return fail(c, G4D_EINVAL, "null options or pointer table");
+  if (n < 0 || step < 1) return fail(c, G4D_EINVAL, "n must be >= 0 and step >= 1");
+  if (!(o->beta1 >= 0.f && o->beta1 < 1.f && o->beta2 >= 0.f && o->beta2 < 1.f && o->eps > 0.f &&
+        std::isfinite(o->eps)))
+    return fail(c, G4D_EINVAL, "need 0 <= beta < 1 and a finite eps > 0");
+  const int64_t K3 = 3ll * (c->opts.t_order + 1) * (c->opts.sh_degree + 1) * (c->opts.sh_degree + 1);
+  const int64_t width[kAdamGroups] = {4, 4, 4, 4, 1, K3};
+  AdamGroups a{};
+  uint64_t end = 0;
+  for (int g = 0; g < kAdamGroups; ++g) {
+    if (!std::isfinite(o->lr[g])) return fail(c, G4D_EINVAL, "non-finite learning rate");
+    if (n > 0 && (!params[g] || !grads[g])) return fail(c, G4D_EINVAL, "null parameter or gradient pointer");
+    a.param[g] = params[g];
+    a.grad[g] = grads[g];
+    a.lr[g] = o->lr[g];
+    end += (uint64_t)n * (uint64_t)width[g];
+    a.end[g] = end;
+  }
+  if (n > 0 && (!exp_avg || !exp_avg_sq)) return fail(c, G4D_EINVAL, "null moment buffer");
+  const double bc1 = 1.0 - std::pow((double)o->beta1, (double)step);
+  const double bc2 = 1.0 - std::pow((double)o->beta2, (double)step);
+  if (!(bc1 > 0.0) || !(bc2 > 0.0)) return fail(c, G4D_EINVAL, "bias corrections vanish (beta = 0 and step 0?)");
+  launch_adam(a, o->beta1, o->beta2, o->eps, (float)bc1, (float)bc2, exp_avg, exp_avg_sq, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status g4d_split_sample(g4d_ctx* c, int64_t count, const int32_t* idx, const float* z, float* out_means4) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
+  if (count < 0) return fail(c, G4D_EINVAL, "count must be >= 0");
+  if (count > 0 && (!idx || !z || !out_means4)) return fail(c, G4D_EINVAL, "null pointer");
+  if (count > 0 && (!aligned16(z) || !aligned16(out_means4)))
+    return fail(c, G4D_EINVAL, "z and out_means4 must be 16-byte aligned");
+  launch_split_sample(make_params(c, 0), (uint64_t)count, idx, z, out_means4, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return G4D_OK;
+}
+
 g4d_status g4d_image_loss(g4d_ctx* c, int32_t kind, int64_t n, const float* img, const float* target, float scale,
                           float* loss_out, float* grad_out) {
   if (!c) return G4D_EINVAL;

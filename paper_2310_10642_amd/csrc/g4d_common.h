@@ -127,6 +127,21 @@ void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStr
 void launch_tile_order(const uint2* ranges, uint32_t tiles, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                        uint32_t* vals_alt, int sort_blocks, uint32_t* scratch, hipStream_t s);
 
+// ---- launchers (optim.hip) ----
+constexpr int kAdamGroups = 6;
+struct AdamGroups {
+  float* param[kAdamGroups];
+  const float* grad[kAdamGroups];
+  uint64_t end[kAdamGroups];  // cumulative element counts
+  float lr[kAdamGroups];
+};
+// bc1 = 1 - beta1^step, bc2 = 1 - beta2^step; m, v: [end[5]] moment buffers.
+void launch_adam(const AdamGroups& a, float b1, float b2, float eps, float bc1, float bc2, float* m, float* v,
+                 hipStream_t s);
+// out[k] = mu_i + R_i S_i z[k], i = idx[k]; NaN rows for i outside [0, n).
+void launch_split_sample(const RenderParams& p, uint64_t count, const int32_t* idx, const float* z, float* out,
+                         hipStream_t s);
+
 // ---- launchers (util.hip) ----
 // Views reach the device through kernel arguments, never a host copy.
 void launch_set_views(const ViewDev* host, int n, ViewDev* dev, hipStream_t s);

@@ -27,7 +27,7 @@ DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_la
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
             "g4d_render", "g4d_render_flow", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
-            "g4d_get_tuning", "g4d_set_densify_stats", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
+            "g4d_get_tuning", "g4d_set_densify_stats", "g4d_adam_step", "g4d_split_sample", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
 
 
 class G4DOptions(ctypes.Structure):
@@ -80,6 +80,9 @@ def load_library(path: str = LIB_PATH):
     lib.g4d_set_tuning.argtypes = [vp, i32, i32]
     lib.g4d_get_tuning.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.g4d_set_densify_stats.argtypes = [vp, fp, fp, vp]
+    lib.g4d_adam_step.argtypes = [vp, i64, ctypes.POINTER(G4DAdamOptions), i64, ctypes.POINTER(vp),
+                                  ctypes.POINTER(vp), fp, fp]
+    lib.g4d_split_sample.argtypes = [vp, i64, vp, fp, fp]
     lib.g4d_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.g4d_last_error.argtypes = [vp]
     lib.g4d_last_error.restype = ctypes.c_char_p
@@ -109,6 +112,11 @@ def to_camera(cam) -> G4DCamera:
     for i in range(3):
         c.center[i] = float(ctr[i])
     return c
+
+
+class G4DAdamOptions(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
 
 
 class Renderer:
@@ -263,6 +271,36 @@ class Renderer:
                 raise ValueError("densify accumulators: contiguous GPU float32, float32, int32 tensors of n values")
         self._densify = ts  # keep alive
         self._check(self.lib.g4d_set_densify_stats(self.ctx, *[_ptr(t) for t in ts]))
+
+    def adam_step(self, params: Sequence[torch.Tensor], grads: Sequence[torch.Tensor], exp_avg: torch.Tensor,
+                  exp_avg_sq: torch.Tensor, step: int, lr: Sequence[float], betas=(0.9, 0.999), eps: float = 1e-15):
+        """One fused Adam step over the six groups (updated in place); the
+        moment buffers hold n (17 + 3K) floats each, group after group."""
+        self._stream()
+        n = int(params[0].shape[0])
+        for t in (*params, *grads, exp_avg, exp_avg_sq):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise ValueError("adam_step tensors must be contiguous float32 on the GPU")
+        if exp_avg.numel() != n * (17 + 3 * self.n_coeffs) or exp_avg_sq.numel() != exp_avg.numel():
+            raise ValueError("moment buffers must hold n (17 + 3K) floats")
+        o = G4DAdamOptions()
+        for i in range(6):
+            o.lr[i] = float(lr[i])
+        o.beta1, o.beta2, o.eps = float(betas[0]), float(betas[1]), float(eps)
+        P = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in params])
+        G = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in grads])
+        self._check(self.lib.g4d_adam_step(self.ctx, n, ctypes.byref(o), int(step), P, G, _ptr(exp_avg),
+                                           _ptr(exp_avg_sq)))
+
+    def split_sample(self, idx: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
+        """New 4D positions mu_i + R_i S_i z_k for i = idx[k] (int32 [K], z [K, 4])."""
+        self._stream()
+        if not (idx.is_cuda and idx.dtype == torch.int32 and z.is_cuda and z.dtype == torch.float32
+                and z.is_contiguous() and idx.is_contiguous() and z.shape == (idx.numel(), 4)):
+            raise ValueError("split_sample needs int32 idx [K] and float32 z [K, 4] on the GPU")
+        out = torch.empty_like(z)
+        self._check(self.lib.g4d_split_sample(self.ctx, idx.numel(), _ptr(idx), _ptr(z), _ptr(out)))
+        return out
 
     def image_loss(self, kind: int, img: torch.Tensor, target: torch.Tensor, scale: float,
                    loss_out: torch.Tensor, grad_out: torch.Tensor):

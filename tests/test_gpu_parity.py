@@ -690,3 +690,58 @@ def test_stage_timing_and_stats():
     assert s["n_views"] == 2 and sum(s["active_per_view"]) == s["active_total"] > 0
     last = r.debug("pix_last").astype(np.int64)
     assert s["fragments"] == int(last.sum())
+
+
+def test_adam_step_matches_oracle():
+    """Three fused Adam steps over all six groups against the FP64 oracle."""
+    _say("[adam step]")
+    from oracle import optim as OP
+    sc = scenegen.random_scene(35, 3000, sh_degree=3, t_order=2)
+    r, params = PT.gpu_setup(sc)
+    n, K = sc.n, sc.coeffs.shape[1]
+    rng = np.random.default_rng(36)
+    shapes = dict(means4=(n, 4), log_scales4=(n, 4), q_left=(n, 4), q_right=(n, 4), opacity_logit=(n,),
+                  coeffs=(n, K, 3))
+    lr = [1.6e-4, 5e-3, 1e-3, 1e-3, 5e-2, 2.5e-3]
+    p_o = {g: getattr(sc, g).astype(np.float64) for g in OP.GROUPS}
+    m_o = {g: np.zeros(shapes[g]) for g in OP.GROUPS}
+    v_o = {g: np.zeros(shapes[g]) for g in OP.GROUPS}
+    m = torch.zeros(n * (17 + 3 * K), device="cuda")
+    v = torch.zeros_like(m)
+    for step in (1, 2, 3):
+        grads = {g: rng.normal(size=shapes[g]).astype(np.float32) for g in OP.GROUPS}
+        r.adam_step(params, [torch.from_numpy(grads[g]).cuda() for g in OP.GROUPS], m, v, step, lr, eps=1e-8)
+        # the oracle takes the float32 values the library receives
+        f32 = lambda x: float(np.float32(x))
+        p_o, m_o, v_o = OP.adam_step(p_o, grads, m_o, v_o, step, [f32(x) for x in lr], f32(0.9), f32(0.999),
+                                     f32(1e-8))
+    torch.cuda.synchronize()
+    # FP32 forms each update lr (m / bc1) / (sqrt(v / bc2) + eps) to ~1e-6 of
+    # its size (|u| <~ 3 over the first steps): three steps move p by at most
+    # ~1e-5 lr beyond the rounding of p itself
+    for gi, (g, t) in enumerate(zip(OP.GROUPS, params)):
+        assert np.allclose(_np(t), p_o[g], rtol=2e-6, atol=1e-5 * lr[gi]), g
+    off = 0
+    for g in OP.GROUPS:
+        cnt = int(np.prod(shapes[g]))
+        assert np.allclose(_np(m)[off:off + cnt], m_o[g].reshape(-1), rtol=1e-5, atol=1e-7), g
+        assert np.allclose(_np(v)[off:off + cnt], v_o[g].reshape(-1), rtol=1e-5, atol=1e-9), g
+        off += cnt
+
+
+def test_split_sample_matches_oracle():
+    """mu + R S z for random primitives and draws; an index outside [0, n)
+    gives a NaN row and reads nothing."""
+    _say("[split sample]")
+    from oracle import optim as OP
+    sc = scenegen.random_scene(37, 500)
+    r, _ = PT.gpu_setup(sc)
+    rng = np.random.default_rng(38)
+    idx = rng.integers(0, sc.n, 2000).astype(np.int32)
+    idx[7] = sc.n                                   # not a primitive
+    z = rng.normal(size=(2000, 4)).astype(np.float32)
+    out = _np(r.split_sample(torch.from_numpy(idx).cuda(), torch.from_numpy(z).cuda()))
+    ok = np.arange(2000) != 7
+    ref = OP.split_sample(sc, idx[ok], z[ok])
+    assert np.isnan(out[7]).all()
+    assert np.allclose(out[ok], ref, rtol=1e-5, atol=1e-6)
