@@ -77,6 +77,32 @@ __device__ __forceinline__ uint32_t quadrant_mask(const Record& r, float log2_op
   return m;
 }
 
+// stage_record written to LDS in pieces that are whole registers of the loaded
+// record (the empty asm statements keep the pieces from being merged into
+// wider writes), so a record loaded a batch ahead needs no repacking moves,
+// which would wait for the load right after issuing it. Returns the quadrant
+// mask.
+__device__ __forceinline__ uint32_t stage_split(const Record& r, float4* sa, float4* sb, float4* sc, float tile_x0,
+                                                float tile_y0) {
+  const float l2o = __log2f(r.a.w);
+  float2* pa = reinterpret_cast<float2*>(sa);
+  pa[0] = make_float2(r.a.x, r.a.y);
+  asm volatile("" ::: "memory");
+  pa[1] = make_float2(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y);
+  float* pb = reinterpret_cast<float*>(sb);
+  pb[0] = -0.5f * kLog2e * r.b.z;
+  pb[1] = l2o;
+  asm volatile("" ::: "memory");
+  pb[2] = r.a.z;
+  asm volatile("" ::: "memory");
+  pb[3] = 0.f;
+  float* pc = reinterpret_cast<float*>(sc);
+  pc[0] = r.c.x;
+  pc[1] = r.c.y;
+  pc[2] = r.c.z;
+  return quadrant_mask(r, l2o, tile_x0, tile_y0);
+}
+
 __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int tile) {
   int lo = 0, hi = n_views - 1;
   while (lo < hi) {
@@ -214,9 +240,9 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
     const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d, bool mark_blended) {
-  __shared__ float4 s_a[kBwdBatch], s_b[kBwdBatch], s_c[kBwdBatch];
-  __shared__ uint32_t s_d[kBwdBatch];
-  __shared__ uint32_t s_qm[kBwdBatch];
+  __shared__ float4 s_a2[2][kBwdBatch], s_b2[2][kBwdBatch], s_c2[2][kBwdBatch];
+  __shared__ uint32_t s_d2[2][kBwdBatch];
+  __shared__ uint32_t s_qm2[2][kBwdBatch];
   __shared__ uint32_t s_act[4];  // per quadrant: bit j when entry j blended somewhere in it
   __shared__ float s_g[kBwdBatch * kGwStride];   // dL/dpower per (primitive, pixel)
   __shared__ float s_w[kBwdBatch * kGwStride];   // a_i T_i per (primitive, pixel)
@@ -269,33 +295,40 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   const int j2 = threadIdx.x >> 4;  // phase 2: primitive within the batch
   const int c2 = threadIdx.x & 15;  // phase 2: pixel column
   const int b_first = ((max_last + kBwdBatch - 1) / kBwdBatch - 1) * kBwdBatch;
-  // records of the next batch are loaded one batch ahead (threads < 16)
+  // Staging pipeline (threads < 16): the record of the batch after the one in
+  // LDS and the list index of the batch after that are in flight, so no wait
+  // covers a load issued in the same batch.
   Record nxt;
-  uint32_t nxt_d = 0;
-  if (threadIdx.x < kBwdBatch && b_first >= 0 && b_first + (int)threadIdx.x < count) {
-    nxt_d = ival[rg.x + b_first + threadIdx.x];
-    nxt = recs[nxt_d];
-  }
-  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch) {
-    __syncthreads();
-    if (threadIdx.x < kBwdBatch) {
-      uint32_t qm = 0u;
-      if (b0 + (int)threadIdx.x < count) {
-        float4 sa, sb, sc;
-        stage_record(nxt, sa, sb, sc);
-        s_a[threadIdx.x] = sa;
-        s_b[threadIdx.x] = sb;
-        s_c[threadIdx.x] = sc;
-        s_d[threadIdx.x] = nxt_d;
-        qm = quadrant_mask(nxt, sb.y, tile_x0, tile_y0);
-      }
-      s_qm[threadIdx.x] = qm;
-      const int en = b0 - kBwdBatch + (int)threadIdx.x;
-      if (en >= 0) {  // prefetch the next (earlier) batch
-        nxt_d = ival[rg.x + en];
-        nxt = recs[nxt_d];
-      }
+  uint32_t nxt_d = 0, nn_d = 0;
+  auto stage = [&](int e0, int bb) {
+    uint32_t qm = 0u;
+    if (e0 + (int)threadIdx.x < count) {
+      qm = stage_split(nxt, &s_a2[bb][threadIdx.x], &s_b2[bb][threadIdx.x], &s_c2[bb][threadIdx.x], tile_x0, tile_y0);
+      s_d2[bb][threadIdx.x] = nxt_d;
     }
+    s_qm2[bb][threadIdx.x] = qm;
+  };
+  if (threadIdx.x < kBwdBatch && b_first >= 0) {
+    if (b_first + (int)threadIdx.x < count) {
+      nxt_d = ival[rg.x + b_first + threadIdx.x];
+      nxt = recs[nxt_d];
+    }
+    stage(b_first, 0);
+    const int e1 = b_first - kBwdBatch + (int)threadIdx.x;
+    if (e1 >= 0) {
+      nxt_d = ival[rg.x + e1];
+      nxt = recs[nxt_d];
+    }
+    const int e2n = e1 - kBwdBatch;
+    if (e2n >= 0) nn_d = ival[rg.x + e2n];
+  }
+  int buf = 0;
+  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1) {
+    const float4* s_a = s_a2[buf];
+    const float4* s_b = s_b2[buf];
+    const float4* s_c = s_c2[buf];
+    const uint32_t* s_d = s_d2[buf];
+    const uint32_t* s_qm = s_qm2[buf];
     __syncthreads();
     // ---- phase 1: this lane's pixel, back to front over the batch ----
     // entries that can reach this wave's quadrant before its last contributor
@@ -396,10 +429,23 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     if (mark_blended && c2 == 15 && e2 < count &&
         (((s_act[0] | s_act[1] | s_act[2] | s_act[3]) >> j2) & 1u))
       grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.f;
+    const uint32_t d_atom = s_d[j2];
+    // stage the next batch into the other buffer (read by nobody until the
+    // next loop-top barrier) and advance the loads, before this batch's atomics
+    if (threadIdx.x < kBwdBatch && b0 >= kBwdBatch) {
+      stage(b0 - kBwdBatch, buf ^ 1);
+      const int e1 = b0 - 2 * kBwdBatch + (int)threadIdx.x;
+      if (e1 >= 0) {
+        nxt_d = nn_d;
+        nxt = recs[nxt_d];
+      }
+      const int e2n = e1 - kBwdBatch;
+      if (e2n >= 0) nn_d = ival[rg.x + e2n];
+    }
     // ten lanes of the primitive's row each add one value of its gradient
     // line, so a wave's atomics for a primitive share one 64-byte line
     if (e2 < count && slot_q >= 0 && val != 0.f)
-      unsafeAtomicAdd(grad2d + (size_t)s_d[j2] * kGrad2dStride + slot_q, val);
+      unsafeAtomicAdd(grad2d + (size_t)d_atom * kGrad2dStride + slot_q, val);
   }
 }
 
