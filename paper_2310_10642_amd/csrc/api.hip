@@ -54,6 +54,7 @@ struct g4d_ctx {
   int64_t round_instances = int64_t(1) << 30;
   bool sync_free = false;          // no host read of device counts inside render/backward
   bool heavy_first = true;         // rasterise tiles by decreasing list length
+  bool quad_cull = true;           // waves skip entries whose ellipse misses their quadrant
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
   bool flow_mode = false;          // the render in progress blends flow (Sec. 4.3), not colour
   float flow_dt = 0.f;
@@ -345,7 +346,8 @@ g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, 
   static const float kZero3[3] = {0.f, 0.f, 0.f};
   launch_raster_forward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, r.v1 - r.v0,
                         P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival), P<Record>(c->rec_sorted),
-                        c->flow_mode ? kZero3 : c->opts.bg, c->flow_mode ? 2 : 3, out_rgb, out_depth, out_alpha,
+                        c->flow_mode ? kZero3 : c->opts.bg, c->flow_mode ? 2 : 3, c->quad_cull, out_rgb,
+                        out_depth, out_alpha,
                         P<float>(c->pix_t), P<uint32_t>(c->pix_last), s);
   stage_end(c, G4D_STAGE_RASTER_FWD);
   HIPCHK(c, hipGetLastError());
@@ -684,7 +686,8 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
-                           P<uint32_t>(c->pix_last), P<float>(c->grad2d), c->densify.blend_count != nullptr, s);
+                           P<uint32_t>(c->pix_last), P<float>(c->grad2d), c->densify.blend_count != nullptr,
+                           c->quad_cull, s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
     RenderParams p = make_params(c, nv);
     stage_begin(c);
@@ -848,6 +851,11 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     c->have_render = false;  // the order of the last render's tiles may be missing
     return G4D_OK;
   }
+  if (key == G4D_TUNE_QUADRANT_CULL) {
+    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "quadrant cull is 0 or 1");
+    c->quad_cull = value == 1;
+    return G4D_OK;
+  }
   if (key == G4D_TUNE_SYNC_FREE) {
     if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "sync-free is 0 or 1");
     c->sync_free = value == 1;
@@ -877,6 +885,7 @@ g4d_status g4d_get_tuning(g4d_ctx* c, int32_t key, int32_t* value) {
     case G4D_TUNE_ROUND_PAIRS: *value = clamp32(c->round_pairs); break;
     case G4D_TUNE_ROUND_INSTANCES: *value = clamp32(c->round_instances); break;
     case G4D_TUNE_SYNC_FREE: *value = c->sync_free ? 1 : 0; break;
+    case G4D_TUNE_QUADRANT_CULL: *value = c->quad_cull ? 1 : 0; break;
     case G4D_TUNE_ARENA_INSTANCES: *value = clamp32((int64_t)arena_instances(c)); break;
     case G4D_TUNE_TILE_ORDER: *value = c->heavy_first ? 1 : 0; break;
     case G4D_TUNE_AUTOTUNE: *value = c->autotune_pending ? 1 : 0; break;

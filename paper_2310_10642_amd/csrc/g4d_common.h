@@ -112,15 +112,18 @@ void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, 
 // ---- launchers (raster.hip) ----
 // order (nullable): the tile each workgroup takes, e.g. heaviest lists first.
 // channels: 3 (rgb planes) or 2 (the first two record colour values, e.g. flow).
+// cull: waves walk only the entries whose alpha-floor ellipse meets their
+// quadrant (false: every entry; same results).
 void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                            const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
-                           int channels, float* out_rgb,
+                           int channels, bool cull, float* out_rgb,
                            float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s);
 void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                             const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, float* grad2d, bool mark_blended, hipStream_t s);
+                            const uint32_t* pix_last, float* grad2d, bool mark_blended, bool cull,
+                            hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
 // Tile ids by decreasing list length (stable within ~4.4 % length bins) into vals.

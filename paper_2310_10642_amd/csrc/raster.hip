@@ -38,7 +38,6 @@ constexpr int kBwdBatch = 16;
 // workgroup at <= 40 KB of LDS, i.e. 4 workgroups per CU.
 constexpr int kGwStride = 256 + 16;
 __device__ __forceinline__ int gw_slot(int row, int col) { return 16 * row + (col ^ (((row >> 1) & 1) << 3)); }
-constexpr float kLn2 = 0.69314718055994531f;
 
 // log2 of opacity * exp(power) at offset (dx, dy) from the mean.
 // sa = (u, v, A, B), sb = (C, log2 opacity, ., .) with
@@ -53,45 +52,43 @@ __device__ __forceinline__ void stage_record(const Record& r, float4& sa, float4
   sc = make_float4(r.c.x, r.c.y, r.c.z, 0.f);
 }
 
-// Bit q set when the alpha-floor box of the record can overlap quadrant q of
-// the tile (quadrant q covers pixel centres x0 + 8 (q & 1) + [0.5, 7.5],
-// y0 + 8 (q >> 1) + [0.5, 7.5]).
-__device__ __forceinline__ uint32_t quadrant_mask(const Record& r, float log2_opacity, float tile_x0, float tile_y0) {
-  const float K = (log2_opacity - kLog2AlphaMin) * kLn2;  // ln(255 opacity)
-  if (!(K > -1e-4f)) return 0u;
-  const float c0 = r.b.x, c1 = r.b.y, c2 = r.b.z;
-  // c0 c2 - c1^2 without cancellation error (the c1^2 rounding error is recovered by an FMA)
-  const float p = c1 * c1;
-  const float idet = 1.f / (fmaf(c0, c2, -p) - fmaf(c1, c1, -p));
-  const float Kc = fmaxf(K, 0.f);
-  const float hx = sqrtf(2.f * Kc * c2 * idet) * 1.001f + 0.05f;
-  const float hy = sqrtf(2.f * Kc * c0 * idet) * 1.001f + 0.05f;
-  const float u = r.a.x, v = r.a.y;
-  uint32_t m = 0u;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float xa = tile_x0 + 8.f * (q & 1) + 0.5f, ya = tile_y0 + 8.f * (q >> 1) + 0.5f;
-    const bool hit = (u + hx >= xa) && (u - hx <= xa + 7.f) && (v + hy >= ya) && (v - hy <= ya + 7.f);
-    m |= hit ? (1u << q) : 0u;
-  }
-  return m;
+// Whether the record's alpha-floor ellipse (where opacity * exp(power) reaches
+// 1/255) meets the 8x8 quadrant q of the tile, whose pixel centres span
+// x0 + 8 (q & 1) + [0.5, 7.5], y0 + 8 (q >> 1) + [0.5, 7.5]. In the staged
+// form a fragment counts when log2 opacity - Q(dx, dy) >= log2(1/255), with
+// Q = A dx^2 + 2 B dx dy + C dy^2 (A = -sa.z, 2B = -sa.w, C = -sb.x), a
+// convex quadratic: its minimum over the quadrant is zero when the quadrant
+// holds the centre, else it lies on an edge, where Q is a 1D quadratic
+// minimised at a clamped point. The bound is loosened (0.1 % + 0.01) so
+// rounding never drops a blended pixel.
+__device__ __forceinline__ bool quadrant_hit(const float4& sa, const float4& sb, float tile_x0, float tile_y0, int q) {
+  const float lim = fmaf(sb.y - kLog2AlphaMin, 1.001f, 0.01f);
+  if (!(lim > 0.f)) return false;
+  const float A = -sa.z, B = -0.5f * sa.w, C = -sb.x;
+  const float ex0 = tile_x0 + 8.f * (q & 1) + 0.5f - sa.x, ex1 = ex0 + 7.f;
+  const float ey0 = tile_y0 + 8.f * (q >> 1) + 0.5f - sa.y, ey1 = ey0 + 7.f;
+  if (ex0 <= 0.f && ex1 >= 0.f && ey0 <= 0.f && ey1 >= 0.f) return true;
+  const auto Q = [&](float dx, float dy) { return fmaf(dx, fmaf(A, dx, 2.f * B * dy), C * dy * dy); };
+  const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+  const float ya = __builtin_amdgcn_fmed3f(-B * ex0 * iC, ey0, ey1);
+  const float yb = __builtin_amdgcn_fmed3f(-B * ex1 * iC, ey0, ey1);
+  const float xa = __builtin_amdgcn_fmed3f(-B * ey0 * iA, ex0, ex1);
+  const float xb = __builtin_amdgcn_fmed3f(-B * ey1 * iA, ex0, ex1);
+  return fminf(fminf(Q(ex0, ya), Q(ex1, yb)), fminf(Q(xa, ey0), Q(xb, ey1))) <= lim;
 }
 
 // stage_record written to LDS in pieces that are whole registers of the loaded
 // record (the empty asm statements keep the pieces from being merged into
 // wider writes), so a record loaded a batch ahead needs no repacking moves,
-// which would wait for the load right after issuing it. Returns the quadrant
-// mask.
-__device__ __forceinline__ uint32_t stage_split(const Record& r, float4* sa, float4* sb, float4* sc, float tile_x0,
-                                                float tile_y0) {
-  const float l2o = __log2f(r.a.w);
+// which would wait for the load right after issuing it.
+__device__ __forceinline__ void stage_split(const Record& r, float4* sa, float4* sb, float4* sc) {
   float2* pa = reinterpret_cast<float2*>(sa);
   pa[0] = make_float2(r.a.x, r.a.y);
   asm volatile("" ::: "memory");
   pa[1] = make_float2(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y);
   float* pb = reinterpret_cast<float*>(sb);
   pb[0] = -0.5f * kLog2e * r.b.z;
-  pb[1] = l2o;
+  pb[1] = __log2f(r.a.w);
   asm volatile("" ::: "memory");
   pb[2] = r.a.z;
   asm volatile("" ::: "memory");
@@ -100,7 +97,6 @@ __device__ __forceinline__ uint32_t stage_split(const Record& r, float4* sa, flo
   pc[0] = r.c.x;
   pc[1] = r.c.y;
   pc[2] = r.c.z;
-  return quadrant_mask(r, l2o, tile_x0, tile_y0);
 }
 
 __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int tile) {
@@ -150,7 +146,8 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ ival,
                                                          const Record* __restrict__ recs, float bg0, float bg1,
-                                                         float bg2, int channels, float* __restrict__ out_rgb,
+                                                         float bg2, int channels, bool cull,
+                                                         float* __restrict__ out_rgb,
                                                          float* __restrict__ out_depth, float* __restrict__ out_alpha,
                                                          float* __restrict__ pix_t, uint32_t* __restrict__ pix_last) {
   __shared__ float4 s_a[kFwdBatch], s_b[kFwdBatch], s_c[kFwdBatch];
@@ -183,7 +180,12 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
       s_a[threadIdx.x] = sa;
       s_b[threadIdx.x] = sb;
       s_c[threadIdx.x] = sc;
-      mask = quadrant_mask(r, sb.y, tile_x0, tile_y0);
+      if (cull) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mask |= quadrant_hit(sa, sb, tile_x0, tile_y0, q) ? (1u << q) : 0u;
+      } else {
+        mask = 0xFu;
+      }
     }
     s_mask[threadIdx.x] = (uint8_t)mask;
     __syncthreads();
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const uint32_t* __restrict__ order, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
-    const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d, bool mark_blended) {
+    const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d, bool mark_blended, bool cull) {
   __shared__ float4 s_a2[2][kBwdBatch], s_b2[2][kBwdBatch], s_c2[2][kBwdBatch];
   __shared__ uint32_t s_d2[2][kBwdBatch];
   __shared__ uint32_t s_qm2[2][kBwdBatch];
@@ -300,27 +302,40 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   // covers a load issued in the same batch.
   Record nxt;
   uint32_t nxt_d = 0, nn_d = 0;
+  // Run by the whole of wave 0: lanes < 16 stage entry e0 + lane; then four
+  // lanes per entry test its quadrants on the staged values (taken from the
+  // staging lane by a shuffle) and a ballot gathers the four bits.
   auto stage = [&](int e0, int bb) {
-    uint32_t qm = 0u;
-    if (e0 + (int)threadIdx.x < count) {
-      qm = stage_split(nxt, &s_a2[bb][threadIdx.x], &s_b2[bb][threadIdx.x], &s_c2[bb][threadIdx.x], tile_x0, tile_y0);
-      s_d2[bb][threadIdx.x] = nxt_d;
+    const int t = (int)threadIdx.x;
+    if (t < kBwdBatch && e0 + t < count) {
+      stage_split(nxt, &s_a2[bb][t], &s_b2[bb][t], &s_c2[bb][t]);
+      s_d2[bb][t] = nxt_d;
     }
-    s_qm2[bb][threadIdx.x] = qm;
+    const int src = t >> 2;
+    float4 qa, qb;
+    qa.x = __shfl(nxt.a.x, src, 64);
+    qa.y = __shfl(nxt.a.y, src, 64);
+    qa.z = -0.5f * kLog2e * __shfl(nxt.b.x, src, 64);
+    qa.w = -kLog2e * __shfl(nxt.b.y, src, 64);
+    qb.x = -0.5f * kLog2e * __shfl(nxt.b.z, src, 64);
+    qb.y = __log2f(__shfl(nxt.a.w, src, 64));
+    const bool hit = e0 + src < count && (!cull || quadrant_hit(qa, qb, tile_x0, tile_y0, t & 3));
+    const uint64_t bits = __ballot(hit);
+    if (t < kBwdBatch) s_qm2[bb][t] = (uint32_t)(bits >> (4 * t)) & 0xFu;
   };
-  if (threadIdx.x < kBwdBatch && b_first >= 0) {
-    if (b_first + (int)threadIdx.x < count) {
+  if (wave == 0 && b_first >= 0) {
+    if (threadIdx.x < kBwdBatch && b_first + (int)threadIdx.x < count) {
       nxt_d = ival[rg.x + b_first + threadIdx.x];
       nxt = recs[nxt_d];
     }
     stage(b_first, 0);
     const int e1 = b_first - kBwdBatch + (int)threadIdx.x;
-    if (e1 >= 0) {
+    if (threadIdx.x < kBwdBatch && e1 >= 0) {
       nxt_d = ival[rg.x + e1];
       nxt = recs[nxt_d];
     }
     const int e2n = e1 - kBwdBatch;
-    if (e2n >= 0) nn_d = ival[rg.x + e2n];
+    if (threadIdx.x < kBwdBatch && e2n >= 0) nn_d = ival[rg.x + e2n];
   }
   int buf = 0;
   for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1) {
@@ -432,15 +447,15 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const uint32_t d_atom = s_d[j2];
     // stage the next batch into the other buffer (read by nobody until the
     // next loop-top barrier) and advance the loads, before this batch's atomics
-    if (threadIdx.x < kBwdBatch && b0 >= kBwdBatch) {
+    if (wave == 0 && b0 >= kBwdBatch) {
       stage(b0 - kBwdBatch, buf ^ 1);
       const int e1 = b0 - 2 * kBwdBatch + (int)threadIdx.x;
-      if (e1 >= 0) {
+      if (threadIdx.x < kBwdBatch && e1 >= 0) {
         nxt_d = nn_d;
         nxt = recs[nxt_d];
       }
       const int e2n = e1 - kBwdBatch;
-      if (e2n >= 0) nn_d = ival[rg.x + e2n];
+      if (threadIdx.x < kBwdBatch && e2n >= 0) nn_d = ival[rg.x + e2n];
     }
     // ten lanes of the primitive's row each add one value of its gradient
     // line, so a wave's atomics for a primitive share one 64-byte line
@@ -453,24 +468,26 @@ __global__ void __launch_bounds__(256) k_raster_backward(
 
 void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                            const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
-                           int channels, float* out_rgb, float* out_depth, float* out_alpha, float* pix_t,
-                           uint32_t* pix_last, hipStream_t s) {
+                           int channels, bool cull, float* out_rgb, float* out_depth, float* out_alpha,
+                           float* pix_t, uint32_t* pix_last, hipStream_t s) {
   if (total_tiles == 0) return;
   hipLaunchKernelGGL(k_raster_forward, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges, ival,
-                     rec_sorted, bg[0], bg[1], bg[2], channels, out_rgb, out_depth, out_alpha, pix_t, pix_last);
+                     rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb, out_depth, out_alpha, pix_t,
+                     pix_last);
 }
 
 void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
                             const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, float* grad2d, bool mark_blended, hipStream_t s) {
+                            const uint32_t* pix_last, float* grad2d, bool mark_blended, bool cull,
+                            hipStream_t s) {
   if (total_tiles == 0) return;
 #define G4D_BWD(HD, HA)                                                                                          \
   hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(total_tiles), dim3(256), 0, s, order, n_views, views,     \
                      ranges,                                                                                      \
                      ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d,      \
-                     mark_blended)
+                     mark_blended, cull)
   if (dl_depth && dl_alpha) G4D_BWD(true, true);
   else if (dl_depth) G4D_BWD(true, false);
   else if (dl_alpha) G4D_BWD(false, true);
