@@ -243,10 +243,14 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *                          of decreasing list length; 0: in tile-id order.
  *                          Results are identical; changing it invalidates
  *                          the state kept for render_backward.
- *   G4D_TUNE_QUADRANT_CULL 1 (default): each 8x8-pixel quarter of a tile
- *                          walks only the list entries whose 1/255-alpha
- *                          ellipse meets it; 0: every entry (slower, same
- *                          results; for checking the test is conservative).
+ *   G4D_TUNE_ELLIPSE_CULL  1 (default): a record is binned only into the
+ *                          tiles of its rectangle that its 1/255-alpha
+ *                          ellipse reaches, and each 8x8-pixel quarter of a
+ *                          tile walks only the entries whose ellipse meets
+ *                          it; 0: whole rectangles, every entry walked
+ *                          (slower, same images; for checking that the
+ *                          ellipse tests are conservative). Changing it
+ *                          invalidates the state kept for render_backward.
  *   G4D_TUNE_AUTOTUNE      1: the next render that is not being captured
  *                          first renders its batch under every combination
  *                          of G4D_TUNE_SORT_BLOCKS in {256, 512, 1024, 2048}
@@ -256,7 +260,7 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
 enum {
   G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2, G4D_TUNE_ROUND_PAIRS = 3, G4D_TUNE_ROUND_INSTANCES = 4,
   G4D_TUNE_SYNC_FREE = 5, G4D_TUNE_ARENA_INSTANCES = 6, G4D_TUNE_TILE_ORDER = 7, G4D_TUNE_AUTOTUNE = 8,
-  G4D_TUNE_QUADRANT_CULL = 9
+  G4D_TUNE_ELLIPSE_CULL = 9
 };
 g4d_status g4d_set_tuning(g4d_ctx* ctx, int32_t key, int32_t value);
 /* Current value of a tuning key (G4D_TUNE_ARENA_INSTANCES: the arena's

@@ -54,7 +54,7 @@ struct g4d_ctx {
   int64_t round_instances = int64_t(1) << 30;
   bool sync_free = false;          // no host read of device counts inside render/backward
   bool heavy_first = true;         // rasterise tiles by decreasing list length
-  bool quad_cull = true;           // waves skip entries whose ellipse misses their quadrant
+  bool ellipse_cull = true;        // bin and walk by the alpha-floor ellipse, not its rectangle
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
   bool flow_mode = false;          // the render in progress blends flow (Sec. 4.3), not colour
   float flow_dt = 0.f;
@@ -277,7 +277,7 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
              (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
   // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
   launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
-                P<int32_t>(c->slot), P<uint32_t>(c->tcount), cnt + kCntInst64, (int)c->n, s);
+                P<int32_t>(c->slot), P<uint32_t>(c->tcount), c->ellipse_cull, cnt + kCntInst64, (int)c->n, s);
   launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
               P<uint32_t>(c->scan_scratch), s);
   stage_end(c, G4D_STAGE_BINNING);
@@ -319,7 +319,8 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   stage_begin(c);
   launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
   launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, P<Record>(c->rec_sorted),
-              P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), P<uint32_t>(c->ikey), P<uint32_t>(c->ival), s);
+              P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), c->ellipse_cull, P<uint32_t>(c->ikey),
+              P<uint32_t>(c->ival), s);
   const int tile_bits = ceil_log2((uint32_t)tiles);
   const int g_tile = radix_grid(cap, c->sort_blocks);
   radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI,
@@ -346,7 +347,7 @@ g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, 
   static const float kZero3[3] = {0.f, 0.f, 0.f};
   launch_raster_forward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, r.v1 - r.v0,
                         P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival), P<Record>(c->rec_sorted),
-                        c->flow_mode ? kZero3 : c->opts.bg, c->flow_mode ? 2 : 3, c->quad_cull, out_rgb,
+                        c->flow_mode ? kZero3 : c->opts.bg, c->flow_mode ? 2 : 3, c->ellipse_cull, out_rgb,
                         out_depth, out_alpha,
                         P<float>(c->pix_t), P<uint32_t>(c->pix_last), s);
   stage_end(c, G4D_STAGE_RASTER_FWD);
@@ -687,7 +688,7 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
                            P<uint32_t>(c->pix_last), P<float>(c->grad2d), c->densify.blend_count != nullptr,
-                           c->quad_cull, s);
+                           c->ellipse_cull, s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
     RenderParams p = make_params(c, nv);
     stage_begin(c);
@@ -851,9 +852,10 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     c->have_render = false;  // the order of the last render's tiles may be missing
     return G4D_OK;
   }
-  if (key == G4D_TUNE_QUADRANT_CULL) {
-    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "quadrant cull is 0 or 1");
-    c->quad_cull = value == 1;
+  if (key == G4D_TUNE_ELLIPSE_CULL) {
+    if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "ellipse cull is 0 or 1");
+    c->ellipse_cull = value == 1;
+    c->have_render = false;  // the last render's bins would come out otherwise
     return G4D_OK;
   }
   if (key == G4D_TUNE_SYNC_FREE) {
@@ -885,7 +887,7 @@ g4d_status g4d_get_tuning(g4d_ctx* c, int32_t key, int32_t* value) {
     case G4D_TUNE_ROUND_PAIRS: *value = clamp32(c->round_pairs); break;
     case G4D_TUNE_ROUND_INSTANCES: *value = clamp32(c->round_instances); break;
     case G4D_TUNE_SYNC_FREE: *value = c->sync_free ? 1 : 0; break;
-    case G4D_TUNE_QUADRANT_CULL: *value = c->quad_cull ? 1 : 0; break;
+    case G4D_TUNE_ELLIPSE_CULL: *value = c->ellipse_cull ? 1 : 0; break;
     case G4D_TUNE_ARENA_INSTANCES: *value = clamp32((int64_t)arena_instances(c)); break;
     case G4D_TUNE_TILE_ORDER: *value = c->heavy_first ? 1 : 0; break;
     case G4D_TUNE_AUTOTUNE: *value = c->autotune_pending ? 1 : 0; break;

@@ -7,7 +7,8 @@
 // passes run on the active records before they are duplicated per tile:
 //   1. stable 4-pass radix sort of the active records by float depth bits
 //      (ties keep (view, index) order from the compaction scan);
-//   2. emission of one (tile, record) instance per covered tile, in that order;
+//   2. emission of one (tile, record) instance per tile of the record's
+//      rectangle that its alpha-floor ellipse reaches, in that order;
 //   3. stable radix sort of the instances by global tile id.
 // Every pass is stable, so the result equals a stable sort by (tile, depth)
 // of the instances emitted in (view, index) order.
@@ -22,6 +23,77 @@ constexpr int kTileElems = kThreads * kItems;  // 4096 elements per block tile
 
 __device__ __forceinline__ uint32_t dev_n(const uint32_t* n_dev, uint32_t n_max) {
   return n_dev ? min(*n_dev, n_max) : n_max;
+}
+
+// A record's footprint for binning: centre, conic, the bound L on
+// Q = a dx^2 + 2 b dx dy + c dy^2 below which opacity * exp(-Q/2) reaches
+// 1/255 (loosened by 0.1 % + 0.02 so FP32 rounding never drops a blended
+// pixel), the ellipse's half-height ymax, the dy of its leftmost point ey
+// (the rightmost is at -ey), and its tile rectangle. D = a c - b^2.
+struct Footprint {
+  float u, v, b, L, D, ia, ymax, ey;
+  uint32_t x0, x1, y0, y1;
+};
+
+// Footprint and row_span are written with explicit rounding and no
+// contraction, so the instance count of a record and its emission agree.
+__device__ __forceinline__ Footprint footprint(const Record& r) {
+#pragma clang fp contract(off)
+  Footprint f;
+  f.u = r.a.x;
+  f.v = r.a.y;
+  const float a = r.b.x, c = r.b.z;
+  f.b = r.b.y;
+  // 2 ln(255 opacity) = 2 ln2 (log2 opacity - log2(1/255))
+  const float L0 = __fmul_rn(2.f * 0.69314718055994531f, __fsub_rn(__log2f(r.a.w), kLog2AlphaMin));
+  f.L = __fmaf_rn(L0, 1.001f, 0.02f);
+  const float p = __fmul_rn(f.b, f.b);
+  f.D = __fsub_rn(__fmaf_rn(a, c, -p), __fmaf_rn(f.b, f.b, -p));  // product error recovered
+  f.ia = __builtin_amdgcn_rcpf(a);
+  const float iD = __builtin_amdgcn_rcpf(f.D);
+  f.ymax = __fsqrt_rn(fmaxf(__fmul_rn(__fmul_rn(f.L, a), iD), 0.f));
+  const float xmax = __fsqrt_rn(fmaxf(__fmul_rn(__fmul_rn(f.L, c), iD), 0.f));
+  f.ey = __fmul_rn(__fmul_rn(f.b, xmax), __builtin_amdgcn_rcpf(c));
+  if (!(f.L > 0.f) || !(f.D > 0.f) || !(f.ymax >= 0.f)) f.ymax = -1.f;  // no tile
+  f.L = __fmul_rn(a, f.L);                           // kept as a L from here on
+  const uint32_t rx = __float_as_uint(r.b.w), ry = __float_as_uint(r.c.w);
+  f.x0 = rx & 0xFFFFu;
+  f.x1 = rx >> 16;
+  f.y0 = ry & 0xFFFFu;
+  f.y1 = ry >> 16;
+  return f;
+}
+
+// Tiles [xa, xb) of tile row ty whose pixel centres the ellipse Q <= L can
+// reach, within the rectangle. Over the row's band of pixel-centre rows the
+// ellipse's left edge x(dy) = (-b dy - sqrt(a L - D dy^2)) / a is convex and
+// its right edge concave, so their extremes over the band sit at the
+// leftmost / rightmost points clamped to the band. exact = false: the
+// rectangle's whole row.
+__device__ __forceinline__ void row_span(const Footprint& f, uint32_t ty, bool exact, uint32_t& xa, uint32_t& xb) {
+#pragma clang fp contract(off)
+  constexpr float kEps = 0.01f;  // px
+  if (!exact) {
+    xa = f.x0;
+    xb = f.x1;
+    return;
+  }
+  xa = xb = f.x0;
+  const float band0 = __fsub_rn((float)(ty * kTile) + (0.5f - kEps), f.v);
+  const float band1 = __fsub_rn((float)(ty * kTile) + (15.5f + kEps), f.v);
+  const float lo = fmaxf(band0, -f.ymax), hi = fminf(band1, f.ymax);
+  if (!(lo <= hi)) return;
+  const float dl = fminf(fmaxf(f.ey, lo), hi), dr = fminf(fmaxf(-f.ey, lo), hi);
+  const float sl = __fsqrt_rn(fmaxf(__fsub_rn(f.L, __fmul_rn(f.D, __fmul_rn(dl, dl))), 0.f));
+  const float sr = __fsqrt_rn(fmaxf(__fsub_rn(f.L, __fmul_rn(f.D, __fmul_rn(dr, dr))), 0.f));
+  const float left = __fadd_rn(f.u, __fmul_rn(__fsub_rn(-__fmul_rn(f.b, dl), sl), f.ia));
+  const float right = __fadd_rn(f.u, __fmul_rn(__fadd_rn(-__fmul_rn(f.b, dr), sr), f.ia));
+  // tile tx holds centres 16 tx + [0.5, 15.5]
+  const float ta = ceilf(__fmul_rn(__fsub_rn(left, 15.5f + kEps), 1.f / kTile));
+  const float tb = floorf(__fmul_rn(__fadd_rn(right, kEps - 0.5f), 1.f / kTile)) + 1.f;
+  const float fx0 = (float)f.x0, fx1 = (float)f.x1;
+  xa = (uint32_t)fminf(fmaxf(ta, fx0), fx1);
+  xb = (uint32_t)fminf(fmaxf(tb, (float)xa), fx1);
 }
 
 // Exclusive scan of one value per thread across a 256-thread block.
@@ -322,7 +394,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
 __global__ void __launch_bounds__(kThreads) k_gather(const uint32_t* n_dev, uint32_t n_max,
                                                       const uint32_t* __restrict__ ids, const Record* __restrict__ rec,
                                                       Record* __restrict__ rec_sorted, int32_t* __restrict__ slot,
-                                                      uint32_t* __restrict__ tcount,
+                                                      uint32_t* __restrict__ tcount, bool exact,
                                                       unsigned long long* __restrict__ inst64) {
   __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
@@ -334,8 +406,12 @@ __global__ void __launch_bounds__(kThreads) k_gather(const uint32_t* n_dev, uint
     const Record r = rec[id];
     rec_sorted[d] = r;
     slot[id] = (int32_t)d;
-    const uint32_t rx = __float_as_uint(r.b.w), ry = __float_as_uint(r.c.w);
-    cnt = ((rx >> 16) - (rx & 0xFFFFu)) * ((ry >> 16) - (ry & 0xFFFFu));
+    const Footprint f = footprint(r);
+    for (uint32_t ty = f.y0; ty < f.y1; ++ty) {
+      uint32_t xa, xb;
+      row_span(f, ty, exact, xa, xb);
+      cnt += xb - xa;
+    }
     tcount[d] = cnt;
   }
   uint32_t total;
@@ -359,50 +435,123 @@ __global__ void k_view_counts(const uint32_t* __restrict__ pos, const uint32_t* 
 }
 
 // ---------------------------------------------------------------- emit ----
-// One block per 256 consecutive records; the block's instances are spread
-// over its threads, each finding its record by binary search in LDS.
+// One block per 128 consecutive records. The block lays out its records'
+// tile rows in LDS (first tile, offset of the row's first instance by a block
+// scan of the row widths) and an instance -> row map, then writes the
+// block's instances coalesced, one per thread in turn. A block whose rows or
+// instances do not fit writes whole rows per thread, or (too many rows)
+// walks each instance's record rows.
+constexpr int kEmitRecs = 128;
+constexpr int kEmitRows = 2048;
+constexpr int kEmitInst = 8192;
+
 __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32_t n_max,
                                                     const uint32_t* __restrict__ toff, const uint32_t* total,
                                                     uint32_t cap, const Record* __restrict__ rec_sorted,
                                                     const uint32_t* __restrict__ ids, uint32_t n_prims,
-                                                    const ViewDev* __restrict__ views, uint32_t* __restrict__ ikey,
-                                                    uint32_t* __restrict__ ival) {
-  __shared__ uint32_t offs[kThreads + 1];
-  __shared__ uint32_t s_rx[kThreads], s_ry[kThreads], s_tb[kThreads], s_tw[kThreads];
+                                                    const ViewDev* __restrict__ views, bool exact,
+                                                    uint32_t* __restrict__ ikey, uint32_t* __restrict__ ival) {
+  __shared__ uint32_t offs[kEmitRecs + 1];
+  __shared__ uint32_t s_rbase[kEmitRecs + 1];
+  __shared__ uint32_t s_tb[kEmitRecs], s_tw[kEmitRecs];
+  __shared__ Footprint s_fp[kEmitRecs];
+  __shared__ uint32_t s_row_off[kEmitRows + 1];  // first instance of each row (block-relative)
+  __shared__ uint32_t s_row_tile[kEmitRows];     // global tile id of the row's first instance
+  __shared__ uint8_t s_row_rec[kEmitRows];
+  __shared__ uint16_t s_inst_row[kEmitInst];
+  __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
-  const uint32_t d0 = blockIdx.x * kThreads;
+  const uint32_t d0 = blockIdx.x * kEmitRecs;
   if (d0 >= n) return;
-  const uint32_t d = d0 + threadIdx.x;
+  const uint32_t nrec = min((uint32_t)kEmitRecs, n - d0);
   const uint32_t tot = *total;
-  offs[threadIdx.x] = d < n ? toff[d] : tot;
-  if (threadIdx.x == 0) offs[kThreads] = (d0 + kThreads < n) ? toff[d0 + kThreads] : tot;
-  if (d < n) {
-    const Record r = rec_sorted[d];
-    s_rx[threadIdx.x] = __float_as_uint(r.b.w);
-    s_ry[threadIdx.x] = __float_as_uint(r.c.w);
-    const uint32_t v = ids[d] / n_prims;
-    s_tb[threadIdx.x] = (uint32_t)views[v].tile_base;
-    s_tw[threadIdx.x] = (uint32_t)views[v].tiles_x;
+  uint32_t h = 0;
+  if (threadIdx.x < kEmitRecs) {
+    const uint32_t d = d0 + threadIdx.x;
+    offs[threadIdx.x] = d < n ? toff[d] : tot;
+    if (threadIdx.x == 0) offs[kEmitRecs] = (d0 + kEmitRecs < n) ? toff[d0 + kEmitRecs] : tot;
+    if (d < n) {
+      const Footprint f = footprint(rec_sorted[d]);
+      s_fp[threadIdx.x] = f;
+      h = f.y1 - f.y0;
+      const uint32_t v = ids[d] / n_prims;
+      s_tb[threadIdx.x] = (uint32_t)views[v].tile_base;
+      s_tw[threadIdx.x] = (uint32_t)views[v].tiles_x;
+    }
   }
+  uint32_t rows;
+  const uint32_t rb = block_exclusive_scan(h, s_wave, rows);  // contains barriers
+  if (threadIdx.x < kEmitRecs) s_rbase[threadIdx.x] = rb;
   __syncthreads();
   const uint32_t lim = min(tot, cap);
-  const uint32_t start = offs[0], end = min(offs[kThreads], lim);
-  for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
-    int lo = 0, hi = kThreads - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (offs[mid] <= i) lo = mid; else hi = mid - 1;
+  const uint32_t start = offs[0], end = min(offs[kEmitRecs], lim);
+  if (rows <= (uint32_t)kEmitRows) {
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0; j0 < rows; j0 += kThreads) {
+      const uint32_t j = j0 + threadIdx.x;
+      uint32_t w = 0;
+      if (j < rows) {
+        int lo = 0, hi = (int)nrec - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_rbase[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        const Footprint& f = s_fp[lo];
+        const uint32_t ty = f.y0 + (j - s_rbase[lo]);
+        uint32_t xa, xb;
+        row_span(f, ty, exact, xa, xb);
+        w = xb - xa;
+        s_row_tile[j] = s_tb[lo] + ty * s_tw[lo] + xa;
+        s_row_rec[j] = (uint8_t)lo;
+      }
+      uint32_t tot_w;
+      const uint32_t ex = block_exclusive_scan(w, s_wave, tot_w);  // contains barriers
+      if (j < rows) s_row_off[j] = carry + ex;
+      carry += tot_w;
     }
-    const uint32_t k = i - offs[lo];
-    const uint32_t rx = s_rx[lo], ry = s_ry[lo];
-    const uint32_t x0 = rx & 0xFFFFu, w = (rx >> 16) - x0, y0 = ry & 0xFFFFu;
-    // k / w through a float reciprocal, corrected to the exact quotient
-    uint32_t q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
-    q -= (q * w > k) ? 1u : 0u;
-    q += ((q + 1u) * w <= k) ? 1u : 0u;
-    const uint32_t ty = y0 + q, tx = x0 + (k - q * w);
-    ikey[i] = s_tb[lo] + ty * s_tw[lo] + tx;
-    ival[i] = d0 + (uint32_t)lo;
+    if (threadIdx.x == 0) s_row_off[rows] = carry;
+    __syncthreads();
+    if (carry <= (uint32_t)kEmitInst) {
+      for (uint32_t j = threadIdx.x; j < rows; j += kThreads)
+        for (uint32_t k = s_row_off[j]; k < s_row_off[j + 1]; ++k) s_inst_row[k] = (uint16_t)j;
+      __syncthreads();
+      const uint32_t iend = min(end, start + carry);  // equal: the counts come from the same spans
+      for (uint32_t i = start + threadIdx.x; i < iend; i += kThreads) {
+        const uint32_t k = i - start, j = s_inst_row[k];
+        ikey[i] = s_row_tile[j] + (k - s_row_off[j]);
+        ival[i] = d0 + s_row_rec[j];
+      }
+    } else {
+      for (uint32_t j = threadIdx.x; j < rows; j += kThreads) {
+        const uint32_t i0 = start + s_row_off[j], i1 = min(start + s_row_off[j + 1], end);
+        const uint32_t tile = s_row_tile[j], rec = d0 + s_row_rec[j];
+        for (uint32_t i = i0; i < i1; ++i) {
+          ikey[i] = tile + (i - i0);
+          ival[i] = rec;
+        }
+      }
+    }
+  } else {
+    for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
+      int lo = 0, hi = (int)nrec - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= i) lo = mid; else hi = mid - 1;
+      }
+      const Footprint& f = s_fp[lo];
+      uint32_t k = i - offs[lo], tile = 0;
+      for (uint32_t ty = f.y0; ty < f.y1; ++ty) {
+        uint32_t xa, xb;
+        row_span(f, ty, exact, xa, xb);
+        if (k < xb - xa) {
+          tile = ty * s_tw[lo] + xa + k;
+          break;
+        }
+        k -= xb - xa;
+      }
+      ikey[i] = s_tb[lo] + tile;
+      ival[i] = d0 + (uint32_t)lo;
+    }
   }
 }
 
@@ -531,11 +680,11 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
 }
 
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
-                   int32_t* slot, uint32_t* tcount, uint32_t* inst64, int n_prims, hipStream_t s) {
+                   int32_t* slot, uint32_t* tcount, bool exact, uint32_t* inst64, int n_prims, hipStream_t s) {
   (void)n_prims;
   if (n_max == 0) return;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, ids, rec,
-                     rec_sorted, slot, tcount, reinterpret_cast<unsigned long long*>(inst64));
+                     rec_sorted, slot, tcount, exact, reinterpret_cast<unsigned long long*>(inst64));
 }
 
 void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, uint32_t n, const uint32_t* total,
@@ -544,11 +693,11 @@ void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, u
 }
 
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
-                 const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, uint32_t* ikey,
-                 uint32_t* ival, hipStream_t s) {
+                 const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
+                 uint32_t* ikey, uint32_t* ival, hipStream_t s) {
   if (n_max == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, toff, total, cap,
-                     rec_sorted, ids, (uint32_t)n_prims, views, ikey, ival);
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kEmitRecs)), dim3(kThreads), 0, s, n_dev, n_max, toff, total, cap,
+                     rec_sorted, ids, (uint32_t)n_prims, views, exact, ikey, ival);
 }
 
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s) {

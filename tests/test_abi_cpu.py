@@ -44,7 +44,7 @@ def test_header_constants_match_binding():
     assert val("G4D_TUNE_ARENA_INSTANCES") == g4d.G4D_TUNE_ARENA_INSTANCES
     assert val("G4D_TUNE_TILE_ORDER") == g4d.G4D_TUNE_TILE_ORDER
     assert val("G4D_TUNE_AUTOTUNE") == g4d.G4D_TUNE_AUTOTUNE
-    assert val("G4D_TUNE_QUADRANT_CULL") == g4d.G4D_TUNE_QUADRANT_CULL
+    assert val("G4D_TUNE_ELLIPSE_CULL") == g4d.G4D_TUNE_ELLIPSE_CULL
     assert val("G4D_NUM_STAGES") == len(g4d.STAGES)
     for k, v in g4d.DBG.items():
         assert val("G4D_DBG_" + k.upper()) == v
