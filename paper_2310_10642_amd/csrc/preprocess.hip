@@ -99,52 +99,74 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
   }
 }
 
-__device__ __forceinline__ float row16_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xF, 0xF, false));  // row_ror:2
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xF, 0xF, false));  // row_ror:1
-  return v;
-}
+constexpr int kColourViews = 8;  // views whose loads k_colour issues together
 
-// 4D spherindrical-harmonic colour (Sec. 3.2): 16 lanes per primitive, one
-// per SH basis function l^2 + l + m, so the coefficients [K][3] are read once
-// and coalesced; per active view each lane weights its basis value by the
-// Fourier terms, and a 16-lane sum gives c = max(0, 0.5 + sum).
+// 4D spherindrical-harmonic colour (Sec. 3.2): a quad of lanes per primitive,
+// lane `sub` owning the basis functions lm = 4 sub + i. The block's 64
+// primitives' coefficients are contiguous in memory; they are staged through
+// LDS with 16-byte loads, and each lane takes its [n][4 sub + i][3] from
+// there. Per active view every lane evaluates the basis, weights its four
+// functions by the Fourier terms, and a quad sum gives c = max(0, 0.5 + sum).
 __global__ void __launch_bounds__(256) k_colour(RenderParams p, const uint32_t* __restrict__ act,
                                                 const float4* __restrict__ cdir, Record* __restrict__ rec) {
-  const int gidx = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
-  const int lm = threadIdx.x & 15;
-  if (gidx >= p.n) return;  // uniform per 16-lane group
+  __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
-  const bool lane_on = lm < nb;
-  const float* kc = p.coeffs + (size_t)gidx * nt * nb * 3;
-  float k[3][3];
+  const int K3 = nt * nb * 3;
+  const int g0 = blockIdx.x * kColourPrims;
+  const int nprim = min(kColourPrims, p.n - g0);
+  copy_in(s_k, p.coeffs + (size_t)g0 * K3, nprim * K3);
+  __syncthreads();
+  const int gidx = g0 + (int)(threadIdx.x >> 2);
+  const int sub = threadIdx.x & 3;
+  if (gidx >= p.n) return;  // uniform per quad
+  const float* kc = s_k + (threadIdx.x >> 2) * K3;
+  float k[3][kBasisPerLane][3];
 #pragma unroll
   for (int n = 0; n < 3; ++n)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) k[n][c] = (lane_on && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
-  for (int vi = 0; vi < p.n_views; ++vi) {
-    const size_t idx = (size_t)vi * p.n + gidx;
-    if (!act[idx]) continue;  // uniform per group
-    const float4 cd = cdir[idx];
-    float Y[16], cs[3] = {0.f, 0.f, 0.f};
-    sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
-    fourier_terms(p.t_order, cd.w, p.t_period, cs);
-    float ylm = 0.f;
+    for (int i = 0; i < kBasisPerLane; ++i) {
+      const int lm = sub * kBasisPerLane + i;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) ylm = (i == lm) ? Y[i] : ylm;
-    if (!lane_on) ylm = 0.f;
-    float col[3];
+      for (int c = 0; c < 3; ++c) k[n][i][c] = (lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+    }
+  // views eight at a time: all flags, then the directions of the active
+  // ones, are loaded before any is used, so the loads overlap
+  for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
+    uint32_t on[kColourViews];
+    float4 cds[kColourViews];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      col[c] = row16_sum(ylm * fmaf(cs[0], k[0][c], fmaf(cs[1], k[1][c], cs[2] * k[2][c])));
-    if (lm == 0) {
-      float* o = reinterpret_cast<float*>(&rec[idx].c);
-      o[0] = fmaxf(col[0] + kColorOffset, 0.f);
-      o[1] = fmaxf(col[1] + kColorOffset, 0.f);
-      o[2] = fmaxf(col[2] + kColorOffset, 0.f);
+    for (int w = 0; w < kColourViews; ++w) on[w] = v0 + w < p.n_views ? act[(size_t)(v0 + w) * p.n + gidx] : 0u;
+#pragma unroll
+    for (int w = 0; w < kColourViews; ++w)
+      cds[w] = on[w] ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
+#pragma unroll
+    for (int w = 0; w < kColourViews; ++w) {
+      if (!on[w]) continue;  // uniform per quad
+      const size_t idx = (size_t)(v0 + w) * p.n + gidx;
+      const float4 cd = cds[w];
+      float Y[16], cs[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Y[j] = 0.f;
+      sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
+      fourier_terms(p.t_order, cd.w, p.t_period, cs);
+      float y[kBasisPerLane];
+      own_basis(Y, sub, y);
+      float col[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < kBasisPerLane; ++i)
+          acc = fmaf(y[i], fmaf(cs[0], k[0][i][c], fmaf(cs[1], k[1][i][c], cs[2] * k[2][i][c])), acc);
+        col[c] = quad_sum(acc);
+      }
+      if (sub == 0) {
+        float* o = reinterpret_cast<float*>(&rec[idx].c);
+        o[0] = fmaxf(col[0] + kColorOffset, 0.f);
+        o[1] = fmaxf(col[1] + kColorOffset, 0.f);
+        o[2] = fmaxf(col[2] + kColorOffset, 0.f);
+      }
     }
   }
 }
@@ -157,8 +179,8 @@ void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Rec
   const int bs = 256;
   hipLaunchKernelGGL(k_preprocess, dim3((p.n + bs - 1) / bs), dim3(bs), 0, s, p, act, dkey, rec, slot, cdir);
   if (!p.flow)
-    hipLaunchKernelGGL(k_colour, dim3((unsigned)(((size_t)p.n * 16 + 255) / 256)), dim3(256), 0, s, p, act, cdir,
-                       rec);
+    hipLaunchKernelGGL(k_colour, dim3((unsigned)((p.n + kColourPrims - 1) / kColourPrims)), dim3(256), 0, s, p, act,
+                       cdir, rec);
 }
 
 }  // namespace g4d

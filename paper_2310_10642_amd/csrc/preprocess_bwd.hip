@@ -28,14 +28,6 @@ constexpr int kGeoFloats = 16;  // G4 upper triangle (10), dL/dmu (4), dL/dlogit
 constexpr int kColFloats = 8;   // dL/draw (3), t - mu_t, view direction (3), 1/|mu_c - c|
 constexpr int kCgFloats = 4;    // dL/dmu_c and dL/d(t - mu_t) through the colour
 
-__device__ __forceinline__ float row16_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xF, 0xF, false));  // row_ror:2
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xF, 0xF, false));  // row_ror:1
-  return v;
-}
-
 __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_t* n_dev, uint32_t n_max,
                                                     const uint32_t* __restrict__ ids, const Record* __restrict__ recs,
                                                     const float* __restrict__ grad2d, float4* __restrict__ geo,
@@ -154,86 +146,111 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
   o[3] = make_float4(gmuc[2], -gdt, glogit, blended ? sqrtf(gu * gu + gv * gv) : -1.f);
 }
 
-// 16 lanes per primitive (lane = SH basis index lm); lanes with lm >= (L+1)^2 idle.
+constexpr int kBwdColourViews = 8;  // views whose slots k_bwd_colour loads together
+
+// A quad of lanes per primitive, lane `sub` owning the basis functions
+// lm = 4 sub + i (as in the forward colour kernel): per active view it adds
+// its share of dL/dcoeffs, and quad sums give the gradients through the view
+// direction and through t - mu_t. The block's coefficients come in, and its
+// coefficient gradients go out, through LDS with 16-byte accesses.
 __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                      const float4* __restrict__ colbuf, float4* __restrict__ cgbuf,
                                                      float* __restrict__ g_coeffs, bool accumulate) {
-  const int gidx = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 4);
-  const int lm = threadIdx.x & 15;
-  if (gidx >= p.n) return;  // uniform per 16-lane group
+  __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
-  const int K = nt * nb;
-  const bool lane_on = lm < nb;
-  const float* kc = p.coeffs + (size_t)gidx * K * 3;
-  float k[3][3], gk[3][3];
+  const int K3 = nt * nb * 3;
+  const int g0 = blockIdx.x * kColourPrims;
+  const int nprim = min(kColourPrims, p.n - g0);
+  copy_in(s_k, p.coeffs + (size_t)g0 * K3, nprim * K3);
+  __syncthreads();
+  const int gidx = g0 + (int)(threadIdx.x >> 2);
+  const int sub = threadIdx.x & 3;
+  const bool live = gidx < p.n;  // uniform per quad
+  float* kc = s_k + (threadIdx.x >> 2) * K3;
+  float k[3][kBasisPerLane][3], gk[3][kBasisPerLane][3];
 #pragma unroll
   for (int n = 0; n < 3; ++n)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      k[n][c] = (lane_on && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
-      gk[n][c] = 0.f;
+    for (int i = 0; i < kBasisPerLane; ++i) {
+      const int lm = sub * kBasisPerLane + i;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        k[n][i][c] = (live && lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+        gk[n][i][c] = 0.f;
+      }
     }
-  bool any = false;
-  for (int vi = 0; vi < p.n_views; ++vi) {
-    const int d = slot[(size_t)vi * p.n + gidx];
-    if (d < 0) continue;
-    any = true;
-    const float4 c0 = colbuf[2 * (size_t)d];
-    const float4 c1 = colbuf[2 * (size_t)d + 1];
-    const float graw[3] = {c0.x, c0.y, c0.z};
-    const float dt = c0.w;
-    float Y[16];
+  __syncthreads();  // s_k is reused for the gradients below
+  // views eight at a time, their slots loaded before any is used
+  for (int v0 = 0; live && v0 < p.n_views; v0 += kBwdColourViews) {
+    int ds[kBwdColourViews];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) Y[i] = 0.f;
-    sh_eval(p.sh_degree, c1.x, c1.y, c1.z, Y);
-    float ylm = 0.f;
+    for (int w = 0; w < kBwdColourViews; ++w) ds[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) ylm = (i == lm) ? Y[i] : ylm;
-    if (!lane_on) ylm = 0.f;
-    float cs[3], sn[3];
-    fourier_terms(p.t_order, dt, p.t_period, cs, sn);
-    // kd_n = sum_ch graw_ch k[n][lm][ch]
-    float kd[3], gy = 0.f;
+    for (int w = 0; w < kBwdColourViews; ++w) {
+      const int d = ds[w];
+      if (d < 0) continue;
+      const float4 c0 = colbuf[2 * (size_t)d];
+      const float4 c1 = colbuf[2 * (size_t)d + 1];
+      const float graw[3] = {c0.x, c0.y, c0.z};
+      const float dt = c0.w;
+      float Y[16];
 #pragma unroll
-    for (int n = 0; n < 3; ++n) {
-      kd[n] = fmaf(graw[0], k[n][0], fmaf(graw[1], k[n][1], graw[2] * k[n][2]));
-      gy = fmaf(cs[n], kd[n], gy);
+      for (int j = 0; j < 16; ++j) Y[j] = 0.f;
+      sh_eval(p.sh_degree, c1.x, c1.y, c1.z, Y);
+      float y[kBasisPerLane];
+      own_basis(Y, sub, y);
+      float cs[3], sn[3];
+      fourier_terms(p.t_order, dt, p.t_period, cs, sn);
+      // kd[n][i] = sum_ch graw_ch k[n][i][ch]; gy[i] = sum_n cs_n kd[n][i]
+      float kd[3][kBasisPerLane], gy[kBasisPerLane];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gk[n][c] = fmaf(cs[n] * ylm, graw[c], gk[n][c]);
-    }
-    // gradient of this lane's basis function in the view direction
-    float gY[16];
+      for (int i = 0; i < kBasisPerLane; ++i) {
+        gy[i] = 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) gY[i] = (i == lm && lane_on) ? gy : 0.f;
-    float gdx, gdy, gdz;
-    sh_grad(p.sh_degree, c1.x, c1.y, c1.z, gY, gdx, gdy, gdz);
-    gdx = row16_sum(gdx);
-    gdy = row16_sum(gdy);
-    gdz = row16_sum(gdz);
-    // d/d(dt) cos(2 pi n dt / T) = -(2 pi n / T) sin(2 pi n dt / T)
-    float gdt = 0.f;
+        for (int n = 0; n < 3; ++n) {
+          kd[n][i] = fmaf(graw[0], k[n][i][0], fmaf(graw[1], k[n][i][1], graw[2] * k[n][i][2]));
+          gy[i] = fmaf(cs[n], kd[n][i], gy[i]);
 #pragma unroll
-    for (int n = 1; n < 3; ++n) {
-      const float gcos = row16_sum(ylm * kd[n]);
-      gdt = fmaf(gcos, -2.f * kPi * n / p.t_period * sn[n], gdt);
-    }
-    if (lm == 0) {
-      const float dd = gdx * c1.x + gdy * c1.y + gdz * c1.z;
-      cgbuf[d] = make_float4((gdx - c1.x * dd) * c1.w, (gdy - c1.y * dd) * c1.w, (gdz - c1.z * dd) * c1.w, gdt);
+          for (int c = 0; c < 3; ++c) gk[n][i][c] = fmaf(cs[n] * y[i], graw[c], gk[n][i][c]);
+        }
+      }
+      // gradient of this lane's basis functions in the view direction
+      float gY[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) gY[j] = (sub == j / kBasisPerLane) ? gy[j % kBasisPerLane] : 0.f;
+      float gdx, gdy, gdz;
+      sh_grad(p.sh_degree, c1.x, c1.y, c1.z, gY, gdx, gdy, gdz);
+      gdx = quad_sum(gdx);
+      gdy = quad_sum(gdy);
+      gdz = quad_sum(gdz);
+      // d/d(dt) cos(2 pi n dt / T) = -(2 pi n / T) sin(2 pi n dt / T)
+      float gdt = 0.f;
+#pragma unroll
+      for (int n = 1; n < 3; ++n) {
+        float gcos = 0.f;
+#pragma unroll
+        for (int i = 0; i < kBasisPerLane; ++i) gcos = fmaf(y[i], kd[n][i], gcos);
+        gcos = quad_sum(gcos);
+        gdt = fmaf(gcos, -2.f * kPi * n / p.t_period * sn[n], gdt);
+      }
+      if (sub == 0) {
+        const float dd = gdx * c1.x + gdy * c1.y + gdz * c1.z;
+        cgbuf[d] = make_float4((gdx - c1.x * dd) * c1.w, (gdy - c1.y * dd) * c1.w, (gdz - c1.z * dd) * c1.w, gdt);
+      }
     }
   }
-  if (!lane_on || (accumulate && !any)) return;
-  float* out = g_coeffs + (size_t)gidx * K * 3;
 #pragma unroll
-  for (int n = 0; n < 3; ++n) {
-    if (n >= nt) break;
+  for (int n = 0; n < 3; ++n)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float* q = out + (n * nb + lm) * 3 + c;
-      *q = accumulate ? *q + gk[n][c] : gk[n][c];
+    for (int i = 0; i < kBasisPerLane; ++i) {
+      const int lm = sub * kBasisPerLane + i;
+      if (!live || lm >= nb || n >= nt) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) kc[(n * nb + lm) * 3 + c] = gk[n][i][c];
     }
-  }
+  __syncthreads();
+  copy_out(g_coeffs + (size_t)g0 * K3, s_k, nprim * K3, accumulate);
 }
 
 __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t* __restrict__ slot,
@@ -392,8 +409,8 @@ void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, cons
   if (n_records_max > 0)
     hipLaunchKernelGGL(k_bwd_pairs, dim3((n_records_max + 255) / 256), dim3(256), 0, s, p, n_records_dev,
                        n_records_max, ids, recs, grad2d, geo, col);
-  hipLaunchKernelGGL(k_bwd_colour, dim3((unsigned)(((size_t)p.n * 16 + 255) / 256)), dim3(256), 0, s, p, slot, col,
-                     cg, g_coeffs, accumulate);
+  hipLaunchKernelGGL(k_bwd_colour, dim3((unsigned)((p.n + kColourPrims - 1) / kColourPrims)), dim3(256), 0, s, p,
+                     slot, col, cg, g_coeffs, accumulate);
   hipLaunchKernelGGL(k_bwd_prims, dim3((p.n + 127) / 128), dim3(128), 0, s, p, slot, geo, cg,
                      reinterpret_cast<float4*>(g_means4), reinterpret_cast<float4*>(g_log_scales4),
                      reinterpret_cast<float4*>(g_q_left), reinterpret_cast<float4*>(g_q_right), g_opacity_logit,

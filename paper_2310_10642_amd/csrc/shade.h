@@ -234,5 +234,55 @@ __device__ __forceinline__ int fourier_terms(int t_order, float dt, float period
   return t_order + 1;
 }
 
+// Sum over the four lanes of a DPP quad (quad_perm [1,0,3,2], then [2,3,0,1]).
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+// The colour kernels give each primitive one quad: lane `sub` owns the basis
+// functions lm = 4 sub + i, i < kBasisPerLane, and their coefficients.
+constexpr int kBasisPerLane = 4;
+
+// Primitives per 256-thread block in the colour kernels, and the LDS floats
+// that stage their coefficients ([(Fourier term) (L+1)^2 + lm][3] each, at
+// most 3 x 16 x 3).
+constexpr int kColourPrims = 64;
+constexpr int kCoeffMax = 3 * 16 * 3;
+
+// Block copies of `count` floats between global memory and LDS (lds 16-byte
+// aligned): 16 bytes per thread and step when g is 16-byte aligned, then
+// single floats for the tail; single floats throughout otherwise.
+__device__ __forceinline__ void copy_in(float* __restrict__ lds, const float* __restrict__ g, int count) {
+  const int n4 = (reinterpret_cast<uintptr_t>(g) & 15u) ? 0 : count >> 2;
+  for (int i = threadIdx.x; i < n4; i += blockDim.x)
+    reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(g)[i];
+  for (int i = 4 * n4 + threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
+}
+
+// g[i] = lds[i] (+ g[i] when accumulate).
+__device__ __forceinline__ void copy_out(float* __restrict__ g, const float* __restrict__ lds, int count,
+                                         bool accumulate) {
+  const int n4 = (reinterpret_cast<uintptr_t>(g) & 15u) ? 0 : count >> 2;
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+    float4 v = reinterpret_cast<const float4*>(lds)[i];
+    if (accumulate) {
+      const float4 o = reinterpret_cast<const float4*>(g)[i];
+      v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+    }
+    reinterpret_cast<float4*>(g)[i] = v;
+  }
+  for (int i = 4 * n4 + threadIdx.x; i < count; i += blockDim.x) g[i] = accumulate ? g[i] + lds[i] : lds[i];
+}
+
+// y[i] = Y[4 sub + i] (selects with constant indices, no register indexing).
+__device__ __forceinline__ void own_basis(const float* Y, int sub, float* y) {
+#pragma unroll
+  for (int i = 0; i < kBasisPerLane; ++i) y[i] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j % kBasisPerLane] = (sub == j / kBasisPerLane) ? Y[j] : y[j % kBasisPerLane];
+}
+
 }  // namespace shade
 }  // namespace g4d
