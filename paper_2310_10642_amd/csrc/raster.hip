@@ -141,6 +141,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// DEPTH: whether the depth plane is written (otherwise its sum is compiled out).
+template <bool DEPTH>
 __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restrict__ order, int n_views,
                                                          const ViewDev* __restrict__ views,
                                                          const uint2* __restrict__ ranges,
@@ -196,11 +198,19 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
     for (int c0 = 0; c0 < nb; c0 += 16) {
       const uint32_t m = lane < 16 ? (uint32_t)s_mask[c0 + lane] : 0u;
       const uint32_t todo = (uint32_t)__ballot((m >> wave) & 1u);
+      // the chunk's first entry as a vector register, so each entry's LDS
+      // reads are immediate offsets from it
+      int cv;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(cv) : "s"(c0));
+      const float4* ca = s_a + cv;
+      const float4* cb = s_b + cv;
+      const float4* cc = s_c + cv;
+      uint32_t last_j = 0u;  // 1 + the chunk's last contributing entry (inline constants)
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         if (!((todo >> j) & 1u)) continue;
-        const float4 sa = s_a[c0 + j];
-        const float4 sb = s_b[c0 + j];
+        const float4 sa = ca[j];
+        const float4 sb = cb[j];
         const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
         float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(p2), 0.f, kAlphaMax);
         a = (p2 >= kLog2AlphaMin && !done) ? a : 0.f;
@@ -208,15 +218,16 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
         const bool stop = Tn < kTStop;  // T >= kTStop always, so stop implies a > 0
         done = done || stop;
         a = stop ? 0.f : a;
-        const float4 sc = s_c[c0 + j];
+        const float4 sc = cc[j];
         const float w = a * T;
         C0 = fmaf(w, sc.x, C0);
         C1 = fmaf(w, sc.y, C1);
         C2 = fmaf(w, sc.z, C2);
-        D = fmaf(w, sb.z, D);
+        if (DEPTH) D = fmaf(w, sb.z, D);
         T = stop ? T : Tn;
-        last = (a > 0.f) ? (uint32_t)(b0 + c0 + j + 1) : last;
+        last_j = (a > 0.f) ? (uint32_t)(j + 1) : last_j;
       }
+      last = last_j ? (uint32_t)(b0 + c0) + last_j : last;
       if (__all(done)) break;
     }
   }
@@ -228,7 +239,7 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
   rgb[0] = fmaf(T, bg0, C0);
   rgb[hw] = fmaf(T, bg1, C1);
   if (channels == 3) rgb[2 * hw] = fmaf(T, bg2, C2);
-  if (out_depth) out_depth[pix] = D;
+  if (DEPTH) out_depth[pix] = D;
   if (out_alpha) out_alpha[pix] = 1.f - T;
   pix_t[pix] = T;
   pix_last[pix] = last;
@@ -339,9 +350,13 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   }
   int buf = 0;
   for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1) {
-    const float4* s_a = s_a2[buf];
-    const float4* s_b = s_b2[buf];
-    const float4* s_c = s_c2[buf];
+    // the stage buffer's first entry as a vector register, so each entry's
+    // LDS reads in phase 1 are immediate offsets from it
+    int bv;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(bv) : "s"(buf * kBwdBatch));
+    const float4* s_a = &s_a2[0][0] + bv;
+    const float4* s_b = &s_b2[0][0] + bv;
+    const float4* s_c = &s_c2[0][0] + bv;
     const uint32_t* s_d = s_d2[buf];
     const uint32_t* s_qm = s_qm2[buf];
     __syncthreads();
@@ -471,9 +486,14 @@ void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, 
                            int channels, bool cull, float* out_rgb, float* out_depth, float* out_alpha,
                            float* pix_t, uint32_t* pix_last, hipStream_t s) {
   if (total_tiles == 0) return;
-  hipLaunchKernelGGL(k_raster_forward, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges, ival,
-                     rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb, out_depth, out_alpha, pix_t,
-                     pix_last);
+  if (out_depth)
+    hipLaunchKernelGGL(k_raster_forward<true>, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges,
+                       ival, rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb, out_depth, out_alpha, pix_t,
+                       pix_last);
+  else
+    hipLaunchKernelGGL(k_raster_forward<false>, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges,
+                       ival, rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb, out_depth, out_alpha, pix_t,
+                       pix_last);
 }
 
 void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
