@@ -213,7 +213,8 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
         const float4 sb = cb[j];
         const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
         float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(p2), 0.f, kAlphaMax);
-        a = (p2 >= kLog2AlphaMin && !done) ? a : 0.f;
+        const bool valid = p2 >= kLog2AlphaMin && !done;  // then a >= 1/255 > 0
+        a = valid ? a : 0.f;
         const float Tn = fmaf(-a, T, T);
         const bool stop = Tn < kTStop;  // T >= kTStop always, so stop implies a > 0
         done = done || stop;
@@ -225,7 +226,7 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
         C2 = fmaf(w, sc.z, C2);
         if (DEPTH) D = fmaf(w, sb.z, D);
         T = stop ? T : Tn;
-        last_j = (a > 0.f) ? (uint32_t)(j + 1) : last_j;
+        last_j = (valid && !stop) ? (uint32_t)(j + 1) : last_j;  // a > 0, as masks
       }
       last = last_j ? (uint32_t)(b0 + c0) + last_j : last;
       if (__all(done)) break;
