@@ -435,15 +435,15 @@ __global__ void k_view_counts(const uint32_t* __restrict__ pos, const uint32_t* 
 }
 
 // ---------------------------------------------------------------- emit ----
-// One block per 128 consecutive records. The block lays out its records'
+// One block per 64 consecutive records. The block lays out its records'
 // tile rows in LDS (first tile, offset of the row's first instance by a block
 // scan of the row widths) and an instance -> row map, then writes the
 // block's instances coalesced, one per thread in turn. A block whose rows or
 // instances do not fit writes whole rows per thread, or (too many rows)
 // walks each instance's record rows.
-constexpr int kEmitRecs = 128;
-constexpr int kEmitRows = 2048;
-constexpr int kEmitInst = 8192;
+constexpr int kEmitRecs = 64;
+constexpr int kEmitRows = 1024;
+constexpr int kEmitInst = 4096;
 
 __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32_t n_max,
                                                     const uint32_t* __restrict__ toff, const uint32_t* total,
@@ -457,8 +457,8 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
   __shared__ Footprint s_fp[kEmitRecs];
   __shared__ uint32_t s_row_off[kEmitRows + 1];  // first instance of each row (block-relative)
   __shared__ uint32_t s_row_tile[kEmitRows];     // global tile id of the row's first instance
-  __shared__ uint8_t s_row_rec[kEmitRows];
-  __shared__ uint16_t s_inst_row[kEmitInst];
+  __shared__ uint32_t s_row_rec[kEmitRows];
+  __shared__ uint32_t s_inst_row[kEmitInst];
   __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
   const uint32_t d0 = blockIdx.x * kEmitRecs;
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
         row_span(f, ty, exact, xa, xb);
         w = xb - xa;
         s_row_tile[j] = s_tb[lo] + ty * s_tw[lo] + xa;
-        s_row_rec[j] = (uint8_t)lo;
+        s_row_rec[j] = (uint32_t)lo;
       }
       uint32_t tot_w;
       const uint32_t ex = block_exclusive_scan(w, s_wave, tot_w);  // contains barriers
@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
     __syncthreads();
     if (carry <= (uint32_t)kEmitInst) {
       for (uint32_t j = threadIdx.x; j < rows; j += kThreads)
-        for (uint32_t k = s_row_off[j]; k < s_row_off[j + 1]; ++k) s_inst_row[k] = (uint16_t)j;
+        for (uint32_t k = s_row_off[j]; k < s_row_off[j + 1]; ++k) s_inst_row[k] = j;
       __syncthreads();
       const uint32_t iend = min(end, start + carry);  // equal: the counts come from the same spans
       for (uint32_t i = start + threadIdx.x; i < iend; i += kThreads) {
