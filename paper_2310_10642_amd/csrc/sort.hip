@@ -201,10 +201,18 @@ __global__ void k_compact(const uint32_t* __restrict__ act, const uint32_t* __re
 }
 
 // ---------------------------------------------------------- radix sort ----
+// Workgroups are dispatched round-robin over the 8 XCDs; the sort's blocks
+// take their ranges of tiles in XCD-major order, so the digit runs that
+// consecutive ranges write next to each other come from one XCD's L2.
+__device__ __forceinline__ uint32_t sort_block() {
+  const uint32_t g = gridDim.x;
+  return (g & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (g >> 3) + (blockIdx.x >> 3);
+}
+
 __device__ __forceinline__ void block_range(uint32_t n, int grid, uint32_t& t0, uint32_t& t1) {
   const uint32_t tiles = (n + kTileElems - 1) / kTileElems;
   const uint32_t tpb = (tiles + grid - 1) / grid;
-  t0 = min(blockIdx.x * tpb, tiles);
+  t0 = min(sort_block() * tpb, tiles);
   t1 = min(t0 + tpb, tiles);
 }
 
@@ -244,7 +252,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restr
   }
   __syncthreads();
   const uint32_t d = threadIdx.x;
-  counts[(size_t)d * gridDim.x + blockIdx.x] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+  counts[(size_t)d * gridDim.x + sort_block()] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
 }
 
 // Exclusive scan across a block of any multiple of 64 threads (<= 1024).
@@ -311,7 +319,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
   {
     uint32_t tot;
     const uint32_t base = block_exclusive_scan(digit_tot[dg], s_wave, tot);
-    run[dg] = base + counts[(size_t)dg * gridDim.x + blockIdx.x];
+    run[dg] = base + counts[(size_t)dg * gridDim.x + sort_block()];
   }
   uint32_t t0, t1;
   block_range(n, gridDim.x, t0, t1);
