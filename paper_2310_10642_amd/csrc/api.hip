@@ -24,6 +24,11 @@ struct DevBuf {
 struct g4d_ctx {
   g4d_options opts{};
   hipStream_t stream = nullptr;
+  // The colour pass runs on a second stream, overlapping the instance
+  // emission and tile sort; the rasterisers wait for it.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool side_pending = false;
   int device = 0;
   std::string err;
   bool hip_failed = false;
@@ -217,6 +222,27 @@ RenderParams make_params(g4d_ctx* c, int n_views) {
   return p;
 }
 
+// The main stream waits for a colour pass still running on the side stream.
+g4d_status join_side(g4d_ctx* c) {
+  if (!c->side_pending) return G4D_OK;
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  c->side_pending = false;
+  return G4D_OK;
+}
+
+// Starts the colour pass of the enqueued pairs on the side stream, after
+// everything enqueued so far on the main stream (the gather in particular).
+g4d_status fork_colour(g4d_ctx* c, const RenderParams& p) {
+  if (p.flow || p.n == 0) return G4D_OK;
+  HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  launch_colour(p, P<int32_t>(c->slot), P<float4>(c->cdir), P<Record>(c->rec_sorted), c->side);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+  c->side_pending = true;
+  return G4D_OK;
+}
+
 int round_tiles(const g4d_ctx* c, int v0, int v1) {
   int64_t t = 0;
   for (int v = v0; v < v1; ++v) t += (int64_t)c->views_h[v].tiles_x * c->views_h[v].tiles_y;
@@ -227,6 +253,8 @@ int round_tiles(const g4d_ctx* c, int v0, int v1) {
 // primitive) pair, compact the active ones, sort them by depth, gather the
 // records in that order and scan their tile counts. Counts stay on the device.
 g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
+  g4d_status st = join_side(c);  // the last colour pass writes buffers reused below
+  if (st) return st;
   c->bound = -1;
   hipStream_t s = c->stream;
   const int nv = v1 - v0;
@@ -237,7 +265,6 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
     tile_base += d.tiles_x * d.tiles_y;
   }
   const uint64_t vn = (uint64_t)c->n * nv;
-  g4d_status st;
   if ((st = ensure(c, c->views_d, sizeof(ViewDev) * nv))) return st;
   if ((st = ensure(c, c->act, 4 * vn))) return st;
   if ((st = ensure(c, c->pos, 4 * vn))) return st;
@@ -278,6 +305,7 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
   // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
   launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
                 P<int32_t>(c->slot), P<uint32_t>(c->tcount), c->ellipse_cull, cnt + kCntInst64, (int)c->n, s);
+  if ((st = fork_colour(c, p))) return st;
   launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
               P<uint32_t>(c->scan_scratch), s);
   stage_end(c, G4D_STAGE_BINNING);
@@ -341,6 +369,8 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
 
 g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, float* out_depth, float* out_alpha) {
   hipStream_t s = c->stream;
+  g4d_status st = join_side(c);  // the records' colours
+  if (st) return st;
   launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, P<uint32_t>(c->counters) + kCntMaxList, s);
   // 9. rasterise the round's views into their places in the outputs
   stage_begin(c);
@@ -437,7 +467,12 @@ g4d_status g4d_create(const g4d_options* opts, void* hip_stream, g4d_ctx** out) 
   g4d_ctx* c = new g4d_ctx();
   c->opts = *opts;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
     return G4D_EHIP;
   }
@@ -453,6 +488,7 @@ g4d_status g4d_create(const g4d_options* opts, void* hip_stream, g4d_ctx** out) 
 g4d_status g4d_destroy(g4d_ctx* c) {
   if (!c) return G4D_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->side);
   DevBuf* bufs[] = {&c->views_d, &c->act, &c->pos, &c->dkey, &c->rec, &c->slot, &c->ckey, &c->cval, &c->ckey2,
                     &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
                     &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
@@ -466,6 +502,9 @@ g4d_status g4d_destroy(g4d_ctx* c) {
   }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->open_ev) (void)hipEventDestroy(c->open_ev);
+  (void)hipEventDestroy(c->ev_fork);
+  (void)hipEventDestroy(c->ev_join);
+  (void)hipStreamDestroy(c->side);
   delete c;
   return G4D_OK;
 }
@@ -684,6 +723,7 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(a_max)))) return st;
     stage_begin(c);
     launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, kGrad2dStride, a_max, s);
+    if ((st = join_side(c))) return st;  // the records' colours of a round binned again
     launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
@@ -924,6 +964,7 @@ g4d_status g4d_debug_copy(g4d_ctx* c, int32_t what, void* host_dst, int64_t byte
   if (st) return st;
   if (bytes != want) return fail(c, G4D_EINVAL, "size mismatch");
   if (bytes == 0) return G4D_OK;
+  if ((st = join_side(c))) return st;
   const void* src = nullptr;
   switch (what) {
     case G4D_DBG_RECORDS: src = c->rec_sorted.ptr; break;

@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
       slot[idx] = -1;
       continue;
     }
-    // colour: k_colour fills c.xyz from the view direction and t - mu_t
+    // colour: k_colour fills c.xyz of the record's depth-ordered copy from
+    // the view direction and t - mu_t
     r.c = make_float4(0.f, 0.f, 0.f, __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
     cdir[idx] = make_float4(g.dir[0], g.dir[1], g.dir[2], g.dt);
     rec[idx] = r;
@@ -107,8 +108,8 @@ constexpr int kColourViews = 8;  // views whose loads k_colour issues together
 // LDS with 16-byte loads, and each lane takes its [n][4 sub + i][3] from
 // there. Per active view every lane evaluates the basis, weights its four
 // functions by the Fourier terms, and a quad sum gives c = max(0, 0.5 + sum).
-__global__ void __launch_bounds__(256) k_colour(RenderParams p, const uint32_t* __restrict__ act,
-                                                const float4* __restrict__ cdir, Record* __restrict__ rec) {
+__global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* __restrict__ slot,
+                                                const float4* __restrict__ cdir, Record* __restrict__ rec_sorted) {
   __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
@@ -133,17 +134,16 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const uint32_t* 
   // views eight at a time: all flags, then the directions of the active
   // ones, are loaded before any is used, so the loads overlap
   for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
-    uint32_t on[kColourViews];
+    int on[kColourViews];
     float4 cds[kColourViews];
 #pragma unroll
-    for (int w = 0; w < kColourViews; ++w) on[w] = v0 + w < p.n_views ? act[(size_t)(v0 + w) * p.n + gidx] : 0u;
+    for (int w = 0; w < kColourViews; ++w) on[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
 #pragma unroll
     for (int w = 0; w < kColourViews; ++w)
-      cds[w] = on[w] ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
+      cds[w] = on[w] >= 0 ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
 #pragma unroll
     for (int w = 0; w < kColourViews; ++w) {
-      if (!on[w]) continue;  // uniform per quad
-      const size_t idx = (size_t)(v0 + w) * p.n + gidx;
+      if (on[w] < 0) continue;  // uniform per quad
       const float4 cd = cds[w];
       float Y[16], cs[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const uint32_t* 
         col[c] = quad_sum(acc);
       }
       if (sub == 0) {
-        float* o = reinterpret_cast<float*>(&rec[idx].c);
+        float* o = reinterpret_cast<float*>(&rec_sorted[on[w]].c);
         o[0] = fmaxf(col[0] + kColorOffset, 0.f);
         o[1] = fmaxf(col[1] + kColorOffset, 0.f);
         o[2] = fmaxf(col[2] + kColorOffset, 0.f);
@@ -178,9 +178,13 @@ void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Rec
   if (p.n == 0) return;
   const int bs = 256;
   hipLaunchKernelGGL(k_preprocess, dim3((p.n + bs - 1) / bs), dim3(bs), 0, s, p, act, dkey, rec, slot, cdir);
-  if (!p.flow)
-    hipLaunchKernelGGL(k_colour, dim3((unsigned)((p.n + kColourPrims - 1) / kColourPrims)), dim3(256), 0, s, p, act,
-                       cdir, rec);
+}
+
+void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdir, Record* rec_sorted,
+                   hipStream_t s) {
+  if (p.n == 0 || p.flow) return;
+  hipLaunchKernelGGL(k_colour, dim3((unsigned)((p.n + kColourPrims - 1) / kColourPrims)), dim3(256), 0, s, p, slot,
+                     cdir, rec_sorted);
 }
 
 }  // namespace g4d
