@@ -270,8 +270,10 @@ g4d_status g4d_get_tuning(g4d_ctx* ctx, int32_t key, int32_t* value);
 /* Per-stage GPU time accumulated since stage timing was switched on
  * (synchronises the stream). ms_out and launches_out: host [G4D_NUM_STAGES]. */
 enum {
-  G4D_STAGE_PREPROCESS = 0,   /* slice, project, colour, cull */
-  G4D_STAGE_BINNING = 1,      /* compaction, depth sort, emission, tile sort, ranges */
+  G4D_STAGE_PREPROCESS = 0,   /* slice, project, cull (geometry) */
+  G4D_STAGE_BINNING = 1,      /* compaction, depth sort, emission, tile sort, ranges; the
+                               * 4DSH colour of the active records runs on a second stream
+                               * alongside, and the forward rasteriser waits for it */
   G4D_STAGE_RASTER_FWD = 2,
   G4D_STAGE_RASTER_BWD = 3,
   G4D_STAGE_PREPROCESS_BWD = 4,
