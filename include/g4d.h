@@ -120,8 +120,9 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
  *   out_alpha  device [sum_v H_v*W_v] or NULL: 1 - final transmittance
  * Keeps per-pixel final transmittance and last-contributor count for backward.
  * Views are processed in rounds of consecutive views: a round holds at most
- * G4D_TUNE_ROUND_PAIRS (view, primitive) pairs (but at least one view) and at
- * most G4D_TUNE_ROUND_INSTANCES tile instances; the first round takes at most
+ * G4D_TUNE_ROUND_PAIRS (view, primitive) pairs (but at least one view), at
+ * most G4D_TUNE_ROUND_INSTANCES tile instances and at most 2^16 16x16 tiles
+ * (unless one view alone has more); the first round takes at most
  * 16 views, later ones are sized from the instances per view seen so far, and
  * a round over the instance cap is shrunk and binned again. Each view's
  * result does not depend on the grouping. Synchronises the stream once per binning attempt, to size the

@@ -94,6 +94,9 @@ constexpr int kCntOverflow = 7;   // sticky: a sync-free render exceeded the ins
 constexpr int kCntViews = 8;      // per-view active counts follow
 constexpr int kMaxViews = 4096;
 constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the device
+// Tiles per round (unless one view alone has more): tile ids then fit 16
+// bits, and the instance sort by tile takes two 8-bit passes.
+constexpr int64_t kRoundTiles = int64_t(1) << 16;
 
 g4d_status fail(g4d_ctx* c, g4d_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -346,13 +349,19 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   // 6. emit (tile, record) instances; 7. stable sort by tile; 8. ranges
   stage_begin(c);
   launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
-  launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, P<Record>(c->rec_sorted),
-              P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), c->ellipse_cull, P<uint32_t>(c->ikey),
-              P<uint32_t>(c->ival), s);
+  // the instances are emitted into whichever buffer pair makes the sort's
+  // last pass land in (ikey, ival), so no copy follows an odd pass count
   const int tile_bits = ceil_log2((uint32_t)tiles);
+  const bool odd = radix_passes(0, tile_bits) & 1;
+  uint32_t* ek = P<uint32_t>(odd ? c->ikey2 : c->ikey);
+  uint32_t* ev = P<uint32_t>(odd ? c->ival2 : c->ival);
+  uint32_t* ak = P<uint32_t>(odd ? c->ikey : c->ikey2);
+  uint32_t* av = P<uint32_t>(odd ? c->ival : c->ival2);
+  launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, P<Record>(c->rec_sorted),
+              P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), c->ellipse_cull, ek, ev, s);
   const int g_tile = radix_grid(cap, c->sort_blocks);
-  radix_sort(P<uint32_t>(c->ikey), P<uint32_t>(c->ival), P<uint32_t>(c->ikey2), P<uint32_t>(c->ival2), cnt + kCntI,
-             cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s);
+  radix_sort(ek, ev, ak, av, cnt + kCntI, cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s,
+             /*copy_back=*/false);
   launch_ranges(cnt + kCntI, cap, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
   if (c->heavy_first) {
     // workgroups take the tiles with the longest lists first, so the launch
@@ -649,16 +658,25 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
     return G4D_OK;
   }
 
-  // Rounds of consecutive views under the pair and instance caps. The first
-  // round takes at most 16 views; each next round's size is predicted from
-  // the last one's instances per view; a round over the instance cap is
-  // shrunk in proportion and binned again.
+  // Rounds of consecutive views under the pair and instance caps, and of at
+  // most 2^16 tiles (a single larger view aside), so that the instance sort
+  // by tile takes two 8-bit passes. The first round takes at most 16 views;
+  // each next round's size is predicted from the last one's instances per
+  // view; a round over the instance cap is shrunk in proportion and binned
+  // again.
   const uint64_t inst_cap = (uint64_t)c->round_instances;
   const int by_pairs = (int)std::min<int64_t>(n_views, std::max<int64_t>(1, c->round_pairs / std::max<int64_t>(c->n, 1)));
   // the first round is kept modest: an over-full attempt costs a preprocess
   int k_next = std::min(by_pairs, 16);
   for (int v0 = 0; v0 < n_views;) {
     int k = std::min(k_next, n_views - v0);
+    for (int64_t t = 0, j = 0; j < k; ++j) {
+      t += (int64_t)c->views_h[v0 + j].tiles_x * c->views_h[v0 + j].tiles_y;
+      if (t > kRoundTiles && j > 0) {
+        k = (int)j;
+        break;
+      }
+    }
     uint32_t A = 0;
     uint64_t inst = 0;
     for (;;) {

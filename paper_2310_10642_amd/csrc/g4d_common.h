@@ -96,11 +96,15 @@ void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint3
                  uint32_t* total, uint32_t* scratch, hipStream_t s);
 void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dkey, uint32_t n,
                     uint32_t* ckey, uint32_t* cval, hipStream_t s);
-// LSD radix sort of (key, value) pairs on bits [bit0, bit1); result ends in keys/vals (ping-pong via alt).
+// LSD radix sort of (key, value) pairs on bits [bit0, bit1) in 8-bit passes
+// that ping-pong via alt; the result ends in keys/vals, copied back after an
+// odd number of passes unless copy_back is false (then it is in the alt pair).
 size_t radix_scratch_words(int grid);
 int radix_grid(uint32_t n_max, int max_blocks);
+int radix_passes(int bit0, int bit1);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
-                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s);
+                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
+                bool copy_back = true);
 // Depth-ordered records, slot map (view*n + index -> depth position), tiles per record,
 // and the 64-bit instance total (to detect 32-bit overflow) in inst64[0..1].
 // exact: count only the rectangle's tiles the record's alpha-floor ellipse reaches.

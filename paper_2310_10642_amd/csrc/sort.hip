@@ -668,10 +668,13 @@ int radix_grid(uint32_t n_max, int max_blocks) {
   return need < 1 ? 1 : (need < max_blocks ? need : max_blocks);
 }
 
+int radix_passes(int bit0, int bit1) { return bit1 > bit0 ? (bit1 - bit0 + 7) / 8 : 0; }
+
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
-                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s) {
+                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s, bool copy_back) {
   // Passes ping-pong between the two buffers; an odd pass count ends with a
-  // copy back so the result is always in (keys, vals).
+  // copy back so the result is in (keys, vals), unless the caller takes it
+  // from (keys_alt, vals_alt).
   uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
   int passes = 0;
   for (int b = bit0; b < bit1; b += 8) {
@@ -684,7 +687,7 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
     t = vin; vin = vout; vout = t;
     ++passes;
   }
-  if (passes & 1) launch_copy_pairs(kin, vin, keys, vals, n_dev, n_max, s);
+  if ((passes & 1) && copy_back) launch_copy_pairs(kin, vin, keys, vals, n_dev, n_max, s);
 }
 
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
