@@ -289,7 +289,8 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
 
   launch_set_views(vr.data(), nv, P<ViewDev>(c->views_d), s);
   launch_fill_u32(cnt, 4, 0u, s);
-  // 1. per (view, primitive): cull, slice, project, colour
+  // 1. per (view, primitive): cull, slice, project (the colour follows the
+  //    gather, on the second stream)
   stage_begin(c);
   launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot),
                     P<float4>(c->cdir), s);

@@ -1,11 +1,13 @@
-// Per-primitive stage of the 4D Gaussian render (one thread per primitive,
-// looping over the views of a batch so the parameters are read once):
-// 4D covariance Sigma = R S S^T R^T with R = L(q_l) R(q_r) (Sec. 3.2,
-// "Representation of 4D Gaussian"), temporal marginal and filter (Sec. 3.2
-// and Sec. 4.2), conditional 3D Gaussian at t (Sec. 3.2), EWA projection
-// (Eqs. 3-4), footprint and tile rectangle, and the 4D spherindrical-harmonic
-// colour (Sec. 3.2) -- or, for a flow render, the image-plane displacement of
-// the conditional mean (Sec. 4.3). The backward is in preprocess_bwd.hip.
+// Per-primitive stages of the 4D Gaussian render. k_preprocess (one thread
+// per primitive, looping over the views of a batch so the parameters are
+// read once): 4D covariance Sigma = R S S^T R^T with R = L(q_l) R(q_r)
+// (Sec. 3.2, "Representation of 4D Gaussian"), temporal marginal and filter
+// (Sec. 3.2 and Sec. 4.2), conditional 3D Gaussian at t (Sec. 3.2), EWA
+// projection (Eqs. 3-4), footprint and tile rectangle -- and, for a flow
+// render, the image-plane displacement of the conditional mean (Sec. 4.3).
+// k_colour: the 4D spherindrical-harmonic colour (Sec. 3.2) of the active
+// pairs, written into their depth-ordered records once the gather has placed
+// them. The backward is in preprocess_bwd.hip.
 #include "shade.h"
 
 namespace g4d {
