@@ -241,6 +241,35 @@ def test_batched_equals_per_view():
         assert nb == 0 or np.linalg.norm(a - b) <= 1e-5 * nb, name
 
 
+def test_round_tile_cap():
+    """Thirteen 1352x1014 views (70 720 tiles) take two rounds under the
+    2^16-tile cap that keeps the instance sort at two passes; every view equals
+    its own single-view render bit for bit and the gradients sum."""
+    _say("[round tile cap, 300k x 13 views]")
+    wl = scenegen.bench_workload(13)
+    r, _ = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    rgb_b, _, _ = r.render(wl.cameras, times, depth=False, alpha=False)
+    s = r.stats()
+    _say(f"  rounds {s['rounds']}, tiles {s['tiles']}")
+    assert s["rounds"] == 2 and s["tiles"] == 13 * 5440
+    views_b = [_np(x[0]) for x in r.split(rgb_b, None, None)]
+    rng = np.random.default_rng(13)
+    dl = rng.uniform(-1, 1, rgb_b.numel()).astype(np.float32)
+    gb = [x.clone() for x in r.backward(torch.from_numpy(dl).cuda())]
+    gsum = [torch.zeros_like(x) for x in gb]
+    o = 0
+    for v, (c, t) in enumerate(zip(wl.cameras, times)):
+        rgb, _, _ = r.render([c], [t], depth=False, alpha=False)
+        assert np.array_equal(_np(rgb).reshape(views_b[v].shape), views_b[v]), v
+        n = 3 * c.width * c.height
+        g = r.backward(torch.from_numpy(dl[o:o + n]).cuda())
+        o += n
+        for a, b in zip(gsum, g):
+            a += b
+    _close_grads(gb, gsum)
+
+
 def test_empty_and_degenerate_inputs():
     _say("[edge cases]")
     bg = (0.25, 0.5, 0.75)
