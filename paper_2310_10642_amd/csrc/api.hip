@@ -301,14 +301,14 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
               P<uint32_t>(c->scan_scratch), s);
   launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
                  P<uint32_t>(c->cval), s);
-  launch_view_counts(P<uint32_t>(c->pos), P<uint32_t>(c->act), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews, s);
+  launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews, s);
   // 3. stable sort by depth
   const int g_depth = radix_grid((uint32_t)vn, c->sort_blocks);
   radix_sort(P<uint32_t>(c->ckey), P<uint32_t>(c->cval), P<uint32_t>(c->ckey2), P<uint32_t>(c->cval2), cnt + kCntA,
              (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
   // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
   launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
-                P<int32_t>(c->slot), P<uint32_t>(c->tcount), c->ellipse_cull, cnt + kCntInst64, (int)c->n, s);
+                P<int32_t>(c->slot), P<uint32_t>(c->tcount), c->ellipse_cull, cnt + kCntInst64, s);
   if ((st = fork_colour(c, p))) return st;
   launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
               P<uint32_t>(c->scan_scratch), s);

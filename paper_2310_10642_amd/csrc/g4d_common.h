@@ -109,9 +109,9 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
 // and the 64-bit instance total (to detect 32-bit overflow) in inst64[0..1].
 // exact: count only the rectangle's tiles the record's alpha-floor ellipse reaches.
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
-                   int32_t* slot, uint32_t* tcount, bool exact, uint32_t* inst64, int n_prims, hipStream_t s);
-void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, uint32_t n, const uint32_t* total,
-                        uint32_t* out, hipStream_t s);
+                   int32_t* slot, uint32_t* tcount, bool exact, uint32_t* inst64, hipStream_t s);
+void launch_view_counts(const uint32_t* pos, int n_views, uint32_t n, const uint32_t* total, uint32_t* out,
+                        hipStream_t s);
 // Instances beyond min(*total, cap) are not written; exact as for launch_gather.
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,

@@ -428,8 +428,8 @@ __global__ void __launch_bounds__(kThreads) k_gather(const uint32_t* n_dev, uint
 }
 
 // Active records per view from the compaction scan: pos[(v+1) n] - pos[v n].
-__global__ void k_view_counts(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ act, int n_views,
-                              uint32_t n, const uint32_t* total, uint32_t* __restrict__ out) {
+__global__ void k_view_counts(const uint32_t* __restrict__ pos, int n_views, uint32_t n, const uint32_t* total,
+                              uint32_t* __restrict__ out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n_views) return;
   if (n == 0) {
@@ -691,16 +691,15 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
 }
 
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
-                   int32_t* slot, uint32_t* tcount, bool exact, uint32_t* inst64, int n_prims, hipStream_t s) {
-  (void)n_prims;
+                   int32_t* slot, uint32_t* tcount, bool exact, uint32_t* inst64, hipStream_t s) {
   if (n_max == 0) return;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(n_max, kThreads)), dim3(kThreads), 0, s, n_dev, n_max, ids, rec,
                      rec_sorted, slot, tcount, exact, reinterpret_cast<unsigned long long*>(inst64));
 }
 
-void launch_view_counts(const uint32_t* pos, const uint32_t* act, int n_views, uint32_t n, const uint32_t* total,
-                        uint32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_view_counts, dim3(grid_for(n_views, 64)), dim3(64), 0, s, pos, act, n_views, n, total, out);
+void launch_view_counts(const uint32_t* pos, int n_views, uint32_t n, const uint32_t* total, uint32_t* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_view_counts, dim3(grid_for(n_views, 64)), dim3(64), 0, s, pos, n_views, n, total, out);
 }
 
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
