@@ -295,7 +295,9 @@ const char* g4d_last_error(const g4d_ctx* ctx);
  *                     u, v, z, opacity*p(t), conic00, conic01, conic11, rect x (x0 | x1<<16 as bits),
  *                     r, g, b, rect y (y0 | y1<<16 as bits)
  *   G4D_DBG_IDS       per active pair in depth order, uint32 view*n + primitive
- *   G4D_DBG_TILE_KEYS sorted instances, uint32 global tile id
+ *   G4D_DBG_TILE_KEYS sorted instances, uint32 global tile id, as delimited by
+ *                     the ranges (the sort's last pass writes ranges, not
+ *                     keys; a position no range covers reads 0xFFFFFFFF)
  *   G4D_DBG_TILE_VALS sorted instances, uint32 depth-order record index
  *   G4D_DBG_RANGES    per global tile, uint32 [start, end)
  *   G4D_DBG_PIX_T     per pixel (views concatenated), float32 final transmittance

@@ -349,11 +349,15 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   uint32_t* cnt = P<uint32_t>(c->counters);
   // 6. emit (tile, record) instances; 7. stable sort by tile; 8. ranges
   stage_begin(c);
-  launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
   // the instances are emitted into whichever buffer pair makes the sort's
-  // last pass land in (ikey, ival), so no copy follows an odd pass count
+  // last pass land in (ikey, ival), so no copy follows an odd pass count;
+  // that pass writes the tile ranges instead of the keys (one tile: no
+  // passes, the ranges come from the emitted keys)
   const int tile_bits = ceil_log2((uint32_t)tiles);
-  const bool odd = radix_passes(0, tile_bits) & 1;
+  const int passes = radix_passes(0, tile_bits);
+  const bool odd = passes & 1;
+  if (passes) launch_ranges_init(P<uint2>(c->ranges), (uint32_t)tiles, s);
+  else launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
   uint32_t* ek = P<uint32_t>(odd ? c->ikey2 : c->ikey);
   uint32_t* ev = P<uint32_t>(odd ? c->ival2 : c->ival);
   uint32_t* ak = P<uint32_t>(odd ? c->ikey : c->ikey2);
@@ -361,9 +365,13 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, P<Record>(c->rec_sorted),
               P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), c->ellipse_cull, ek, ev, s);
   const int g_tile = radix_grid(cap, c->sort_blocks);
-  radix_sort(ek, ev, ak, av, cnt + kCntI, cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s,
-             /*copy_back=*/false);
-  launch_ranges(cnt + kCntI, cap, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+  if (passes) {
+    radix_sort(ek, ev, ak, av, cnt + kCntI, cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s,
+               /*copy_back=*/false, P<uint2>(c->ranges));
+    launch_ranges_fix(P<uint2>(c->ranges), (uint32_t)tiles, s);
+  } else {
+    launch_ranges(cnt + kCntI, cap, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+  }
   if (c->heavy_first) {
     // workgroups take the tiles with the longest lists first, so the launch
     // does not end on a few heavy tiles
@@ -984,11 +992,24 @@ g4d_status g4d_debug_copy(g4d_ctx* c, int32_t what, void* host_dst, int64_t byte
   if (bytes != want) return fail(c, G4D_EINVAL, "size mismatch");
   if (bytes == 0) return G4D_OK;
   if ((st = join_side(c))) return st;
+  if (what == G4D_DBG_TILE_KEYS) {
+    // the sort's last pass writes the ranges, not the keys: each position
+    // gets the tile whose range covers it (0xFFFFFFFF where none does)
+    const g4d_ctx::Round& r = c->rounds[c->bound];
+    std::vector<uint2> rg((size_t)r.tiles);
+    HIPCHK(c, hipMemcpyAsync(rg.data(), c->ranges.ptr, sizeof(uint2) * rg.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint32_t* keys = static_cast<uint32_t*>(host_dst);
+    const uint64_t n = (uint64_t)bytes / 4;
+    std::fill(keys, keys + n, 0xFFFFFFFFu);
+    for (uint32_t t = 0; t < (uint32_t)rg.size(); ++t)
+      for (uint64_t p = rg[t].x; p < rg[t].y && p < n; ++p) keys[p] = t;
+    return G4D_OK;
+  }
   const void* src = nullptr;
   switch (what) {
     case G4D_DBG_RECORDS: src = c->rec_sorted.ptr; break;
     case G4D_DBG_IDS: src = c->cval.ptr; break;
-    case G4D_DBG_TILE_KEYS: src = c->ikey.ptr; break;
     case G4D_DBG_TILE_VALS: src = c->ival.ptr; break;
     case G4D_DBG_RANGES: src = c->ranges.ptr; break;
     case G4D_DBG_PIX_T: src = c->pix_t.ptr; break;

@@ -99,12 +99,17 @@ void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dk
 // LSD radix sort of (key, value) pairs on bits [bit0, bit1) in 8-bit passes
 // that ping-pong via alt; the result ends in keys/vals, copied back after an
 // odd number of passes unless copy_back is false (then it is in the alt pair).
+// With last_ranges (keys < 2^bit1, bit0 = 0, at least one pass, ranges set up
+// by launch_ranges_init) the last pass writes no keys: it bounds each key's
+// run in last_ranges[key] instead (launch_ranges_fix then empties the unused).
 size_t radix_scratch_words(int grid);
 int radix_grid(uint32_t n_max, int max_blocks);
 int radix_passes(int bit0, int bit1);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                 uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
-                bool copy_back = true);
+                bool copy_back = true, uint2* last_ranges = nullptr);
+void launch_ranges_init(uint2* ranges, uint32_t tiles, hipStream_t s);
+void launch_ranges_fix(uint2* ranges, uint32_t tiles, hipStream_t s);
 // Depth-ordered records, slot map (view*n + index -> depth position), tiles per record,
 // and the 64-bit instance total (to detect 32-bit overflow) in inst64[0..1].
 // exact: count only the rectangle's tiles the record's alpha-floor ellipse reaches.

@@ -305,7 +305,8 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
                                                             uint32_t* __restrict__ vals_out, const uint32_t* n_dev,
                                                             uint32_t n_max, int shift, int bits,
                                                             const uint32_t* __restrict__ counts,
-                                                            const uint32_t* __restrict__ digit_tot) {
+                                                            const uint32_t* __restrict__ digit_tot,
+                                                            uint2* __restrict__ ranges) {
   __shared__ uint32_t s_k[kTileElems], s_v[kTileElems];
   __shared__ uint32_t wcnt[4][256];
   __shared__ uint32_t run[256];
@@ -388,7 +389,14 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
         const uint32_t d = (key >> shift) & mask;
         const uint32_t p = run[d] + lp - tstart[d];
         if (p < n) {  // always true for consistent counts; keeps a ranking fault in bounds
-          keys_out[p] = key;
+          if (ranges) {
+            // last pass over the whole key: the staged tile is ordered by key,
+            // so the first and last of each key's run here bound its range
+            if (lp == 0 || s_k[lp - 1] != key) atomicMin(&ranges[key].x, p);
+            if (lp + 1 == nvalid || s_k[lp + 1] != key) atomicMax(&ranges[key].y, p + 1);
+          } else {
+            keys_out[p] = key;
+          }
           vals_out[p] = s_v[lp];
         }
       }
@@ -563,6 +571,20 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
   }
 }
 
+// Ranges filled by the last radix pass: (max, 0) before it, and tiles it did
+// not reach (no instances) set to (0, 0) after it.
+__global__ void k_ranges_init(uint2* __restrict__ ranges, uint32_t tiles) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) ranges[t] = make_uint2(0xFFFFFFFFu, 0u);
+}
+
+__global__ void k_ranges_fix(uint2* __restrict__ ranges, uint32_t tiles) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const uint2 r = ranges[t];
+  if (r.x > r.y) ranges[t] = make_uint2(0u, 0u);
+}
+
 __global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* __restrict__ ikey,
                          uint2* __restrict__ ranges) {
   // four consecutive keys per thread (one 16-byte load when in bounds)
@@ -671,7 +693,8 @@ int radix_grid(uint32_t n_max, int max_blocks) {
 int radix_passes(int bit0, int bit1) { return bit1 > bit0 ? (bit1 - bit0 + 7) / 8 : 0; }
 
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
-                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s, bool copy_back) {
+                uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s, bool copy_back,
+                uint2* last_ranges) {
   // Passes ping-pong between the two buffers; an odd pass count ends with a
   // copy back so the result is in (keys, vals), unless the caller takes it
   // from (keys_alt, vals_alt).
@@ -682,7 +705,7 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
     hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
     hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, scratch, grid, scratch + (size_t)256 * grid);
     hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b, bits,
-                       scratch, scratch + (size_t)256 * grid);
+                       scratch, scratch + (size_t)256 * grid, b + 8 >= bit1 ? last_ranges : nullptr);
     uint32_t* t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;
     ++passes;
@@ -708,6 +731,14 @@ void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, co
   if (n_max == 0) return;
   hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kEmitRecs)), dim3(kThreads), 0, s, n_dev, n_max, toff, total, cap,
                      rec_sorted, ids, (uint32_t)n_prims, views, exact, ikey, ival);
+}
+
+void launch_ranges_init(uint2* ranges, uint32_t tiles, hipStream_t s) {
+  if (tiles) hipLaunchKernelGGL(k_ranges_init, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles);
+}
+
+void launch_ranges_fix(uint2* ranges, uint32_t tiles, hipStream_t s) {
+  if (tiles) hipLaunchKernelGGL(k_ranges_fix, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles);
 }
 
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s) {

@@ -180,8 +180,13 @@ def test_binning_is_a_valid_stable_sort(name, mk_scene, mk_cam, t, bg):
                 may.add((tile, d))
     assert must <= got_set, sorted(must - got_set)[:10]
     assert got_set <= may, sorted(got_set - may)[:10]
+    # the ranges (keys are read back as the tile whose range covers them)
+    # cover every instance once, in tile order
+    assert (keys != 0xFFFFFFFF).all()
+    assert int((ranges[:, 1].astype(np.int64) - ranges[:, 0]).clip(min=0).sum()) == len(keys)
     for tid in range(ranges.shape[0]):
         s, e = ranges[tid]
+        assert e >= s
         if e > s:
             assert (keys[s:e] == tid).all()
             assert s == 0 or keys[s - 1] != tid
