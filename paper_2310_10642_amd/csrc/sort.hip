@@ -453,10 +453,9 @@ __global__ void k_view_counts(const uint32_t* __restrict__ pos, int n_views, uin
 // ---------------------------------------------------------------- emit ----
 // One block per 64 consecutive records. The block lays out its records'
 // tile rows in LDS (first tile, offset of the row's first instance by a block
-// scan of the row widths) and an instance -> row map, then writes the
-// block's instances coalesced, one per thread in turn. A block whose rows or
-// instances do not fit writes whole rows per thread, or (too many rows)
-// walks each instance's record rows.
+// scan of the row widths) and, chunk by chunk, an instance -> row map, then
+// writes the block's instances coalesced, one per thread in turn. A block
+// whose rows do not fit walks each instance's record rows.
 constexpr int kEmitRecs = 64;
 constexpr int kEmitRows = 1024;
 constexpr int kEmitInst = 4096;
@@ -527,24 +526,22 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
     }
     if (threadIdx.x == 0) s_row_off[rows] = carry;
     __syncthreads();
-    if (carry <= (uint32_t)kEmitInst) {
-      for (uint32_t j = threadIdx.x; j < rows; j += kThreads)
-        for (uint32_t k = s_row_off[j]; k < s_row_off[j + 1]; ++k) s_inst_row[k] = j;
+    // the block's instances in chunks of kEmitInst: each chunk's instances
+    // are mapped to their rows, then written coalesced, one per thread in turn
+    const uint32_t iend = min(end, start + carry);  // equal: the counts come from the same spans
+    for (uint32_t c0 = 0; start + c0 < iend; c0 += kEmitInst) {
+      const uint32_t c1 = min(carry, c0 + (uint32_t)kEmitInst);
+      if (c0) __syncthreads();  // the previous chunk's reads of the map are done
+      for (uint32_t j = threadIdx.x; j < rows; j += kThreads) {
+        const uint32_t a = max(s_row_off[j], c0), b = min(s_row_off[j + 1], c1);
+        for (uint32_t k = a; k < b; ++k) s_inst_row[k - c0] = j;
+      }
       __syncthreads();
-      const uint32_t iend = min(end, start + carry);  // equal: the counts come from the same spans
-      for (uint32_t i = start + threadIdx.x; i < iend; i += kThreads) {
-        const uint32_t k = i - start, j = s_inst_row[k];
+      const uint32_t ie = min(iend, start + c1);
+      for (uint32_t i = start + c0 + threadIdx.x; i < ie; i += kThreads) {
+        const uint32_t k = i - start, j = s_inst_row[k - c0];
         ikey[i] = s_row_tile[j] + (k - s_row_off[j]);
         ival[i] = d0 + s_row_rec[j];
-      }
-    } else {
-      for (uint32_t j = threadIdx.x; j < rows; j += kThreads) {
-        const uint32_t i0 = start + s_row_off[j], i1 = min(start + s_row_off[j + 1], end);
-        const uint32_t tile = s_row_tile[j], rec = d0 + s_row_rec[j];
-        for (uint32_t i = i0; i < i1; ++i) {
-          ikey[i] = tile + (i - i0);
-          ival[i] = rec;
-        }
       }
     }
   } else {
