@@ -54,6 +54,7 @@ struct g4d_ctx {
   int bound = -1;                // round whose records and bins are resident
   uint64_t A_total = 0, I_total = 0;
   std::vector<uint32_t> view_active;
+  uint32_t active_hint = 0;      // most active records seen in one view (sizes the depth sort's grid)
   int sort_blocks = 1024;
   int64_t round_pairs = int64_t(1) << 28;
   int64_t round_instances = int64_t(1) << 30;
@@ -302,8 +303,11 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
   launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
                  P<uint32_t>(c->cval), s);
   launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews, s);
-  // 3. stable sort by depth
-  const int g_depth = radix_grid((uint32_t)vn, c->sort_blocks);
+  // 3. stable sort by depth; its grid is sized from the active records seen
+  // so far (any grid gives the same order: blocks take ranges of the count
+  // the device holds)
+  const uint64_t est = c->active_hint ? std::min<uint64_t>(vn, (uint64_t)c->active_hint * nv * 5 / 4 + 4096) : vn;
+  const int g_depth = radix_grid((uint32_t)est, c->sort_blocks);
   radix_sort(P<uint32_t>(c->ckey), P<uint32_t>(c->cval), P<uint32_t>(c->ckey2), P<uint32_t>(c->cval2), cnt + kCntA,
              (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
   // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
@@ -327,6 +331,7 @@ g4d_status read_pairs(g4d_ctx* c, int v0, int nv, uint32_t& A, uint64_t& inst64)
   A = c->counters_h[kCntA];
   std::memcpy(&inst64, c->counters_h + kCntInst64, sizeof(inst64));
   std::copy(c->counters_h + kCntViews, c->counters_h + kCntViews + nv, c->view_active.begin() + v0);
+  for (int v = 0; v < nv; ++v) c->active_hint = std::max(c->active_hint, c->counters_h[kCntViews + v]);
   return G4D_OK;
 }
 
@@ -547,6 +552,7 @@ g4d_status g4d_set_primitives(g4d_ctx* c, int64_t n, const float* means4, const 
     if (!aligned4(opacity_logit) || !aligned4(coeffs)) return fail(c, G4D_EINVAL, "misaligned pointer");
   }
   c->n = n;
+  c->active_hint = 0;
   c->means4 = means4;
   c->log_scales4 = log_scales4;
   c->q_left = q_left;
