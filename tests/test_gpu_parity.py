@@ -275,6 +275,48 @@ def test_round_tile_cap():
     _close_grads(gb, gsum)
 
 
+def test_autograd_function():
+    """g4d.render through torch.autograd: the parameters' .grad equal the
+    library's backward for the same output gradients (rgb, depth, alpha of two
+    views); a central difference along the colour coefficients, which enter
+    the image linearly inside the clamp, matches the directional derivative;
+    and a render in between makes the pending backward an error."""
+    _say("[autograd function]")
+    from paper_2310_10642_amd import g4d
+    scene = _big_splat_scene(11, 3000, grow=0.6, sh=3, to=2)
+    # colours kept well above the clamp at 0, where the image is not smooth in the coefficients
+    scene.coeffs[:, 0, :] += np.float32(1.5)
+    cams = [scenegen.look_at_camera((0.5, 0.3, 3.4), 72, 56), scenegen.look_at_camera((-1.0, 0.2, 3.3), 48, 64)]
+    times = [0.3, 0.7]
+    r = g4d.Renderer(scene.sh_degree, scene.t_order, scene.t_period)
+    leaves = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+              for a in (scene.means4, scene.log_scales4, scene.q_left, scene.q_right, scene.opacity_logit,
+                        scene.coeffs)]
+    rgb, dep, alp = g4d.render(r, cams, times, *leaves)
+    rng = np.random.default_rng(21)
+    w = [torch.from_numpy(rng.uniform(-1, 1, t.numel()).astype(np.float32)).cuda() for t in (rgb, dep, alp)]
+    ((rgb * w[0]).sum() + (dep * w[1]).sum() + (alp * w[2]).sum()).backward()
+    direct = [x.clone() for x in r.backward(*w)]
+    _close_grads([x.grad for x in leaves], direct)
+    # directional derivative along the coefficients
+    d = torch.from_numpy(rng.normal(size=scene.coeffs.shape).astype(np.float32)).cuda()
+    eps = 2e-4
+
+    def f(coeffs):
+        with torch.no_grad():
+            o = g4d.render(r, cams, times, *leaves[:5], coeffs)
+            return float(sum((t.double() * wt.double()).sum() for t, wt in zip(o, w)))
+
+    fd = (f(leaves[5].detach() + eps * d) - f(leaves[5].detach() - eps * d)) / (2 * eps)
+    an = float((leaves[5].grad.double() * d.double()).sum())
+    _say(f"  directional derivative: analytic {an:.6g}, central difference {fd:.6g}")
+    assert abs(fd - an) <= 1e-2 * abs(an) + 1e-3
+    rgb2, _, _ = g4d.render(r, cams, times, *leaves)
+    g4d.render(r, cams, times, *leaves)
+    with pytest.raises(RuntimeError):
+        rgb2.sum().backward()
+
+
 def test_empty_and_degenerate_inputs():
     _say("[edge cases]")
     bg = (0.25, 0.5, 0.75)
