@@ -433,20 +433,22 @@ def test_batched_forward_1m_16_mixed_views_sampled():
 
 
 def test_batched_fwd_bwd_500k_8_views():
-    """500k primitives, 8 views at 1352x1014, L2 loss: the batched gradient
-    equals the sum of per-view gradients, and sampled tiles of two views
-    match the oracle in value and gradient."""
+    """500k primitives, 8 views at 1352x1014, L2 loss: the batched gradient,
+    taken through the torch.autograd wrapper, equals the sum of the per-view
+    plain backwards, and sampled tiles of two views match the oracle in value
+    and gradient."""
     _say("[500k, 8 views, fwd+bwd]")
+    from paper_2310_10642_amd import g4d
     wl = scenegen.make_workload(3)
     r, params = PT.gpu_setup(wl.scene)
     times = [float(x) for x in wl.times]
-    rgb, _, _ = r.render(wl.cameras, times, depth=False, alpha=False)
     target = torch.from_numpy(np.concatenate([x.reshape(-1) for x in wl.targets])).cuda()
-    loss = torch.zeros(1, device="cuda")
-    dl = torch.empty_like(rgb)
     scale = 1.0 / (3 * wl.cameras[0].width * wl.cameras[0].height)
-    r.image_loss(2, rgb, target, scale, loss, dl)          # L2, per-view mean, summed over views
-    gb = r.backward(dl)
+    leaves = [p.clone().requires_grad_(True) for p in params]
+    rgb = g4d.render(r, wl.cameras, times, *leaves)[0]
+    (scale * ((rgb - target) ** 2).sum()).backward()      # L2, per-view mean, summed over views
+    gb = [x.grad for x in leaves]
+    dl = (2.0 * scale) * (rgb.detach() - target)
     gsum = r.grad_buffers()
     o = 0
     for v, (c, t) in enumerate(zip(wl.cameras, times)):
