@@ -139,30 +139,29 @@ def other_workloads(log_fn, steps: int):
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t1) / n
         st = r.stats()
-        # a one-round batch also as a sync-free call captured into a HIP graph
+        # the batch also as a sync-free call captured into a HIP graph
         graph_sec = None
-        if st["rounds"] == 1:
-            try:
-                r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+        try:
+            r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+            step()
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
                 step()
-                torch.cuda.synchronize()
-                graph = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(graph):
-                    step()
+            graph.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(n):
                 graph.replay()
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                for _ in range(n):
-                    graph.replay()
-                torch.cuda.synchronize()
-                graph_sec = (time.perf_counter() - t1) / n
-                r.stats()  # raises if a replay overflowed the instance arena
-                del graph
-            except Exception as e:
-                log_fn(f"[bench] {wl.name}: graph replay unavailable: {e}")
-                graph_sec = None
-            finally:
-                r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
+            torch.cuda.synchronize()
+            graph_sec = (time.perf_counter() - t1) / n
+            r.stats()  # raises if a replay overflowed the instance arena
+            del graph
+        except Exception as e:
+            log_fn(f"[bench] {wl.name}: graph replay unavailable: {e}")
+            graph_sec = None
+        finally:
+            r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
         res[wl.name] = dict(kind=kind, ms_per_call=sec * 1e3, mpix_per_s=P / sec / 1e6, views=len(cams),
                             primitives=sc.n, rounds=st["rounds"], instances=st["instances"],
                             active_mean=float(np.mean(st["active_per_view"])), calls_timed=n,

@@ -227,13 +227,15 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *   G4D_TUNE_SYNC_FREE     1: render and render_backward read no device
  *                          count on the host and never synchronise, so a
  *                          caller may capture them (with image_loss) into a
- *                          HIP graph. The batch is one round (n * n_views
- *                          within G4D_TUNE_ROUND_PAIRS) and the tile-instance
- *                          arena keeps the capacity that earlier synchronous
- *                          renders or G4D_TUNE_ARENA_INSTANCES gave it. A
- *                          render that needs more raises a sticky device
- *                          flag and outputs background only; get_stats
- *                          reports it as G4D_ECAPACITY and clears it.
+ *                          HIP graph. Rounds are planned from the views
+ *                          alone (G4D_TUNE_ROUND_PAIRS pairs and 2^16 tiles
+ *                          at most; the instance cap does not apply) and the
+ *                          tile-instance arena keeps the capacity that
+ *                          earlier synchronous renders or
+ *                          G4D_TUNE_ARENA_INSTANCES gave it. A round that
+ *                          needs more raises a sticky device flag and
+ *                          outputs background only; get_stats reports it as
+ *                          G4D_ECAPACITY and clears it.
  *                          Scratch that must grow grows (synchronising) when
  *                          the stream is not capturing; during capture that
  *                          is G4D_ECAPACITY, so make one uncaptured call of

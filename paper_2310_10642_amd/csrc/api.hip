@@ -59,6 +59,7 @@ struct g4d_ctx {
   int64_t round_pairs = int64_t(1) << 28;
   int64_t round_instances = int64_t(1) << 30;
   bool sync_free = false;          // no host read of device counts inside render/backward
+  bool totals_on_device = false;   // the last render was sync-free: its totals are device counters
   bool heavy_first = true;         // rasterise tiles by decreasing list length
   bool ellipse_cull = true;        // bin and walk by the alpha-floor ellipse, not its rectangle
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
@@ -94,6 +95,10 @@ constexpr int kCntMaxList = 6;    // longest tile list over the rounds of a rend
 constexpr int kCntOverflow = 7;   // sticky: a sync-free render exceeded the instance arena
 constexpr int kCntViews = 8;      // per-view active counts follow
 constexpr int kMaxViews = 4096;
+// after the views: a sync-free render's totals over its rounds, active
+// records (u32) and instances (64-bit, words +2, +3)
+constexpr int kCntTot = kCntViews + kMaxViews;
+constexpr int kCntWords = kCntTot + 4;
 constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the device
 // Tiles per round (unless one view alone has more): tile ids then fit 16
 // bits, and the instance sort by tile takes two 8-bit passes.
@@ -302,7 +307,10 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
               P<uint32_t>(c->scan_scratch), s);
   launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
                  P<uint32_t>(c->cval), s);
-  launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews, s);
+  // per-view counts: at the round's place in sync-free mode, which reads
+  // them only after the last round
+  launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews + (c->sync_free ? v0 : 0),
+                     s);
   // 3. stable sort by depth; its grid is sized from the active records seen
   // so far (any grid gives the same order: blocks take ranges of the count
   // the device holds)
@@ -325,14 +333,24 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
 // (synchronises the stream).
 g4d_status read_pairs(g4d_ctx* c, int v0, int nv, uint32_t& A, uint64_t& inst64) {
   uint32_t* cnt = P<uint32_t>(c->counters);
-  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (kCntViews + nv), hipMemcpyDeviceToHost,
-                           c->stream));
+  const int vb = kCntViews + (c->sync_free ? v0 : 0);  // where enqueue_pairs put the view counts
+  HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (vb + nv), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   A = c->counters_h[kCntA];
   std::memcpy(&inst64, c->counters_h + kCntInst64, sizeof(inst64));
-  std::copy(c->counters_h + kCntViews, c->counters_h + kCntViews + nv, c->view_active.begin() + v0);
-  for (int v = 0; v < nv; ++v) c->active_hint = std::max(c->active_hint, c->counters_h[kCntViews + v]);
+  std::copy(c->counters_h + vb, c->counters_h + vb + nv, c->view_active.begin() + v0);
+  for (int v = 0; v < nv; ++v) c->active_hint = std::max(c->active_hint, c->counters_h[vb + v]);
   return G4D_OK;
+}
+
+// Views [v0, v0 + k) cut to at most kRoundTiles tiles (at least one view).
+int cap_round_tiles(const g4d_ctx* c, int v0, int k) {
+  int64_t t = 0;
+  for (int j = 0; j < k; ++j) {
+    t += (int64_t)c->views_h[v0 + j].tiles_x * c->views_h[v0 + j].tiles_y;
+    if (t > kRoundTiles && j > 0) return j;
+  }
+  return k;
 }
 
 uint64_t arena_instances(const g4d_ctx* c) {
@@ -417,8 +435,6 @@ g4d_status resolve_round(g4d_ctx* c, g4d_ctx::Round& r) {
   if (st) return st;
   r.A = A;
   r.I = c->counters_h[kCntI];  // zero after an overflow
-  c->A_total = A;
-  c->I_total = r.I;
   return G4D_OK;
 }
 
@@ -499,7 +515,7 @@ g4d_status g4d_create(const g4d_options* opts, void* hip_stream, g4d_ctx** out) 
     delete c;
     return G4D_EHIP;
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->counters_h), (kCntViews + kMaxViews) * sizeof(uint32_t),
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->counters_h), kCntWords * sizeof(uint32_t),
                     hipHostMallocDefault) != hipSuccess) {
     delete c;
     return G4D_ENOMEM;
@@ -641,7 +657,7 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
   hipStream_t s = c->stream;
   g4d_status st;
   const bool fresh_counters = c->counters.ptr == nullptr;
-  if ((st = ensure(c, c->counters, sizeof(uint32_t) * (kCntViews + kMaxViews)))) return st;
+  if ((st = ensure(c, c->counters, sizeof(uint32_t) * kCntWords))) return st;
   if (fresh_counters) launch_fill_u32(P<uint32_t>(c->counters), kCntViews, 0u, s);  // the overflow flag starts clear
   if ((st = ensure(c, c->pix_t, 4 * pix))) return st;
   if ((st = ensure(c, c->pix_last, 4 * pix))) return st;
@@ -657,18 +673,27 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
   uint32_t* cnt = P<uint32_t>(c->counters);
   launch_fill_u32(cnt + kCntMaxList, 1, 0u, s);
 
+  c->totals_on_device = c->sync_free;
   if (c->sync_free) {
-    // One round; counts stay on the device and the arena keeps its capacity.
-    if ((uint64_t)c->n * n_views > (uint64_t)c->round_pairs)
-      return fail(c, G4D_ECAPACITY, "a sync-free render is one round: n * n_views exceeds the pair cap");
-    g4d_ctx::Round r{0, n_views, (int)tiles, kOnDevice, kOnDevice};
-    if ((st = enqueue_pairs(c, 0, n_views))) return st;
+    // Rounds planned from the views alone (pair and tile caps); counts stay
+    // on the device and add up there, and the arena keeps its capacity: a
+    // round over it raises the overflow flag and renders background only.
+    launch_fill_u32(cnt + kCntTot, kCntWords - kCntTot, 0u, s);
     const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(arena_instances(c), 1), 0xFFFFFFF0ull);
-    launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
-    if ((st = bin_tiles(c, r.tiles, (uint32_t)((uint64_t)c->n * n_views), (uint32_t)cap))) return st;
-    c->rounds.push_back(r);
-    c->bound = 0;
-    if ((st = rasterise_round(c, r, out_rgb, out_depth, out_alpha))) return st;
+    const int by_pairs =
+        (int)std::min<int64_t>(n_views, std::max<int64_t>(1, c->round_pairs / std::max<int64_t>(c->n, 1)));
+    for (int v0 = 0; v0 < n_views;) {
+      const int k = cap_round_tiles(c, v0, std::min(by_pairs, n_views - v0));
+      g4d_ctx::Round r{v0, v0 + k, round_tiles(c, v0, v0 + k), kOnDevice, kOnDevice};
+      if ((st = enqueue_pairs(c, v0, v0 + k))) return st;
+      launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
+      launch_add_totals(cnt + kCntA, cnt + kCntI, cnt + kCntTot, cnt + kCntTot + 2, s);
+      if ((st = bin_tiles(c, r.tiles, (uint32_t)((uint64_t)c->n * k), (uint32_t)cap))) return st;
+      c->rounds.push_back(r);
+      c->bound = (int)c->rounds.size() - 1;
+      if ((st = rasterise_round(c, r, out_rgb, out_depth, out_alpha))) return st;
+      v0 += k;
+    }
     c->have_render = true;
     return G4D_OK;
   }
@@ -684,14 +709,8 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
   // the first round is kept modest: an over-full attempt costs a preprocess
   int k_next = std::min(by_pairs, 16);
   for (int v0 = 0; v0 < n_views;) {
-    int k = std::min(k_next, n_views - v0);
-    for (int64_t t = 0, j = 0; j < k; ++j) {
-      t += (int64_t)c->views_h[v0 + j].tiles_x * c->views_h[v0 + j].tiles_y;
-      if (t > kRoundTiles && j > 0) {
-        k = (int)j;
-        break;
-      }
-    }
+    const int k0 = std::min(k_next, n_views - v0);
+    int k = cap_round_tiles(c, v0, k0);
     uint32_t A = 0;
     uint64_t inst = 0;
     for (;;) {
@@ -741,13 +760,19 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     const g4d_ctx::Round r = c->rounds[ri];
     const int nv = r.v1 - r.v0;
     if (c->bound != ri) {
-      uint32_t A = 0;
-      uint64_t inst = 0;
       if ((st = enqueue_pairs(c, r.v0, r.v1))) return st;
-      if ((st = read_pairs(c, r.v0, nv, A, inst))) return st;
-      if (A != r.A || inst != r.I)
-        return fail(c, G4D_ESTATE, "binning a round again gave other counts; primitives changed since render");
-      if ((st = bin_tiles(c, r.tiles, r.A, r.I))) return st;
+      if (r.A == kOnDevice) {  // a sync-free round: no host read
+        const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(arena_instances(c), 1), 0xFFFFFFF0ull);
+        launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
+        if ((st = bin_tiles(c, r.tiles, (uint32_t)((uint64_t)c->n * nv), (uint32_t)cap))) return st;
+      } else {
+        uint32_t A = 0;
+        uint64_t inst = 0;
+        if ((st = read_pairs(c, r.v0, nv, A, inst))) return st;
+        if (A != r.A || inst != r.I)
+          return fail(c, G4D_ESTATE, "binning a round again gave other counts; primitives changed since render");
+        if ((st = bin_tiles(c, r.tiles, r.A, r.I))) return st;
+      }
       c->bound = ri;
     }
     // records bound: exact for a synchronous round, every pair for a sync-free one
@@ -862,16 +887,22 @@ g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
   if (!c || !out) return G4D_EINVAL;
   if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
-  g4d_status st;
-  for (auto& r : c->rounds)
-    if ((st = resolve_round(c, r))) return st;
+  uint32_t* cnt = P<uint32_t>(c->counters);
+  if (c->totals_on_device) {
+    // a sync-free render: totals and per-view counts were added up on the device
+    HIPCHK(c, hipMemcpyAsync(c->counters_h + kCntViews, cnt + kCntViews, sizeof(uint32_t) * (kCntWords - kCntViews),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::copy(c->counters_h + kCntViews, c->counters_h + kCntViews + c->n_views, c->view_active.begin());
+    c->A_total = c->counters_h[kCntTot];
+    std::memcpy(&c->I_total, c->counters_h + kCntTot + 2, sizeof(uint64_t));
+  }
   out->n_views = c->n_views;
   out->active_total = (int64_t)c->A_total;
   out->instances = (int64_t)c->I_total;
   out->tiles = c->total_tiles;
   out->rounds = (int64_t)c->rounds.size();
   // longest list, overflow flag and fragment total need device reads
-  uint32_t* cnt = P<uint32_t>(c->counters);
   launch_fill_u32(cnt + kCntFrag, 2, 0u, c->stream);
   launch_sum_u32(P<uint32_t>(c->pix_last), (uint64_t)c->total_pix, reinterpret_cast<unsigned long long*>(cnt + kCntFrag),
                  c->stream);

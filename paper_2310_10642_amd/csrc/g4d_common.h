@@ -168,6 +168,8 @@ void launch_zero_counted(float* p, const uint32_t* n_dev, uint32_t floats_per_it
                          hipStream_t s);
 // If the 64-bit instance total at inst64 exceeds cap: *overflow = 1 and *n_inst = 0.
 void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s);
+// *a_tot += *a; *(uint64*)i_tot64 += *i (one thread).
+void launch_add_totals(const uint32_t* a, const uint32_t* i, uint32_t* a_tot, uint32_t* i_tot64, hipStream_t s);
 void launch_copy_pairs(const uint32_t* ka, const uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
                        uint32_t n_max, hipStream_t s);
 

@@ -44,6 +44,14 @@ __global__ void k_cap_check(const unsigned long long* __restrict__ inst64, uint3
   }
 }
 
+// A sync-free round's active records and instances added to the render's totals.
+__global__ void k_add_totals(const uint32_t* __restrict__ a, const uint32_t* __restrict__ i,
+                             uint32_t* __restrict__ a_tot, unsigned long long* __restrict__ i_tot) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *a_tot += *a;
+  *i_tot += *i;
+}
+
 __global__ void k_copy_pairs(const uint32_t* __restrict__ ka, const uint32_t* __restrict__ va,
                              uint32_t* __restrict__ kb, uint32_t* __restrict__ vb, const uint32_t* __restrict__ n_dev,
                              uint32_t n_max) {
@@ -86,6 +94,11 @@ void launch_zero_counted(float* p, const uint32_t* n_dev, uint32_t floats_per_it
 void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s) {
   hipLaunchKernelGGL(k_cap_check, dim3(1), dim3(64), 0, s, reinterpret_cast<const unsigned long long*>(inst64),
                      n_inst, overflow, (unsigned long long)cap);
+}
+
+void launch_add_totals(const uint32_t* a, const uint32_t* i, uint32_t* a_tot, uint32_t* i_tot64, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_totals, dim3(1), dim3(64), 0, s, a, i, a_tot,
+                     reinterpret_cast<unsigned long long*>(i_tot64));
 }
 
 void launch_copy_pairs(const uint32_t* ka, const uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,

@@ -275,6 +275,59 @@ def test_round_tile_cap():
     _close_grads(gb, gsum)
 
 
+def test_sync_free_rounds_and_graph():
+    """A sync-free render of thirteen full-size views plans its two rounds
+    from the tile cap alone: images, per-view counts and totals equal the
+    synchronous render's, its backward (which bins the first round again
+    without host reads) gives the same gradients, and the whole step
+    captured into a HIP graph replays it."""
+    _say("[sync-free rounds, 300k x 13 views]")
+    from paper_2310_10642_amd import g4d
+    wl = scenegen.bench_workload(13)
+    r, _ = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    P = sum(c.width * c.height for c in wl.cameras)
+    rng = np.random.default_rng(31)
+    dl = torch.from_numpy(rng.uniform(-1, 1, 3 * P).astype(np.float32)).cuda()
+    ref = [x.clone() for x in r.render(wl.cameras, times)]
+    s_ref = r.stats()
+    g_ref = [x.clone() for x in r.backward(dl)]
+    assert s_ref["rounds"] == 2
+    r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+    try:
+        outs = (torch.empty_like(ref[0]), torch.empty_like(ref[1]), torch.empty_like(ref[2]))
+        grads = r.grad_buffers()
+
+        def step():
+            r.render(wl.cameras, times, out=outs)
+            r.backward(dl, out=grads)
+
+        step()
+        torch.cuda.synchronize()
+        s_sf = r.stats()
+        for a, b in zip(ref, outs):
+            assert torch.equal(a, b)
+        for k in ("rounds", "active_total", "instances", "fragments", "max_tile_list", "active_per_view"):
+            assert s_ref[k] == s_sf[k], k
+        _close_grads(grads, g_ref)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for rep in range(2):
+            for t in (*outs, *grads):
+                t.fill_(float("nan"))
+            graph.replay()
+            torch.cuda.synchronize()
+            for a, b in zip(ref, outs):
+                assert torch.equal(a, b), rep
+            _close_grads(grads, g_ref)
+            _say(f"  replay {rep} ok")
+        del graph
+        assert r.stats()["instances"] == s_ref["instances"]
+    finally:
+        r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
+
+
 def test_autograd_function():
     """g4d.render through torch.autograd: the parameters' .grad equal the
     library's backward for the same output gradients (rgb, depth, alpha of two
