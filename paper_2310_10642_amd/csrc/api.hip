@@ -307,10 +307,10 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
               P<uint32_t>(c->scan_scratch), s);
   launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
                  P<uint32_t>(c->cval), s);
-  // per-view counts: at the round's place in sync-free mode, which reads
-  // them only after the last round
-  launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA, cnt + kCntViews + (c->sync_free ? v0 : 0),
-                     s);
+  // per-view counts: at the round's place for a sync-free render, which
+  // reads them only after its last round
+  launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA,
+                     cnt + kCntViews + (c->totals_on_device ? v0 : 0), s);
   // 3. stable sort by depth; its grid is sized from the active records seen
   // so far (any grid gives the same order: blocks take ranges of the count
   // the device holds)
@@ -333,7 +333,7 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
 // (synchronises the stream).
 g4d_status read_pairs(g4d_ctx* c, int v0, int nv, uint32_t& A, uint64_t& inst64) {
   uint32_t* cnt = P<uint32_t>(c->counters);
-  const int vb = kCntViews + (c->sync_free ? v0 : 0);  // where enqueue_pairs put the view counts
+  const int vb = kCntViews + (c->totals_on_device ? v0 : 0);  // where enqueue_pairs put the view counts
   HIPCHK(c, hipMemcpyAsync(c->counters_h, cnt, sizeof(uint32_t) * (vb + nv), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   A = c->counters_h[kCntA];
