@@ -91,7 +91,7 @@ def cpu_oracle_baseline(wl, seconds: float):
                 seconds=round(sum(ts), 2))
 
 
-def other_workloads(log_fn, steps: int):
+def other_workloads(log_fn, steps: int, cfgs=(2, 3, 4)):
     """The other seeded workloads in their own right (not the headline):
     batched forward of 1M primitives over 16 mixed views, batched fwd+bwd of
     500k over 8 views with an L2 loss, and one call rendering 3M primitives
@@ -103,7 +103,7 @@ def other_workloads(log_fn, steps: int):
 
     dev = torch.device("cuda", 0)
     res = {}
-    for cfg in (2, 3, 4):
+    for cfg in cfgs:
         t0 = time.perf_counter()
         wl = scenegen.make_workload(cfg)
         sc = wl.scene
@@ -206,6 +206,9 @@ def main():
                     help="skip the 1M x 16-view, 500k x 8-view and 3M x 240-view figures")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (counter calibration)")
+    ap.add_argument("--only-other", type=int, choices=(2, 3, 4), default=None,
+                    help="profiling aid: time only that other workload (2: 1M x 16 views, 3: 500k x 8 views, "
+                         "4: 3M x 240 views) and print its figures as the JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by view "
@@ -219,6 +222,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only_other is not None:
+        print(json.dumps(other_workloads(log, args.steps, (args.only_other,))), flush=True)
+        return
     if args.copy_probe_mb > 0:
         nfl = args.copy_probe_mb * (1 << 20) // 4
         src = torch.ones(nfl, device=dev)
