@@ -472,8 +472,9 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
   __shared__ Footprint s_fp[kEmitRecs];
   __shared__ uint32_t s_row_off[kEmitRows + 1];  // first instance of each row (block-relative)
   __shared__ uint32_t s_row_tile[kEmitRows];     // global tile id of the row's first instance
-  __shared__ uint32_t s_row_rec[kEmitRows];
-  __shared__ uint32_t s_inst_row[kEmitInst];
+  __shared__ uint8_t s_row_rec[kEmitRows];       // record of the row (block-relative, < kEmitRecs)
+  __shared__ uint16_t s_inst_row[kEmitInst];     // row of each instance of the chunk (< kEmitRows)
+  static_assert(kEmitRecs <= 256 && kEmitRows <= 65536, "narrow LDS maps: 21 KB, 7 workgroups per CU");
   __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
   const uint32_t d0 = blockIdx.x * kEmitRecs;
@@ -517,7 +518,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
         row_span(f, ty, exact, xa, xb);
         w = xb - xa;
         s_row_tile[j] = s_tb[lo] + ty * s_tw[lo] + xa;
-        s_row_rec[j] = (uint32_t)lo;
+        s_row_rec[j] = (uint8_t)lo;
       }
       uint32_t tot_w;
       const uint32_t ex = block_exclusive_scan(w, s_wave, tot_w);  // contains barriers
@@ -534,7 +535,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
       if (c0) __syncthreads();  // the previous chunk's reads of the map are done
       for (uint32_t j = threadIdx.x; j < rows; j += kThreads) {
         const uint32_t a = max(s_row_off[j], c0), b = min(s_row_off[j + 1], c1);
-        for (uint32_t k = a; k < b; ++k) s_inst_row[k - c0] = j;
+        for (uint32_t k = a; k < b; ++k) s_inst_row[k - c0] = (uint16_t)j;
       }
       __syncthreads();
       const uint32_t ie = min(iend, start + c1);
