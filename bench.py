@@ -211,8 +211,8 @@ def main():
                          "4: 3M x 240 views) and print its figures as the JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by view "
-              f"with one process per GPU, which this build does not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard by "
+              f"view with one process per GPU; only the one-GPU path exists)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

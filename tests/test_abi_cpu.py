@@ -73,3 +73,14 @@ def test_validation_before_any_hip_call():
     assert lib.g4d_create(ctypes.byref(o), None, ctypes.byref(h)) == g4d.G4D_EINVAL
     assert lib.g4d_render(None, 1, None, None, None, None, None) == g4d.G4D_EINVAL
     assert lib.g4d_destroy(None) == g4d.G4D_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before
+    touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert p.returncode == 2 and "one GPU only" in p.stderr
