@@ -85,6 +85,12 @@ typedef struct {
   int64_t max_tile_list;  /* longest per-tile list */
   int64_t fragments;      /* list entries visited per pixel up to its last contributor, summed */
   int64_t rounds;         /* view groups the render was binned and rasterised in */
+  int64_t culled_nonfinite; /* (view, primitive) pairs left out because a parameter is not finite:
+                             * every view of a primitive with a NaN or infinite mean, log scale,
+                             * quaternion component or opacity logit; the views in which a
+                             * primitive with a non-finite 4DSH coefficient passes every other
+                             * cull (it is rendered fully transparent). Such primitives receive
+                             * zero gradients. */
 } g4d_stats;
 
 /* Fills the defaults: L=3, N_t=2, T=1, t_cull=0.05, near=0.2, black background. */
@@ -132,7 +138,7 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
 g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
                       float* out_rgb, float* out_depth, float* out_alpha);
 
-/* Rendered optical flow (Sec. 4.3): for each view, the alpha blend of Eq. (6)
+/* Rendered optical flow (Sec. 4.4, "Ablation and analysis"): for each view, the alpha blend of Eq. (6)
  * (the render's weights, zero background) of every primitive's image-plane
  * displacement between t and t + frame_dt of its conditional mean
  * mu_xyz|t: f_i = pi(mu_c(t + frame_dt)) - pi(mu_c(t)) with pi the view's
@@ -304,8 +310,9 @@ const char* g4d_last_error(const g4d_ctx* ctx);
  *   G4D_DBG_RANGES    per global tile, uint32 [start, end)
  *   G4D_DBG_PIX_T     per pixel (views concatenated), float32 final transmittance
  *   G4D_DBG_PIX_LAST  per pixel, uint32 list entries up to the last contributor
- *   G4D_DBG_GRAD2D    after a backward: per active pair, 16 x float32
- *                     dL/du, dL/dv, dL/dconic00, 01, 11, dL/d(opacity*p), dL/dr, g, b, dL/dz, 0 x 6 */
+ *   G4D_DBG_GRAD2D    after a backward: per active pair, 16 x float64
+ *                     dL/du, dL/dv, dL/dconic00, 01, 11, dL/d(opacity*p), dL/dr, g, b, dL/dz, 0 x 5,
+ *                     blended flag (1 when densification statistics are on and the pair blended) */
 enum {
   G4D_DBG_RECORDS = 1, G4D_DBG_IDS = 2, G4D_DBG_TILE_KEYS = 3, G4D_DBG_TILE_VALS = 4,
   G4D_DBG_RANGES = 5, G4D_DBG_PIX_T = 6, G4D_DBG_PIX_LAST = 7, G4D_DBG_GRAD2D = 8

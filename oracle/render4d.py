@@ -36,10 +36,14 @@ import torch
 
 F64 = torch.float64
 TILE = 16
-# FP32 reach used by the parity margin policy: decisions closer than these to
-# their threshold may be taken either way by a float32 implementation.
-MARGIN_REL = 1e-5   # relative, for p(t), z, alpha floor, stop threshold
-MARGIN_PX = 2e-3    # pixels, for footprint radius and tile-edge decisions
+U32 = 2.0 ** -24    # unit roundoff of float32
+# Margins of the parity policy for the per-primitive decisions. An
+# implementation that evaluates these formulas in FP64 may still decide the
+# other way within: the thresholds it receives as float32 options (0.05f and
+# 0.2f differ from 0.05 and 0.2 by 1.5e-8, relative), and the last bits of
+# FP64 arithmetic in another order.
+MARGIN_REL = 1e-7   # relative: p(t) vs t_cull, z vs near, x/z vs the Jacobian limit
+MARGIN_PX = 1e-6    # pixels: 3 sqrt(lambda_max) vs an integer, rectangle edges vs tile edges
 IMG_TOL = 1e-4      # image tolerance the flags are sized for
 
 # Readings of points the paper leaves open (the same constants are restated,
@@ -308,11 +312,45 @@ def preprocess(params: Dict[str, torch.Tensor], cam: OCamera, t: float,
     dirs = dirs / dirs.norm(dim=-1, keepdim=True)
     color, color_raw = color_4dsh(params["coeffs"], dirs, t - mean4[:, 3], sh_degree, t_order, period)
     opac = torch.sigmoid(params["opacity_logit"]) * pt
-    return dict(u=u, v=v, z=z, conic=conic, opac=opac, color=color, color_raw=color_raw,
-                pt=pt, mu_c=mu_c, cov_c=cov_c, cov4=cov4, cov2=torch.stack([a2, b2, c2], -1),
-                radius=rad, rect=torch.stack([x0, y0, x1, y1], -1).long(), active=active,
-                rect_sure=rect_sure, rect_maybe=rect_maybe,
-                m_t=m_t, m_z=m_z, m_rad=m_rad, m_jac=m_jac)
+    out = dict(u=u, v=v, z=z, conic=conic, opac=opac, color=color, color_raw=color_raw,
+               pt=pt, mu_c=mu_c, cov_c=cov_c, cov4=cov4, cov2=torch.stack([a2, b2, c2], -1),
+               radius=rad, rect=torch.stack([x0, y0, x1, y1], -1).long(), active=active,
+               rect_sure=rect_sure, rect_maybe=rect_maybe,
+               m_t=m_t, m_z=m_z, m_rad=m_rad, m_jac=m_jac)
+    out.update(record_as_float32(out))
+    return out
+
+
+def _f32(x: torch.Tensor) -> torch.Tensor:
+    """The float32 value nearest to x (round to nearest even), as float64."""
+    return x.detach().to(torch.float32).to(F64)
+
+
+def _rounding_in_doubt(x: torch.Tensor, rel: float = 1e-12) -> torch.Tensor:
+    """x within rel of a float32 rounding midpoint: an FP64 evaluation in
+    another order (about 1e-15 relative here, 1e-12 leaves room for the
+    conditioning of the conic's inverse) may round it to the other
+    neighbour."""
+    x = x.detach()
+    x32 = x.to(torch.float32)
+    inf = torch.tensor(float("inf"), dtype=torch.float32)
+    up = torch.nextafter(x32, inf).to(F64)
+    dn = torch.nextafter(x32, -inf).to(F64)
+    c = x32.to(F64)
+    d = torch.minimum((x - 0.5 * (c + up)).abs(), (x - 0.5 * (c + dn)).abs())
+    return d <= rel * x.abs()
+
+
+def record_as_float32(pre) -> Dict[str, torch.Tensor]:
+    """The per-primitive values a GPU record holds when it evaluates the
+    geometry in FP64 and rounds each value to float32 once: u, v, z, the
+    conic and opacity * p(t), and whether any of them sits so close to a
+    rounding midpoint that the stored neighbour is in doubt."""
+    con = pre["conic"].detach()
+    doubt = _rounding_in_doubt(pre["u"]) | _rounding_in_doubt(pre["v"]) | _rounding_in_doubt(pre["z"])
+    doubt = doubt | _rounding_in_doubt(pre["opac"]) | _rounding_in_doubt(con).any(-1)
+    return dict(u32=_f32(pre["u"]), v32=_f32(pre["v"]), z32=_f32(pre["z"]), conic32=_f32(con),
+                opac32=_f32(pre["opac"]), rec_doubt=doubt)
 
 
 # ---------------------------------------------------------------------------
@@ -320,13 +358,69 @@ def preprocess(params: Dict[str, torch.Tensor], cam: OCamera, t: float,
 # ---------------------------------------------------------------------------
 @dataclass
 class Margins:
-    """Relative/absolute thresholds below which a decision counts as one that
-    FP32 arithmetic may legitimately take the other way."""
-    rel: float = 3e-5        # alpha vs the 1/255 floor (FP32 error of alpha is ~1e-6 |power|)
-    stop_rel: float = 3e-4   # T(1-a) vs the stop threshold: FP32 T after hundreds of fragments,
-                             # with (1-a) of alphas near the clamp, drifts up to ~1e-4 relative
-    depth_rel: float = 5e-7  # relative depth gap within which FP32 may order two primitives either way
-    clamp_rel: float = 1e-4  # alpha clamp / colour clamp / Jacobian clamp (gradients only)
+    """How far an FP32 implementation may legitimately take each decision the
+    other way (see alpha_reach and stop_band), and which of the resulting
+    differences count as value flags."""
+    frag_ulps: float = 6.0   # float32 ulps of |Q|/2 + |ln opacity| lost in the fragment's exponent
+    value_frac: float = 0.3  # a decision raises a value flag when the other way moves an output by more
+                             # than this fraction of the image tolerance
+    clamp_rel: float = 1e-4  # colour at its clamp at 0 (a float32 4DSH sum; gradients only)
+
+    def alpha_fp32(self, pre, ids, pxc, pyc):
+        """Per (pixel, list entry): the definition's unclamped alpha
+        opacity * exp(power) in FP64, the same alpha evaluated (in FP64) from
+        the record rounded to float32 (record_as_float32), which is what an
+        FP32 implementation evaluates, and the relative reach of its float32
+        evaluation of the fragment. With A, B, C the staged conic terms and L
+        the log2 opacity, the exponent A dx^2 + B dx dy + C dy^2 + L is formed
+        from the offsets dx = px + 0.5 - u (1 rounding each), the three staged
+        products (1 each), B dy and C dy (1 each) and three FMAs (1 each):
+        at most 4 ulps of |A dx^2|, 5 of |B dx dy| and 5 of |C dy^2|, 2 of |L|
+        (one rounding, log2) and 1 of the result, i.e. frag_ulps = 6 ulps of
+        |Q|/2 + |ln opacity| in natural units; then the float32 constants
+        log2(e) (relative 1.3e-8) and log2(1/255), and exp2 (2 ulps), 4 ulps
+        of alpha in all. A record whose rounding is in doubt also takes one
+        ulp of each of its values."""
+        det = lambda k: pre[k].detach()[ids]
+        u, v, con, op = det("u"), det("v"), det("conic"), det("opac")
+        dx, dy = pxc[:, None] - u[None, :], pyc[:, None] - v[None, :]
+        q = con[None, :, 0] * dx * dx + 2 * con[None, :, 1] * dx * dy + con[None, :, 2] * dy * dy
+        gv = op[None, :] * torch.exp(-0.5 * q)
+        u32, v32, c32, o32 = det("u32"), det("v32"), det("conic32"), det("opac32")
+        dx, dy = pxc[:, None] - u32[None, :], pyc[:, None] - v32[None, :]
+        q32 = c32[None, :, 0] * dx * dx + 2 * c32[None, :, 1] * dx * dy + c32[None, :, 2] * dy * dy
+        gv32 = o32[None, :] * torch.exp(-0.5 * q32)
+        tabs = 0.5 * (c32[None, :, 0].abs() * dx * dx + 2 * (c32[None, :, 1] * dx * dy).abs() +
+                      c32[None, :, 2].abs() * dy * dy)
+        eps = self.frag_ulps * U32 * (tabs + o32.log().abs()[None, :]) + 1.3e-8 * (0.5 * q32.abs() + 8.0) + 4 * U32
+        doubt = det("rec_doubt")
+        if bool(doubt.any()):
+            gu = (c32[None, :, 0] * dx + c32[None, :, 1] * dy).abs()
+            gw = (c32[None, :, 1] * dx + c32[None, :, 2] * dy).abs()
+            one_ulp = 2 * U32 * (gu * u32.abs()[None, :] + gw * v32.abs()[None, :] + tabs + 1.0)
+            eps = eps + torch.where(doubt[None, :], one_ulp, torch.zeros_like(eps))
+        return gv, gv32, eps
+
+    def alpha_reach(self, pre, ids, pxc, pyc):
+        """The definition's unclamped alpha (FP64) and how far an FP32
+        implementation's value of it may lie from it, absolute."""
+        gv, gv32, eps = self.alpha_fp32(pre, ids, pxc, pyc)
+        return gv, (gv32 - gv).abs() + gv32 * eps
+
+    @staticmethod
+    def stop_band(a_v: torch.Tensor, reach: torch.Tensor, clamped: torch.Tensor) -> torch.Tensor:
+        """FP32 reach of the transmittance after each list entry, relative,
+        for the stop decision T (1 - a) vs 1e-4 (Eq. 6 taken front to back).
+
+        T_k is the product of the factors (1 - a_i), i <= k. A factor whose
+        alpha may be off by `reach` is off by reach / (1 - a), relative; its
+        product is rounded once more (1 ulp). A surely clamped alpha is the
+        constant 0.99 on both sides, whose float32 representation moves
+        (1 - a) by 9.5e-7, relative. Summed over the entries up to k, the
+        bound grows with the list position."""
+        term = torch.where(clamped, torch.full_like(a_v, 9.6e-7), reach / (1.0 - a_v))
+        term = torch.where(a_v > 0, term + 2 * U32, torch.zeros_like(a_v))
+        return torch.cumsum(term, dim=1)
 
 
 def _order(pre, ids: torch.Tensor) -> torch.Tensor:
@@ -337,7 +431,7 @@ def _order(pre, ids: torch.Tensor) -> torch.Tensor:
 
 
 def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
-                   margins: Optional[Margins] = None, with_flags: bool = True):
+                   margins: Optional[Margins] = None, with_flags: bool = True, gval_fn=None):
     """Render the pixels of one 16x16 tile by the plain per-pixel definition.
 
     A primitive takes part at a pixel iff it is active and the pixel's tile
@@ -345,7 +439,9 @@ def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
     (camera z, index); a fragment with alpha < 1/255 is skipped; blending stops
     before a fragment that would bring the transmittance below 1e-4.
     Returns dict with rgb [3,h,w], depth, alpha, T, n_contrib, last (list
-    position of the last contributor + 1), uncertain masks."""
+    position of the last contributor + 1), uncertain masks. gval_fn (tests of
+    the margin policy only) replaces the unclamped alphas: gval_fn(ids, px, py)
+    -> [pixels, list]."""
     C = CONVENTIONS
     mg = margins or Margins()
     tx, ty = tile_id % cam.tiles_x, tile_id // cam.tiles_x
@@ -374,6 +470,8 @@ def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
         dy = pyc[:, None] - v[None, :]
         power = -0.5 * (conic[None, :, 0] * dx * dx + conic[None, :, 2] * dy * dy) - conic[None, :, 1] * dx * dy
         gval = pre["opac"][ids][None, :] * torch.exp(power)
+        if gval_fn is not None:
+            gval = gval_fn(ids, pxc, pyc)
         alpha = torch.clamp(gval, max=C["alpha_max"])
         with torch.no_grad():
             valid = gval >= C["alpha_min"]
@@ -402,87 +500,123 @@ def composite_tile(pre, cam: OCamera, tile_id: int, bg: Sequence[float],
 
 
 def _tile_flags(pre, cam, tx, ty, pxc, pyc, ids, mg: Margins, h, w):
-    """Pixels whose result depends on a decision within FP32 reach of its
-    threshold. A value flag is raised when taking such a decision the other
-    way can move an output (rgb, depth or alpha) by more than a tenth of the
-    image tolerance; a gradient flag whenever the decision touches a fragment
-    that contributes (the tests zero dL/dI there on both sides)."""
+    """Pixels whose result depends on a decision that an FP32 implementation
+    may take the other way (Margins: the float32 record and fragment
+    arithmetic for alpha decisions, MARGIN_REL / MARGIN_PX for the
+    per-primitive ones, float32 depth keys for the order). A value flag is
+    raised when taking such a decision the other way can move an output (rgb,
+    depth or alpha) by more than value_frac of the image tolerance; a gradient
+    flag whenever the decision touches a fragment that contributes (the tests
+    zero dL/dI there on both sides). Value flags are also returned per cause:
+    "rect" (a primitive whose rectangle edge is in doubt reaches the floor),
+    "floor" (alpha at the 1/255 floor), "stop" (the transmittance crosses the
+    stop threshold within its reach), "tie" (two depths that float32 keys may
+    order the other way, blended in either order)."""
     C = CONVENTIONS
     P = pxc.shape[0]
-    tol_v = 0.1 * IMG_TOL
+    tol_v = mg.value_frac * IMG_TOL
+    thr = C["alpha_min"]
     with torch.no_grad():
         rs, rm = pre["rect_sure"], pre["rect_maybe"]
         in_maybe = (rm[:, 0] <= tx) & (tx < rm[:, 2]) & (rm[:, 1] <= ty) & (ty < rm[:, 3])
         in_sure = (rs[:, 0] <= tx) & (tx < rs[:, 2]) & (rs[:, 1] <= ty) & (ty < rs[:, 3])
         cand = torch.nonzero(in_maybe & ~in_sure).reshape(-1)
-        flag_v = torch.zeros(P, dtype=torch.bool)
-        flag_g = torch.zeros(P, dtype=torch.bool)
-        flag_o = torch.zeros(P, dtype=torch.bool)   # some valid pair may be ordered either way
+        zeros = lambda: torch.zeros(P, dtype=torch.bool)
+        f_rect, f_floor, f_stop, f_tie = zeros(), zeros(), zeros(), zeros()
+        flag_g = zeros()
+        flag_o = zeros()   # some valid pair may be ordered either way
+        # primitives that surely blend some pixel of the tile, and that may
+        # (an FP32 implementation may blend them here or not when in maybe only)
+        sure_ids, maybe_ids = [torch.zeros(0, dtype=torch.long)], [torch.zeros(0, dtype=torch.long)]
         if cand.numel() > 0:
-            gv = _gval(pre, cand, pxc, pyc)
-            flag_v |= (gv >= C["alpha_min"] * (1 - mg.rel)).any(1)
+            gv, reach = mg.alpha_reach(pre, cand, pxc, pyc)
+            above = gv + reach >= thr
+            f_rect |= above.any(1)
+            maybe_ids.append(cand[above.any(0)])
         if ids.numel() > 0:
-            gv = _gval(pre, ids, pxc, pyc)
+            gv, reach = mg.alpha_reach(pre, ids, pxc, pyc)
             z = pre["z"].detach()[ids]
+            z32 = pre["z32"][ids]
             col = pre["color"].detach()[ids]
             # largest change one fragment can make to any output, per unit weight a*T
-            reach = (col.abs().amax(-1) + z.abs() + 1.0)[None, :]
-            valid = gv >= C["alpha_min"]
+            reach_out = (col.abs().amax(-1) + z.abs() + 1.0)[None, :]
+            valid = gv >= thr
             a = torch.clamp(gv, max=C["alpha_max"])
             a_v = torch.where(valid, a, torch.zeros_like(a))
+            clamped = gv - reach >= C["alpha_max"]
             t_incl = torch.cumprod(1.0 - a_v, dim=1)
             t_ex_v = torch.cat([torch.ones_like(t_incl[:, :1]), t_incl[:, :-1]], 1)
-            alive = t_incl >= C["t_stop"] * (1 - mg.stop_rel)
+            band = mg.stop_band(a_v, torch.where(valid, reach, torch.zeros_like(reach)), clamped)
+            band_ex = torch.cat([torch.zeros_like(band[:, :1]), band[:, :-1]], 1)
+            lo, hi = C["t_stop"] * (1 - band), C["t_stop"] * (1 + band)
+            alive = t_incl >= lo
             # alpha floor: a fragment within reach of 1/255 may be skipped or not
-            near_floor = (gv - C["alpha_min"]).abs() < mg.rel * C["alpha_min"]
-            nf = near_floor & (t_ex_v >= C["t_stop"] * (1 - mg.stop_rel))
-            flag_v |= (nf & (C["alpha_min"] * t_ex_v * reach > tol_v)).any(1)
+            near_floor = (gv - thr).abs() <= reach
+            nf = near_floor & (t_ex_v >= C["t_stop"] * (1 - band_ex))
+            f_floor |= (nf & (thr * t_ex_v * reach_out > tol_v)).any(1)
             flag_g |= nf.any(1)
             # stop threshold: fragments whose T after them lies in the FP32 band
             # around the threshold may or may not be blended
-            maybe = valid & (t_incl >= C["t_stop"] * (1 - mg.stop_rel)) & (t_incl < C["t_stop"] * (1 + mg.stop_rel))
-            eff = torch.where(maybe, (t_ex_v - t_incl) * reach, torch.zeros_like(t_incl)).sum(1)
-            flag_v |= eff > tol_v
+            maybe = valid & (t_incl >= lo) & (t_incl < hi)
+            eff = torch.where(maybe, (t_ex_v - t_incl) * reach_out, torch.zeros_like(t_incl)).sum(1)
+            f_stop |= eff > tol_v
             flag_g |= maybe.any(1)
-            contrib = valid & alive
-            # Depth near-ties: two consecutive fragments of a pixel whose depths
-            # are within FP32 reach may be blended in either order.
+            # blended surely: above the floor and still alive after it, both
+            # beyond reach (T is monotone, so no earlier stop is within reach);
+            # blended maybe: above the floor and alive within reach
+            sure_e = (gv - reach >= thr) & (t_incl >= hi)
+            maybe_e = (gv + reach >= thr) & alive
+            # Depth order: float32 keys that are equal are ordered by primitive
+            # index, which may reverse two consecutive fragments of a pixel
+            # (or FP64 evaluations in another order may, within 1e-12).
             if ids.numel() > 1:
                 nxt_z, nxt_i = _next_of(valid, z)
-                tie = valid & ((nxt_z - z[None, :]) < mg.depth_rel * z[None, :])
+                nz32 = z32[nxt_i]
+                nid = ids[nxt_i]
+                swap = ((nz32 == z32[None, :]) & (nid < ids[None, :])) | ((nxt_z - z[None, :]) < 1e-12 * z[None, :])
+                tie = valid & torch.isfinite(nxt_z) & swap
                 flag_o |= tie.any(1)
+                tie_any = tie | (torch.zeros_like(nxt_i).scatter_add_(1, nxt_i, tie.long()) > 0)
+                sure_e &= ~tie_any
                 if tie.any():
                     # (a) the stop can fall inside the pair in one order and not
                     # the other: T before the pair >= stop > T after both;
                     # either fragment may then be blended or not
                     a_nv = torch.gather(a_v, 1, nxt_i)
                     t_after = t_ex_v * (1.0 - a_v) * (1.0 - a_nv)
-                    straddle = tie & (t_ex_v >= C["t_stop"] * (1 - mg.stop_rel)) & \
-                        (t_after < C["t_stop"] * (1 + mg.stop_rel))
-                    eff_s = (a_v + a_nv) * t_ex_v * torch.maximum(reach, torch.gather(reach.expand_as(a_v), 1, nxt_i))
-                    flag_v |= (straddle & (eff_s > tol_v)).any(1)
+                    straddle = tie & (t_ex_v >= C["t_stop"] * (1 - band_ex)) & (t_after < hi)
+                    eff_s = (a_v + a_nv) * t_ex_v * torch.maximum(reach_out,
+                                                                  torch.gather(reach_out.expand_as(a_v), 1, nxt_i))
+                    f_tie |= (straddle & (eff_s > tol_v)).any(1)
                     flag_g |= straddle.any(1)
                     # (b) both blended: swapping adjacent contributors i, j changes
                     # the pixel by exactly a_i a_j T_i (c_i - c_j); flag the value
-                    # when that can exceed a tenth of the image tolerance, the
-                    # gradient when a_i a_j T_i does
-                    nxt_zc, nxt_ic = _next_of(contrib, z)
-                    tie_c = contrib & ((nxt_zc - z[None, :]) < mg.depth_rel * z[None, :])
+                    # when that can exceed value_frac of the image tolerance, the
+                    # gradient when a_i a_j T_i exceeds 1 % of the tolerance
+                    contrib = valid & alive
                     a_c = torch.where(contrib, a, torch.zeros_like(a))
                     t_ex = torch.cat([torch.ones_like(a_c[:, :1]), torch.cumprod(1.0 - a_c, 1)[:, :-1]], 1)
-                    a_n = torch.gather(a_c, 1, nxt_ic)
-                    dc = (col[None, :, :] - col[nxt_ic]).abs().amax(-1)
+                    a_n = torch.gather(a_c, 1, nxt_i)
+                    dc = (col[None, :, :] - col[nxt_i]).abs().amax(-1)
+                    dz = (z[None, :] - z[nxt_i]).abs()
                     w2 = a_c * a_n * t_ex
-                    flag_v |= (tie_c & (w2 * dc > tol_v)).any(1)
-                    flag_g |= (tie_c & (w2 > 0.1 * tol_v)).any(1)
+                    tie_c = tie & contrib
+                    f_tie |= (tie_c & (w2 * torch.maximum(dc, dz) > tol_v)).any(1)
+                    flag_g |= (tie_c & (w2 > 0.01 * IMG_TOL)).any(1)
+            contrib = valid & alive
             # gradient-only: alpha clamp, colour clamp, Jacobian clamp
-            near_clamp = ((gv - C["alpha_max"]).abs() < mg.clamp_rel) & contrib
+            near_clamp = ((gv - C["alpha_max"]).abs() <= reach) & contrib
             col_m = (pre["color_raw"][ids].abs() < mg.clamp_rel).any(1)
-            jac_m = pre["m_jac"][ids] < mg.clamp_rel
+            jac_m = pre["m_jac"][ids] < MARGIN_REL
             flag_g |= near_clamp.any(1) | (contrib & (col_m | jac_m)[None, :]).any(1)
+            sure_ids.append(ids[sure_e.any(0) & in_sure[ids]])
+            maybe_ids.append(ids[maybe_e.any(0)])
+        flag_v = f_rect | f_floor | f_stop | f_tie
         flag_g |= flag_v
-    return dict(uncertain=flag_v.reshape(h, w), uncertain_grad=flag_g.reshape(h, w),
-                uncertain_order=(flag_o | flag_v).reshape(h, w))
+    shp = lambda m: m.reshape(h, w)
+    return dict(uncertain=shp(flag_v), uncertain_grad=shp(flag_g), uncertain_order=shp(flag_o | flag_v),
+                cause_rect=shp(f_rect), cause_floor=shp(f_floor), cause_stop=shp(f_stop), cause_tie=shp(f_tie),
+                sure_ids=torch.unique(torch.cat(sure_ids)), maybe_ids=torch.unique(torch.cat(maybe_ids)))
 
 
 def _next_of(mask: torch.Tensor, z: torch.Tensor):
@@ -494,15 +628,6 @@ def _next_of(mask: torch.Tensor, z: torch.Tensor):
     nxt_z = torch.cat([nz[:, 1:], torch.full_like(nz[:, :1], float("inf"))], 1)
     nxt_i = torch.cat([nidx[:, 1:], torch.zeros_like(nidx[:, :1])], 1)
     return nxt_z, nxt_i
-
-
-def _gval(pre, ids, pxc, pyc):
-    u, v = pre["u"].detach()[ids], pre["v"].detach()[ids]
-    conic = pre["conic"].detach()[ids]
-    dx = pxc[:, None] - u[None, :]
-    dy = pyc[:, None] - v[None, :]
-    power = -0.5 * (conic[None, :, 0] * dx * dx + conic[None, :, 2] * dy * dy) - conic[None, :, 1] * dx * dy
-    return pre["opac"].detach()[ids][None, :] * torch.exp(power)
 
 
 def render_view(params, cam, t: float, sh_degree: int, t_order: int, period: float = 1.0,
@@ -527,7 +652,7 @@ def assemble(out, cam, key: str, channels: int = 0) -> torch.Tensor:
     H, W = ocam.height, ocam.width
     shape = (channels, H, W) if channels else (H, W)
     img = torch.full(shape, float("nan"), dtype=F64)
-    if key in ("uncertain", "uncertain_grad", "uncertain_order"):
+    if key in ("uncertain", "uncertain_grad", "uncertain_order") or key.startswith("cause_"):
         img = torch.zeros(shape, dtype=torch.bool)
     if key == "last":
         img = torch.zeros(shape, dtype=torch.long)
@@ -557,7 +682,8 @@ def tile_linear_loss(out, dl_rgb=None, dl_depth=None, dl_alpha=None, cam=None) -
     return total
 
 
-def densify_stats(scene, cams, times, dl_rgb, dl_depth=None, dl_alpha=None, bg=(0.0, 0.0, 0.0)):
+def densify_stats(scene, cams, times, dl_rgb, dl_depth=None, dl_alpha=None, bg=(0.0, 0.0, 0.0),
+                  margins: Optional[Margins] = None):
     """Densification statistics of Sec. 3.3 ("Densification in spacetime"):
     the view-space position gradient magnitude and the mu_t gradient
     magnitude, accumulated per primitive over the views in which it blended
@@ -567,20 +693,29 @@ def densify_stats(scene, cams, times, dl_rgb, dl_depth=None, dl_alpha=None, bg=(
     backward computes): uv[i] += |(dL_v/du_i, dL_v/dv_i)| (pixel units),
     t[i] += |dL_v/dmu_t,i|, count[i] += 1, for every primitive i that has a
     blended fragment (alpha >= 1/255 before the stop) in view v.
-    Returns float64 uv [N], t [N] and int64 count [N]."""
+    Returns float64 uv [N], t [N], int64 count [N] and int64 unsure [N]: the
+    number of views in which primitive i's blended-or-not decision rests on a
+    decision within FP32 reach of its threshold (the margin policy), so that
+    an FP32 implementation may count that view or not."""
     n = scene.means4.shape[0]
     uv = torch.zeros(n, dtype=F64)
     tg = torch.zeros(n, dtype=F64)
     cnt = torch.zeros(n, dtype=torch.long)
+    unsure = torch.zeros(n, dtype=torch.long)
     for v, (cam, t) in enumerate(zip(cams, times)):
         params = params_from_scene(scene, requires_grad=True)
         out = render_view(params, cam, float(t), scene.sh_degree, scene.t_order, scene.t_period, bg,
-                          with_flags=False)
+                          margins=margins, with_flags=True)
         pre = out["pre"]
         blended = torch.zeros(n, dtype=torch.bool)
+        sure = torch.zeros(n, dtype=torch.bool)
+        maybe = torch.zeros(n, dtype=torch.bool)
         for part in out["parts"].values():
             if part["n_list"]:
                 blended[part["ids"][part["blended"]]] = True
+            sure[part["sure_ids"]] = True
+            maybe[part["maybe_ids"]] = True
+        doubt = maybe & ~sure
         loss = tile_linear_loss(out, torch.as_tensor(dl_rgb[v]),
                                 None if dl_depth is None else torch.as_tensor(dl_depth[v]),
                                 None if dl_alpha is None else torch.as_tensor(dl_alpha[v]), cam)
@@ -591,11 +726,12 @@ def densify_stats(scene, cams, times, dl_rgb, dl_depth=None, dl_alpha=None, bg=(
         uv = uv + torch.where(blended, torch.sqrt(gu * gu + gv * gv), torch.zeros_like(uv))
         tg = tg + torch.where(blended, gm[:, 3].abs(), torch.zeros_like(tg))
         cnt = cnt + blended.long()
-    return uv.detach(), tg.detach(), cnt
+        unsure = unsure + doubt.long()
+    return uv.detach(), tg.detach(), cnt, unsure
 
 
 def flow_displacement(params: Dict[str, torch.Tensor], cam: OCamera, t: float, dt: float) -> torch.Tensor:
-    """Sec. 4.3 ("Render Flow"): the image-plane displacement of each
+    """Sec. 4.4 (rendered flow, "Ablation and analysis"): the image-plane displacement of each
     primitive's conditional mean mu_xyz|t between t and t + dt, both points
     projected by the view's pinhole camera; zero when the later point is not in
     front of the near plane. Returns [N, 2] (du, dv) in pixels."""
@@ -615,7 +751,7 @@ def flow_displacement(params: Dict[str, torch.Tensor], cam: OCamera, t: float, d
 
 
 def render_flow(scene, cam, t: float, dt: float, tiles=None, margins=None, with_flags=True):
-    """Optical flow of one view (Sec. 4.3): each primitive's displacement
+    """Optical flow of one view (Sec. 4.4): each primitive's displacement
     (flow_displacement) blended with the render's weights of Eq. (6) over a
     zero background. Same primitives, footprints and order as the render.
     Returns render_view's structure whose "rgb" planes 0-1 hold the flow."""

@@ -63,7 +63,7 @@ struct g4d_ctx {
   bool heavy_first = true;         // rasterise tiles by decreasing list length
   bool ellipse_cull = true;        // bin and walk by the alpha-floor ellipse, not its rectangle
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
-  bool flow_mode = false;          // the render in progress blends flow (Sec. 4.3), not colour
+  bool flow_mode = false;          // the render in progress blends flow (Sec. 4.4), not colour
   float flow_dt = 0.f;
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
@@ -98,7 +98,9 @@ constexpr int kMaxViews = 4096;
 // after the views: a sync-free render's totals over its rounds, active
 // records (u32) and instances (64-bit, words +2, +3)
 constexpr int kCntTot = kCntViews + kMaxViews;
-constexpr int kCntWords = kCntTot + 4;
+// then per view: (view, primitive) pairs culled for a non-finite parameter
+constexpr int kCntNF = kCntTot + 4;
+constexpr int kCntWords = kCntNF + kMaxViews;
 constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the device
 // Tiles per round (unless one view alone has more): tile ids then fit 16
 // bits, and the instance sort by tile takes two 8-bit passes.
@@ -228,6 +230,8 @@ RenderParams make_params(g4d_ctx* c, int n_views) {
   p.views = P<ViewDev>(c->views_d);
   p.flow = c->flow_mode ? 1 : 0;
   p.flow_dt = c->flow_dt;
+  p.ellipse_cull = c->ellipse_cull ? 1 : 0;
+  p.nonfinite = nullptr;
   return p;
 }
 
@@ -261,7 +265,9 @@ int round_tiles(const g4d_ctx* c, int v0, int v1) {
 // Per-pair stage of one round, views [v0, v1): preprocess every (view,
 // primitive) pair, compact the active ones, sort them by depth, gather the
 // records in that order and scan their tile counts. Counts stay on the device.
-g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
+// count: the pairs culled for a non-finite parameter are counted per view
+// (a render; not the binning again of a backward).
+g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1, bool count) {
   g4d_status st = join_side(c);  // the last colour pass writes buffers reused below
   if (st) return st;
   c->bound = -1;
@@ -292,9 +298,11 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1) {
   if ((st = ensure(c, c->radix_scratch, 4 * radix_scratch_words(c->sort_blocks)))) return st;
   RenderParams p = make_params(c, nv);
   uint32_t* cnt = P<uint32_t>(c->counters);
+  if (count) p.nonfinite = cnt + kCntNF + v0;
 
   launch_set_views(vr.data(), nv, P<ViewDev>(c->views_d), s);
   launch_fill_u32(cnt, 4, 0u, s);
+  if (count) launch_fill_u32(cnt + kCntNF + v0, (uint64_t)nv, 0u, s);
   // 1. per (view, primitive): cull, slice, project (the colour follows the
   //    gather, on the second stream)
   stage_begin(c);
@@ -685,7 +693,7 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
     for (int v0 = 0; v0 < n_views;) {
       const int k = cap_round_tiles(c, v0, std::min(by_pairs, n_views - v0));
       g4d_ctx::Round r{v0, v0 + k, round_tiles(c, v0, v0 + k), kOnDevice, kOnDevice};
-      if ((st = enqueue_pairs(c, v0, v0 + k))) return st;
+      if ((st = enqueue_pairs(c, v0, v0 + k, true))) return st;
       launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
       launch_add_totals(cnt + kCntA, cnt + kCntI, cnt + kCntTot, cnt + kCntTot + 2, s);
       if ((st = bin_tiles(c, r.tiles, (uint32_t)((uint64_t)c->n * k), (uint32_t)cap))) return st;
@@ -714,7 +722,7 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
     uint32_t A = 0;
     uint64_t inst = 0;
     for (;;) {
-      if ((st = enqueue_pairs(c, v0, v0 + k))) return st;
+      if ((st = enqueue_pairs(c, v0, v0 + k, true))) return st;
       if ((st = read_pairs(c, v0, k, A, inst))) return st;
       if (inst <= inst_cap) break;
       if (k == 1)
@@ -760,7 +768,7 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     const g4d_ctx::Round r = c->rounds[ri];
     const int nv = r.v1 - r.v0;
     if (c->bound != ri) {
-      if ((st = enqueue_pairs(c, r.v0, r.v1))) return st;
+      if ((st = enqueue_pairs(c, r.v0, r.v1, false))) return st;
       if (r.A == kOnDevice) {  // a sync-free round: no host read
         const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(arena_instances(c), 1), 0xFFFFFFF0ull);
         launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
@@ -777,20 +785,20 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     }
     // records bound: exact for a synchronous round, every pair for a sync-free one
     const uint32_t a_max = r.A == kOnDevice ? (uint32_t)((uint64_t)c->n * nv) : r.A;
-    if ((st = ensure(c, c->grad2d, sizeof(float) * kGrad2dStride * (size_t)a_max))) return st;
+    if ((st = ensure(c, c->grad2d, sizeof(double) * kGrad2dStride * (size_t)a_max))) return st;
     if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(a_max)))) return st;
     stage_begin(c);
-    launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, kGrad2dStride, a_max, s);
+    launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, 2 * kGrad2dStride, a_max, s);
     if ((st = join_side(c))) return st;  // the records' colours of a round binned again
     launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
-                           P<uint32_t>(c->pix_last), P<float>(c->grad2d), c->densify.blend_count != nullptr,
+                           P<uint32_t>(c->pix_last), P<double>(c->grad2d), c->densify.blend_count != nullptr,
                            c->ellipse_cull, s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
     RenderParams p = make_params(c, nv);
     stage_begin(c);
-    launch_preprocess_backward(p, P<int32_t>(c->slot), P<float>(c->grad2d), cnt + kCntA, a_max, P<uint32_t>(c->cval),
+    launch_preprocess_backward(p, P<int32_t>(c->slot), P<double>(c->grad2d), cnt + kCntA, a_max, P<uint32_t>(c->cval),
                                P<Record>(c->rec_sorted), P<float>(c->bwd_scratch), g_means4, g_log_scales4, g_q_left,
                                g_q_right, g_opacity_logit, g_coeffs, accumulate, c->densify, s);
     stage_end(c, G4D_STAGE_PREPROCESS_BWD);
@@ -885,6 +893,7 @@ g4d_status g4d_stage_times(g4d_ctx* c, double* ms_out, int64_t* launches_out) {
 
 g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
   if (!c || !out) return G4D_EINVAL;
+  g4d_status st_join = G4D_OK;
   if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render");
   uint32_t* cnt = P<uint32_t>(c->counters);
@@ -902,15 +911,21 @@ g4d_status g4d_get_stats(g4d_ctx* c, g4d_stats* out, int64_t* active_per_view) {
   out->instances = (int64_t)c->I_total;
   out->tiles = c->total_tiles;
   out->rounds = (int64_t)c->rounds.size();
-  // longest list, overflow flag and fragment total need device reads
+  // longest list, overflow flag, fragment total and non-finite culls need
+  // device reads (the colour pass, which counts some of the latter, joined)
+  if ((st_join = join_side(c))) return st_join;
   launch_fill_u32(cnt + kCntFrag, 2, 0u, c->stream);
   launch_sum_u32(P<uint32_t>(c->pix_last), (uint64_t)c->total_pix, reinterpret_cast<unsigned long long*>(cnt + kCntFrag),
                  c->stream);
   uint32_t words[4] = {0, 0, 0, 0};
   uint64_t need = 0;
+  std::vector<uint32_t> nf((size_t)c->n_views, 0u);
   HIPCHK(c, hipMemcpyAsync(words, cnt + kCntFrag, sizeof(words), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&need, cnt + kCntInst64, sizeof(need), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(nf.data(), cnt + kCntNF, sizeof(uint32_t) * nf.size(), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->culled_nonfinite = 0;
+  for (uint32_t x : nf) out->culled_nonfinite += x;
   uint64_t frag = 0;
   std::memcpy(&frag, words, sizeof(frag));
   out->max_tile_list = words[kCntMaxList - kCntFrag];
@@ -1015,7 +1030,7 @@ g4d_status g4d_debug_size(g4d_ctx* c, int32_t what, int64_t* bytes) {
     case G4D_DBG_TILE_KEYS: case G4D_DBG_TILE_VALS: *bytes = 4ll * r.I; break;
     case G4D_DBG_RANGES: *bytes = 8ll * r.tiles; break;
     case G4D_DBG_PIX_T: case G4D_DBG_PIX_LAST: *bytes = 4ll * c->total_pix; break;
-    case G4D_DBG_GRAD2D: *bytes = 4ll * kGrad2dStride * r.A; break;
+    case G4D_DBG_GRAD2D: *bytes = 8ll * kGrad2dStride * r.A; break;
     default: return fail(c, G4D_EINVAL, "unknown debug item");
   }
   return G4D_OK;

@@ -8,7 +8,10 @@ namespace g4d {
 
 constexpr int kTile = 16;                 // 16x16 pixel tiles
 constexpr float kLowpass = 0.3f;          // EWA dilation, px^2
+constexpr double kLowpass64 = 0.3;        // the same, for the FP64 forward geometry
 constexpr float kFrustumSlack = 1.3f;     // Jacobian clamp, x half-fov
+constexpr double kFrustumSlack64 = 1.3;
+constexpr double kSigmaExtent64 = 3.0;
 constexpr float kSigmaExtent = 3.0f;      // footprint radius in sigmas
 constexpr float kAlphaMax = 0.99f;        // alpha clamp
 constexpr float kTStop = 1e-4f;           // transmittance stop threshold
@@ -31,9 +34,11 @@ struct ViewDev {
   float lim_x, lim_y;   // Jacobian clamp limits on x/z, y/z
 };
 
-// Floats per active record in the screen-space gradient buffer: one 64-byte
+// Doubles per active record in the screen-space gradient buffer: one 128-byte
 // line holding dL/du, dL/dv, dL/dconic (3), dL/d(opacity p), dL/drgb (3),
-// dL/dz and padding.
+// dL/dz, padding and (last) the blended flag. The tiles' shares are added in
+// FP64: a long footprint adds terms of both signs from many tiles, whose
+// float32 sum would lose the small total.
 constexpr int kGrad2dStride = 16;
 
 // Per active (view, primitive) record used by binning and rasterisation.
@@ -60,6 +65,13 @@ struct RenderParams {
   const ViewDev* views;
   int flow;             // 1: records carry the image-plane flow over flow_dt instead of the colour
   float flow_dt;
+  // 1 (default): a record's rectangle is cut to the box of its alpha-floor
+  // ellipse and records that can never reach alpha 1/255 are culled; 0: the
+  // plain 3-sigma rectangle and no opacity cull (the reference footprint rule)
+  int ellipse_cull;
+  // per-view counters of (view, primitive) pairs culled for a non-finite
+  // parameter, indexed by the view within the call (null: not counted)
+  uint32_t* nonfinite;
 };
 
 // Per-primitive densification accumulators (all null: off).
@@ -79,7 +91,7 @@ void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdi
                    hipStream_t s);
 // ---- launchers (preprocess_bwd.hip) ----
 size_t preprocess_backward_scratch_floats(size_t n_records);
-void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const float* grad2d,
+void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const double* grad2d,
                                 const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
                                 const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,
                                 float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
@@ -136,7 +148,7 @@ void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views,
                             const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, float* grad2d, bool mark_blended, bool cull,
+                            const uint32_t* pix_last, double* grad2d, bool mark_blended, bool cull,
                             hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);

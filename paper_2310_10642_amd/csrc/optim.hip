@@ -39,9 +39,8 @@ __global__ void __launch_bounds__(256) k_split_sample(RenderParams p, uint64_t c
     out[k] = make_float4(nan, nan, nan, nan);
     return;
   }
-  float inl, inr;
   Shape4 sh;
-  build_shape(normalize4(p.q_left[i], inl), normalize4(p.q_right[i], inr), p.log_scales4[i], sh);
+  build_shape<float>(p.q_left[i], p.q_right[i], p.log_scales4[i], sh);
   const float4 mu = p.means4[i], zz = z[k];
   float o[4];
 #pragma unroll

@@ -4,10 +4,15 @@
 // (Sec. 3.2, "Representation of 4D Gaussian"), temporal marginal and filter
 // (Sec. 3.2 and Sec. 4.2), conditional 3D Gaussian at t (Sec. 3.2), EWA
 // projection (Eqs. 3-4), footprint and tile rectangle -- and, for a flow
-// render, the image-plane displacement of the conditional mean (Sec. 4.3).
+// render, the image-plane displacement of the conditional mean (Sec. 4.4).
+// This geometry is evaluated in FP64 and every value a record holds is
+// rounded to FP32 once, so a record differs from the exact value by that
+// rounding alone and the cull, near-plane and rectangle decisions are those of
+// the exact arithmetic.
 // k_colour: the 4D spherindrical-harmonic colour (Sec. 3.2) of the active
 // pairs, written into their depth-ordered records once the gather has placed
-// them. The backward is in preprocess_bwd.hip.
+// them; it reads the coefficients of the primitives active in some view only.
+// The backward is in preprocess_bwd.hip.
 #include "shade.h"
 
 namespace g4d {
@@ -15,89 +20,122 @@ namespace {
 
 using namespace shade;
 
+__device__ __forceinline__ bool finite4(float4 a) {
+  return isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w);
+}
+
+// Adds, per view, the lanes of the wave whose primitive is culled for a
+// non-finite parameter (one atomic per view and wave, only when some lane is).
+__device__ __forceinline__ void count_nonfinite(uint32_t* nf, int n_views, bool bad) {
+  const uint64_t m = __ballot(bad);
+  if (!nf || m == 0ull) return;
+  if ((threadIdx.x & 63) == 0)
+    for (int v = 0; v < n_views; ++v) atomicAdd(nf + v, (uint32_t)__popcll(m));
+}
+
 __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __restrict__ act,
                                                     uint32_t* __restrict__ dkey, Record* __restrict__ rec,
                                                     int32_t* __restrict__ slot, float4* __restrict__ cdir) {
   const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gidx >= p.n) return;
-  const float4 mu = p.means4[gidx];
-  const float4 ls = p.log_scales4[gidx];
-  float inl, inr;
-  const float4 ql = normalize4(p.q_left[gidx], inl);
-  const float4 qr = normalize4(p.q_right[gidx], inr);
-  const float opa = 1.f / (1.f + __expf(-p.opacity_logit[gidx]));
-  Shape4 sh;
-  build_shape(ql, qr, ls, sh);
+  const bool live = gidx < p.n;
+  const int gi = live ? gidx : 0;
+  const float4 mu = p.means4[gi];
+  const float4 ls = p.log_scales4[gi];
+  const float4 qlf = p.q_left[gi];
+  const float4 qrf = p.q_right[gi];
+  const float logit = p.opacity_logit[gi];
+  // a primitive with a non-finite parameter is culled in every view (and counted)
+  const bool bad = live && !(finite4(mu) && finite4(ls) && finite4(qlf) && finite4(qrf) && isfinite(logit));
+  count_nonfinite(p.nonfinite, p.n_views, bad);
+  if (!live) return;
+  if (bad) {
+    for (int vi = 0; vi < p.n_views; ++vi) {
+      const size_t idx = (size_t)vi * p.n + gidx;
+      act[idx] = 0u;
+      slot[idx] = -1;
+    }
+    return;
+  }
+  Shape4T<double> sh;
+  build_shape<double>(qlf, qrf, ls, sh);
+  const double opa = 1.0 / (1.0 + exp(-(double)logit));
+  const double t_cull = p.t_cull, near = p.near_plane;
 
   for (int vi = 0; vi < p.n_views; ++vi) {
     const size_t idx = (size_t)vi * p.n + gidx;
     const ViewDev& vw = p.views[vi];
-    ViewGeom g;
-    bool ok = view_geometry(mu, sh, vw, p.t_cull, p.near_plane, g);
+    // temporal marginal and filter, slice, camera, EWA projection
+    ViewGeomT<double> g;
+    bool ok = view_geometry<double>(mu, sh, vw, t_cull, near, g);
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     if (ok) {
-      ok = g.det > 0.f;
-      const float mid = 0.5f * (g.a2 + g.c2);
-      const float lmax = mid + sqrtf(fmaxf(mid * mid - g.det, 0.f));
-      const float rad = ceilf(kSigmaExtent * sqrtf(lmax));
-      const float ft = 1.f / kTile;
-      x0 = (int)fminf(fmaxf(floorf((g.u - rad) * ft), 0.f), (float)vw.tiles_x);
-      x1 = (int)fminf(fmaxf(floorf((g.u + rad) * ft) + 1.f, 0.f), (float)vw.tiles_x);
-      y0 = (int)fminf(fmaxf(floorf((g.v - rad) * ft), 0.f), (float)vw.tiles_y);
-      y1 = (int)fminf(fmaxf(floorf((g.v + rad) * ft) + 1.f, 0.f), (float)vw.tiles_y);
-      // Binning footprint: only tiles that can hold a pixel with
-      // opacity * exp(power) >= 1/255, i.e. inside the ellipse
-      // 1/2 d^T conic d <= ln(255 opacity); its bounding box has half-widths
-      // sqrt(2 K Sigma2d_00), sqrt(2 K Sigma2d_11). Every other tile of the
-      // 3-sigma rectangle would skip this primitive at every pixel, so the
-      // blend is unchanged. The slack keeps the box conservative under FP32.
-      const float K = __logf(255.f * opa * g.pt);
-      ok = ok && K > -1e-4f;
-      const float Kc = fmaxf(K, 0.f);
-      const float hx = sqrtf(2.f * Kc * g.a2) * 1.001f + 0.05f;
-      const float hy = sqrtf(2.f * Kc * g.c2) * 1.001f + 0.05f;
-      const float bx = (float)vw.tiles_x + 1.f, by = (float)vw.tiles_y + 1.f;
-      x0 = max(x0, (int)fminf(fmaxf(floorf((g.u - hx) * ft), -1.f), bx));
-      x1 = min(x1, (int)fminf(fmaxf(floorf((g.u + hx) * ft) + 1.f, -1.f), bx));
-      y0 = max(y0, (int)fminf(fmaxf(floorf((g.v - hy) * ft), -1.f), by));
-      y1 = min(y1, (int)fminf(fmaxf(floorf((g.v + hy) * ft) + 1.f, -1.f), by));
-      ok = ok && (x1 > x0) && (y1 > y0) && isfinite(g.u) && isfinite(g.v);
+      // ---- footprint: integer 3-sigma radius, half-open tile rectangle ----
+      const double mid = 0.5 * (g.a2 + g.c2);
+      const double lmax = mid + sqrt(fmax(mid * mid - g.det, 0.0));
+      const double rad = ceil(kSigmaExtent64 * sqrt(lmax));
+      const double tx = vw.tiles_x, ty = vw.tiles_y;
+      x0 = (int)fmin(fmax(floor((g.u - rad) / kTile), 0.0), tx);
+      x1 = (int)fmin(fmax(floor((g.u + rad) / kTile) + 1.0, 0.0), tx);
+      y0 = (int)fmin(fmax(floor((g.v - rad) / kTile), 0.0), ty);
+      y1 = (int)fmin(fmax(floor((g.v + rad) / kTile) + 1.0, 0.0), ty);
+      ok = g.det > 0.0 && isfinite(g.u) && isfinite(g.v);
+      if (p.ellipse_cull) {
+        // Binning footprint: only tiles that can hold a pixel with
+        // opacity * exp(power) >= 1/255, i.e. inside the ellipse
+        // 1/2 d^T conic d <= ln(255 opacity); its bounding box has
+        // half-widths sqrt(2 K Sigma2d_00), sqrt(2 K Sigma2d_11). Every other
+        // tile of the 3-sigma rectangle would skip this primitive at every
+        // pixel, so the blend is unchanged; the slack covers the FP32
+        // evaluation of the fragments.
+        const double K = log(255.0 * opa * g.pt);
+        ok = ok && K > -1e-4;
+        const double Kc = fmax(K, 0.0);
+        const double hx = sqrt(2.0 * Kc * g.a2) * 1.001 + 0.05;
+        const double hy = sqrt(2.0 * Kc * g.c2) * 1.001 + 0.05;
+        const double bx = tx + 1.0, by = ty + 1.0;
+        x0 = max(x0, (int)fmin(fmax(floor((g.u - hx) / kTile), -1.0), bx));
+        x1 = min(x1, (int)fmin(fmax(floor((g.u + hx) / kTile) + 1.0, -1.0), bx));
+        y0 = max(y0, (int)fmin(fmax(floor((g.v - hy) / kTile), -1.0), by));
+        y1 = min(y1, (int)fmin(fmax(floor((g.v + hy) / kTile) + 1.0, -1.0), by));
+      }
+      ok = ok && (x1 > x0) && (y1 > y0);
     }
     if (!ok) {
       act[idx] = 0u;
       slot[idx] = -1;
       continue;
     }
+    const double z = g.pc[2];
+    const double u = g.u, v = g.v;
+    const float zf = (float)z;
     Record r;
-    r.a = make_float4(g.u, g.v, g.pc[2], opa * g.pt);
-    r.b = make_float4(g.conic[0], g.conic[1], g.conic[2], __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)));
+    r.a = make_float4((float)u, (float)v, zf, (float)(opa * g.pt));
+    r.b = make_float4((float)g.conic[0], (float)g.conic[1], (float)g.conic[2],
+                      __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)));
+    const float yr = __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16));
     if (p.flow) {
-      // Sec. 4.3: the conditional mean moves by v3 dt / S44 (it is linear in
-      // t); its projection moves by f (x' z - x z') / (z z') per axis
-      const float s = p.flow_dt / g.s44;
-      float dp[3];
+      // Sec. 4.4: the conditional mean moves by v dt' / Sigma_44 (it is
+      // linear in t); its projection moves by f (x' z - x z') / (z z') per axis
+      const double sc = (double)p.flow_dt / g.s44;
+      double dp[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
-        dp[i] = s * (vw.rot[3 * i] * g.v3[0] + vw.rot[3 * i + 1] * g.v3[1] + vw.rot[3 * i + 2] * g.v3[2]);
-      const float x = g.pc[0], y = g.pc[1], z = g.pc[2], z1 = z + dp[2];
-      const bool front = z1 > p.near_plane;
-      const float q = front ? 1.f / (z * z1) : 0.f;
-      const float fu = vw.fx * (dp[0] * z - x * dp[2]) * q;
-      const float fv = vw.fy * (dp[1] * z - y * dp[2]) * q;
-      r.c = make_float4(fu, fv, 0.f, __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
-      rec[idx] = r;
-      act[idx] = 1u;
-      dkey[idx] = __float_as_uint(g.pc[2]);
-      slot[idx] = -1;
-      continue;
+        dp[i] = sc * ((double)vw.rot[3 * i] * g.v3[0] + (double)vw.rot[3 * i + 1] * g.v3[1] +
+                      (double)vw.rot[3 * i + 2] * g.v3[2]);
+      const double z1 = z + dp[2];
+      const bool front = z1 > near;
+      const double q = front ? 1.0 / (z * z1) : 0.0;
+      r.c = make_float4((float)(vw.fx * (dp[0] * z - g.pc[0] * dp[2]) * q),
+                        (float)(vw.fy * (dp[1] * z - g.pc[1] * dp[2]) * q), 0.f, yr);
+    } else {
+      // colour: k_colour fills c.xyz of the record's depth-ordered copy from
+      // the view direction and t - mu_t
+      r.c = make_float4(0.f, 0.f, 0.f, yr);
+      cdir[idx] = make_float4((float)g.dir[0], (float)g.dir[1], (float)g.dir[2], (float)g.dt);
     }
-    // colour: k_colour fills c.xyz of the record's depth-ordered copy from
-    // the view direction and t - mu_t
-    r.c = make_float4(0.f, 0.f, 0.f, __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16)));
-    cdir[idx] = make_float4(g.dir[0], g.dir[1], g.dir[2], g.dt);
     rec[idx] = r;
     act[idx] = 1u;
-    dkey[idx] = __float_as_uint(g.pc[2]);  // z > near > 0: bit order = numeric order
+    dkey[idx] = __float_as_uint(zf);  // z > near > 0: bit order = numeric order
     slot[idx] = -1;
   }
 }
@@ -106,33 +144,46 @@ constexpr int kColourViews = 8;  // views whose loads k_colour issues together
 
 // 4D spherindrical-harmonic colour (Sec. 3.2): a quad of lanes per primitive,
 // lane `sub` owning the basis functions lm = 4 sub + i. The block's 64
-// primitives' coefficients are contiguous in memory; they are staged through
-// LDS with 16-byte loads, and each lane takes its [n][4 sub + i][3] from
-// there. Per active view every lane evaluates the basis, weights its four
-// functions by the Fourier terms, and a quad sum gives c = max(0, 0.5 + sum).
+// primitives' coefficients are contiguous in memory; those of primitives
+// active in some view are staged through LDS with 16-byte loads, and each
+// lane takes its [n][4 sub + i][3] from there. Per active view every lane
+// evaluates the basis, weights its four functions by the Fourier terms, and a
+// quad sum gives c = max(0, 0.5 + sum). A primitive with a non-finite
+// coefficient gets a NaN colour, which the rasterisers read as fully
+// transparent (and the pair is counted as culled).
 __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                 const float4* __restrict__ cdir, Record* __restrict__ rec_sorted) {
   __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
+  __shared__ uint8_t s_any[kColourPrims];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
   const int g0 = blockIdx.x * kColourPrims;
   const int nprim = min(kColourPrims, p.n - g0);
-  copy_in(s_k, p.coeffs + (size_t)g0 * K3, nprim * K3);
-  __syncthreads();
   const int gidx = g0 + (int)(threadIdx.x >> 2);
   const int sub = threadIdx.x & 3;
-  if (gidx >= p.n) return;  // uniform per quad
+  const bool live = gidx < p.n;  // uniform per quad
+  const bool any = live && any_view_active(p, slot, gidx);
+  if (sub == 0) s_any[threadIdx.x >> 2] = any ? 1 : 0;
+  __syncthreads();
+  copy_in_active(s_k, p.coeffs + (size_t)g0 * K3, nprim, K3, s_any);
+  __syncthreads();
+  if (!any) return;  // uniform per quad
   const float* kc = s_k + (threadIdx.x >> 2) * K3;
   float k[3][kBasisPerLane][3];
+  bool finite = true;
 #pragma unroll
   for (int n = 0; n < 3; ++n)
 #pragma unroll
     for (int i = 0; i < kBasisPerLane; ++i) {
       const int lm = sub * kBasisPerLane + i;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) k[n][i][c] = (lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+      for (int c = 0; c < 3; ++c) {
+        k[n][i][c] = (lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+        finite = finite && isfinite(k[n][i][c]);
+      }
     }
+  const bool bad = quad_any(!finite);
   // views eight at a time: all flags, then the directions of the active
   // ones, are loaded before any is used, so the loads overlap
   for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
@@ -146,6 +197,17 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* _
 #pragma unroll
     for (int w = 0; w < kColourViews; ++w) {
       if (on[w] < 0) continue;  // uniform per quad
+      float* o = reinterpret_cast<float*>(&rec_sorted[on[w]].c);
+      if (bad) {
+        if (sub == 0) {
+          const float nan = __int_as_float(0x7FC00000);
+          o[0] = nan;
+          o[1] = nan;
+          o[2] = nan;
+          if (p.nonfinite) atomicAdd(p.nonfinite + v0 + w, 1u);
+        }
+        continue;
+      }
       const float4 cd = cds[w];
       float Y[16], cs[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -164,7 +226,6 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* _
         col[c] = quad_sum(acc);
       }
       if (sub == 0) {
-        float* o = reinterpret_cast<float*>(&rec_sorted[on[w]].c);
         o[0] = fmaxf(col[0] + kColorOffset, 0.f);
         o[1] = fmaxf(col[1] + kColorOffset, 0.f);
         o[2] = fmaxf(col[2] + kColorOffset, 0.f);

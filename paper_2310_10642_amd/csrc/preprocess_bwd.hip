@@ -16,6 +16,9 @@
 //   prims:   one thread per primitive: sums the views, adds the colour part
 //            through the slice, then Sigma = M M^T, M = R S, R = L(q_l) R(q_r)
 //            and the quaternion normalisation.
+// The pairs and prims chains run in FP64 (as the forward geometry does): the
+// conditional covariance of a long, thin primitive is a difference of nearly
+// equal terms, which float32 would leave with few correct bits.
 #include "shade.h"
 
 namespace g4d {
@@ -30,7 +33,7 @@ constexpr int kCgFloats = 4;    // dL/dmu_c and dL/d(t - mu_t) through the colou
 
 __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_t* n_dev, uint32_t n_max,
                                                     const uint32_t* __restrict__ ids, const Record* __restrict__ recs,
-                                                    const float* __restrict__ grad2d, float4* __restrict__ geo,
+                                                    const double* __restrict__ grad2d, float4* __restrict__ geo,
                                                     float4* __restrict__ colbuf) {
   const uint32_t n = min(*n_dev, n_max);
   const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,111 +42,111 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
   const int vi = (int)(id / (uint32_t)p.n);
   const int gidx = (int)(id - (uint32_t)vi * (uint32_t)p.n);
   const float4 mu = p.means4[gidx];
-  const float4 ls = p.log_scales4[gidx];
-  float inl, inr;
-  const float4 ql = normalize4(p.q_left[gidx], inl);
-  const float4 qr = normalize4(p.q_right[gidx], inr);
-  const float opa = 1.f / (1.f + __expf(-p.opacity_logit[gidx]));
-  Shape4 sh;
-  build_shape(ql, qr, ls, sh);
+  Shape4T<double> sh;
+  build_shape<double>(p.q_left[gidx], p.q_right[gidx], p.log_scales4[gidx], sh);
+  const double opa = 1.0 / (1.0 + exp(-(double)p.opacity_logit[gidx]));
   const ViewDev& vw = p.views[vi];
-  ViewGeom g;
-  view_geometry(mu, sh, vw, p.t_cull, p.near_plane, g);
-  const float4 q0 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride);
-  const float4 q1 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride + 4);
-  const float4 q2 = *reinterpret_cast<const float4*>(grad2d + (size_t)d * kGrad2dStride + 8);
-  const float gu = q0.x, gv = q0.y, gC0 = q0.z, gC1 = q0.w, gC2 = q1.x, go = q1.y;
-  const float gdepth = q2.y;
-  // last float of the line: 1 when the record blended some pixel (set by the
+  ViewGeomT<double> g;
+  view_geometry<double>(mu, sh, vw, (double)p.t_cull, (double)p.near_plane, g);
+  const double* ln = grad2d + (size_t)d * kGrad2dStride;
+  const double2 q0 = *reinterpret_cast<const double2*>(ln), q1 = *reinterpret_cast<const double2*>(ln + 2);
+  const double2 q2 = *reinterpret_cast<const double2*>(ln + 4), q3 = *reinterpret_cast<const double2*>(ln + 6);
+  const double2 q4 = *reinterpret_cast<const double2*>(ln + 8);
+  const double gu = q0.x, gv = q0.y, gC0 = q1.x, gC1 = q1.y, gC2 = q2.x, go = q2.y, gdepth = q4.y;
+  // last value of the line: 1 when the record blended some pixel (set by the
   // rasteriser's backward when statistics are on)
-  const bool blended = grad2d[(size_t)d * kGrad2dStride + 15] > 0.5f;
+  const bool blended = ln[15] > 0.5;
   // colour = max(0, raw + 0.5): the clamp passes the gradient where the blended colour is positive
   const float4 rc = recs[d].c;
-  const float graw0 = rc.x > 0.f ? q1.z : 0.f;
-  const float graw1 = rc.y > 0.f ? q1.w : 0.f;
-  const float graw2 = rc.z > 0.f ? q2.x : 0.f;
-  colbuf[2 * (size_t)d] = make_float4(graw0, graw1, graw2, g.dt);
-  colbuf[2 * (size_t)d + 1] = make_float4(g.dir[0], g.dir[1], g.dir[2], g.rinv);
+  const float graw0 = rc.x > 0.f ? (float)q3.x : 0.f;
+  const float graw1 = rc.y > 0.f ? (float)q3.y : 0.f;
+  const float graw2 = rc.z > 0.f ? (float)q4.x : 0.f;
+  colbuf[2 * (size_t)d] = make_float4(graw0, graw1, graw2, (float)g.dt);
+  colbuf[2 * (size_t)d + 1] = make_float4((float)g.dir[0], (float)g.dir[1], (float)g.dir[2], (float)g.rinv);
 
   // ---- opacity * p(t) ----
-  const float gpt = go * opa;
-  const float glogit = go * g.pt * opa * (1.f - opa);
+  const double gpt = go * opa;
+  const double glogit = go * g.pt * opa * (1.0 - opa);
   // ---- conic -> Sigma_2d: G_S = -Q G_Q Q ----
-  const float C0 = g.conic[0], C1 = g.conic[1], C2 = g.conic[2];
-  const float h1 = 0.5f * gC1;
-  const float X00 = C0 * gC0 + C1 * h1, X01 = C0 * h1 + C1 * gC2;
-  const float X10 = C1 * gC0 + C2 * h1, X11 = C1 * h1 + C2 * gC2;
-  const float G00 = -(X00 * C0 + X01 * C1);
-  const float G01 = -(X00 * C1 + X01 * C2);
-  const float G11 = -(X10 * C1 + X11 * C2);
+  const double C0 = g.conic[0], C1 = g.conic[1], C2 = g.conic[2];
+  const double h1 = 0.5 * gC1;
+  const double X00 = C0 * gC0 + C1 * h1, X01 = C0 * h1 + C1 * gC2;
+  const double X10 = C1 * gC0 + C2 * h1, X11 = C1 * h1 + C2 * gC2;
+  const double G00 = -(X00 * C0 + X01 * C1);
+  const double G01 = -(X00 * C1 + X01 * C2);
+  const double G11 = -(X10 * C1 + X11 * C2);
   // ---- Sigma_2d = T Sc T^T:  g_Sc = T^T G T,  g_T = 2 G T Sc ----
-  float GT[2][3];
+  double GT[2][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    GT[0][k] = G00 * g.T[0][k] + G01 * g.T[1][k];
-    GT[1][k] = G01 * g.T[0][k] + G11 * g.T[1][k];
+    GT[0][k] = G00 * g.T_[0][k] + G01 * g.T_[1][k];
+    GT[1][k] = G01 * g.T_[0][k] + G11 * g.T_[1][k];
   }
-  float gSc[3][3];
+  double gSc[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) gSc[i][j] = g.T[0][i] * GT[0][j] + g.T[1][i] * GT[1][j];
-  float gT[2][3];
+    for (int j = 0; j < 3; ++j) gSc[i][j] = g.T_[0][i] * GT[0][j] + g.T_[1][i] * GT[1][j];
+  double gT[2][3];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      gT[r][k] = 2.f * (GT[r][0] * g.Sc[0][k] + GT[r][1] * g.Sc[1][k] + GT[r][2] * g.Sc[2][k]);
+      gT[r][k] = 2.0 * (GT[r][0] * g.Sc[0][k] + GT[r][1] * g.Sc[1][k] + GT[r][2] * g.Sc[2][k]);
   // ---- T = J W:  g_J = g_T W^T ----
-  const float* W = vw.rot;
-  const float gJ00 = gT[0][0] * W[0] + gT[0][1] * W[1] + gT[0][2] * W[2];
-  const float gJ02 = gT[0][0] * W[6] + gT[0][1] * W[7] + gT[0][2] * W[8];
-  const float gJ11 = gT[1][0] * W[3] + gT[1][1] * W[4] + gT[1][2] * W[5];
-  const float gJ12 = gT[1][0] * W[6] + gT[1][1] * W[7] + gT[1][2] * W[8];
+  double W[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W[k] = vw.rot[k];
+  const double gJ00 = gT[0][0] * W[0] + gT[0][1] * W[1] + gT[0][2] * W[2];
+  const double gJ02 = gT[0][0] * W[6] + gT[0][1] * W[7] + gT[0][2] * W[8];
+  const double gJ11 = gT[1][0] * W[3] + gT[1][1] * W[4] + gT[1][2] * W[5];
+  const double gJ12 = gT[1][0] * W[6] + gT[1][1] * W[7] + gT[1][2] * W[8];
   // ---- camera-space point (x, y, z) ----
-  const float x = g.pc[0], y = g.pc[1], iz = g.iz, iz2 = iz * iz;
-  float gx = gu * vw.fx * iz;
-  float gy = gv * vw.fy * iz;
-  float gz = gdepth - gu * vw.fx * x * iz2 - gv * vw.fy * y * iz2;
-  gz += -gJ00 * vw.fx * iz2 - gJ11 * vw.fy * iz2;
+  const double fx = vw.fx, fy = vw.fy;
+  const double x = g.pc[0], y = g.pc[1], iz = g.iz, iz2 = iz * iz;
+  double gx = gu * fx * iz;
+  double gy = gv * fy * iz;
+  double gz = gdepth - gu * fx * x * iz2 - gv * fy * y * iz2;
+  gz += -gJ00 * fx * iz2 - gJ11 * fy * iz2;
   if (g.clx) {
-    gz += gJ02 * vw.fx * g.xi * iz2;
+    gz += gJ02 * fx * g.xi * iz2;
   } else {
-    gx += -gJ02 * vw.fx * iz2;
-    gz += 2.f * gJ02 * vw.fx * g.xi * iz2;
+    gx += -gJ02 * fx * iz2;
+    gz += 2.0 * gJ02 * fx * g.xi * iz2;
   }
   if (g.cly) {
-    gz += gJ12 * vw.fy * g.eta * iz2;
+    gz += gJ12 * fy * g.eta * iz2;
   } else {
-    gy += -gJ12 * vw.fy * iz2;
-    gz += 2.f * gJ12 * vw.fy * g.eta * iz2;
+    gy += -gJ12 * fy * iz2;
+    gz += 2.0 * gJ12 * fy * g.eta * iz2;
   }
   // p_cam = W mu_c + w
-  float gmuc[3];
+  double gmuc[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) gmuc[i] = W[i] * gx + W[3 + i] * gy + W[6 + i] * gz;
   // ---- slice: Sc = Sxyz - v v^T / S44, mu_c = mu_xyz + v lam ----
-  const float inv44 = 1.f / g.s44;
-  float Gv[3];
+  const double inv44 = 1.0 / g.s44;
+  double Gv[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) Gv[i] = gSc[i][0] * g.v3[0] + gSc[i][1] * g.v3[1] + gSc[i][2] * g.v3[2];
-  const float vGv = g.v3[0] * Gv[0] + g.v3[1] * Gv[1] + g.v3[2] * Gv[2];
-  float gv3[3];
+  const double vGv = g.v3[0] * Gv[0] + g.v3[1] * Gv[1] + g.v3[2] * Gv[2];
+  double gv3[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) gv3[i] = -2.f * Gv[i] * inv44 + gmuc[i] * g.lam;
-  float gs44 = vGv * inv44 * inv44;
-  const float glam = gmuc[0] * g.v3[0] + gmuc[1] * g.v3[1] + gmuc[2] * g.v3[2];
-  float gdt = glam * inv44;
+  for (int i = 0; i < 3; ++i) gv3[i] = -2.0 * Gv[i] * inv44 + gmuc[i] * g.lam;
+  double gs44 = vGv * inv44 * inv44;
+  const double glam = gmuc[0] * g.v3[0] + gmuc[1] * g.v3[1] + gmuc[2] * g.v3[2];
+  double gdt = glam * inv44;
   gs44 += -glam * g.lam * inv44;
   // p(t) = exp(-dt^2 / (2 S44))
   gdt += -gpt * g.pt * g.lam;
-  gs44 += gpt * g.pt * 0.5f * g.lam * g.lam;
+  gs44 += gpt * g.pt * 0.5 * g.lam * g.lam;
   // upper triangle of the symmetric dL/dSigma: (00 01 02 03 | 11 12 13 22 | 23 33)
   float4* o = geo + 4 * (size_t)d;
-  o[0] = make_float4(gSc[0][0], 0.5f * (gSc[0][1] + gSc[1][0]), 0.5f * (gSc[0][2] + gSc[2][0]), 0.5f * gv3[0]);
-  o[1] = make_float4(gSc[1][1], 0.5f * (gSc[1][2] + gSc[2][1]), 0.5f * gv3[1], gSc[2][2]);
-  o[2] = make_float4(0.5f * gv3[2], gs44, gmuc[0], gmuc[1]);
-  o[3] = make_float4(gmuc[2], -gdt, glogit, blended ? sqrtf(gu * gu + gv * gv) : -1.f);
+  o[0] = make_float4((float)gSc[0][0], (float)(0.5 * (gSc[0][1] + gSc[1][0])), (float)(0.5 * (gSc[0][2] + gSc[2][0])),
+                     (float)(0.5 * gv3[0]));
+  o[1] = make_float4((float)gSc[1][1], (float)(0.5 * (gSc[1][2] + gSc[2][1])), (float)(0.5 * gv3[1]), (float)gSc[2][2]);
+  o[2] = make_float4((float)(0.5 * gv3[2]), (float)gs44, (float)gmuc[0], (float)gmuc[1]);
+  o[3] = make_float4((float)gmuc[2], (float)-gdt, (float)glogit, blended ? (float)sqrt(gu * gu + gv * gv) : -1.f);
 }
 
 constexpr int kBwdColourViews = 8;  // views whose slots k_bwd_colour loads together
@@ -151,24 +154,31 @@ constexpr int kBwdColourViews = 8;  // views whose slots k_bwd_colour loads toge
 // A quad of lanes per primitive, lane `sub` owning the basis functions
 // lm = 4 sub + i (as in the forward colour kernel): per active view it adds
 // its share of dL/dcoeffs, and quad sums give the gradients through the view
-// direction and through t - mu_t. The block's coefficients come in, and its
-// coefficient gradients go out, through LDS with 16-byte accesses.
+// direction and through t - mu_t. The coefficients of the block's primitives
+// that are active in some view come in, and the block's coefficient
+// gradients go out, through LDS with 16-byte accesses. A primitive with a
+// non-finite coefficient was rendered transparent: it gets zero gradients.
 __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                      const float4* __restrict__ colbuf, float4* __restrict__ cgbuf,
                                                      float* __restrict__ g_coeffs, bool accumulate) {
   __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
+  __shared__ uint8_t s_any[kColourPrims];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
   const int g0 = blockIdx.x * kColourPrims;
   const int nprim = min(kColourPrims, p.n - g0);
-  copy_in(s_k, p.coeffs + (size_t)g0 * K3, nprim * K3);
-  __syncthreads();
   const int gidx = g0 + (int)(threadIdx.x >> 2);
   const int sub = threadIdx.x & 3;
   const bool live = gidx < p.n;  // uniform per quad
+  const bool any = live && any_view_active(p, slot, gidx);
+  if (sub == 0) s_any[threadIdx.x >> 2] = any ? 1 : 0;
+  __syncthreads();
+  copy_in_active(s_k, p.coeffs + (size_t)g0 * K3, nprim, K3, s_any);
+  __syncthreads();
   float* kc = s_k + (threadIdx.x >> 2) * K3;
   float k[3][kBasisPerLane][3], gk[3][kBasisPerLane][3];
+  bool finite = true;
 #pragma unroll
   for (int n = 0; n < 3; ++n)
 #pragma unroll
@@ -176,13 +186,15 @@ __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_
       const int lm = sub * kBasisPerLane + i;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        k[n][i][c] = (live && lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+        k[n][i][c] = (any && lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+        finite = finite && isfinite(k[n][i][c]);
         gk[n][i][c] = 0.f;
       }
     }
+  const bool bad = quad_any(!finite);
   __syncthreads();  // s_k is reused for the gradients below
   // views eight at a time, their slots loaded before any is used
-  for (int v0 = 0; live && v0 < p.n_views; v0 += kBwdColourViews) {
+  for (int v0 = 0; any && v0 < p.n_views; v0 += kBwdColourViews) {
     int ds[kBwdColourViews];
 #pragma unroll
     for (int w = 0; w < kBwdColourViews; ++w) ds[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
@@ -190,6 +202,10 @@ __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_
     for (int w = 0; w < kBwdColourViews; ++w) {
       const int d = ds[w];
       if (d < 0) continue;
+      if (bad) {
+        if (sub == 0) cgbuf[d] = make_float4(0.f, 0.f, 0.f, 0.f);
+        continue;
+      }
       const float4 c0 = colbuf[2 * (size_t)d];
       const float4 c1 = colbuf[2 * (size_t)d + 1];
       const float graw[3] = {c0.x, c0.y, c0.z};
@@ -250,7 +266,7 @@ __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_
       for (int c = 0; c < 3; ++c) kc[(n * nb + lm) * 3 + c] = gk[n][i][c];
     }
   __syncthreads();
-  copy_out(g_coeffs + (size_t)g0 * K3, s_k, nprim * K3, accumulate);
+  copy_out(g_coeffs + (size_t)g0 * K3, s_k, nprim, K3, accumulate, s_any);
 }
 
 __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t* __restrict__ slot,
@@ -274,22 +290,18 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
     return;
   }
   const float4 mu = p.means4[gidx];
-  const float4 ls = p.log_scales4[gidx];
-  float inl, inr;
-  const float4 ql = normalize4(p.q_left[gidx], inl);
-  const float4 qr = normalize4(p.q_right[gidx], inr);
-  Shape4 sh;
-  build_shape(ql, qr, ls, sh);
-  const float s44 = sh.S[3][3], inv44 = 1.f / s44;
-  const float v3[3] = {sh.S[0][3], sh.S[1][3], sh.S[2][3]};
+  Shape4T<double> sh;
+  build_shape<double>(p.q_left[gidx], p.q_right[gidx], p.log_scales4[gidx], sh);
+  const double s44 = sh.S[3][3], inv44 = 1.0 / s44;
+  const double v3[3] = {sh.S[0][3], sh.S[1][3], sh.S[2][3]};
 
-  float G4[4][4];
+  double G4[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) G4[i][j] = 0.f;
-  float gmu[4] = {0.f, 0.f, 0.f, 0.f};
-  float glogit = 0.f;
+    for (int j = 0; j < 4; ++j) G4[i][j] = 0.0;
+  double gmu[4] = {0.0, 0.0, 0.0, 0.0};
+  double glogit = 0.0;
   float st_uv = 0.f, st_t = 0.f;
   int st_n = 0;
   for (int vi = 0; vi < p.n_views; ++vi) {
@@ -304,18 +316,18 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
     glogit += e.z;
     // colour part through the slice: mu_c = mu_xyz + v lam, lam = (t - mu_t) / S44
     const float4 cg = cgbuf[d];
-    const float lam = (p.views[vi].t - mu.w) * inv44;
-    const float glam = cg.x * v3[0] + cg.y * v3[1] + cg.z * v3[2];
+    const double lam = ((double)p.views[vi].t - (double)mu.w) * inv44;
+    const double glam = cg.x * v3[0] + cg.y * v3[1] + cg.z * v3[2];
     gmu[0] += cg.x; gmu[1] += cg.y; gmu[2] += cg.z;
-    G4[0][3] += 0.5f * cg.x * lam;
-    G4[1][3] += 0.5f * cg.y * lam;
-    G4[2][3] += 0.5f * cg.z * lam;
+    G4[0][3] += 0.5 * cg.x * lam;
+    G4[1][3] += 0.5 * cg.y * lam;
+    G4[2][3] += 0.5 * cg.z * lam;
     G4[3][3] += -glam * lam * inv44;
-    const float gmt_col = -(glam * inv44 + cg.w);
+    const double gmt_col = -(glam * inv44 + cg.w);
     gmu[3] += gmt_col;
     if (e.w >= 0.f) {  // blended in this view: densification statistics (Sec. 3.3)
       st_uv += e.w;
-      st_t += fabsf(e.y + gmt_col);
+      st_t += (float)fabs(e.y + gmt_col);
       ++st_n;
     }
   }
@@ -330,65 +342,67 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
     for (int j = 0; j < i; ++j) G4[i][j] = G4[j][i];
 
   // ---- Sigma = M M^T, M = R S:  g_M = 2 G4 M ----
-  float gR[4][4], gs[4] = {0.f, 0.f, 0.f, 0.f};
+  double gR[4][4], gs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float gm = 2.f * (G4[i][0] * sh.M[0][k] + G4[i][1] * sh.M[1][k] + G4[i][2] * sh.M[2][k] +
-                              G4[i][3] * sh.M[3][k]);
+      const double gm = 2.0 * (G4[i][0] * sh.M[0][k] + G4[i][1] * sh.M[1][k] + G4[i][2] * sh.M[2][k] +
+                               G4[i][3] * sh.M[3][k]);
       gR[i][k] = gm * sh.s[k];
-      gs[k] = fmaf(gm, sh.R[i][k], gs[k]);
+      gs[k] = fma(gm, sh.R[i][k], gs[k]);
     }
   // ---- R = L Rr:  g_L = g_R Rr^T,  g_Rr = L^T g_R ----
-  float L[4][4], Rr[4][4], gL[4][4], gRr[4][4];
-  isoclinic_left(ql, L);
-  isoclinic_right(qr, Rr);
+  double L[4][4], Rr[4][4], gL[4][4], gRr[4][4];
+  isoclinic_left<double>(sh.ql[0], sh.ql[1], sh.ql[2], sh.ql[3], L);
+  isoclinic_right<double>(sh.qr[0], sh.qr[1], sh.qr[2], sh.qr[3], Rr);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float a = 0.f, b = 0.f;
+      double a = 0.0, b = 0.0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        a = fmaf(gR[i][k], Rr[j][k], a);
-        b = fmaf(L[k][i], gR[k][j], b);
+        a = fma(gR[i][k], Rr[j][k], a);
+        b = fma(L[k][i], gR[k][j], b);
       }
       gL[i][j] = a;
       gRr[i][j] = b;
     }
   // matrix-entry gradients to quaternion components (sign patterns of the two matrices)
-  float4 gql, gqr;
-  gql.x = gL[0][0] + gL[1][1] + gL[2][2] + gL[3][3];
-  gql.y = -gL[0][1] + gL[1][0] - gL[2][3] + gL[3][2];
-  gql.z = -gL[0][2] + gL[1][3] + gL[2][0] - gL[3][1];
-  gql.w = -gL[0][3] - gL[1][2] + gL[2][1] + gL[3][0];
-  gqr.x = gRr[0][0] + gRr[1][1] + gRr[2][2] + gRr[3][3];
-  gqr.y = -gRr[0][1] + gRr[1][0] + gRr[2][3] - gRr[3][2];
-  gqr.z = -gRr[0][2] - gRr[1][3] + gRr[2][0] + gRr[3][1];
-  gqr.w = -gRr[0][3] + gRr[1][2] - gRr[2][1] + gRr[3][0];
+  double gql[4], gqr[4];
+  gql[0] = gL[0][0] + gL[1][1] + gL[2][2] + gL[3][3];
+  gql[1] = -gL[0][1] + gL[1][0] - gL[2][3] + gL[3][2];
+  gql[2] = -gL[0][2] + gL[1][3] + gL[2][0] - gL[3][1];
+  gql[3] = -gL[0][3] - gL[1][2] + gL[2][1] + gL[3][0];
+  gqr[0] = gRr[0][0] + gRr[1][1] + gRr[2][2] + gRr[3][3];
+  gqr[1] = -gRr[0][1] + gRr[1][0] + gRr[2][3] - gRr[3][2];
+  gqr[2] = -gRr[0][2] - gRr[1][3] + gRr[2][0] + gRr[3][1];
+  gqr[3] = -gRr[0][3] + gRr[1][2] - gRr[2][1] + gRr[3][0];
   // normalisation q_hat = q / |q|
-  const float dl = gql.x * ql.x + gql.y * ql.y + gql.z * ql.z + gql.w * ql.w;
-  const float dr = gqr.x * qr.x + gqr.y * qr.y + gqr.z * qr.z + gqr.w * qr.w;
-  float4 o_ql = make_float4((gql.x - ql.x * dl) * inl, (gql.y - ql.y * dl) * inl, (gql.z - ql.z * dl) * inl,
-                            (gql.w - ql.w * dl) * inl);
-  float4 o_qr = make_float4((gqr.x - qr.x * dr) * inr, (gqr.y - qr.y * dr) * inr, (gqr.z - qr.z * dr) * inr,
-                            (gqr.w - qr.w * dr) * inr);
-  float4 o_ls = make_float4(gs[0] * sh.s[0], gs[1] * sh.s[1], gs[2] * sh.s[2], gs[3] * sh.s[3]);
-  float4 o_mu = make_float4(gmu[0], gmu[1], gmu[2], gmu[3]);
+  const double dl = gql[0] * sh.ql[0] + gql[1] * sh.ql[1] + gql[2] * sh.ql[2] + gql[3] * sh.ql[3];
+  const double dr = gqr[0] * sh.qr[0] + gqr[1] * sh.qr[1] + gqr[2] * sh.qr[2] + gqr[3] * sh.qr[3];
+  float4 o_ql = make_float4((float)((gql[0] - sh.ql[0] * dl) * sh.inl), (float)((gql[1] - sh.ql[1] * dl) * sh.inl),
+                            (float)((gql[2] - sh.ql[2] * dl) * sh.inl), (float)((gql[3] - sh.ql[3] * dl) * sh.inl));
+  float4 o_qr = make_float4((float)((gqr[0] - sh.qr[0] * dr) * sh.inr), (float)((gqr[1] - sh.qr[1] * dr) * sh.inr),
+                            (float)((gqr[2] - sh.qr[2] * dr) * sh.inr), (float)((gqr[3] - sh.qr[3] * dr) * sh.inr));
+  float4 o_ls = make_float4((float)(gs[0] * sh.s[0]), (float)(gs[1] * sh.s[1]), (float)(gs[2] * sh.s[2]),
+                            (float)(gs[3] * sh.s[3]));
+  float4 o_mu = make_float4((float)gmu[0], (float)gmu[1], (float)gmu[2], (float)gmu[3]);
+  float o_logit = (float)glogit;
   if (accumulate) {
     const float4 a = g_q_left[gidx], b = g_q_right[gidx], c = g_log_scales4[gidx], d = g_means4[gidx];
     o_ql = make_float4(o_ql.x + a.x, o_ql.y + a.y, o_ql.z + a.z, o_ql.w + a.w);
     o_qr = make_float4(o_qr.x + b.x, o_qr.y + b.y, o_qr.z + b.z, o_qr.w + b.w);
     o_ls = make_float4(o_ls.x + c.x, o_ls.y + c.y, o_ls.z + c.z, o_ls.w + c.w);
     o_mu = make_float4(o_mu.x + d.x, o_mu.y + d.y, o_mu.z + d.z, o_mu.w + d.w);
-    glogit += g_logit[gidx];
+    o_logit += g_logit[gidx];
   }
   g_q_left[gidx] = o_ql;
   g_q_right[gidx] = o_qr;
   g_log_scales4[gidx] = o_ls;
   g_means4[gidx] = o_mu;
-  g_logit[gidx] = glogit;
+  g_logit[gidx] = o_logit;
 }
 
 }  // namespace
@@ -397,7 +411,7 @@ size_t preprocess_backward_scratch_floats(size_t n_records) {
   return n_records * (kGeoFloats + kColFloats + kCgFloats);
 }
 
-void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const float* grad2d,
+void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const double* grad2d,
                                 const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
                                 const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,
                                 float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,

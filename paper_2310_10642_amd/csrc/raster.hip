@@ -21,12 +21,14 @@
 // over the tile's pixels (only over quadrants where the primitive blended).
 // A 16-lane DPP reduce-scatter per batch combines the columns, leaving each
 // of ten lanes of a primitive's row with one value of its gradient line, and
-// those lanes add the tile's share with one atomic instruction into one
-// 64-byte line.
-#include "g4d_common.h"
+// those lanes add the tile's share with one FP64 atomic instruction into one
+// 128-byte line.
+#include "shade.h"
 
 namespace g4d {
 namespace {
+
+using shade::sc_fma;
 
 constexpr int kFwdBatch = 256;
 constexpr int kBwdBatch = 16;
@@ -46,10 +48,20 @@ __device__ __forceinline__ float frag_log2(float dx, float dy, float4 sa, float4
   return fmaf(dx, fmaf(sa.z, dx, sa.w * dy), fmaf(sb.x * dy, dy, sb.y));
 }
 
+// A record whose colour is NaN (its primitive has a non-finite 4DSH
+// coefficient) is staged fully transparent: log2 opacity far below the 1/255
+// floor at every pixel (finite, so its reciprocal stays finite), colour 0.
+constexpr float kHiddenLog2 = -100.f;
+
+__device__ __forceinline__ float staged_log2_opacity(const Record& r) {
+  return isnan(r.c.x) ? kHiddenLog2 : __log2f(r.a.w);
+}
+
 __device__ __forceinline__ void stage_record(const Record& r, float4& sa, float4& sb, float4& sc) {
+  const bool hide = isnan(r.c.x);
   sa = make_float4(r.a.x, r.a.y, -0.5f * kLog2e * r.b.x, -kLog2e * r.b.y);
-  sb = make_float4(-0.5f * kLog2e * r.b.z, __log2f(r.a.w), r.a.z, 0.f);
-  sc = make_float4(r.c.x, r.c.y, r.c.z, 0.f);
+  sb = make_float4(-0.5f * kLog2e * r.b.z, staged_log2_opacity(r), r.a.z, 0.f);
+  sc = hide ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(r.c.x, r.c.y, r.c.z, 0.f);
 }
 
 // Whether the record's alpha-floor ellipse (where opacity * exp(power) reaches
@@ -81,22 +93,23 @@ __device__ __forceinline__ bool quadrant_hit(const float4& sa, const float4& sb,
 // record (the empty asm statements keep the pieces from being merged into
 // wider writes), so a record loaded a batch ahead needs no repacking moves,
 // which would wait for the load right after issuing it.
-__device__ __forceinline__ void stage_split(const Record& r, float4* sa, float4* sb, float4* sc) {
+__device__ __forceinline__ void stage_split(const Record& r, float l2o, float4* sa, float4* sb, float4* sc) {
   float2* pa = reinterpret_cast<float2*>(sa);
   pa[0] = make_float2(r.a.x, r.a.y);
   asm volatile("" ::: "memory");
   pa[1] = make_float2(-0.5f * kLog2e * r.b.x, -kLog2e * r.b.y);
   float* pb = reinterpret_cast<float*>(sb);
   pb[0] = -0.5f * kLog2e * r.b.z;
-  pb[1] = __log2f(r.a.w);
+  pb[1] = l2o;
   asm volatile("" ::: "memory");
   pb[2] = r.a.z;
   asm volatile("" ::: "memory");
   pb[3] = 0.f;
+  const bool hide = isnan(r.c.x);
   float* pc = reinterpret_cast<float*>(sc);
-  pc[0] = r.c.x;
-  pc[1] = r.c.y;
-  pc[2] = r.c.z;
+  pc[0] = hide ? 0.f : r.c.x;
+  pc[1] = hide ? 0.f : r.c.y;
+  pc[2] = hide ? 0.f : r.c.z;
 }
 
 __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int tile) {
@@ -112,24 +125,32 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Reduce-scatter of ten values over each 16-lane row: afterwards lane c holds
 // the row sum of value slot(c), slot = 5 (c >> 3) + 3 ((c >> 2) & 1) +
 // 2 ((c >> 1) & 1) + (c & 1), on lanes 0-2, 4-5, 8-10, 12-13 (slot -1
 // elsewhere). Pairs: row mirror (c <-> 15 - c), half-row mirror, quad
 // (c <-> 3 - c), quad (c <-> c ^ 1); each step keeps half of the values.
-__device__ __forceinline__ float row16_reduce_scatter10(const float (&q)[10], int c, int& slot) {
+template <typename V>
+__device__ __forceinline__ V row16_reduce_scatter10(const V (&q)[10], int c, int& slot) {
   const bool hi = c & 8, b = c & 4, cc = c & 2, d = c & 1;
-  float r[6], s[4], t[2];
+  V r[6], s[4], t[2];
 #pragma unroll
   for (int i = 0; i < 5; ++i) r[i] = (hi ? q[i + 5] : q[i]) + dpp<0x140>(hi ? q[i] : q[i + 5]);
-  r[5] = 0.f;
+  r[5] = 0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) s[i] = (b ? r[i + 3] : r[i]) + dpp<0x141>(b ? r[i] : r[i + 3]);
-  s[3] = 0.f;
+  s[3] = 0;
 #pragma unroll
   for (int i = 0; i < 2; ++i) t[i] = (cc ? s[i + 2] : s[i]) + dpp<0x1B>(cc ? s[i] : s[i + 2]);
-  const float out = (d ? t[1] : t[0]) + dpp<0xB1>(d ? t[0] : t[1]);
+  const V out = (d ? t[1] : t[0]) + dpp<0xB1>(d ? t[0] : t[1]);
   const int e = 2 * (int)cc + (int)d;
   slot = (e <= (b ? 1 : 2)) ? 5 * (int)hi + 3 * (int)b + e : -1;
   return out;
@@ -246,6 +267,82 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
   pix_last[pix] = last;
 }
 
+// Whether a record's footprint is so elongated (condition number of its
+// conic above ~100: 4 det < 0.04 trace^2) that its gradient must be summed in
+// FP64: the short axis's share of dL/dconic is then a small part of much
+// larger long-axis terms, which float32 tile sums would lose.
+__device__ __forceinline__ bool ill_conditioned(const Record& r) {
+  const float tr = r.b.x + r.b.z;
+  const float det = fmaf(r.b.x, r.b.z, -r.b.y * r.b.y);
+  return det < 0.01f * tr * tr;
+}
+
+// Phase 2 of the backward for primitive j2 of the staged batch and pixel
+// column c2: its share of the tile sums over the rows of the quadrants where
+// it blended, formed into the ten values of its gradient line (before the row
+// sum). G is the type of the position moments and of the line (float, or
+// double for ill-conditioned footprints); the colour and depth sums stay float.
+template <typename G, bool HAS_D>
+__device__ __forceinline__ void phase2_line(G (&q)[10], bool live, int j2, int c2, int tx, int ty,
+                                            const float4* __restrict__ s_a, const float4* __restrict__ s_b,
+                                            const uint32_t* __restrict__ s_act, const float* __restrict__ s_g,
+                                            const float* __restrict__ s_w, const float4* __restrict__ s_pix) {
+  // Row moments are taken about the tile's middle row (offset m = k - 7.5)
+  // and moved to the primitive's centre afterwards: with dy = dc + m,
+  // sum g dy = dc Sg + Sgm and sum g dy^2 = dc^2 Sg + 2 dc Sgm + Sgmm.
+  G Sg = 0, Sgm = 0, Sgmm = 0;
+  float Sr = 0.f, Sgc = 0.f, Sb = 0.f, Sd = 0.f;
+  G dx = 0, dc = 0;
+  if (live) {
+    const float4 sa = s_a[j2];
+    dx = (G)(tx * kTile + c2) + (G)0.5 - (G)sa.x;
+    dc = (G)(ty * kTile) + (G)8 - (G)sa.y;
+    const uint32_t act = (s_act[c2 >> 3] | (s_act[2 + (c2 >> 3)] << 16)) >> j2;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (!((act >> (16 * half)) & 1u)) continue;
+#pragma unroll
+      for (int k = 8 * half; k < 8 * half + 8; ++k) {
+        const int p = k * 16 + c2;
+        const int slot = j2 * kGwStride + gw_slot(k, c2);
+        const float2 gw = make_float2(s_g[slot], s_w[slot]);
+        const float4 pd = s_pix[p];
+        const G g = gw.x;
+        const G m = (G)k - (G)7.5;
+        Sg += g;
+        Sgm = sc_fma(g, m, Sgm);
+        Sgmm = sc_fma(g, m * m, Sgmm);
+        Sr = fmaf(gw.y, pd.x, Sr);
+        Sgc = fmaf(gw.y, pd.y, Sgc);
+        Sb = fmaf(gw.y, pd.z, Sb);
+        if (HAS_D) Sd = fmaf(gw.y, pd.w, Sd);
+      }
+    }
+  }
+  const G Sgy = sc_fma(dc, Sg, Sgm);
+  const G Sgyy = sc_fma(dc, sc_fma(dc, Sg, (G)2 * Sgm), Sgmm);
+  // v: Sg, Sgx, Sgy, Sgxx, Sgxy, Sgyy, w*dL/dr, w*dL/dg, w*dL/db, w*dL/dD
+  // This column's share of the primitive's gradient line (the 2D-mean,
+  // conic and opacity entries are linear in the moments, so they are formed
+  // before the row sum): dL/du, dL/dv, dL/dconic (3), dL/d(opacity p),
+  // dL/drgb (3), dL/dz.
+  const float4 pa = s_a[j2], pb = s_b[j2];
+  const G k0 = live ? (G)pa.z * (G)(-2.f / kLog2e) : (G)0, k1 = live ? (G)pa.w * (G)(-1.f / kLog2e) : (G)0;
+  const G k2 = live ? (G)pb.x * (G)(-2.f / kLog2e) : (G)0;
+  const G iop = live ? (G)__builtin_amdgcn_exp2f(-pb.y) : (G)0;
+  const G Sgx = dx * Sg, Sgxy = dx * Sgy;
+  q[0] = sc_fma(k0, Sgx, k1 * Sgy);
+  q[1] = sc_fma(k1, Sgx, k2 * Sgy);
+  q[2] = (G)-0.5 * dx * Sgx;
+  q[3] = -Sgxy;
+  q[4] = (G)-0.5 * Sgyy;
+  q[5] = Sg * iop;
+  q[6] = Sr;
+  q[7] = Sgc;
+  q[8] = Sb;
+  q[9] = HAS_D ? (G)Sd : (G)0;
+}
+
 // HAS_D / HAS_A: whether dL/d(depth) and dL/d(alpha) are given (otherwise
 // their terms are compiled out).
 template <bool HAS_D, bool HAS_A>
@@ -253,10 +350,11 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const uint32_t* __restrict__ order, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
-    const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d, bool mark_blended, bool cull) {
+    const uint32_t* __restrict__ pix_last, double* __restrict__ grad2d, bool mark_blended, bool cull) {
   __shared__ float4 s_a2[2][kBwdBatch], s_b2[2][kBwdBatch], s_c2[2][kBwdBatch];
   __shared__ uint32_t s_d2[2][kBwdBatch];
   __shared__ uint32_t s_qm2[2][kBwdBatch];
+  __shared__ uint32_t s_ill2[2];  // the staged batch holds an ill-conditioned footprint (FP64 phase 2)
   __shared__ uint32_t s_act[4];  // per quadrant: bit j when entry j blended somewhere in it
   __shared__ float s_g[kBwdBatch * kGwStride];   // dL/dpower per (primitive, pixel)
   __shared__ float s_w[kBwdBatch * kGwStride];   // a_i T_i per (primitive, pixel)
@@ -319,8 +417,9 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   // staging lane by a shuffle) and a ballot gathers the four bits.
   auto stage = [&](int e0, int bb) {
     const int t = (int)threadIdx.x;
+    const float l2o = staged_log2_opacity(nxt);
     if (t < kBwdBatch && e0 + t < count) {
-      stage_split(nxt, &s_a2[bb][t], &s_b2[bb][t], &s_c2[bb][t]);
+      stage_split(nxt, l2o, &s_a2[bb][t], &s_b2[bb][t], &s_c2[bb][t]);
       s_d2[bb][t] = nxt_d;
     }
     const int src = t >> 2;
@@ -330,10 +429,12 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     qa.z = -0.5f * kLog2e * __shfl(nxt.b.x, src, 64);
     qa.w = -kLog2e * __shfl(nxt.b.y, src, 64);
     qb.x = -0.5f * kLog2e * __shfl(nxt.b.z, src, 64);
-    qb.y = __log2f(__shfl(nxt.a.w, src, 64));
+    qb.y = __shfl(l2o, src, 64);
     const bool hit = e0 + src < count && (!cull || quadrant_hit(qa, qb, tile_x0, tile_y0, t & 3));
     const uint64_t bits = __ballot(hit);
     if (t < kBwdBatch) s_qm2[bb][t] = (uint32_t)(bits >> (4 * t)) & 0xFu;
+    const uint64_t ill = __ballot(t < kBwdBatch && e0 + t < count && ill_conditioned(nxt));
+    if (t == 0) s_ill2[bb] = ill != 0ull ? 1u : 0u;
   };
   if (wave == 0 && b_first >= 0) {
     if (threadIdx.x < kBwdBatch && b_first + (int)threadIdx.x < count) {
@@ -396,70 +497,24 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     if (lane == 0) s_act[wave] = blended;
     __syncthreads();
     // ---- phase 2: primitive j2, pixel column c2, rows of active quadrants ----
-    // Row moments are taken about the tile's middle row (offset m = k - 7.5)
-    // and moved to the primitive's centre afterwards: with dy = dc + m,
-    // sum g dy = dc Sg + Sgm and sum g dy^2 = dc^2 Sg + 2 dc Sgm + Sgmm.
     const int e2 = b0 + j2;
-    float Sg = 0.f, Sgm = 0.f, Sgmm = 0.f, Sr = 0.f, Sgc = 0.f, Sb = 0.f, Sd = 0.f;
-    float dx = 0.f, dc = 0.f;
-    if (e2 < count) {
-      const float4 sa = s_a[j2];
-      dx = (float)(tx * kTile + c2) + 0.5f - sa.x;
-      dc = (float)(ty * kTile) + 8.f - sa.y;
-      const uint32_t act = (s_act[c2 >> 3] | (s_act[2 + (c2 >> 3)] << 16)) >> j2;
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        if (!((act >> (16 * half)) & 1u)) continue;
-#pragma unroll
-        for (int k = 8 * half; k < 8 * half + 8; ++k) {
-          const int p = k * 16 + c2;
-          const int slot = j2 * kGwStride + gw_slot(k, c2);
-          const float2 gw = make_float2(s_g[slot], s_w[slot]);
-          const float4 pd = s_pix[p];
-          const float m = (float)k - 7.5f;
-          Sg += gw.x;
-          Sgm = fmaf(gw.x, m, Sgm);
-          Sgmm = fmaf(gw.x, m * m, Sgmm);
-          Sr = fmaf(gw.y, pd.x, Sr);
-          Sgc = fmaf(gw.y, pd.y, Sgc);
-          Sb = fmaf(gw.y, pd.z, Sb);
-          if (HAS_D) Sd = fmaf(gw.y, pd.w, Sd);
-        }
-      }
-    }
-    const float Sgy = fmaf(dc, Sg, Sgm);
-    const float Sgyy = fmaf(dc, fmaf(dc, Sg, 2.f * Sgm), Sgmm);
-    // v: Sg, Sgx, Sgy, Sgxx, Sgxy, Sgyy, w*dL/dr, w*dL/dg, w*dL/db, w*dL/dD
-    // This column's share of the primitive's gradient line (the 2D-mean,
-    // conic and opacity entries are linear in the moments, so they are formed
-    // before the row sum): dL/du, dL/dv, dL/dconic (3), dL/d(opacity p),
-    // dL/drgb (3), dL/dz.
-    float q[10];
-    {
-      const bool live = e2 < count;
-      const float4 pa = s_a[j2], pb = s_b[j2];
-      const float k0 = live ? pa.z * (-2.f / kLog2e) : 0.f, k1 = live ? pa.w * (-1.f / kLog2e) : 0.f;
-      const float k2 = live ? pb.x * (-2.f / kLog2e) : 0.f;
-      const float iop = live ? __builtin_amdgcn_exp2f(-pb.y) : 0.f;
-      const float Sgx = dx * Sg, Sgxy = dx * Sgy;
-      q[0] = fmaf(k0, Sgx, k1 * Sgy);
-      q[1] = fmaf(k1, Sgx, k2 * Sgy);
-      q[2] = -0.5f * dx * Sgx;
-      q[3] = -Sgxy;
-      q[4] = -0.5f * Sgyy;
-      q[5] = Sg * iop;
-      q[6] = Sr;
-      q[7] = Sgc;
-      q[8] = Sb;
-      q[9] = HAS_D ? Sd : 0.f;
-    }
+    const bool live = e2 < count;
     int slot_q;
-    const float val = row16_reduce_scatter10(q, c2, slot_q);
+    double val;
+    if (s_ill2[buf]) {  // block-uniform
+      double q[10];
+      phase2_line<double, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
+      val = row16_reduce_scatter10(q, c2, slot_q);
+    } else {
+      float q[10];
+      phase2_line<float, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
+      val = (double)row16_reduce_scatter10(q, c2, slot_q);
+    }
     // the record blended in this tile: flag it in the gradient line's last
     // float (the same 1 from every tile, so plain stores suffice)
     if (mark_blended && c2 == 15 && e2 < count &&
         (((s_act[0] | s_act[1] | s_act[2] | s_act[3]) >> j2) & 1u))
-      grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.f;
+      grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.0;
     const uint32_t d_atom = s_d[j2];
     // stage the next batch into the other buffer (read by nobody until the
     // next loop-top barrier) and advance the loads, before this batch's atomics
@@ -474,8 +529,8 @@ __global__ void __launch_bounds__(256) k_raster_backward(
       if (threadIdx.x < kBwdBatch && e2n >= 0) nn_d = ival[rg.x + e2n];
     }
     // ten lanes of the primitive's row each add one value of its gradient
-    // line, so a wave's atomics for a primitive share one 64-byte line
-    if (e2 < count && slot_q >= 0 && val != 0.f)
+    // line, so a wave's atomics for a primitive share one 128-byte line
+    if (live && slot_q >= 0 && val != 0.0)
       unsafeAtomicAdd(grad2d + (size_t)d_atom * kGrad2dStride + slot_q, val);
   }
 }
@@ -501,7 +556,7 @@ void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views,
                             const uint2* ranges,
                             const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
                             const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, float* grad2d, bool mark_blended, bool cull,
+                            const uint32_t* pix_last, double* grad2d, bool mark_blended, bool cull,
                             hipStream_t s) {
   if (total_tiles == 0) return;
 #define G4D_BWD(HD, HA)                                                                                          \

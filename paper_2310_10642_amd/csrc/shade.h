@@ -74,49 +74,80 @@ __device__ __forceinline__ void sh_grad(int deg, float x, float y, float z, cons
   gx += -3.f * SH_C3a * (xx - yy) * gY[15]; gy += 6.f * SH_C3a * x * y * gY[15];
 }
 
-// R = L(ql) R(qr) for unit quaternions, the two matrices of Sec. 3.2.
-__device__ __forceinline__ void isoclinic_left(float4 q, float L[4][4]) {
-  const float a = q.x, b = q.y, c = q.z, d = q.w;
+// R = L(ql) R(qr) for unit quaternions, the two matrices of Sec. 3.2
+// (written once, for float and double).
+template <typename T>
+__device__ __forceinline__ void isoclinic_left(T a, T b, T c, T d, T L[4][4]) {
   L[0][0] = a;  L[0][1] = -b; L[0][2] = -c; L[0][3] = -d;
   L[1][0] = b;  L[1][1] = a;  L[1][2] = -d; L[1][3] = c;
   L[2][0] = c;  L[2][1] = d;  L[2][2] = a;  L[2][3] = -b;
   L[3][0] = d;  L[3][1] = -c; L[3][2] = b;  L[3][3] = a;
 }
-__device__ __forceinline__ void isoclinic_right(float4 q, float Rr[4][4]) {
-  const float p = q.x, qq = q.y, r = q.z, s = q.w;
+template <typename T>
+__device__ __forceinline__ void isoclinic_right(T p, T qq, T r, T s, T Rr[4][4]) {
   Rr[0][0] = p;  Rr[0][1] = -qq; Rr[0][2] = -r;  Rr[0][3] = -s;
   Rr[1][0] = qq; Rr[1][1] = p;   Rr[1][2] = s;   Rr[1][3] = -r;
   Rr[2][0] = r;  Rr[2][1] = -s;  Rr[2][2] = p;   Rr[2][3] = qq;
   Rr[3][0] = s;  Rr[3][1] = r;   Rr[3][2] = -qq; Rr[3][3] = p;
 }
+__device__ __forceinline__ void isoclinic_left(float4 q, float L[4][4]) { isoclinic_left(q.x, q.y, q.z, q.w, L); }
+__device__ __forceinline__ void isoclinic_right(float4 q, float Rr[4][4]) { isoclinic_right(q.x, q.y, q.z, q.w, Rr); }
 
 __device__ __forceinline__ float4 normalize4(float4 q, float& inv_norm) {
   inv_norm = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
   return make_float4(q.x * inv_norm, q.y * inv_norm, q.z * inv_norm, q.w * inv_norm);
 }
 
-// View-independent part: rotation, scaled rotation M = R S and Sigma = M M^T.
-struct Shape4 {
-  float R[4][4];
-  float s[4];
-  float M[4][4];
-  float S[4][4];  // symmetric
-};
+// Scalar helpers for the geometry, written once for float and double (the
+// per-primitive forward and backward chains run in FP64, see k_preprocess).
+__device__ __forceinline__ float sc_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double sc_fma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float sc_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double sc_exp(double x) { return exp(x); }
+__device__ __forceinline__ float sc_rsqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double sc_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sc_abs(float x) { return fabsf(x); }
+__device__ __forceinline__ double sc_abs(double x) { return fabs(x); }
+__device__ __forceinline__ float sc_clamp(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+__device__ __forceinline__ double sc_clamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
-__device__ __forceinline__ void build_shape(float4 ql, float4 qr, float4 ls, Shape4& sh) {
-  float L[4][4], Rr[4][4];
-  isoclinic_left(ql, L);
-  isoclinic_right(qr, Rr);
+// A quaternion normalised in precision T; inv_norm = 1 / |q|.
+template <typename T>
+__device__ __forceinline__ void normalize_q(float4 q, T out[4], T& inv_norm) {
+  const T a = q.x, b = q.y, c = q.z, d = q.w;
+  inv_norm = sc_rsqrt(a * a + b * b + c * c + d * d);
+  out[0] = a * inv_norm; out[1] = b * inv_norm; out[2] = c * inv_norm; out[3] = d * inv_norm;
+}
+
+// View-independent part: unit quaternions, rotation, scaled rotation M = R S
+// and Sigma = M M^T.
+template <typename T>
+struct Shape4T {
+  T ql[4], qr[4], inl, inr;
+  T R[4][4];
+  T s[4];
+  T M[4][4];
+  T S[4][4];  // symmetric
+};
+using Shape4 = Shape4T<float>;
+
+template <typename T>
+__device__ __forceinline__ void build_shape(float4 qlf, float4 qrf, float4 ls, Shape4T<T>& sh) {
+  normalize_q<T>(qlf, sh.ql, sh.inl);
+  normalize_q<T>(qrf, sh.qr, sh.inr);
+  T L[4][4], Rr[4][4];
+  isoclinic_left<T>(sh.ql[0], sh.ql[1], sh.ql[2], sh.ql[3], L);
+  isoclinic_right<T>(sh.qr[0], sh.qr[1], sh.qr[2], sh.qr[3], Rr);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float acc = 0.f;
+      T acc = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc = fmaf(L[i][k], Rr[k][j], acc);
+      for (int k = 0; k < 4; ++k) acc = sc_fma(L[i][k], Rr[k][j], acc);
       sh.R[i][j] = acc;
     }
-  sh.s[0] = __expf(ls.x); sh.s[1] = __expf(ls.y); sh.s[2] = __expf(ls.z); sh.s[3] = __expf(ls.w);
+  sh.s[0] = sc_exp((T)ls.x); sh.s[1] = sc_exp((T)ls.y); sh.s[2] = sc_exp((T)ls.z); sh.s[3] = sc_exp((T)ls.w);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -125,94 +156,114 @@ __device__ __forceinline__ void build_shape(float4 ql, float4 qr, float4 ls, Sha
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = i; j < 4; ++j) {
-      float acc = 0.f;
+      T acc = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc = fmaf(sh.M[i][k], sh.M[j][k], acc);
+      for (int k = 0; k < 4; ++k) acc = sc_fma(sh.M[i][k], sh.M[j][k], acc);
       sh.S[i][j] = acc;
       sh.S[j][i] = acc;
     }
 }
 
-// Everything one view needs from a primitive, forward.
-struct ViewGeom {
-  float dt, s44, pt, lam;
-  float v3[3];      // Sigma_{xyz,t}
-  float muc[3];     // conditional mean
-  float Sc[3][3];   // conditional covariance
-  float pc[3];      // camera-space mean
-  float iz;
-  bool clx, cly;    // Jacobian clamps taken
-  float xi, eta;
-  float T[2][3];    // J W
-  float a2, b2, c2, det;
-  float conic[3];
-  float u, v;
-  float dir[3], rinv;
+// Everything one view needs from a primitive.
+template <typename T>
+struct ViewGeomT {
+  T dt, s44, pt, lam;
+  T v3[3];      // Sigma_{xyz,t}
+  T muc[3];     // conditional mean
+  T Sc[3][3];   // conditional covariance
+  T pc[3];      // camera-space mean
+  T iz;
+  bool clx, cly;  // Jacobian clamps taken
+  T xi, eta;
+  T T_[2][3];   // J W
+  T a2, b2, c2, det;
+  T conic[3];
+  T u, v;
+  T dir[3], rinv;
 };
 
-// Slice, camera transform and EWA projection. Returns false when culled by
-// the temporal filter or the near plane.
-__device__ __forceinline__ bool view_geometry(const float4 mu, const Shape4& sh, const ViewDev& vw, float t_cull,
-                                              float near_plane, ViewGeom& g) {
-  g.dt = vw.t - mu.w;
+// Jacobian clamp limits on x/z, y/z: 1.3x the half field of view.
+__device__ __forceinline__ void clamp_limits(const ViewDev& vw, float& lx, float& ly) {
+  lx = vw.lim_x;
+  ly = vw.lim_y;
+}
+__device__ __forceinline__ void clamp_limits(const ViewDev& vw, double& lx, double& ly) {
+  lx = kFrustumSlack64 * (0.5 * vw.width) / (double)vw.fx;
+  ly = kFrustumSlack64 * (0.5 * vw.height) / (double)vw.fy;
+}
+
+// Slice, camera transform and EWA projection (Sec. 3.2, Eqs. 3-4) in
+// precision T. Returns false when culled by the temporal filter or the near
+// plane (then only dt, s44 and pt are set).
+template <typename T>
+__device__ __forceinline__ bool view_geometry(const float4 mu, const Shape4T<T>& sh, const ViewDev& vw, T t_cull,
+                                              T near_plane, ViewGeomT<T>& g) {
+  g.dt = (T)vw.t - (T)mu.w;
   g.s44 = sh.S[3][3];
-  g.pt = __expf(-0.5f * g.dt * g.dt / g.s44);
+  g.pt = sc_exp((T)-0.5 * g.dt * g.dt / g.s44);
   if (!(g.pt >= t_cull)) return false;
   g.lam = g.dt / g.s44;
   g.v3[0] = sh.S[0][3]; g.v3[1] = sh.S[1][3]; g.v3[2] = sh.S[2][3];
-  g.muc[0] = fmaf(g.v3[0], g.lam, mu.x);
-  g.muc[1] = fmaf(g.v3[1], g.lam, mu.y);
-  g.muc[2] = fmaf(g.v3[2], g.lam, mu.z);
-  const float inv44 = 1.f / g.s44;
+  g.muc[0] = sc_fma(g.v3[0], g.lam, (T)mu.x);
+  g.muc[1] = sc_fma(g.v3[1], g.lam, (T)mu.y);
+  g.muc[2] = sc_fma(g.v3[2], g.lam, (T)mu.z);
+  const T inv44 = (T)1 / g.s44;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) g.Sc[i][j] = sh.S[i][j] - g.v3[i] * g.v3[j] * inv44;
-  const float* W = vw.rot;
+  T W[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W[k] = vw.rot[k];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
-    g.pc[i] = fmaf(W[3 * i + 0], g.muc[0], fmaf(W[3 * i + 1], g.muc[1], fmaf(W[3 * i + 2], g.muc[2], vw.trans[i])));
+    g.pc[i] = sc_fma(W[3 * i + 0], g.muc[0],
+                     sc_fma(W[3 * i + 1], g.muc[1], sc_fma(W[3 * i + 2], g.muc[2], (T)vw.trans[i])));
   if (!(g.pc[2] > near_plane)) return false;
-  g.iz = 1.f / g.pc[2];
-  const float x = g.pc[0], y = g.pc[1];
-  g.u = fmaf(vw.fx * x, g.iz, vw.cx);
-  g.v = fmaf(vw.fy * y, g.iz, vw.cy);
-  const float xz = x * g.iz, yz = y * g.iz;
-  g.clx = fabsf(xz) > vw.lim_x;
-  g.cly = fabsf(yz) > vw.lim_y;
-  g.xi = fminf(fmaxf(xz, -vw.lim_x), vw.lim_x);
-  g.eta = fminf(fmaxf(yz, -vw.lim_y), vw.lim_y);
+  g.iz = (T)1 / g.pc[2];
+  const T fx = vw.fx, fy = vw.fy;
+  const T x = g.pc[0], y = g.pc[1];
+  g.u = sc_fma(fx * x, g.iz, (T)vw.cx);
+  g.v = sc_fma(fy * y, g.iz, (T)vw.cy);
+  T lim_x, lim_y;
+  clamp_limits(vw, lim_x, lim_y);
+  const T xz = x * g.iz, yz = y * g.iz;
+  g.clx = sc_abs(xz) > lim_x;
+  g.cly = sc_abs(yz) > lim_y;
+  g.xi = sc_clamp(xz, -lim_x, lim_x);
+  g.eta = sc_clamp(yz, -lim_y, lim_y);
   // J = [[fx/z, 0, -fx xi/z], [0, fy/z, -fy eta/z]]; T = J W
-  const float j00 = vw.fx * g.iz, j02 = -vw.fx * g.xi * g.iz;
-  const float j11 = vw.fy * g.iz, j12 = -vw.fy * g.eta * g.iz;
+  const T j00 = fx * g.iz, j02 = -fx * g.xi * g.iz;
+  const T j11 = fy * g.iz, j12 = -fy * g.eta * g.iz;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    g.T[0][k] = fmaf(j00, W[k], j02 * W[6 + k]);
-    g.T[1][k] = fmaf(j11, W[3 + k], j12 * W[6 + k]);
+    g.T_[0][k] = sc_fma(j00, W[k], j02 * W[6 + k]);
+    g.T_[1][k] = sc_fma(j11, W[3 + k], j12 * W[6 + k]);
   }
   // Sigma_2d = T Sc T^T
-  float TS[2][3];
+  T TS[2][3];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      TS[r][k] = fmaf(g.T[r][0], g.Sc[0][k], fmaf(g.T[r][1], g.Sc[1][k], g.T[r][2] * g.Sc[2][k]));
-  const float s00 = fmaf(TS[0][0], g.T[0][0], fmaf(TS[0][1], g.T[0][1], TS[0][2] * g.T[0][2]));
-  const float s01 = fmaf(TS[0][0], g.T[1][0], fmaf(TS[0][1], g.T[1][1], TS[0][2] * g.T[1][2]));
-  const float s11 = fmaf(TS[1][0], g.T[1][0], fmaf(TS[1][1], g.T[1][1], TS[1][2] * g.T[1][2]));
-  g.a2 = s00 + kLowpass;
+      TS[r][k] = sc_fma(g.T_[r][0], g.Sc[0][k], sc_fma(g.T_[r][1], g.Sc[1][k], g.T_[r][2] * g.Sc[2][k]));
+  const T s00 = sc_fma(TS[0][0], g.T_[0][0], sc_fma(TS[0][1], g.T_[0][1], TS[0][2] * g.T_[0][2]));
+  const T s01 = sc_fma(TS[0][0], g.T_[1][0], sc_fma(TS[0][1], g.T_[1][1], TS[0][2] * g.T_[1][2]));
+  const T s11 = sc_fma(TS[1][0], g.T_[1][0], sc_fma(TS[1][1], g.T_[1][1], TS[1][2] * g.T_[1][2]));
+  const T lowpass = sizeof(T) == 8 ? (T)kLowpass64 : (T)kLowpass;
+  g.a2 = s00 + lowpass;
   g.b2 = s01;
-  g.c2 = s11 + kLowpass;
+  g.c2 = s11 + lowpass;
   {  // a2 c2 - b2^2 without cancellation error (the b2^2 rounding error is recovered by an FMA)
-    const float p = g.b2 * g.b2;
-    g.det = fmaf(g.a2, g.c2, -p) - fmaf(g.b2, g.b2, -p);
+    const T p = g.b2 * g.b2;
+    g.det = sc_fma(g.a2, g.c2, -p) - sc_fma(g.b2, g.b2, -p);
   }
-  const float idet = 1.f / g.det;
+  const T idet = (T)1 / g.det;
   g.conic[0] = g.c2 * idet;
   g.conic[1] = -g.b2 * idet;
   g.conic[2] = g.a2 * idet;
-  float rx = g.muc[0] - vw.center[0], ry = g.muc[1] - vw.center[1], rz = g.muc[2] - vw.center[2];
-  g.rinv = rsqrtf(rx * rx + ry * ry + rz * rz);
+  const T rx = g.muc[0] - (T)vw.center[0], ry = g.muc[1] - (T)vw.center[1], rz = g.muc[2] - (T)vw.center[2];
+  g.rinv = sc_rsqrt(rx * rx + ry * ry + rz * rz);
   g.dir[0] = rx * g.rinv; g.dir[1] = ry * g.rinv; g.dir[2] = rz * g.rinv;
   return true;
 }
@@ -261,19 +312,57 @@ __device__ __forceinline__ void copy_in(float* __restrict__ lds, const float* __
   for (int i = 4 * n4 + threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
 }
 
-// g[i] = lds[i] (+ g[i] when accumulate).
-__device__ __forceinline__ void copy_out(float* __restrict__ g, const float* __restrict__ lds, int count,
-                                         bool accumulate) {
-  const int n4 = (reinterpret_cast<uintptr_t>(g) & 15u) ? 0 : count >> 2;
-  for (int i = threadIdx.x; i < n4; i += blockDim.x) {
-    float4 v = reinterpret_cast<const float4*>(lds)[i];
-    if (accumulate) {
-      const float4 o = reinterpret_cast<const float4*>(g)[i];
-      v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
-    }
-    reinterpret_cast<float4*>(g)[i] = v;
+// copy_in of the coefficients of `nprim` primitives (k3 floats each) whose
+// flag in `on` is set; the others' LDS slots are left as they are.
+__device__ __forceinline__ void copy_in_active(float* __restrict__ lds, const float* __restrict__ g, int nprim, int k3,
+                                               const uint8_t* __restrict__ on) {
+  const int count = nprim * k3;
+  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
+    const int per = k3 >> 2;  // 16-byte pieces per primitive
+    for (int i = threadIdx.x; i < (count >> 2); i += blockDim.x)
+      if (on[i / per]) reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(g)[i];
+  } else {
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+      if (on[i / k3]) lds[i] = g[i];
   }
-  for (int i = 4 * n4 + threadIdx.x; i < count; i += blockDim.x) g[i] = accumulate ? g[i] + lds[i] : lds[i];
+}
+
+// Whether b holds on some lane of this lane's quad (all four lanes active).
+__device__ __forceinline__ bool quad_any(bool b) {
+  const uint64_t m = __ballot(b);
+  return ((m >> (threadIdx.x & 60u)) & 0xFull) != 0ull;
+}
+
+// Whether the primitive is active in some view of the batch (by its slots).
+__device__ __forceinline__ bool any_view_active(const RenderParams& p, const int32_t* __restrict__ slot, int gidx) {
+  bool any = false;
+  for (int v = 0; v < p.n_views; ++v) any |= slot[(size_t)v * p.n + gidx] >= 0;
+  return any;
+}
+
+// g[i] = lds[i] for the `nprim` primitives (k3 floats each), or g[i] +=
+// lds[i] when accumulate, skipping then the primitives whose flag in `on` is
+// clear (they add nothing).
+__device__ __forceinline__ void copy_out(float* __restrict__ g, const float* __restrict__ lds, int nprim, int k3,
+                                         bool accumulate, const uint8_t* __restrict__ on) {
+  const int count = nprim * k3;
+  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
+    const int per = k3 >> 2;
+    for (int i = threadIdx.x; i < (count >> 2); i += blockDim.x) {
+      float4 v = reinterpret_cast<const float4*>(lds)[i];
+      if (accumulate) {
+        if (!on[i / per]) continue;
+        const float4 o = reinterpret_cast<const float4*>(g)[i];
+        v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+      }
+      reinterpret_cast<float4*>(g)[i] = v;
+    }
+  } else {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+      if (accumulate && !on[i / k3]) continue;
+      g[i] = accumulate ? g[i] + lds[i] : lds[i];
+    }
+  }
 }
 
 // y[i] = Y[4 sub + i] (selects with constant indices, no register indexing).

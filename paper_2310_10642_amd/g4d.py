@@ -45,7 +45,7 @@ class G4DCamera(ctypes.Structure):
 class G4DStats(ctypes.Structure):
     _fields_ = [("n_views", ctypes.c_int64), ("active_total", ctypes.c_int64), ("instances", ctypes.c_int64),
                 ("tiles", ctypes.c_int64), ("max_tile_list", ctypes.c_int64), ("fragments", ctypes.c_int64),
-                ("rounds", ctypes.c_int64)]
+                ("rounds", ctypes.c_int64), ("culled_nonfinite", ctypes.c_int64)]
 
 
 class G4DError(RuntimeError):
@@ -143,6 +143,8 @@ class Renderer:
         self.generation = 0
         self._prims = None
         self._views = None
+        self._densify = None
+        self.n = -1
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -177,9 +179,19 @@ class Renderer:
                 raise ValueError("primitive tensors disagree on n")
         if coeffs.numel() != n * self.n_coeffs * 3:
             raise ValueError(f"coeffs must hold n x {self.n_coeffs} x 3 values")
+        if self._densify is not None and n != self.n:
+            # the registered accumulators have the old primitive count
+            self.set_densify_stats(None, None, None)
+            raise ValueError(f"densification accumulators were registered for {self.n} primitives, not {n}; "
+                             "register accumulators of the new size after set_primitives")
         self._prims = ts  # keep alive
         self._check(self.lib.g4d_set_primitives(self.ctx, n, *[_ptr(t) for t in ts]))
         self.n = n
+        if self._densify is not None:
+            # the library drops the accumulators on set_primitives; the same
+            # primitive count keeps them registered (e.g. the autograd path,
+            # which sets the primitives on every forward)
+            self._check(self.lib.g4d_set_densify_stats(self.ctx, *[_ptr(t) for t in self._densify]))
 
     def render(self, cameras: Sequence, times: Sequence[float], depth: bool = True, alpha: bool = True,
                out: Optional[Sequence[Optional[torch.Tensor]]] = None):
@@ -332,8 +344,8 @@ class Renderer:
         code = DBG[what]
         nb = ctypes.c_int64()
         self._check(self.lib.g4d_debug_size(self.ctx, code, ctypes.byref(nb)))
-        dt = np.float32 if what in ("records", "pix_t", "grad2d") else np.uint32
-        arr = np.empty(int(nb.value) // 4, dtype=dt)
+        dt = {"records": np.float32, "pix_t": np.float32, "grad2d": np.float64}.get(what, np.uint32)
+        arr = np.empty(int(nb.value) // np.dtype(dt).itemsize, dtype=dt)
         if arr.size:
             self._check(self.lib.g4d_debug_copy(self.ctx, code, arr.ctypes.data_as(ctypes.c_void_p), nb.value))
         if what == "records":
@@ -363,6 +375,9 @@ class Render4DGS(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_alpha):
+        # unpacking makes autograd check that no parameter was modified in
+        # place since the forward: the library reads them again here
+        _ = ctx.saved_tensors
         r = ctx.renderer
         if r.generation != ctx.generation:
             raise RuntimeError("g4d: another render ran on this Renderer before this backward")

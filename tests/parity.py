@@ -30,16 +30,48 @@ def gpu_setup(scene, bg=(0.0, 0.0, 0.0)):
     return r, params
 
 
+CAUSES = ("rect", "floor", "stop", "tie")
+
+
+def f32(x) -> float:
+    """The float32 value the library receives for a time or interval passed
+    as a Python float (its C ABI takes float32): the oracle gets the same."""
+    return float(np.float32(x))
+
+
 def oracle_view(scene, cam, t, bg=(0.0, 0.0, 0.0), tiles=None, requires_grad=False):
-    out = O.render_full(scene, cam, float(t), bg=bg, requires_grad=requires_grad, tiles=tiles)
+    out = O.render_full(scene, cam, f32(t), bg=bg, requires_grad=requires_grad, tiles=tiles)
     img = dict(rgb=O.assemble(out, cam, "rgb", 3), depth=O.assemble(out, cam, "depth"),
                alpha=O.assemble(out, cam, "alpha"), T=O.assemble(out, cam, "T"), last=O.assemble(out, cam, "last"),
                unc=O.assemble(out, cam, "uncertain"), unc_g=O.assemble(out, cam, "uncertain_grad"),
                unc_o=O.assemble(out, cam, "uncertain_order"))
+    for c in CAUSES:
+        img["cause_" + c] = O.assemble(out, cam, "cause_" + c)
     return out, img
 
 
-def compare_images(gpu_rgb, gpu_depth, gpu_alpha, img, max_flag_frac=1e-2, atol=IMG_ATOL):
+def flag_report(img, rendered=None):
+    """Flagged pixels per cause (a pixel may have several causes)."""
+    if rendered is None:
+        rendered = ~np.isnan(img["depth"].detach().numpy())
+    rep = {c: int((img["cause_" + c].numpy() & rendered).sum()) for c in CAUSES if "cause_" + c in img}
+    rep["any"] = int((img["unc"].numpy() & rendered).sum())
+    rep["grad"] = int((img["unc_g"].numpy() & rendered).sum())
+    return rep
+
+
+# Flagged pixels allowed per parity comparison (at least 2). The flags hold
+# the pixels whose value a decision an FP32 implementation may take the other
+# way can move by more than 0.3 of the image tolerance; the reach of each
+# decision is derived from the float32 records and fragment arithmetic
+# (oracle Margins), so how many there are follows from the scene, not from a
+# choice. The cap catches an oracle that flags too much: over the parity
+# scenes the observed rate is 0 - 0.2 % of a view's sampled pixels (2 of
+# 1024 at most), 0.02 % over all of them.
+MAX_FLAG_FRAC = 3e-3
+
+
+def compare_images(gpu_rgb, gpu_depth, gpu_alpha, img, max_flag_frac=MAX_FLAG_FRAC, atol=IMG_ATOL):
     """gpu_*: numpy [3,H,W] / [H,W]; img from oracle_view. NaN in the oracle
     marks pixels not rendered there (sampled tiles)."""
     rgb = img["rgb"].detach().numpy()
@@ -50,13 +82,14 @@ def compare_images(gpu_rgb, gpu_depth, gpu_alpha, img, max_flag_frac=1e-2, atol=
     ok = rendered & ~unc
     n_rendered = int(rendered.sum())
     assert n_rendered > 0
-    assert unc.sum() <= max(2, max_flag_frac * n_rendered), f"{int(unc.sum())} flagged of {n_rendered}"
+    flags = flag_report(img, rendered)
+    assert unc.sum() <= max(2, max_flag_frac * n_rendered), f"{int(unc.sum())} flagged of {n_rendered}: {flags}"
     err_rgb = np.abs(gpu_rgb - rgb).max(0)
     err = np.maximum(err_rgb, np.maximum(np.abs(gpu_depth - dep), np.abs(gpu_alpha - alp)))
     bad = ok & ~(err <= atol)
     assert not bad.any(), (f"{int(bad.sum())} pixels off; worst {float(err[ok].max()):.3g} at "
                            f"{np.unravel_index(np.argmax(np.where(ok, err, 0)), err.shape)}")
-    return dict(max_err=float(err[ok].max()), flagged=int(unc.sum()), pixels=n_rendered)
+    return dict(max_err=float(err[ok].max()), pixels=n_rendered, flagged=flags)
 
 
 def compare_grads(gpu_grads, oracle_params, rel=GRAD_REL, report=None):

@@ -51,10 +51,38 @@ def test_header_constants_match_binding():
 
 
 def test_struct_layouts():
+    """The binding's ctypes structs have the sizes and field offsets that a C
+    compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    import tempfile
     from paper_2310_10642_amd import g4d
-    assert ctypes.sizeof(g4d.G4DOptions) == 32
-    assert ctypes.sizeof(g4d.G4DCamera) == 4 * (2 + 4 + 12 + 3)
-    assert ctypes.sizeof(g4d.G4DStats) == 56
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"g4d_options": g4d.G4DOptions, "g4d_camera": g4d.G4DCamera, "g4d_stats": g4d.G4DStats,
+               "g4d_adam_options": g4d.G4DAdamOptions}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "g4d.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        with open(src, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            parts = line.split()
+            got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_validation_before_any_hip_call():

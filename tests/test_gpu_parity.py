@@ -81,12 +81,20 @@ def test_forward_image_parity(name, mk_scene, mk_cam, t, bg):
 
 @pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
 def test_preprocess_records_parity(name, mk_scene, mk_cam, t, bg):
+    """The forward geometry is evaluated in FP64 and rounded once: every
+    record value (u, v, z, conic, opacity * p(t)) equals the oracle's FP64
+    value rounded to float32, bit for bit (a value within 1e-10 of a rounding
+    midpoint may take the other neighbour); the colour (a float32 4DSH sum)
+    is within 2e-6. The active set is the oracle's minus the primitives
+    that cannot reach alpha 1/255 anywhere in their rectangle (the default
+    binning culls those), and each rectangle is the oracle's 3-sigma
+    rectangle cut to the alpha-floor box."""
     _say(f"[preprocess parity] {name}")
     scene, cam = mk_scene(), mk_cam()
     r, _ = PT.gpu_setup(scene, bg)
     r.render([cam], [t])
     recs, ids = r.debug("records"), r.debug("ids")
-    pre = O.preprocess(O.params_from_scene(scene), O.to_ocamera(cam), float(t), scene.sh_degree, scene.t_order,
+    pre = O.preprocess(O.params_from_scene(scene), O.to_ocamera(cam), PT.f32(t), scene.sh_degree, scene.t_order,
                        scene.t_period)
     act_o = pre["active"].numpy()
     rs, rm = pre["rect_sure"].numpy(), pre["rect_maybe"].numpy()
@@ -94,9 +102,6 @@ def test_preprocess_records_parity(name, mk_scene, mk_cam, t, bg):
     unsure = (area(rs) == 0) & (area(rm) > 0)
     act_g = np.zeros(scene.n, bool)
     act_g[ids] = True
-    # the GPU keeps a subset of the definition's active primitives: those whose
-    # alpha-floor box (where opacity * exp(power) can reach 1/255) meets their
-    # 3-sigma rectangle; every primitive with a non-empty such box is kept
     tight, visible = PT.alpha_floor_box(pre, cam)
     assert not (act_g & ~act_o & ~unsure).any(), np.nonzero(act_g & ~act_o & ~unsure)[0][:10]
     dropped = act_o & ~act_g & ~unsure
@@ -105,16 +110,16 @@ def test_preprocess_records_parity(name, mk_scene, mk_cam, t, bg):
     row = {int(g): i for i, g in enumerate(ids)}
     sel = np.array([row[int(g)] for g in common])
     R = recs[sel]
-    u, v, z = pre["u"].detach().numpy()[common], pre["v"].detach().numpy()[common], pre["z"].detach().numpy()[common]
-    assert np.allclose(R[:, 0], u, atol=2e-3, rtol=0)
-    assert np.allclose(R[:, 1], v, atol=2e-3, rtol=0)
-    assert np.allclose(R[:, 2], z, rtol=2e-6, atol=0)
-    assert np.allclose(R[:, 3], pre["opac"].detach().numpy()[common], rtol=2e-5, atol=1e-7)
-    con = pre["conic"].detach().numpy()[common]
-    scale = np.abs(con).max(1, keepdims=True)
-    assert np.allclose(R[:, 4:7] / scale, con / scale, atol=2e-4, rtol=0)
+    doubt = pre["rec_doubt"].numpy()[common]
+    f32 = lambda k: pre[k].numpy()[common].astype(np.float32)
+    for col, key in ((0, "u32"), (1, "v32"), (2, "z32"), (3, "opac32")):
+        same = R[:, col] == f32(key)
+        assert (same | doubt).all(), (key, int((~same & ~doubt).sum()))
+    same = R[:, 4:7] == pre["conic32"].numpy()[common].astype(np.float32)
+    assert (same.all(1) | doubt).all(), int((~same.all(1) & ~doubt).sum())
+    _say(f"  {len(common)} records bit-exact ({int(doubt.sum())} with a rounding in doubt)")
     col = pre["color"].detach().numpy()[common]
-    assert np.allclose(R[:, 8:11], col, atol=2e-5, rtol=0)
+    assert np.allclose(R[:, 8:11], col, atol=2e-6, rtol=0)
     rx = R[:, 7].view(np.uint32)
     ry = R[:, 11].view(np.uint32)
     rect_g = np.stack([rx & 0xFFFF, ry & 0xFFFF, rx >> 16, ry >> 16], 1).astype(np.int64)
@@ -134,7 +139,94 @@ def test_preprocess_records_parity(name, mk_scene, mk_cam, t, bg):
     assert (np.diff(ids.astype(np.int64))[tie] > 0).all()
 
 
-@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+BIG_CASES = [
+    # footprints taller than 256 px: blocks of 64 records span more than 1024
+    # tile rows (the emission's per-instance row walk)
+    ("big_splats_1352x1014", lambda: _big_splat_scene(41, 600, grow=1.9, sh=1, to=1),
+     lambda: scenegen.look_at_camera((0.3, 0.2, 3.3), 1352, 1014), 0.5, (0.0, 0.0, 0.0)),
+    # medium footprints: some blocks of 64 records hold more than 4096
+    # instances in at most 1024 rows (the emission's chunked instance map)
+    ("medium_splats_1352x1014", lambda: _big_splat_scene(42, 3000, grow=0.3, sh=1, to=1),
+     lambda: scenegen.look_at_camera((0.3, 0.2, 3.5), 1352, 1014), 0.5, (0.0, 0.0, 0.0)),
+]
+REF_CASES = CASES + BIG_CASES
+
+
+def _emit_blocks(recs):
+    """Per block of 64 depth-ordered records (one emission workgroup): tile
+    rows and instances of the records' rectangles."""
+    rx, ry = recs[:, 7].view(np.uint32), recs[:, 11].view(np.uint32)
+    rows = (ry >> 16).astype(np.int64) - (ry & 0xFFFF)
+    cols = (rx >> 16).astype(np.int64) - (rx & 0xFFFF)
+    br = np.array([rows[i:i + 64].sum() for i in range(0, len(rows), 64)], np.int64)
+    bi = np.array([(rows * cols)[i:i + 64].sum() for i in range(0, len(rows), 64)], np.int64)
+    return br, bi
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", REF_CASES, ids=[c[0] for c in REF_CASES])
+def test_reference_footprint_tile_lists_bit_exact(name, mk_scene, mk_cam, t, bg):
+    """With G4D_TUNE_ELLIPSE_CULL = 0 the library bins by the plain
+    footprint rule of the definition: the active set, every record's 3-sigma
+    tile rectangle and therefore the instance count equal the oracle's, and
+    every tile's sorted list equals the oracle's list of the primitives whose
+    rectangle covers it, ordered by (float32 depth, index) -- the order of the
+    identical float32 keys. Primitives with a decision within the FP64 margin
+    (p(t), near plane, radius or rectangle edge) are left out of the
+    comparison and counted (expected: none or a few)."""
+    _say(f"[reference footprint] {name}")
+    from paper_2310_10642_amd import g4d
+    scene, cam = mk_scene(), mk_cam()
+    r, _ = PT.gpu_setup(scene, bg)
+    r.set_tuning(g4d.G4D_TUNE_ELLIPSE_CULL, 0)
+    rgb, dep, alp = r.render([cam], [t])
+    torch.cuda.synchronize()
+    recs, ids = r.debug("records"), r.debug("ids").astype(np.int64)
+    vals, ranges = r.debug("tile_vals"), r.debug("ranges")
+    stats = r.stats()
+    pre = O.preprocess(O.params_from_scene(scene), O.to_ocamera(cam), PT.f32(t), scene.sh_degree, scene.t_order,
+                       scene.t_period)
+    act_o = pre["active"].numpy()
+    rs, rm = pre["rect_sure"].numpy(), pre["rect_maybe"].numpy()
+    doubtful = (rs != rm).any(1)
+    act_g = np.zeros(scene.n, bool)
+    act_g[ids] = True
+    assert ((act_g == act_o) | doubtful).all(), np.nonzero((act_g != act_o) & ~doubtful)[0][:10]
+    rx, ry = recs[:, 7].view(np.uint32), recs[:, 11].view(np.uint32)
+    rect_g = np.stack([rx & 0xFFFF, ry & 0xFFFF, rx >> 16, ry >> 16], 1).astype(np.int64)
+    rect_o = pre["rect"].numpy()[ids]
+    ok = ~doubtful[ids]
+    assert (rect_g[ok] == rect_o[ok]).all()
+    area = (rect_g[:, 2] - rect_g[:, 0]) * (rect_g[:, 3] - rect_g[:, 1])
+    assert stats["instances"] == int(area.sum())
+    br, bi = _emit_blocks(recs)
+    _say(f"  {len(ids)} records, {stats['instances']} instances, {int(doubtful[act_o | act_g].sum())} in doubt; "
+         f"emission blocks over 1024 rows: {int((br > 1024).sum())}, chunked (> 4096 instances): "
+         f"{int(((br <= 1024) & (bi > 4096)).sum())}")
+    if name == "big_splats_1352x1014":
+        assert (br > 1024).any()
+    if name == "medium_splats_1352x1014":
+        assert ((br <= 1024) & (bi > 4096)).any()
+    # per-tile lists: the oracle's primitives covering the tile by (float32 z, index)
+    z32 = pre["z32"].numpy().astype(np.float32)
+    skip = set(np.nonzero(doubtful)[0].tolist())
+    tx = (cam.width + 15) // 16
+    rect_all = pre["rect"].numpy()
+    act_idx = np.nonzero(act_o & ~doubtful)[0]
+    order = act_idx[np.lexsort((act_idx, z32[act_idx]))]
+    ro = rect_all[order]
+    for tid in range(ranges.shape[0]):
+        txi, tyi = tid % tx, tid // tx
+        cov = (ro[:, 0] <= txi) & (txi < ro[:, 2]) & (ro[:, 1] <= tyi) & (tyi < ro[:, 3])
+        want = order[cov]
+        s0, e0 = ranges[tid]
+        got = [int(g) for g in ids[vals[s0:e0]] if int(g) not in skip]
+        assert got == want.tolist(), (tid, got[:8], want[:8].tolist())
+    # and the images are those of the default binning
+    r.set_tuning(g4d.G4D_TUNE_ELLIPSE_CULL, 1)
+    rgb1, dep1, alp1 = r.render([cam], [t])
+    assert torch.equal(rgb, rgb1) and torch.equal(dep, dep1) and torch.equal(alp, alp1)
+
+
 def _box_min_q(a, b, c, ex0, ex1, ey0, ey1):
     """FP64 minimum of a dx^2 + 2 b dx dy + c dy^2 over [ex0, ex1] x [ey0, ey1]
     (a convex quadratic: 0 when the box holds the origin, else the smallest
@@ -146,7 +238,7 @@ def _box_min_q(a, b, c, ex0, ex1, ey0, ey1):
     return np.where(inside, 0.0, np.minimum.reduce(cands))
 
 
-@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", REF_CASES, ids=[c[0] for c in REF_CASES])
 def test_binning_is_a_valid_stable_sort(name, mk_scene, mk_cam, t, bg):
     """The (tile, record) instances are ordered by tile then by depth position
     and delimited by the tile ranges; each record is listed in the tiles of
@@ -194,7 +286,9 @@ def test_binning_is_a_valid_stable_sort(name, mk_scene, mk_cam, t, bg):
     stats = r.stats()
     assert stats["instances"] == len(got)
     assert stats["active_total"] == recs.shape[0]
-    _say(f"  instances {len(got)}: {len(must)} required, {len(may)} allowed")
+    br, bi = _emit_blocks(r.debug("records"))
+    _say(f"  instances {len(got)}: {len(must)} required, {len(may)} allowed; emission blocks over 1024 rows: "
+         f"{int((br > 1024).sum())}, with more than 4096 instances: {int((bi > 4096).sum())}")
 
 
 @pytest.mark.parametrize("name,mk_scene,mk_cam,t,bg", CASES, ids=[c[0] for c in CASES])
@@ -523,10 +617,13 @@ def test_batched_fwd_bwd_500k_8_views():
     for v in sel:
         cam, t = wl.cameras[v], times[v]
         tiles = scenegen.sample_pixels_dlddi(30 + v, [cam], 5)[0].tolist()
-        out = O.render_view(params_o, cam, t, wl.scene.sh_degree, wl.scene.t_order, wl.scene.t_period, tiles=tiles)
+        out = O.render_view(params_o, cam, PT.f32(t), wl.scene.sh_degree, wl.scene.t_order, wl.scene.t_period,
+                            tiles=tiles)
         img = dict(rgb=O.assemble(out, cam, "rgb", 3), depth=O.assemble(out, cam, "depth"),
                    alpha=O.assemble(out, cam, "alpha"), unc=O.assemble(out, cam, "uncertain"),
                    unc_g=O.assemble(out, cam, "uncertain_grad"))
+        for c in PT.CAUSES:
+            img["cause_" + c] = O.assemble(out, cam, "cause_" + c)
         rendered = ~np.isnan(img["depth"].detach().numpy())
         mask = (rendered & ~img["unc_g"].numpy()).astype(np.float64)
         drgb, _, _ = PT.dl_maps(40 + v, cam.height, cam.width, mask)
@@ -683,7 +780,7 @@ def test_flow_parity(name, mk_scene, mk_cam, t, bg):
     _, img = PT.oracle_view(scene, cam, t, bg)
     assert np.abs(g_rgb - img["rgb"].numpy())[:, ~img["unc"].numpy()].max() <= PT.IMG_ATOL
     for v, tv in enumerate((t, t2)):
-        out = O.render_flow(scene, cam, tv, dt)
+        out = O.render_flow(scene, cam, PT.f32(tv), PT.f32(dt))
         ref = O.assemble(out, cam, "rgb", 3)[:2].detach().numpy()
         # value flags: a decision FP32 may flip moves the blend weights by at
         # most 1e-5 at unflagged pixels, i.e. the flow by 1e-5 x a few pixels
@@ -693,14 +790,17 @@ def test_flow_parity(name, mk_scene, mk_cam, t, bg):
         tol = 1e-4 * (1.0 + np.abs(ref)[:, ok])
         _say(f"  view {v}: max |flow| {np.abs(ref).max():.3g} px, max err {err.max():.3g}, "
              f"flagged {unc.mean():.3%}")
-        assert unc.mean() <= 1e-2 and (err <= tol).all()
+        assert unc.sum() <= max(2, PT.MAX_FLAG_FRAC * unc.size) and (err <= tol).all()
         assert np.abs(ref).max() > 1e-3           # the scene moves
 
 
 def test_densify_stats_parity():
     """Densification statistics of two views in one batch against the
-    oracle's: per-view |dL/d(u,v)|, |dL/dmu_t| and the blended-view count;
-    then the same batch split into two rounds accumulates the same values."""
+    oracle's: per-view |dL/d(u,v)|, |dL/dmu_t| and the blended-view count.
+    Counts agree exactly except at primitives whose blended-or-not decision
+    in a view the oracle flags as within FP32 reach (they may differ by at
+    most that many views); the sums agree where the counts do. The same batch
+    split into two rounds accumulates the same values."""
     _say("[densification statistics, 3000 primitives x 2 views]")
     from paper_2310_10642_amd import g4d
     scene = _big_splat_scene(5, 3000, grow=0.8)
@@ -711,7 +811,7 @@ def test_densify_stats_parity():
         _, img = PT.oracle_view(scene, cam, t)
         mask = (~img["unc_g"].numpy()).astype(np.float64)
         dls.append(PT.dl_maps(60 + v, cam.height, cam.width, mask)[0])
-    uv_o, t_o, cnt_o = (x.numpy() for x in O.densify_stats(scene, cams, times, dls))
+    uv_o, t_o, cnt_o, unsure = (x.numpy() for x in O.densify_stats(scene, cams, [PT.f32(x) for x in times], dls))
     r, _ = PT.gpu_setup(scene)
     n = scene.n
     dl = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dls]).astype(np.float32)).cuda()
@@ -727,10 +827,12 @@ def test_densify_stats_parity():
         assert r.stats()["rounds"] == (1 if pairs > n else 2)
         runs.append([_np(x) for x in acc])
     uv_g, t_g, cnt_g = runs[0]
-    same = cnt_g == cnt_o
-    _say(f"  blended-view counts equal for {same.mean():.4%} of primitives; "
-         f"{int((cnt_o > 0).sum())} blended somewhere")
-    assert (cnt_o > 0).sum() > 100 and same.mean() >= 0.995
+    diff = np.abs(cnt_g.astype(np.int64) - cnt_o)
+    _say(f"  {int((cnt_o > 0).sum())} primitives blended somewhere; {int((unsure > 0).sum())} with a flagged "
+         f"blend decision; counts differ at {int((diff > 0).sum())}")
+    assert (cnt_o > 0).sum() > 100
+    assert (diff <= unsure).all(), np.nonzero(diff > unsure)[0][:10]
+    same = (diff == 0) & (unsure == 0)
     for name, a, b in (("uv", uv_g, uv_o), ("t", t_g, t_o)):
         a, b = a[same].astype(np.float64), b[same]
         assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), name
@@ -798,11 +900,9 @@ def test_ellipse_cull_is_exact():
     footprints in a batch of views: images, transmittance and last
     contributors (as primitives) bit for bit, and the same (record, tile)
     pairs blended.
-    Gradients agree up to the order of the float atomic sums: a needle adds
-    terms of both signs from a hundred or more tiles, and the two modes visit
-    tiles in different orders (the heavy-first order follows list lengths),
-    so they are held to 1e-2 of the norm (observed: up to 3e-3; two runs of
-    one mode differ by up to 1.4e-4)."""
+    Gradients agree up to the order of the FP64 atomic sums of the tiles'
+    shares (each tile's share is the same float32 value in both modes; the
+    modes visit tiles in different orders): 1e-6 of the norm."""
     _say("[ellipse cull is exact]")
     from paper_2310_10642_amd import g4d
     scene = _needle_scene(12, 6000, 2.0, 1.5)
@@ -838,7 +938,7 @@ def test_ellipse_cull_is_exact():
         spread = np.linalg.norm(c - b)
         _say(f"  {name}: |cull - all| / |g| = {np.linalg.norm(a - b) / max(nb, 1e-30):.2e}, "
              f"two runs {spread / max(nb, 1e-30):.2e}")
-        assert np.isfinite(a).all() and np.linalg.norm(a - b) <= 1e-2 * nb, name
+        assert np.isfinite(a).all() and np.linalg.norm(a - b) <= 1e-6 * nb, name
 
 
 def test_sync_free_arena_overflow():
@@ -980,3 +1080,180 @@ def test_split_sample_matches_oracle():
     ref = OP.split_sample(sc, idx[ok], z[ok])
     assert np.isnan(out[7]).all()
     assert np.allclose(out[ok], ref, rtol=1e-5, atol=1e-6)
+
+
+def _oracle_views_grad(scene, cams, times, tiles_per_view, dl_seed, bg=(0.0, 0.0, 0.0), planes=("rgb",)):
+    """The oracle over sampled tiles of several views sharing one set of
+    parameters: images per view, and the gradient of sum_v <dL/dI_v, I_v> for
+    random output gradients (zero on gradient-flagged pixels) of the given
+    planes. Returns (params, [(img, dl dict)] per view)."""
+    params = O.params_from_scene(scene, requires_grad=True)
+    total = torch.zeros((), dtype=torch.float64)
+    views = []
+    for v, (cam, t) in enumerate(zip(cams, times)):
+        tiles = tiles_per_view[v]
+        out = O.render_view(params, cam, PT.f32(t), scene.sh_degree, scene.t_order, scene.t_period, bg, tiles=tiles)
+        img = dict(rgb=O.assemble(out, cam, "rgb", 3), depth=O.assemble(out, cam, "depth"),
+                   alpha=O.assemble(out, cam, "alpha"), unc=O.assemble(out, cam, "uncertain"),
+                   unc_g=O.assemble(out, cam, "uncertain_grad"))
+        for c in PT.CAUSES:
+            img["cause_" + c] = O.assemble(out, cam, "cause_" + c)
+        rendered = ~np.isnan(img["depth"].detach().numpy())
+        mask = (rendered & ~img["unc_g"].numpy()).astype(np.float64)
+        drgb, ddep, dalp = PT.dl_maps(dl_seed + v, cam.height, cam.width, mask)
+        dl = dict(rgb=drgb, depth=ddep if "depth" in planes else None, alpha=dalp if "alpha" in planes else None)
+        total = total + O.tile_linear_loss(out, torch.as_tensor(drgb),
+                                           None if dl["depth"] is None else torch.as_tensor(ddep),
+                                           None if dl["alpha"] is None else torch.as_tensor(dalp), cam)
+        views.append((img, dl))
+    total.backward()
+    return params, views
+
+
+def _cat_planes(cams, per_view, key, channels):
+    """Concatenated device buffer of one output-gradient plane (zeros where a
+    view has none); None when no view has it."""
+    if all(dl[key] is None for _, dl in per_view):
+        return None
+    parts = []
+    for cam, (_, dl) in zip(cams, per_view):
+        x = dl[key]
+        parts.append(np.zeros((channels, cam.height, cam.width)) if x is None else x)
+    return torch.from_numpy(np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)).cuda()
+
+
+def test_bench_step_variants_match_oracle():
+    """Exactly what the benchmark times: the 300k scene over 8 views at
+    1352x1014 rendered with no depth or alpha planes, and the rgb-only
+    backward; on sampled tiles of two views, the images and the gradients
+    match the oracle. The backward with a depth plane only and with an alpha
+    plane only (the other two compiled variants) match it too."""
+    _say("[bench step variants, 300k x 8 views]")
+    wl = scenegen.bench_workload(8)
+    cams, times = wl.cameras, [float(x) for x in wl.times]
+    sel = [2, 6]
+    tiles = {v: scenegen.sample_pixels_dlddi(80 + v, [cams[v]], 4)[0].tolist() for v in sel}
+    r, _ = PT.gpu_setup(wl.scene)
+    rgb, dep, alp = r.render(cams, times, depth=False, alpha=False)
+    assert dep is None and alp is None
+    items = r.split(rgb)
+    for planes in (("rgb",), ("rgb", "depth"), ("rgb", "alpha")):
+        params, views = _oracle_views_grad(wl.scene, [cams[v] for v in sel], [times[v] for v in sel],
+                                           [tiles[v] for v in sel], 90, planes=planes)
+        if planes == ("rgb",):
+            for v, (img, _) in zip(sel, views):
+                g_rgb = _np(items[v][0])
+                rendered = ~np.isnan(img["depth"].detach().numpy())
+                ok = rendered & ~img["unc"].numpy()
+                err = np.abs(g_rgb - img["rgb"].detach().numpy()).max(0)
+                _say(f"  view {v}: max rgb err {float(err[ok].max()):.3g}, flags {PT.flag_report(img, rendered)}")
+                assert (err[ok] <= PT.IMG_ATOL).all()
+                assert (rendered & img["unc"].numpy()).sum() <= max(2, PT.MAX_FLAG_FRAC * rendered.sum())
+        per_view = []
+        for v, cam in enumerate(cams):
+            per_view.append(views[sel.index(v)] if v in sel else (None, dict(rgb=None, depth=None, alpha=None)))
+        dl_rgb = _cat_planes(cams, per_view, "rgb", 3)
+        dl_dep = _cat_planes(cams, per_view, "depth", 1)
+        dl_alp = _cat_planes(cams, per_view, "alpha", 1)
+        if planes != ("rgb",):
+            # the depth / alpha variants need a render that kept those planes' state
+            r.render(cams, times, depth="depth" in planes, alpha="alpha" in planes)
+        g = r.backward(dl_rgb, dl_dep, dl_alp)
+        torch.cuda.synchronize()
+        rep = {}
+        PT.compare_grads(g, params, report=rep)
+        _say(f"  backward {planes}: rel L2 {rep}")
+
+
+def test_needle_scene_gradients_match_oracle_in_both_cull_modes():
+    """The 6000-needle, 3-view scene of the ellipse-cull test: with the
+    ellipse tests on and off, the batched gradients match the oracle's on
+    sampled tiles of every view at the gradient tolerance (the needles add
+    terms of both signs from many tiles in an order the two modes do not
+    share)."""
+    _say("[needles x 3 views: gradients in both cull modes]")
+    from paper_2310_10642_amd import g4d
+    scene = _needle_scene(12, 6000, 2.0, 1.5)
+    cams = [scenegen.look_at_camera((math.sin(a) * 3.2, 0.25, math.cos(a) * 3.2), w, h)
+            for a, (w, h) in zip([0.0, 1.7, 3.6], [(160, 120), (131, 97), (64, 200)])]
+    times = [0.3, 0.55, 0.8]
+    bg = (0.1, 0.2, 0.3)
+    tiles = [scenegen.sample_pixels_dlddi(100 + v, [c], 10)[0].tolist() for v, c in enumerate(cams)]
+    params, views = _oracle_views_grad(scene, cams, times, tiles, 110, bg=bg, planes=("rgb", "depth", "alpha"))
+    r, _ = PT.gpu_setup(scene, bg)
+    for cull in (1, 0):
+        r.set_tuning(g4d.G4D_TUNE_ELLIPSE_CULL, cull)
+        rgb, dep, alp = r.render(cams, times)
+        for v, (img, _) in enumerate(views):
+            # aspect ratios of ~33: the quadratic form of a fragment cancels
+            # terms far larger than itself, which widens the float32 reach of
+            # its alpha (Margins.alpha_fp32) and the flags with it
+            res = PT.compare_images(*(_np(x) for x in r.split(rgb, dep, alp)[v]), img, max_flag_frac=1e-2)
+            _say(f"  cull {cull} view {v}: {res}")
+        g = r.backward(_cat_planes(cams, views, "rgb", 3), _cat_planes(cams, views, "depth", 1),
+                       _cat_planes(cams, views, "alpha", 1))
+        torch.cuda.synchronize()
+        rep = {}
+        PT.compare_grads(g, params, report=rep)
+        _say(f"  cull {cull}: grads rel L2 {rep}")
+    r.set_tuning(g4d.G4D_TUNE_ELLIPSE_CULL, 1)
+
+
+def test_nonfinite_parameters_are_culled_and_counted():
+    """Primitives with a NaN or infinite parameter are left out: one with a
+    non-finite mean, scale, quaternion or opacity in every view, one with a
+    non-finite 4DSH coefficient where it would otherwise be drawn (rendered
+    fully transparent). Images equal, bit for bit, those of the scene without
+    those primitives; stats count the pairs left out; their gradients are
+    zero and every other gradient matches the scene without them."""
+    _say("[non-finite parameters]")
+    base = _big_splat_scene(5, 3000, grow=0.8)
+    cams = [scenegen.look_at_camera((1.0, 0.5, 3.5), 100, 70), scenegen.look_at_camera((-1.2, -0.2, 3.2), 96, 64)]
+    times = [0.37, 0.52]
+    r, _ = PT.gpu_setup(base)
+    r.render(cams, times)
+    n = base.n
+    ids = r.debug("ids").astype(np.int64)
+    pairs = np.bincount(ids % n, minlength=n)              # active views per primitive
+    visible = np.nonzero(pairs > 0)[0]
+    rng = np.random.default_rng(7)
+    pick = rng.choice(visible, size=12, replace=False)
+    geo_bad, coef_bad = pick[:7], pick[7:]
+    bad = scenegen.Scene(*(np.array(getattr(base, k)) for k in ("means4", "log_scales4", "q_left", "q_right",
+                                                                "opacity_logit", "coeffs")),
+                         base.sh_degree, base.t_order, base.t_period)
+    nan, inf = np.float32(np.nan), np.float32(np.inf)
+    bad.means4[geo_bad[0], 0] = nan
+    bad.means4[geo_bad[1], 3] = -inf
+    bad.log_scales4[geo_bad[2], 2] = inf
+    bad.q_left[geo_bad[3], 1] = nan
+    bad.q_right[geo_bad[4], 0] = -inf
+    bad.opacity_logit[geo_bad[5]] = nan
+    bad.log_scales4[geo_bad[6], 3] = nan
+    bad.coeffs[coef_bad[0], 0, 0] = nan
+    bad.coeffs[coef_bad[1], 3, 2] = inf
+    bad.coeffs[coef_bad[2], 5, 1] = -inf
+    bad.coeffs[coef_bad[3], 1, 0] = nan
+    bad.coeffs[coef_bad[4], 2, 2] = inf
+    keep = np.setdiff1d(np.arange(n), pick)
+    clean = scenegen.Scene(base.means4[keep], base.log_scales4[keep], base.q_left[keep], base.q_right[keep],
+                           base.opacity_logit[keep], base.coeffs[keep], base.sh_degree, base.t_order, base.t_period)
+    rb, _ = PT.gpu_setup(bad)
+    rc, _ = PT.gpu_setup(clean)
+    out_b = [x.clone() for x in rb.render(cams, times)]
+    st = rb.stats()
+    out_c = [x.clone() for x in rc.render(cams, times)]
+    for a, b in zip(out_b, out_c):
+        assert torch.equal(a, b)
+    want = len(geo_bad) * len(cams) + int(pairs[coef_bad].sum())
+    _say(f"  culled_nonfinite {st['culled_nonfinite']} (expected {want})")
+    assert st["culled_nonfinite"] == want
+    assert rc.stats()["culled_nonfinite"] == 0
+    dl = torch.from_numpy(np.random.default_rng(8).uniform(-1, 1, out_b[0].numel()).astype(np.float32)).cuda()
+    gb = [_np(x).astype(np.float64) for x in rb.backward(dl)]
+    gc = [_np(x).astype(np.float64) for x in rc.backward(dl)]
+    for name, a, b in zip(PT.GROUPS, gb, gc):
+        assert np.isfinite(a).all(), name
+        assert (a[pick] == 0).all(), name
+        nb = np.linalg.norm(b)
+        assert np.linalg.norm(a[keep] - b) <= 1e-5 * nb, name

@@ -291,6 +291,170 @@ def test_centred_isotropic_gaussian_projects_to_circle():
     assert abs(float(pre["z"][0]) - 4.0) < 1e-12
 
 
+def _rot4_hamilton(ql, qr):
+    """4x4 rotation v -> ql (x) v (x) qr built column by column from the
+    scalar/vector quaternion product (independent of the oracle's matrices)."""
+    qln = ql / ql.norm(dim=-1, keepdim=True)
+    qrn = qr / qr.norm(dim=-1, keepdim=True)
+    cols = []
+    for j in range(4):
+        e = torch.zeros(qln.shape[0], 4, dtype=F64)
+        e[:, j] = 1.0
+        cols.append(hamilton(hamilton(qln, e), qrn))
+    return torch.stack(cols, -1)
+
+
+def _sliced_cov_independent(sc, t):
+    """Conditional mean and covariance of (x, y, z) at t, by an independent
+    route: Sigma from the Hamilton-product rotation, the conditional
+    covariance as the inverse of the precision's xyz block, the conditional
+    mean by solving the precision's xyz block against its t column."""
+    ls = torch.as_tensor(sc.log_scales4.astype(np.float64))
+    R = _rot4_hamilton(torch.as_tensor(sc.q_left.astype(np.float64)), torch.as_tensor(sc.q_right.astype(np.float64)))
+    prec = R @ torch.diag_embed(torch.exp(-2 * ls)) @ R.transpose(-1, -2)
+    cov_c = torch.linalg.inv(prec[:, :3, :3])
+    mu = torch.as_tensor(sc.means4.astype(np.float64))
+    # the conditional mean minimises the quadratic form over xyz at fixed t
+    mu_c = mu[:, :3] - (cov_c @ prec[:, :3, 3:4])[..., 0] * (t - mu[:, 3])[:, None]
+    return mu_c, cov_c
+
+
+def _pinhole(cam, p_world):
+    pc = p_world @ cam.rot.T + cam.trans
+    return torch.stack([cam.fx * pc[..., 0] / pc[..., 2] + cam.cx, cam.fy * pc[..., 1] / pc[..., 2] + cam.cy], -1)
+
+
+def _fd_jacobian(fn, p, h=1e-5):
+    """Central-difference Jacobian [N, 2, 3] of fn: [N, 3] -> [N, 2]."""
+    cols = []
+    for k in range(3):
+        d = torch.zeros_like(p)
+        d[:, k] = h
+        cols.append((fn(p + d) - fn(p - d)) / (2 * h))
+    return torch.stack(cols, -1)
+
+
+def _offaxis_scene(seed, n, spread, aniso=1.0):
+    sc = scenegen.random_scene(seed, n, sh_degree=1, t_order=1, mu_log_t=-0.5, spread=spread)
+    rng = np.random.default_rng(seed + 100)
+    sc.log_scales4[:, :3] = (rng.normal(-2.5, aniso, size=(n, 3))).astype(np.float32)
+    return sc
+
+
+def test_offaxis_ewa_is_pinhole_jacobian_sandwich():
+    """Eqs. (3)-(4) off the axis: for rotated anisotropic primitives at time t
+    away from their temporal mean, Sigma_2d - 0.3 I = J (Sigma_c) J^T with J the
+    central-difference Jacobian of the world-to-pixel pinhole map at the
+    conditional mean (which holds W Sigma W^T, the -f x / z^2 column and
+    its sign), and (u, v) is the pinhole image of the conditional mean. Only
+    primitives inside the 1.3x Jacobian limit are checked here."""
+    sc = _offaxis_scene(21, 200, 1.6)
+    cam = O.to_ocamera(scenegen.look_at_camera((1.3, -0.8, 3.6), 160, 120))
+    t = 0.37
+    pre = O.preprocess(O.params_from_scene(sc), cam, t, 1, 1)
+    mu_c, cov_c = _sliced_cov_independent(sc, t)
+    pc = mu_c @ cam.rot.T + cam.trans
+    lim_x, lim_y = 1.3 * 80.0 / cam.fx, 1.3 * 60.0 / cam.fy
+    ok = (pc[:, 2] > 0.5) & ((pc[:, 0] / pc[:, 2]).abs() < 0.98 * lim_x) & ((pc[:, 1] / pc[:, 2]).abs() < 0.98 * lim_y)
+    assert int(ok.sum()) > 100
+    off = ((pc[:, 0] / pc[:, 2]).abs() > 0.3 * lim_x) & ok
+    assert int(off.sum()) > 20                       # genuinely off-axis
+    J = _fd_jacobian(lambda p: _pinhole(cam, p), mu_c)
+    ref = J @ cov_c @ J.transpose(-1, -2)
+    cov2 = pre["cov2"]
+    got = torch.stack([torch.stack([cov2[:, 0] - 0.3, cov2[:, 1]], -1), torch.stack([cov2[:, 1], cov2[:, 2] - 0.3], -1)], -2)
+    scale = ref.abs().amax((-1, -2), keepdim=True)
+    assert torch.allclose(got[ok] / scale[ok], ref[ok] / scale[ok], atol=1e-8, rtol=0)
+    uv = _pinhole(cam, mu_c)
+    assert torch.allclose(torch.stack([pre["u"], pre["v"]], -1)[ok], uv[ok], atol=1e-9, rtol=0)
+    # a dropped depth column or a transposed camera rotation (W^T Sigma W)
+    # would fail the sandwich on these primitives: check that both differ
+    bad = J.clone()
+    bad[..., 2] = 0.0
+    dropped = bad @ cov_c @ bad.transpose(-1, -2)
+    assert not torch.allclose(got[off] / scale[off], dropped[off] / scale[off], atol=1e-3, rtol=0)
+    Wc = torch.as_tensor(cam.rot)
+    J_cam = _fd_jacobian(lambda q: torch.stack([cam.fx * q[:, 0] / q[:, 2] + cam.cx,
+                                                 cam.fy * q[:, 1] / q[:, 2] + cam.cy], -1), pc)
+    transposed = J_cam @ Wc.T @ cov_c @ Wc @ J_cam.transpose(-1, -2)
+    assert not torch.allclose(got[off] / scale[off], transposed[off] / scale[off], atol=1e-3, rtol=0)
+
+
+def test_ewa_jacobian_clamp_beyond_the_limit():
+    """Beyond 1.3x the half field of view the Jacobian is the pinhole
+    Jacobian at the camera-space point moved onto the limit, x/z -> xi =
+    clamp(x/z), y/z -> eta = clamp(y/z), at the same depth:
+    Sigma_2d - 0.3 I = J(xi z, eta z, z) W Sigma_c W^T J(...)^T."""
+    sc = _offaxis_scene(22, 400, 3.0)
+    cam = O.to_ocamera(scenegen.look_at_camera((0.2, 0.1, 3.0), 96, 64))
+    t = 0.61
+    pre = O.preprocess(O.params_from_scene(sc), cam, t, 1, 1)
+    mu_c, cov_c = _sliced_cov_independent(sc, t)
+    pc = mu_c @ cam.rot.T + cam.trans
+    lim_x, lim_y = 1.3 * 48.0 / cam.fx, 1.3 * 32.0 / cam.fy
+    z = pc[:, 2]
+    xr, yr = pc[:, 0] / z, pc[:, 1] / z
+    front = z > 0.5
+    clx = front & (xr.abs() > 1.02 * lim_x)
+    cly = front & (yr.abs() > 1.02 * lim_y)
+    assert int(clx.sum()) > 20 and int(cly.sum()) > 20 and int((clx & cly).sum()) > 5
+    q = torch.stack([xr.clamp(-lim_x, lim_x) * z, yr.clamp(-lim_y, lim_y) * z, z], -1)
+    J = _fd_jacobian(lambda p: torch.stack([cam.fx * p[:, 0] / p[:, 2] + cam.cx, cam.fy * p[:, 1] / p[:, 2] + cam.cy], -1), q)
+    Wc = torch.as_tensor(cam.rot)
+    ref = J @ (Wc @ cov_c @ Wc.T) @ J.transpose(-1, -2)
+    cov2 = pre["cov2"]
+    got = torch.stack([torch.stack([cov2[:, 0] - 0.3, cov2[:, 1]], -1), torch.stack([cov2[:, 1], cov2[:, 2] - 0.3], -1)], -2)
+    sel = clx | cly
+    scale = ref.abs().amax((-1, -2), keepdim=True)
+    assert torch.allclose(got[sel] / scale[sel], ref[sel] / scale[sel], atol=1e-8, rtol=0)
+    # unclamped, the sandwich would differ for these primitives
+    J_raw = _fd_jacobian(lambda p: torch.stack([cam.fx * p[:, 0] / p[:, 2] + cam.cx, cam.fy * p[:, 1] / p[:, 2] + cam.cy], -1), pc)
+    raw = J_raw @ (Wc @ cov_c @ Wc.T) @ J_raw.transpose(-1, -2)
+    assert not torch.allclose(got[sel] / scale[sel], raw[sel] / scale[sel], atol=1e-3, rtol=0)
+
+
+def _rotate_scene_and_camera(sc, cam, a):
+    """The scene and the camera turned together by the 3D rotation that the
+    unit quaternion a induces on (x, y, z) with t fixed: as a 4D rotation it
+    is v -> a (x) v (x) b with b = -k conj(a) k, so each primitive's pair
+    becomes (a (x) q_l, q_r (x) b), its mean Q mu, and the camera
+    W' = W Q^T, centre Q c."""
+    a = a / a.norm()
+    k = torch.tensor([0.0, 0.0, 0.0, 1.0], dtype=F64)
+    ac = a * torch.tensor([1.0, -1.0, -1.0, -1.0], dtype=F64)
+    b = -hamilton(hamilton(k[None], ac[None]), k[None])[0]
+    M = _rot4_hamilton(a[None], b[None])[0]
+    assert torch.allclose(M[3], torch.tensor([0.0, 0.0, 0.0, 1.0], dtype=F64), atol=1e-14)
+    Q = M[:3, :3]
+    n = sc.n
+    ql = hamilton(a[None].expand(n, 4), torch.as_tensor(sc.q_left.astype(np.float64)))
+    qr = hamilton(torch.as_tensor(sc.q_right.astype(np.float64)), b[None].expand(n, 4))
+    params = O.params_from_scene(sc)
+    params["q_left"], params["q_right"] = ql, qr
+    params["means4"] = torch.cat([params["means4"][:, :3] @ Q.T, params["means4"][:, 3:]], 1)
+    cam2 = dataclasses.replace(cam, rot=cam.rot @ Q.T, center=Q @ cam.center)
+    return params, cam2
+
+
+def test_projection_invariant_under_joint_rotation():
+    """Turning the scene and the camera together by one rotation changes
+    nothing the camera sees: u, v, z, Sigma_2d and the view direction
+    relative to the camera are unchanged (Eqs. 3-4 with the view transform
+    applied as W Sigma W^T; W^T Sigma W would not be invariant)."""
+    sc = _offaxis_scene(23, 300, 1.5)
+    cam = O.to_ocamera(scenegen.look_at_camera((1.0, 0.7, 3.4), 120, 90))
+    t = 0.45
+    pre = O.preprocess(O.params_from_scene(sc), cam, t, 1, 1)
+    for seed in range(3):
+        a = torch.as_tensor(np.random.default_rng(seed).normal(size=4))
+        params2, cam2 = _rotate_scene_and_camera(sc, cam, a)
+        pre2 = O.preprocess(params2, cam2, t, 1, 1)
+        keep = pre["z"] > 0.3
+        for key in ("u", "v", "z", "cov2", "conic", "pt"):
+            assert torch.allclose(pre2[key][keep], pre[key][keep], rtol=1e-9, atol=1e-9), key
+        assert torch.equal(pre2["active"], pre["active"])
+
+
 # --- Eqs. (5)-(6): compositing ----------------------------------------------------
 def sequential_pixel(px, py, gauss, bg):
     """Independent front-to-back loop for one pixel over a list of
@@ -467,7 +631,7 @@ def test_densify_count_matches_sequential_loop():
     times = [0.35, 0.6]
     rng = np.random.default_rng(24)
     dl = [rng.normal(size=(3, 32, 32)) for _ in cams]
-    _, _, cnt = O.densify_stats(sc, cams, times, dl)
+    _, _, cnt, _ = O.densify_stats(sc, cams, times, dl)
     ref = np.zeros(sc.means4.shape[0], np.int64)
     for cam, t in zip(cams, times):
         for i in _blend_sets_by_sequential_loop(sc, cam, t):
@@ -486,7 +650,7 @@ def test_densify_uv_gradient_is_principal_point_derivative():
     cam = scenegen.look_at_camera((0.0, 0.0, 3.0), 32, 32)
     t = 0.5
     dl = np.random.default_rng(26).normal(size=(3, 32, 32))
-    uv, _, cnt = O.densify_stats(sc, [cam], [t], [dl])
+    uv, _, cnt, _ = O.densify_stats(sc, [cam], [t], [dl])
     assert int(cnt[0]) == 1
 
     def loss(c):
@@ -508,7 +672,7 @@ def test_densify_t_gradient_sums_per_view_magnitudes():
     cam = scenegen.look_at_camera((0.0, 0.0, 3.0), 32, 32)
     times = [0.4, 0.62]
     ones = np.ones((3, 32, 32))
-    _, tg, cnt = O.densify_stats(sc, [cam, cam], times, [ones, ones])
+    _, tg, cnt, _ = O.densify_stats(sc, [cam, cam], times, [ones, ones])
     assert int(cnt[0]) == 2
     h = 1e-6
     fd = []
@@ -525,7 +689,7 @@ def test_densify_t_gradient_sums_per_view_magnitudes():
     assert abs(float(tg[0]) - ref) <= 1e-5 * (1 + ref)
 
 
-# --- Sec. 4.3: rendered optical flow -------------------------------------------------
+# --- Sec. 4.4: rendered optical flow -------------------------------------------------
 def _xt_rotation_scene(theta, sx=0.3, st=0.1):
     """One primitive at the origin rotated by theta in the (x, t) plane:
     q_l = q_r = (cos theta/2, 0, 0, sin theta/2) (x <-> 1, t <-> k)."""
@@ -580,3 +744,60 @@ def test_flow_of_xt_rotated_primitive_closed_form():
         assert abs(float(flow[1, 15, 15])) < 1e-12 and float(flow[2].abs().max()) == 0.0
         flows.append(float(flow[0, 15, 15]))
     assert flows[0] != 0.0 and abs(flows[0] + flows[1]) <= 1e-12   # opposite rotations, opposite ways
+
+
+# --- the parity margin policy ----------------------------------------------------
+def _dense_scene(seed, n, grow, spread, sh, to):
+    sc = scenegen.random_scene(seed, n, sh_degree=sh, t_order=to, spread=spread, mu_log_t=-1.5)
+    sc.log_scales4[:, :3] += np.float32(grow)
+    return sc
+
+
+@pytest.mark.parametrize("seed,n,grow,spread,eye,w,h,t", [
+    (6, 2500, 1.5, 0.5, (0.0, -0.3, 3.0), 48, 40, 0.6),
+    (5, 3000, 0.8, 1.0, (1.0, 0.5, 3.5), 100, 70, 0.37),
+])
+def test_flags_cover_every_decision_within_fp32_reach(seed, n, grow, spread, eye, w, h, t):
+    """The value flags are what the parity tests exclude, so they must hold
+    every pixel whose value an FP32 implementation may move beyond the image
+    tolerance by taking a decision the other way. Simulated here: the records
+    rounded to float32 (depth order by the float32 depth, ties by index, as
+    the GPU sorts), every fragment's alpha moved by a random amount within
+    the float32 evaluation reach the margins assume. No unflagged pixel may
+    change by more than the 1e-4 image tolerance. With the alphas moved 30x
+    beyond that reach some unflagged pixel does (the check has teeth)."""
+    sc = _dense_scene(seed, n, grow, spread, 3, 1)
+    cam = O.to_ocamera(scenegen.look_at_camera(eye, w, h))
+    params = O.params_from_scene(sc)
+    pre = O.preprocess(params, cam, t, sc.sh_degree, sc.t_order)
+    mg = O.Margins()
+    tiles = range(cam.tiles_x * cam.tiles_y)
+    base = {tid: O.composite_tile(pre, cam, tid, (0.0, 0.0, 0.0), mg) for tid in tiles}
+    n_flagged = sum(int(b["uncertain"].sum()) for b in base.values())
+    # the FP32 record: float32 u, v, conic, opacity and depth key
+    p32 = dict(pre)
+    p32["z"] = pre["z32"]
+    p32["color"] = pre["color"].detach().to(torch.float32).to(F64)
+
+    def worst(scale, trials, rng):
+        w_unf = 0.0
+        for _ in range(trials):
+            def gval32(ids, pxc, pyc):
+                _, gv32, eps = mg.alpha_fp32(pre, ids, pxc, pyc)
+                k = torch.as_tensor(rng.uniform(-1.0, 1.0, size=tuple(gv32.shape)))
+                return gv32 * (1.0 + scale * eps * k)
+            for tid in tiles:
+                a = base[tid]
+                b = O.composite_tile(p32, cam, tid, (0.0, 0.0, 0.0), with_flags=False, gval_fn=gval32)
+                d = torch.maximum((a["rgb"].detach() - b["rgb"].detach()).abs().amax(0),
+                                  torch.maximum((a["depth"].detach() - b["depth"].detach()).abs(),
+                                                (a["alpha"].detach() - b["alpha"].detach()).abs()))
+                unf = ~a["uncertain"]
+                if bool(unf.any()):
+                    w_unf = max(w_unf, float(d[unf].max()))
+        return w_unf
+
+    rng = np.random.default_rng(seed)
+    w1 = worst(1.0, 6, rng)
+    assert w1 <= O.IMG_TOL, (w1, n_flagged)
+    assert worst(30.0, 3, rng) > O.IMG_TOL
