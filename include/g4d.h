@@ -138,6 +138,24 @@ g4d_status g4d_set_primitives(g4d_ctx* ctx, int64_t n, const float* means4, cons
 g4d_status g4d_render(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
                       float* out_rgb, float* out_depth, float* out_alpha);
 
+/* g4d_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, outputs and kernels as g4d_render (images are identical), but it
+ * calls no hipMalloc, hipFree or other allocating routine: every scratch
+ * buffer of the render lives in one fixed array per GPU (about 164 MiB,
+ * allocated with the library's code when it is loaded on that GPU and held
+ * until the process ends). Limits: at most 2^19 primitives (one view's
+ * (view, primitive) pairs per round), 2^22 tile instances per round, 2^21
+ * pixels per call (e.g. one 1920x1080 view) and 2^16 16x16 tiles per view;
+ * beyond them the call returns G4D_ECAPACITY before enqueuing anything (the
+ * instance limit: when one view alone needs more). It keeps no state for
+ * render_backward (and invalidates a previous render's), and g4d_get_stats
+ * does not describe it. Every call on one GPU, from any context, shares that
+ * GPU's array: calls whose work overlaps on one GPU (other streams, other
+ * threads) race; serialise them. Stage timing is off during the call. */
+g4d_status g4d_render_noalloc(g4d_ctx* ctx, int32_t n_views, const g4d_camera* cams, const float* times,
+                              float* out_rgb, float* out_depth, float* out_alpha);
+
 /* Rendered optical flow (Sec. 4.4, "Ablation and analysis"): for each view, the alpha blend of Eq. (6)
  * (the render's weights, zero background) of every primitive's image-plane
  * displacement between t and t + frame_dt of its conditional mean

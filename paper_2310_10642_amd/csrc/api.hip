@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,8 @@ struct g4d_ctx {
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
   bool flow_mode = false;          // the render in progress blends flow (Sec. 4.4), not colour
   float flow_dt = 0.f;
+  bool no_alloc = false;           // a render_noalloc is in progress: scratch never grows
+  void* fixed_scratch = nullptr;   // this device's no-allocation scratch (see g4d_render_noalloc)
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
@@ -106,6 +109,72 @@ constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the 
 // bits, and the instance sort by tile takes two 8-bit passes.
 constexpr int64_t kRoundTiles = int64_t(1) << 16;
 
+// ---- the no-allocation render's scratch ----
+// Limits of g4d_render_noalloc: (view, primitive) pairs per round (and
+// primitives), tile instances per round, pixels per call, 16x16 tiles per
+// round, radix-sort workgroups.
+constexpr size_t kNAPairs = size_t(1) << 19;
+constexpr size_t kNAInstances = size_t(1) << 22;
+constexpr size_t kNAPixels = size_t(1) << 21;
+constexpr size_t kNATiles = size_t(1) << 16;
+constexpr int kNASortBlocks = 2048;
+
+size_t na_align(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of each scratch buffer of a render at the limits, in carving order
+// (the order of g4d_ctx::render_bufs).
+void na_sizes(size_t* out) {
+  const size_t P = kNAPairs, I = kNAInstances, X = kNAPixels, T = kNATiles;
+  const size_t sizes[] = {
+      sizeof(ViewDev) * kMaxViews,                                    // views_d
+      4 * P, 4 * P, 4 * P, 4 * P, 4 * P, 4 * P, 4 * P, 4 * P,         // act pos dkey slot ckey cval ckey2 cval2
+      4 * P, 4 * P,                                                   // tcount toff
+      sizeof(Record) * P, sizeof(Record) * P, sizeof(float4) * P,     // rec rec_sorted cdir
+      4 * scan_scratch_words(P), 4 * radix_scratch_words(kNASortBlocks),
+      4 * I, 4 * I, 4 * I, 4 * I,                                     // ikey ival ikey2 ival2
+      8 * T, 4 * T, 4 * T, 4 * T, 4 * T,                              // ranges okey oval okey2 oval2
+      4 * X, 4 * X,                                                   // pix_t pix_last
+      sizeof(uint32_t) * kCntWords};                                  // counters
+  for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) out[i] = sizes[i];
+}
+constexpr int kNABufs = 28;
+
+constexpr size_t na_total_bytes() {
+  // an upper bound of the carved total (each buffer 256-byte aligned)
+  return (size_t(120) * kMaxViews + 256) + 12 * (4 * kNAPairs + 256) + 2 * (48 * kNAPairs + 256) +
+         (16 * kNAPairs + 256) + (4 * (kNAPairs / 4096 + 2) + 256) + (4 * (256 * kNASortBlocks + 256) + 256) +
+         4 * (4 * kNAInstances + 256) + (8 * kNATiles + 256) + 4 * (4 * kNATiles + 256) + 2 * (4 * kNAPixels + 256) +
+         (4 * kCntWords + 256);
+}
+
+}  // namespace
+
+// The no-allocation render's scratch: one array per GPU, held until the
+// process ends. Host code reaches it only through the address that
+// hipGetSymbolAddress gives per device (g4d_create), never through its name.
+static __device__ __align__(256) unsigned char scratch[na_total_bytes()];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// This device's address of `scratch` (the device is current); null on failure.
+void* device_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_dev[device] = ptr;
+  }
+  return g_scratch_dev[device];
+}
+
 g4d_status fail(g4d_ctx* c, g4d_status s, const std::string& msg) {
   if (c) c->err = msg;
   return s;
@@ -138,6 +207,9 @@ bool capturing(g4d_ctx* c) {
 g4d_status ensure(g4d_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return G4D_OK;
+  if (c->no_alloc)
+    return fail(c, G4D_ECAPACITY, "the render needs " + std::to_string(bytes) + " bytes of a scratch buffer that "
+                                  "holds " + std::to_string(b.cap) + " in the no-allocation render");
   if (capturing(c))
     return fail(c, G4D_ECAPACITY, "a scratch buffer would grow during stream capture; make the same call "
                                   "uncaptured first");
@@ -446,6 +518,15 @@ g4d_status resolve_round(g4d_ctx* c, g4d_ctx::Round& r) {
   return G4D_OK;
 }
 
+// The render's scratch buffers in the carving order of na_sizes.
+void render_bufs(g4d_ctx* c, DevBuf** b) {
+  DevBuf* l[kNABufs] = {&c->views_d, &c->act,  &c->pos,   &c->dkey,  &c->slot,   &c->ckey,         &c->cval,
+                        &c->ckey2,   &c->cval2, &c->tcount, &c->toff, &c->rec,    &c->rec_sorted,   &c->cdir,
+                        &c->scan_scratch, &c->radix_scratch, &c->ikey, &c->ival, &c->ikey2, &c->ival2, &c->ranges,
+                        &c->okey,    &c->oval,  &c->okey2, &c->oval2, &c->pix_t,  &c->pix_last,     &c->counters};
+  for (int i = 0; i < kNABufs; ++i) b[i] = l[i];
+}
+
 // Times the render of this batch under every combination of the knobs that
 // do not change results (radix-sort workgroups, tile order) and keeps the
 // fastest. Each candidate renders once to size its scratch, then twice timed.
@@ -527,6 +608,16 @@ g4d_status g4d_create(const g4d_options* opts, void* hip_stream, g4d_ctx** out) 
                     hipHostMallocDefault) != hipSuccess) {
     delete c;
     return G4D_ENOMEM;
+  }
+  // this device's copy of the no-allocation scratch (looked up once per device)
+  c->fixed_scratch = device_scratch(c->device);
+  if (!c->fixed_scratch) {
+    (void)hipHostFree(c->counters_h);
+    (void)hipEventDestroy(c->ev_fork);
+    (void)hipEventDestroy(c->ev_join);
+    (void)hipStreamDestroy(c->side);
+    delete c;
+    return G4D_EHIP;
   }
   *out = c;
   return G4D_OK;
@@ -620,6 +711,71 @@ g4d_status g4d_render_flow(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, 
   const g4d_status st = render_impl(c, n_views, cams, times, out_flow, nullptr, nullptr);
   c->flow_mode = false;
   c->have_render = false;  // the kept records hold flow, not colour: no backward
+  return st;
+}
+
+g4d_status g4d_render_noalloc(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times,
+                              float* out_rgb, float* out_depth, float* out_alpha) {
+  if (!c) return G4D_EINVAL;
+  if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
+  if (c->n < 0) return fail(c, G4D_ESTATE, "set_primitives was not called");
+  if (n_views < 1 || n_views > kMaxViews) return fail(c, G4D_EINVAL, "n_views must be in [1, 4096]");
+  if (!cams || !times || !out_rgb) return fail(c, G4D_EINVAL, "null cams/times/out_rgb");
+  if ((size_t)c->n > kNAPairs)
+    return fail(c, G4D_ECAPACITY, "the no-allocation render takes at most " + std::to_string(kNAPairs) + " primitives");
+  size_t pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const g4d_camera& cm = cams[v];
+    if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
+      return fail(c, G4D_EINVAL, "camera size out of [1, 16384]");
+    const size_t tiles = (size_t)((cm.width + kTile - 1) / kTile) * ((cm.height + kTile - 1) / kTile);
+    if (tiles > kNATiles)
+      return fail(c, G4D_ECAPACITY, "the no-allocation render takes at most " + std::to_string(kNATiles) +
+                                        " 16x16 tiles per view");
+    pix += (size_t)cm.width * cm.height;
+  }
+  if (pix > kNAPixels)
+    return fail(c, G4D_ECAPACITY, "the no-allocation render takes at most " + std::to_string(kNAPixels) +
+                                      " pixels per call");
+  size_t sz[kNABufs];
+  na_sizes(sz);
+  size_t total = 0;
+  for (int i = 0; i < kNABufs; ++i) total += na_align(sz[i]);
+  if (total > sizeof(scratch)) return fail(c, G4D_ECAPACITY, "no-allocation scratch layout exceeds its array");
+  // the render's buffers point into this device's scratch for the call
+  DevBuf* bufs[kNABufs];
+  DevBuf saved[kNABufs];
+  render_bufs(c, bufs);
+  char* base = static_cast<char*>(c->fixed_scratch);
+  size_t off = 0;
+  for (int i = 0; i < kNABufs; ++i) {
+    saved[i] = *bufs[i];
+    bufs[i]->ptr = base + off;
+    bufs[i]->cap = sz[i];
+    off += na_align(sz[i]);
+  }
+  const int64_t round_pairs = c->round_pairs, round_instances = c->round_instances;
+  const int sort_blocks = c->sort_blocks;
+  const bool timing = c->timing;
+  c->round_pairs = std::min<int64_t>(round_pairs, (int64_t)kNAPairs);
+  c->round_instances = std::min<int64_t>(round_instances, (int64_t)kNAInstances);
+  c->sort_blocks = std::min(sort_blocks, kNASortBlocks);
+  c->timing = false;  // stage timing would create events
+  c->no_alloc = true;
+  c->flow_mode = false;
+  // the array keeps the last call's contents: the counters start at zero
+  launch_fill_u32(P<uint32_t>(c->counters), kCntWords, 0u, c->stream);
+  g4d_status st = check_hip(c, hipGetLastError(), "launch");
+  if (!st) st = render_impl(c, n_views, cams, times, out_rgb, out_depth, out_alpha);
+  for (int i = 0; i < kNABufs; ++i) *bufs[i] = saved[i];
+  c->round_pairs = round_pairs;
+  c->round_instances = round_instances;
+  c->sort_blocks = sort_blocks;
+  c->timing = timing;
+  c->no_alloc = false;
+  // the render's state lives in the shared scratch: nothing is kept
+  c->have_render = false;
+  c->bound = -1;
   return st;
 }
 

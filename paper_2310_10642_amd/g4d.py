@@ -27,7 +27,7 @@ STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd",
 DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_last=7, grad2d=8)
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
-            "g4d_render", "g4d_render_flow", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
+            "g4d_render", "g4d_render_noalloc", "g4d_render_flow", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
             "g4d_get_tuning", "g4d_set_densify_stats", "g4d_adam_step", "g4d_split_sample", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
 
 
@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH):
     lib.g4d_set_stream.argtypes = [vp, vp]
     lib.g4d_set_primitives.argtypes = [vp, i64, fp, fp, fp, fp, fp, fp]
     lib.g4d_render.argtypes = [vp, i32, ctypes.POINTER(G4DCamera), ctypes.POINTER(ctypes.c_float), fp, fp, fp]
+    lib.g4d_render_noalloc.argtypes = [vp, i32, ctypes.POINTER(G4DCamera), ctypes.POINTER(ctypes.c_float), fp, fp,
+                                       fp]
     lib.g4d_render_flow.argtypes = [vp, i32, ctypes.POINTER(G4DCamera), ctypes.POINTER(ctypes.c_float), ctypes.c_float,
                                     fp]
     lib.g4d_render_backward.argtypes = [vp, fp, fp, fp, fp, fp, fp, fp, fp, fp, i32]
@@ -214,6 +216,25 @@ class Renderer:
             dep = torch.empty(npix, device=dev, dtype=torch.float32) if depth else None
             alp = torch.empty(npix, device=dev, dtype=torch.float32) if alpha else None
         self._check(self.lib.g4d_render(self.ctx, V, cams, tarr, _ptr(rgb), _ptr(dep), _ptr(alp)))
+        self.generation += 1
+        self._views = [(int(c.height), int(c.width)) for c in cameras]
+        return rgb, dep, alp
+
+    def render_noalloc(self, cameras: Sequence, times: Sequence[float], out: Sequence[Optional[torch.Tensor]]):
+        """g4d_render_noalloc into the caller's `out` = (rgb, depth or None,
+        alpha or None): the library allocates nothing (fixed per-GPU scratch,
+        limits in the header); no state is kept for backward."""
+        self._stream()
+        V = len(cameras)
+        cams = (G4DCamera * V)(*[to_camera(c) for c in cameras])
+        tarr = (ctypes.c_float * V)(*[float(t) for t in times])
+        npix = sum(int(c.width) * int(c.height) for c in cameras)
+        rgb, dep, alp = out
+        for t, k in ((rgb, 3), (dep, 1), (alp, 1)):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                                      and t.numel() == k * npix):
+                raise ValueError("render outputs must be contiguous float32 GPU tensors of the batch's size")
+        self._check(self.lib.g4d_render_noalloc(self.ctx, V, cams, tarr, _ptr(rgb), _ptr(dep), _ptr(alp)))
         self.generation += 1
         self._views = [(int(c.height), int(c.width)) for c in cameras]
         return rgb, dep, alp
