@@ -71,7 +71,7 @@ struct g4d_ctx {
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
-  DevBuf bwd_scratch, okey, oval, okey2, oval2, cdir;
+  DevBuf bwd_scratch, okey, oval, okey2, oval2, cdir, pany, plist;
   uint32_t* counters_h = nullptr;  // pinned
 
   // stage timing (HIP events on the context's stream)
@@ -103,7 +103,9 @@ constexpr int kMaxViews = 4096;
 constexpr int kCntTot = kCntViews + kMaxViews;
 // then per view: (view, primitive) pairs culled for a non-finite parameter
 constexpr int kCntNF = kCntTot + 4;
-constexpr int kCntWords = kCntNF + kMaxViews;
+// then the length of the round's list of primitives active in some view
+constexpr int kCntPList = kCntNF + kMaxViews;
+constexpr int kCntWords = kCntPList + 4;
 constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the device
 // Tiles per round (unless one view alone has more): tile ids then fit 16
 // bits, and the instance sort by tile takes two 8-bit passes.
@@ -130,6 +132,7 @@ void na_sizes(size_t* out) {
       4 * P, 4 * P, 4 * P, 4 * P, 4 * P, 4 * P, 4 * P, 4 * P,         // act pos dkey slot ckey cval ckey2 cval2
       4 * P, 4 * P,                                                   // tcount toff
       sizeof(Record) * P, sizeof(Record) * P, sizeof(float4) * P,     // rec rec_sorted cdir
+      P, 4 * P,                                                       // pany plist (primitives <= P)
       4 * scan_scratch_words(P), 4 * radix_scratch_words(kNASortBlocks),
       4 * I, 4 * I, 4 * I, 4 * I,                                     // ikey ival ikey2 ival2
       8 * T, 4 * T, 4 * T, 4 * T, 4 * T,                              // ranges okey oval okey2 oval2
@@ -137,12 +140,12 @@ void na_sizes(size_t* out) {
       sizeof(uint32_t) * kCntWords};                                  // counters
   for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) out[i] = sizes[i];
 }
-constexpr int kNABufs = 28;
+constexpr int kNABufs = 30;
 
 constexpr size_t na_total_bytes() {
   // an upper bound of the carved total (each buffer 256-byte aligned)
-  return (size_t(120) * kMaxViews + 256) + 12 * (4 * kNAPairs + 256) + 2 * (48 * kNAPairs + 256) +
-         (16 * kNAPairs + 256) + (4 * (kNAPairs / 4096 + 2) + 256) + (4 * (256 * kNASortBlocks + 256) + 256) +
+  return (sizeof(ViewDev) * kMaxViews + 256) + 12 * (4 * kNAPairs + 256) + 2 * (48 * kNAPairs + 256) +
+         (16 * kNAPairs + 256) + (5 * kNAPairs + 512) + (4 * (kNAPairs / 4096 + 2) + 256) + (4 * (256 * kNASortBlocks + 256) + 256) +
          4 * (4 * kNAInstances + 256) + (8 * kNATiles + 256) + 4 * (4 * kNATiles + 256) + 2 * (4 * kNAPixels + 256) +
          (4 * kCntWords + 256);
 }
@@ -304,6 +307,9 @@ RenderParams make_params(g4d_ctx* c, int n_views) {
   p.flow_dt = c->flow_dt;
   p.ellipse_cull = c->ellipse_cull ? 1 : 0;
   p.nonfinite = nullptr;
+  p.pany = P<uint8_t>(c->pany);
+  p.plist = P<uint32_t>(c->plist);
+  p.plist_n = c->counters.ptr ? P<uint32_t>(c->counters) + kCntPList : nullptr;
   return p;
 }
 
@@ -366,6 +372,8 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1, bool count) {
   if ((st = ensure(c, c->rec_sorted, sizeof(Record) * vn))) return st;
   if ((st = ensure(c, c->tcount, 4 * vn))) return st;
   if ((st = ensure(c, c->toff, 4 * vn))) return st;
+  if ((st = ensure(c, c->pany, (size_t)c->n))) return st;
+  if ((st = ensure(c, c->plist, 4 * (size_t)c->n))) return st;
   if ((st = ensure(c, c->scan_scratch, 4 * scan_scratch_words(vn)))) return st;
   if ((st = ensure(c, c->radix_scratch, 4 * radix_scratch_words(c->sort_blocks)))) return st;
   RenderParams p = make_params(c, nv);
@@ -374,6 +382,7 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1, bool count) {
 
   launch_set_views(vr.data(), nv, P<ViewDev>(c->views_d), s);
   launch_fill_u32(cnt, 4, 0u, s);
+  launch_fill_u32(cnt + kCntPList, 1, 0u, s);
   if (count) launch_fill_u32(cnt + kCntNF + v0, (uint64_t)nv, 0u, s);
   // 1. per (view, primitive): cull, slice, project (the colour follows the
   //    gather, on the second stream)
@@ -522,7 +531,7 @@ g4d_status resolve_round(g4d_ctx* c, g4d_ctx::Round& r) {
 void render_bufs(g4d_ctx* c, DevBuf** b) {
   DevBuf* l[kNABufs] = {&c->views_d, &c->act,  &c->pos,   &c->dkey,  &c->slot,   &c->ckey,         &c->cval,
                         &c->ckey2,   &c->cval2, &c->tcount, &c->toff, &c->rec,    &c->rec_sorted,   &c->cdir,
-                        &c->scan_scratch, &c->radix_scratch, &c->ikey, &c->ival, &c->ikey2, &c->ival2, &c->ranges,
+                        &c->pany,    &c->plist, &c->scan_scratch, &c->radix_scratch, &c->ikey, &c->ival, &c->ikey2, &c->ival2, &c->ranges,
                         &c->okey,    &c->oval,  &c->okey2, &c->oval2, &c->pix_t,  &c->pix_last,     &c->counters};
   for (int i = 0; i < kNABufs; ++i) b[i] = l[i];
 }
@@ -630,7 +639,8 @@ g4d_status g4d_destroy(g4d_ctx* c) {
   DevBuf* bufs[] = {&c->views_d, &c->act, &c->pos, &c->dkey, &c->rec, &c->slot, &c->ckey, &c->cval, &c->ckey2,
                     &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
                     &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
-                    &c->counters, &c->bwd_scratch, &c->okey, &c->oval, &c->okey2, &c->oval2, &c->cdir};
+                    &c->counters, &c->bwd_scratch, &c->okey, &c->oval, &c->okey2, &c->oval2, &c->cdir,
+                    &c->pany, &c->plist};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->counters_h) (void)hipHostFree(c->counters_h);
@@ -813,6 +823,8 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
     d.t = times[v];
     d.lim_x = kFrustumSlack * (0.5f * (float)cm.width) / cm.fx;
     d.lim_y = kFrustumSlack * (0.5f * (float)cm.height) / cm.fy;
+    d.lim_x64 = kFrustumSlack64 * (0.5 * cm.width) / (double)cm.fx;
+    d.lim_y64 = kFrustumSlack64 * (0.5 * cm.height) / (double)cm.fy;
     tiles += (int64_t)d.tiles_x * d.tiles_y;
     pix += (int64_t)cm.width * cm.height;
   }

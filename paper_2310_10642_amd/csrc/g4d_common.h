@@ -32,6 +32,7 @@ struct ViewDev {
   float center[3];      // camera position (world)
   float t;              // render time
   float lim_x, lim_y;   // Jacobian clamp limits on x/z, y/z
+  double lim_x64, lim_y64;  // the same limits in FP64: 1.3 (W/2) / fx, 1.3 (H/2) / fy
 };
 
 // Doubles per active record in the screen-space gradient buffer: one 128-byte
@@ -72,6 +73,12 @@ struct RenderParams {
   // per-view counters of (view, primitive) pairs culled for a non-finite
   // parameter, indexed by the view within the call (null: not counted)
   uint32_t* nonfinite;
+  // written by the preprocess: per primitive, 1 when it is active in some
+  // view of the call; the list of those primitives (in no particular order)
+  // and its length
+  uint8_t* pany;
+  uint32_t* plist;
+  uint32_t* plist_n;
 };
 
 // Per-primitive densification accumulators (all null: off).
@@ -91,6 +98,10 @@ void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdi
                    hipStream_t s);
 // ---- launchers (preprocess_bwd.hip) ----
 size_t preprocess_backward_scratch_floats(size_t n_records);
+// Lanes per primitive in k_preprocess for a call of n_views views.
+int preprocess_lanes(int n_views);
+// Workgroups of the kernels that walk the active-primitive list of n primitives.
+unsigned list_grid(int n);
 void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, const double* grad2d,
                                 const uint32_t* n_records_dev, uint32_t n_records_max, const uint32_t* ids,
                                 const Record* recs, float* scratch, float* g_means4, float* g_log_scales4,

@@ -24,21 +24,20 @@ __device__ __forceinline__ bool finite4(float4 a) {
   return isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w);
 }
 
-// Adds, per view, the lanes of the wave whose primitive is culled for a
-// non-finite parameter (one atomic per view and wave, only when some lane is).
-__device__ __forceinline__ void count_nonfinite(uint32_t* nf, int n_views, bool bad) {
-  const uint64_t m = __ballot(bad);
-  if (!nf || m == 0ull) return;
-  if ((threadIdx.x & 63) == 0)
-    for (int v = 0; v < n_views; ++v) atomicAdd(nf + v, (uint32_t)__popcll(m));
-}
-
-__global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __restrict__ act,
+// One thread per primitive, looping over the views of the call (the FP64
+// shape is built once); `lanes` adjacent threads may share a primitive's
+// views (1 here: the FP64 shape would be built once per lane). The lanes of a
+// primitive then agree whether it is active in some view; the first appends
+// it to the list that the colour passes walk.
+__global__ void __launch_bounds__(256) k_preprocess(RenderParams p, int lanes, uint32_t* __restrict__ act,
                                                     uint32_t* __restrict__ dkey, Record* __restrict__ rec,
                                                     int32_t* __restrict__ slot, float4* __restrict__ cdir) {
-  const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gidx = t / lanes, sub = t - gidx * lanes;
   const bool live = gidx < p.n;
   const int gi = live ? gidx : 0;
+  const int vpl = (p.n_views + lanes - 1) / lanes;
+  const int v0 = min(sub * vpl, p.n_views), v1 = min(v0 + vpl, p.n_views);
   const float4 mu = p.means4[gi];
   const float4 ls = p.log_scales4[gi];
   const float4 qlf = p.q_left[gi];
@@ -46,189 +45,210 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, uint32_t* __
   const float logit = p.opacity_logit[gi];
   // a primitive with a non-finite parameter is culled in every view (and counted)
   const bool bad = live && !(finite4(mu) && finite4(ls) && finite4(qlf) && finite4(qrf) && isfinite(logit));
-  count_nonfinite(p.nonfinite, p.n_views, bad);
-  if (!live) return;
+  bool any = false;
   if (bad) {
-    for (int vi = 0; vi < p.n_views; ++vi) {
+    for (int vi = v0; vi < v1; ++vi) {
       const size_t idx = (size_t)vi * p.n + gidx;
       act[idx] = 0u;
       slot[idx] = -1;
+      if (p.nonfinite) atomicAdd(p.nonfinite + vi, 1u);
     }
-    return;
-  }
-  Shape4T<double> sh;
-  build_shape<double>(qlf, qrf, ls, sh);
-  const double opa = 1.0 / (1.0 + exp(-(double)logit));
-  const double t_cull = p.t_cull, near = p.near_plane;
-
-  for (int vi = 0; vi < p.n_views; ++vi) {
-    const size_t idx = (size_t)vi * p.n + gidx;
-    const ViewDev& vw = p.views[vi];
-    // temporal marginal and filter, slice, camera, EWA projection
-    ViewGeomT<double> g;
-    bool ok = view_geometry<double>(mu, sh, vw, t_cull, near, g);
-    int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
-    if (ok) {
-      // ---- footprint: integer 3-sigma radius, half-open tile rectangle ----
-      const double mid = 0.5 * (g.a2 + g.c2);
-      const double lmax = mid + sqrt(fmax(mid * mid - g.det, 0.0));
-      const double rad = ceil(kSigmaExtent64 * sqrt(lmax));
-      const double tx = vw.tiles_x, ty = vw.tiles_y;
-      x0 = (int)fmin(fmax(floor((g.u - rad) / kTile), 0.0), tx);
-      x1 = (int)fmin(fmax(floor((g.u + rad) / kTile) + 1.0, 0.0), tx);
-      y0 = (int)fmin(fmax(floor((g.v - rad) / kTile), 0.0), ty);
-      y1 = (int)fmin(fmax(floor((g.v + rad) / kTile) + 1.0, 0.0), ty);
-      ok = g.det > 0.0 && isfinite(g.u) && isfinite(g.v);
-      if (p.ellipse_cull) {
-        // Binning footprint: only tiles that can hold a pixel with
-        // opacity * exp(power) >= 1/255, i.e. inside the ellipse
-        // 1/2 d^T conic d <= ln(255 opacity); its bounding box has
-        // half-widths sqrt(2 K Sigma2d_00), sqrt(2 K Sigma2d_11). Every other
-        // tile of the 3-sigma rectangle would skip this primitive at every
-        // pixel, so the blend is unchanged; the slack covers the FP32
-        // evaluation of the fragments.
-        const double K = log(255.0 * opa * g.pt);
-        ok = ok && K > -1e-4;
-        const double Kc = fmax(K, 0.0);
-        const double hx = sqrt(2.0 * Kc * g.a2) * 1.001 + 0.05;
-        const double hy = sqrt(2.0 * Kc * g.c2) * 1.001 + 0.05;
-        const double bx = tx + 1.0, by = ty + 1.0;
-        x0 = max(x0, (int)fmin(fmax(floor((g.u - hx) / kTile), -1.0), bx));
-        x1 = min(x1, (int)fmin(fmax(floor((g.u + hx) / kTile) + 1.0, -1.0), bx));
-        y0 = max(y0, (int)fmin(fmax(floor((g.v - hy) / kTile), -1.0), by));
-        y1 = min(y1, (int)fmin(fmax(floor((g.v + hy) / kTile) + 1.0, -1.0), by));
+  } else if (live) {
+    Shape4T<double> sh;
+    build_shape<double>(qlf, qrf, ls, sh);
+    const double opa = 1.0 / (1.0 + exp(-(double)logit));
+    const double t_cull = p.t_cull, near = p.near_plane;
+    for (int vi = v0; vi < v1; ++vi) {
+      const size_t idx = (size_t)vi * p.n + gidx;
+      const ViewDev& vw = p.views[vi];
+      // temporal marginal and filter, slice, camera, EWA projection
+      ViewGeomT<double> g;
+      bool ok = view_geometry<double>(mu, sh, vw, t_cull, near, g);
+      int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+      if (ok) {
+        // ---- footprint: integer 3-sigma radius, half-open tile rectangle ----
+        const double mid = 0.5 * (g.a2 + g.c2);
+        const double lmax = mid + sqrt(fmax(mid * mid - g.det, 0.0));
+        const double rad = ceil(kSigmaExtent64 * sqrt(lmax));
+        const double tx = vw.tiles_x, ty = vw.tiles_y;
+        const double ft = 1.0 / kTile;  // a power of two: the product is exact
+        x0 = (int)fmin(fmax(floor((g.u - rad) * ft), 0.0), tx);
+        x1 = (int)fmin(fmax(floor((g.u + rad) * ft) + 1.0, 0.0), tx);
+        y0 = (int)fmin(fmax(floor((g.v - rad) * ft), 0.0), ty);
+        y1 = (int)fmin(fmax(floor((g.v + rad) * ft) + 1.0, 0.0), ty);
+        ok = g.det > 0.0 && isfinite(g.u) && isfinite(g.v);
+        if (p.ellipse_cull) {
+          // Binning footprint: only tiles that can hold a pixel with
+          // opacity * exp(power) >= 1/255, i.e. inside the ellipse
+          // 1/2 d^T conic d <= ln(255 opacity); its bounding box has
+          // half-widths sqrt(2 K Sigma2d_00), sqrt(2 K Sigma2d_11). Every other
+          // tile of the 3-sigma rectangle would skip this primitive at every
+          // pixel, so the blend is unchanged. The box only narrows the exact
+          // rectangle, so it is formed in FP32 with slack for that and for the
+          // FP32 evaluation of the fragments.
+          const float K = __logf(255.f * (float)(opa * g.pt));
+          ok = ok && K > -1e-4f;
+          const float Kc = fmaxf(K, 0.f);
+          const float hx = sqrtf(2.f * Kc * (float)g.a2) * 1.001f + 0.05f;
+          const float hy = sqrtf(2.f * Kc * (float)g.c2) * 1.001f + 0.05f;
+          const float uf = (float)g.u, vf = (float)g.v, ft = 1.f / kTile;
+          const float bx = (float)vw.tiles_x + 1.f, by = (float)vw.tiles_y + 1.f;
+          x0 = max(x0, (int)fminf(fmaxf(floorf((uf - hx) * ft), -1.f), bx));
+          x1 = min(x1, (int)fminf(fmaxf(floorf((uf + hx) * ft) + 1.f, -1.f), bx));
+          y0 = max(y0, (int)fminf(fmaxf(floorf((vf - hy) * ft), -1.f), by));
+          y1 = min(y1, (int)fminf(fmaxf(floorf((vf + hy) * ft) + 1.f, -1.f), by));
+        }
+        ok = ok && (x1 > x0) && (y1 > y0);
       }
-      ok = ok && (x1 > x0) && (y1 > y0);
-    }
-    if (!ok) {
-      act[idx] = 0u;
-      slot[idx] = -1;
-      continue;
-    }
-    const double z = g.pc[2];
-    const double u = g.u, v = g.v;
-    const float zf = (float)z;
-    Record r;
-    r.a = make_float4((float)u, (float)v, zf, (float)(opa * g.pt));
-    r.b = make_float4((float)g.conic[0], (float)g.conic[1], (float)g.conic[2],
-                      __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)));
-    const float yr = __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16));
-    if (p.flow) {
-      // Sec. 4.4: the conditional mean moves by v dt' / Sigma_44 (it is
-      // linear in t); its projection moves by f (x' z - x z') / (z z') per axis
-      const double sc = (double)p.flow_dt / g.s44;
-      double dp[3];
+      if (!ok) {
+        act[idx] = 0u;
+        slot[idx] = -1;
+        continue;
+      }
+      any = true;
+      const double z = g.pc[2];
+      const float zf = (float)z;
+      Record r;
+      r.a = make_float4((float)g.u, (float)g.v, zf, (float)(opa * g.pt));
+      r.b = make_float4((float)g.conic[0], (float)g.conic[1], (float)g.conic[2],
+                        __uint_as_float((uint32_t)x0 | ((uint32_t)x1 << 16)));
+      const float yr = __uint_as_float((uint32_t)y0 | ((uint32_t)y1 << 16));
+      if (p.flow) {
+        // Sec. 4.4: the conditional mean moves by v dt' / Sigma_44 (it is
+        // linear in t); its projection moves by f (x' z - x z') / (z z') per axis
+        const double sc = (double)p.flow_dt * sh.inv44;
+        double dp[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        dp[i] = sc * ((double)vw.rot[3 * i] * g.v3[0] + (double)vw.rot[3 * i + 1] * g.v3[1] +
-                      (double)vw.rot[3 * i + 2] * g.v3[2]);
-      const double z1 = z + dp[2];
-      const bool front = z1 > near;
-      const double q = front ? 1.0 / (z * z1) : 0.0;
-      r.c = make_float4((float)(vw.fx * (dp[0] * z - g.pc[0] * dp[2]) * q),
-                        (float)(vw.fy * (dp[1] * z - g.pc[1] * dp[2]) * q), 0.f, yr);
-    } else {
-      // colour: k_colour fills c.xyz of the record's depth-ordered copy from
-      // the view direction and t - mu_t
-      r.c = make_float4(0.f, 0.f, 0.f, yr);
-      cdir[idx] = make_float4((float)g.dir[0], (float)g.dir[1], (float)g.dir[2], (float)g.dt);
+        for (int i = 0; i < 3; ++i)
+          dp[i] = sc * ((double)vw.rot[3 * i] * g.v3[0] + (double)vw.rot[3 * i + 1] * g.v3[1] +
+                        (double)vw.rot[3 * i + 2] * g.v3[2]);
+        const double z1 = z + dp[2];
+        const bool front = z1 > near;
+        const double q = front ? 1.0 / (z * z1) : 0.0;
+        r.c = make_float4((float)(vw.fx * (dp[0] * z - g.pc[0] * dp[2]) * q),
+                          (float)(vw.fy * (dp[1] * z - g.pc[1] * dp[2]) * q), 0.f, yr);
+      } else {
+        // colour: k_colour fills c.xyz of the record's depth-ordered copy from
+        // the view direction and t - mu_t
+        r.c = make_float4(0.f, 0.f, 0.f, yr);
+        cdir[idx] = make_float4((float)g.dir[0], (float)g.dir[1], (float)g.dir[2], (float)g.dt);
+      }
+      rec[idx] = r;
+      act[idx] = 1u;
+      dkey[idx] = __float_as_uint(zf);  // z > near > 0: bit order = numeric order
+      slot[idx] = -1;
     }
-    rec[idx] = r;
-    act[idx] = 1u;
-    dkey[idx] = __float_as_uint(zf);  // z > near > 0: bit order = numeric order
-    slot[idx] = -1;
+  }
+  // the primitive's lanes agree on "active in some view"; the first records
+  // it and appends it to the list (one atomic per wave)
+  const int lane = threadIdx.x & 63;
+  const int lead = lane - sub;  // lanes of a primitive never straddle a wave (lanes divides 64)
+  const uint64_t m = __ballot(any);
+  const bool gany = ((m >> lead) & ((lanes >= 64 ? ~0ull : (1ull << lanes) - 1ull))) != 0ull;
+  const bool append = live && sub == 0 && gany;
+  if (live && sub == 0) p.pany[gidx] = gany ? 1 : 0;
+  const uint64_t am = __ballot(append);
+  if (am) {
+    uint32_t base = 0;
+    if (lane == __ffsll((long long)am) - 1) base = atomicAdd(p.plist_n, (uint32_t)__popcll(am));
+    base = __shfl(base, __ffsll((long long)am) - 1, 64);
+    const uint64_t below = lane ? (am & (~0ull >> (64 - lane))) : 0ull;
+    if (append) p.plist[base + (uint32_t)__popcll(below)] = (uint32_t)gidx;
   }
 }
 
 constexpr int kColourViews = 8;  // views whose loads k_colour issues together
 
-// 4D spherindrical-harmonic colour (Sec. 3.2): a quad of lanes per primitive,
-// lane `sub` owning the basis functions lm = 4 sub + i. The block's 64
-// primitives' coefficients are contiguous in memory; those of primitives
-// active in some view are staged through LDS with 16-byte loads, and each
-// lane takes its [n][4 sub + i][3] from there. Per active view every lane
-// evaluates the basis, weights its four functions by the Fourier terms, and a
-// quad sum gives c = max(0, 0.5 + sum). A primitive with a non-finite
-// coefficient gets a NaN colour, which the rasterisers read as fully
-// transparent (and the pair is counted as culled).
+// 4D spherindrical-harmonic colour (Sec. 3.2) of the primitives active in
+// some view (the list the preprocess built), 64 per block step: a quad of
+// lanes per primitive, lane `sub` owning the basis functions lm = 4 sub + i.
+// The 64 primitives' coefficients (576 contiguous bytes each at SH degree 3 x
+// Fourier order 2) are staged through LDS with 16-byte loads, and each lane
+// takes its [n][4 sub + i][3] from there. Per active view every lane evaluates
+// the basis, weights its four functions by the Fourier terms, and a quad sum
+// gives c = max(0, 0.5 + sum). A primitive with a non-finite coefficient gets
+// a NaN colour, which the rasterisers read as fully transparent (and the pair
+// is counted as culled).
 __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                 const float4* __restrict__ cdir, Record* __restrict__ rec_sorted) {
   __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
-  __shared__ uint8_t s_any[kColourPrims];
+  __shared__ uint32_t s_id[kColourPrims];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
-  const int g0 = blockIdx.x * kColourPrims;
-  const int nprim = min(kColourPrims, p.n - g0);
-  const int gidx = g0 + (int)(threadIdx.x >> 2);
+  const uint32_t count = *p.plist_n;
   const int sub = threadIdx.x & 3;
-  const bool live = gidx < p.n;  // uniform per quad
-  const bool any = live && any_view_active(p, slot, gidx);
-  if (sub == 0) s_any[threadIdx.x >> 2] = any ? 1 : 0;
-  __syncthreads();
-  copy_in_active(s_k, p.coeffs + (size_t)g0 * K3, nprim, K3, s_any);
-  __syncthreads();
-  if (!any) return;  // uniform per quad
-  const float* kc = s_k + (threadIdx.x >> 2) * K3;
-  float k[3][kBasisPerLane][3];
-  bool finite = true;
+  for (uint32_t c0 = blockIdx.x * kColourPrims; c0 < count; c0 += gridDim.x * kColourPrims) {
+    const int nprim = (int)min((uint32_t)kColourPrims, count - c0);
+    __syncthreads();  // the previous step's reads of s_k and s_id are done
+    if (threadIdx.x < kColourPrims) s_id[threadIdx.x] = (int)threadIdx.x < nprim ? p.plist[c0 + threadIdx.x] : 0u;
+    __syncthreads();
+    copy_in_list(s_k, p.coeffs, s_id, nprim, K3);
+    __syncthreads();
+    const int j = (int)(threadIdx.x >> 2);
+    if (j >= nprim) continue;  // uniform per quad
+    const int gidx = (int)s_id[j];
+    const float* kc = s_k + j * K3;
+    float k[3][kBasisPerLane][3];
+    bool finite = true;
 #pragma unroll
-  for (int n = 0; n < 3; ++n)
+    for (int n = 0; n < 3; ++n)
 #pragma unroll
-    for (int i = 0; i < kBasisPerLane; ++i) {
-      const int lm = sub * kBasisPerLane + i;
+      for (int i = 0; i < kBasisPerLane; ++i) {
+        const int lm = sub * kBasisPerLane + i;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        k[n][i][c] = (lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
-        finite = finite && isfinite(k[n][i][c]);
-      }
-    }
-  const bool bad = quad_any(!finite);
-  // views eight at a time: all flags, then the directions of the active
-  // ones, are loaded before any is used, so the loads overlap
-  for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
-    int on[kColourViews];
-    float4 cds[kColourViews];
-#pragma unroll
-    for (int w = 0; w < kColourViews; ++w) on[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
-#pragma unroll
-    for (int w = 0; w < kColourViews; ++w)
-      cds[w] = on[w] >= 0 ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
-#pragma unroll
-    for (int w = 0; w < kColourViews; ++w) {
-      if (on[w] < 0) continue;  // uniform per quad
-      float* o = reinterpret_cast<float*>(&rec_sorted[on[w]].c);
-      if (bad) {
-        if (sub == 0) {
-          const float nan = __int_as_float(0x7FC00000);
-          o[0] = nan;
-          o[1] = nan;
-          o[2] = nan;
-          if (p.nonfinite) atomicAdd(p.nonfinite + v0 + w, 1u);
+        for (int c = 0; c < 3; ++c) {
+          k[n][i][c] = (lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+          finite = finite && isfinite(k[n][i][c]);
         }
-        continue;
       }
-      const float4 cd = cds[w];
-      float Y[16], cs[3] = {0.f, 0.f, 0.f};
+    const bool bad = quad_any(!finite);
+    // views eight at a time: all flags, then the directions of the active
+    // ones, are loaded before any is used, so the loads overlap
+    for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
+      int on[kColourViews];
+      float4 cds[kColourViews];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) Y[j] = 0.f;
-      sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
-      fourier_terms(p.t_order, cd.w, p.t_period, cs);
-      float y[kBasisPerLane];
-      own_basis(Y, sub, y);
-      float col[3];
+      for (int w = 0; w < kColourViews; ++w) on[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float acc = 0.f;
+      for (int w = 0; w < kColourViews; ++w)
+        cds[w] = on[w] >= 0 ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < kBasisPerLane; ++i)
-          acc = fmaf(y[i], fmaf(cs[0], k[0][i][c], fmaf(cs[1], k[1][i][c], cs[2] * k[2][i][c])), acc);
-        col[c] = quad_sum(acc);
-      }
-      if (sub == 0) {
-        o[0] = fmaxf(col[0] + kColorOffset, 0.f);
-        o[1] = fmaxf(col[1] + kColorOffset, 0.f);
-        o[2] = fmaxf(col[2] + kColorOffset, 0.f);
+      for (int w = 0; w < kColourViews; ++w) {
+        if (on[w] < 0) continue;  // uniform per quad
+        float* o = reinterpret_cast<float*>(&rec_sorted[on[w]].c);
+        if (bad) {
+          if (sub == 0) {
+            const float nan = __int_as_float(0x7FC00000);
+            o[0] = nan;
+            o[1] = nan;
+            o[2] = nan;
+            if (p.nonfinite) atomicAdd(p.nonfinite + v0 + w, 1u);
+          }
+          continue;
+        }
+        const float4 cd = cds[w];
+        float Y[16], cs[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) Y[jj] = 0.f;
+        sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
+        fourier_terms(p.t_order, cd.w, p.t_period, cs);
+        float y[kBasisPerLane];
+        own_basis(Y, sub, y);
+        float col[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int i = 0; i < kBasisPerLane; ++i)
+            acc = fmaf(y[i], fmaf(cs[0], k[0][i][c], fmaf(cs[1], k[1][i][c], cs[2] * k[2][i][c])), acc);
+          col[c] = quad_sum(acc);
+        }
+        if (sub == 0) {
+          o[0] = fmaxf(col[0] + kColorOffset, 0.f);
+          o[1] = fmaxf(col[1] + kColorOffset, 0.f);
+          o[2] = fmaxf(col[2] + kColorOffset, 0.f);
+        }
       }
     }
   }
@@ -236,18 +256,28 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* _
 
 }  // namespace
 
+int preprocess_lanes(int) { return 1; }
+
 void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
                        float4* cdir, hipStream_t s) {
   if (p.n == 0) return;
-  const int bs = 256;
-  hipLaunchKernelGGL(k_preprocess, dim3((p.n + bs - 1) / bs), dim3(bs), 0, s, p, act, dkey, rec, slot, cdir);
+  const int lanes = preprocess_lanes(p.n_views);
+  const uint64_t threads = (uint64_t)p.n * lanes;
+  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, p, lanes, act, dkey, rec,
+                     slot, cdir);
+}
+
+// Workgroups of the kernels that walk the active-primitive list (each takes
+// 64 listed primitives per step).
+unsigned list_grid(int n) {
+  const unsigned need = (unsigned)((n + kColourPrims - 1) / kColourPrims);
+  return need < 1 ? 1 : (need < 2048 ? need : 2048);
 }
 
 void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdir, Record* rec_sorted,
                    hipStream_t s) {
   if (p.n == 0 || p.flow) return;
-  hipLaunchKernelGGL(k_colour, dim3((unsigned)((p.n + kColourPrims - 1) / kColourPrims)), dim3(256), 0, s, p, slot,
-                     cdir, rec_sorted);
+  hipLaunchKernelGGL(k_colour, dim3(list_grid(p.n)), dim3(256), 0, s, p, slot, cdir, rec_sorted);
 }
 
 }  // namespace g4d

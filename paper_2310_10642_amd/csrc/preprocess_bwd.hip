@@ -151,122 +151,142 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
 
 constexpr int kBwdColourViews = 8;  // views whose slots k_bwd_colour loads together
 
-// A quad of lanes per primitive, lane `sub` owning the basis functions
-// lm = 4 sub + i (as in the forward colour kernel): per active view it adds
-// its share of dL/dcoeffs, and quad sums give the gradients through the view
-// direction and through t - mu_t. The coefficients of the block's primitives
-// that are active in some view come in, and the block's coefficient
-// gradients go out, through LDS with 16-byte accesses. A primitive with a
-// non-finite coefficient was rendered transparent: it gets zero gradients.
+// The primitives active in some view of the call (the preprocess's list), 64
+// per block step, a quad of lanes per primitive, lane `sub` owning the basis
+// functions lm = 4 sub + i (as in the forward colour kernel): per active view
+// it adds its share of dL/dcoeffs, and quad sums give the gradients through
+// the view direction and through t - mu_t. The coefficients come in, and the
+// coefficient gradients go out (written, or added when accumulating), through
+// LDS with 16-byte accesses. A primitive with a non-finite coefficient was
+// rendered transparent: it gets zero gradients.
 __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                      const float4* __restrict__ colbuf, float4* __restrict__ cgbuf,
                                                      float* __restrict__ g_coeffs, bool accumulate) {
   __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
-  __shared__ uint8_t s_any[kColourPrims];
+  __shared__ uint32_t s_id[kColourPrims];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
-  const int g0 = blockIdx.x * kColourPrims;
-  const int nprim = min(kColourPrims, p.n - g0);
-  const int gidx = g0 + (int)(threadIdx.x >> 2);
+  const uint32_t count = *p.plist_n;
   const int sub = threadIdx.x & 3;
-  const bool live = gidx < p.n;  // uniform per quad
-  const bool any = live && any_view_active(p, slot, gidx);
-  if (sub == 0) s_any[threadIdx.x >> 2] = any ? 1 : 0;
-  __syncthreads();
-  copy_in_active(s_k, p.coeffs + (size_t)g0 * K3, nprim, K3, s_any);
-  __syncthreads();
-  float* kc = s_k + (threadIdx.x >> 2) * K3;
-  float k[3][kBasisPerLane][3], gk[3][kBasisPerLane][3];
-  bool finite = true;
+  for (uint32_t c0 = blockIdx.x * kColourPrims; c0 < count; c0 += gridDim.x * kColourPrims) {
+    const int nprim = (int)min((uint32_t)kColourPrims, count - c0);
+    __syncthreads();  // the previous step's copy-out is done
+    if (threadIdx.x < kColourPrims) s_id[threadIdx.x] = (int)threadIdx.x < nprim ? p.plist[c0 + threadIdx.x] : 0u;
+    __syncthreads();
+    copy_in_list(s_k, p.coeffs, s_id, nprim, K3);
+    __syncthreads();
+    const int j = (int)(threadIdx.x >> 2);
+    const bool live = j < nprim;  // uniform per quad
+    const int gidx = live ? (int)s_id[j] : 0;
+    float* kc = s_k + j * K3;
+    float k[3][kBasisPerLane][3], gk[3][kBasisPerLane][3];
+    bool finite = true;
 #pragma unroll
-  for (int n = 0; n < 3; ++n)
-#pragma unroll
-    for (int i = 0; i < kBasisPerLane; ++i) {
-      const int lm = sub * kBasisPerLane + i;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        k[n][i][c] = (any && lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
-        finite = finite && isfinite(k[n][i][c]);
-        gk[n][i][c] = 0.f;
-      }
-    }
-  const bool bad = quad_any(!finite);
-  __syncthreads();  // s_k is reused for the gradients below
-  // views eight at a time, their slots loaded before any is used
-  for (int v0 = 0; any && v0 < p.n_views; v0 += kBwdColourViews) {
-    int ds[kBwdColourViews];
-#pragma unroll
-    for (int w = 0; w < kBwdColourViews; ++w) ds[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
-#pragma unroll
-    for (int w = 0; w < kBwdColourViews; ++w) {
-      const int d = ds[w];
-      if (d < 0) continue;
-      if (bad) {
-        if (sub == 0) cgbuf[d] = make_float4(0.f, 0.f, 0.f, 0.f);
-        continue;
-      }
-      const float4 c0 = colbuf[2 * (size_t)d];
-      const float4 c1 = colbuf[2 * (size_t)d + 1];
-      const float graw[3] = {c0.x, c0.y, c0.z};
-      const float dt = c0.w;
-      float Y[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) Y[j] = 0.f;
-      sh_eval(p.sh_degree, c1.x, c1.y, c1.z, Y);
-      float y[kBasisPerLane];
-      own_basis(Y, sub, y);
-      float cs[3], sn[3];
-      fourier_terms(p.t_order, dt, p.t_period, cs, sn);
-      // kd[n][i] = sum_ch graw_ch k[n][i][ch]; gy[i] = sum_n cs_n kd[n][i]
-      float kd[3][kBasisPerLane], gy[kBasisPerLane];
+    for (int n = 0; n < 3; ++n)
 #pragma unroll
       for (int i = 0; i < kBasisPerLane; ++i) {
-        gy[i] = 0.f;
+        const int lm = sub * kBasisPerLane + i;
 #pragma unroll
-        for (int n = 0; n < 3; ++n) {
-          kd[n][i] = fmaf(graw[0], k[n][i][0], fmaf(graw[1], k[n][i][1], graw[2] * k[n][i][2]));
-          gy[i] = fmaf(cs[n], kd[n][i], gy[i]);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) gk[n][i][c] = fmaf(cs[n] * y[i], graw[c], gk[n][i][c]);
+        for (int c = 0; c < 3; ++c) {
+          k[n][i][c] = (live && lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+          finite = finite && isfinite(k[n][i][c]);
+          gk[n][i][c] = 0.f;
         }
       }
-      // gradient of this lane's basis functions in the view direction
-      float gY[16];
+    const bool bad = quad_any(!finite);
+    __syncthreads();  // s_k is reused for the gradients below
+    // views eight at a time, their slots loaded before any is used
+    for (int v0 = 0; live && v0 < p.n_views; v0 += kBwdColourViews) {
+      int ds[kBwdColourViews];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) gY[j] = (sub == j / kBasisPerLane) ? gy[j % kBasisPerLane] : 0.f;
-      float gdx, gdy, gdz;
-      sh_grad(p.sh_degree, c1.x, c1.y, c1.z, gY, gdx, gdy, gdz);
-      gdx = quad_sum(gdx);
-      gdy = quad_sum(gdy);
-      gdz = quad_sum(gdz);
-      // d/d(dt) cos(2 pi n dt / T) = -(2 pi n / T) sin(2 pi n dt / T)
-      float gdt = 0.f;
+      for (int w = 0; w < kBwdColourViews; ++w)
+        ds[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
 #pragma unroll
-      for (int n = 1; n < 3; ++n) {
-        float gcos = 0.f;
+      for (int w = 0; w < kBwdColourViews; ++w) {
+        const int d = ds[w];
+        if (d < 0) continue;
+        if (bad) {
+          if (sub == 0) cgbuf[d] = make_float4(0.f, 0.f, 0.f, 0.f);
+          continue;
+        }
+        const float4 c0v = colbuf[2 * (size_t)d];
+        const float4 c1 = colbuf[2 * (size_t)d + 1];
+        const float graw[3] = {c0v.x, c0v.y, c0v.z};
+        const float dt = c0v.w;
+        float Y[16];
 #pragma unroll
-        for (int i = 0; i < kBasisPerLane; ++i) gcos = fmaf(y[i], kd[n][i], gcos);
-        gcos = quad_sum(gcos);
-        gdt = fmaf(gcos, -2.f * kPi * n / p.t_period * sn[n], gdt);
-      }
-      if (sub == 0) {
-        const float dd = gdx * c1.x + gdy * c1.y + gdz * c1.z;
-        cgbuf[d] = make_float4((gdx - c1.x * dd) * c1.w, (gdy - c1.y * dd) * c1.w, (gdz - c1.z * dd) * c1.w, gdt);
+        for (int jj = 0; jj < 16; ++jj) Y[jj] = 0.f;
+        sh_eval(p.sh_degree, c1.x, c1.y, c1.z, Y);
+        float y[kBasisPerLane];
+        own_basis(Y, sub, y);
+        float cs[3], sn[3];
+        fourier_terms(p.t_order, dt, p.t_period, cs, sn);
+        // kd[n][i] = sum_ch graw_ch k[n][i][ch]; gy[i] = sum_n cs_n kd[n][i]
+        float kd[3][kBasisPerLane], gy[kBasisPerLane];
+#pragma unroll
+        for (int i = 0; i < kBasisPerLane; ++i) {
+          gy[i] = 0.f;
+#pragma unroll
+          for (int n = 0; n < 3; ++n) {
+            kd[n][i] = fmaf(graw[0], k[n][i][0], fmaf(graw[1], k[n][i][1], graw[2] * k[n][i][2]));
+            gy[i] = fmaf(cs[n], kd[n][i], gy[i]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gk[n][i][c] = fmaf(cs[n] * y[i], graw[c], gk[n][i][c]);
+          }
+        }
+        // gradient of this lane's basis functions in the view direction
+        float gY[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) gY[jj] = (sub == jj / kBasisPerLane) ? gy[jj % kBasisPerLane] : 0.f;
+        float gdx, gdy, gdz;
+        sh_grad(p.sh_degree, c1.x, c1.y, c1.z, gY, gdx, gdy, gdz);
+        gdx = quad_sum(gdx);
+        gdy = quad_sum(gdy);
+        gdz = quad_sum(gdz);
+        // d/d(dt) cos(2 pi n dt / T) = -(2 pi n / T) sin(2 pi n dt / T)
+        float gdt = 0.f;
+#pragma unroll
+        for (int n = 1; n < 3; ++n) {
+          float gcos = 0.f;
+#pragma unroll
+          for (int i = 0; i < kBasisPerLane; ++i) gcos = fmaf(y[i], kd[n][i], gcos);
+          gcos = quad_sum(gcos);
+          gdt = fmaf(gcos, -2.f * kPi * n / p.t_period * sn[n], gdt);
+        }
+        if (sub == 0) {
+          const float dd = gdx * c1.x + gdy * c1.y + gdz * c1.z;
+          cgbuf[d] = make_float4((gdx - c1.x * dd) * c1.w, (gdy - c1.y * dd) * c1.w, (gdz - c1.z * dd) * c1.w, gdt);
+        }
       }
     }
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+      for (int i = 0; i < kBasisPerLane; ++i) {
+        const int lm = sub * kBasisPerLane + i;
+        if (!live || lm >= nb || n >= nt) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) kc[(n * nb + lm) * 3 + c] = gk[n][i][c];
+      }
+    __syncthreads();
+    copy_out_list(g_coeffs, s_k, s_id, nprim, K3, accumulate);
   }
-#pragma unroll
-  for (int n = 0; n < 3; ++n)
-#pragma unroll
-    for (int i = 0; i < kBasisPerLane; ++i) {
-      const int lm = sub * kBasisPerLane + i;
-      if (!live || lm >= nb || n >= nt) continue;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) kc[(n * nb + lm) * 3 + c] = gk[n][i][c];
-    }
-  __syncthreads();
-  copy_out(g_coeffs + (size_t)g0 * K3, s_k, nprim, K3, accumulate, s_any);
+}
+
+// Zero coefficient gradients of the primitives active in no view of the call
+// (the listed ones are written by k_bwd_colour), coalesced over all of them:
+// 16-byte stores when a primitive's K3 floats are whole 16-byte pieces.
+__global__ void __launch_bounds__(256) k_zero_inactive_coeffs(RenderParams p, float* __restrict__ g_coeffs) {
+  const uint32_t K3 = (uint32_t)((p.t_order + 1) * (p.sh_degree + 1) * (p.sh_degree + 1) * 3);
+  const bool vec = (K3 & 3u) == 0u && (reinterpret_cast<uintptr_t>(g_coeffs) & 15u) == 0u;
+  const uint32_t per = vec ? K3 >> 2 : K3;  // pieces per primitive
+  const uint32_t total = (uint32_t)p.n * per;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    if (p.pany[i / per]) continue;
+    if (vec) reinterpret_cast<float4*>(g_coeffs)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    else g_coeffs[i] = 0.f;
+  }
 }
 
 __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t* __restrict__ slot,
@@ -277,9 +297,7 @@ __global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t
                                                    DensifyStats st) {
   const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (gidx >= p.n) return;
-  bool any = false;
-  for (int vi = 0; vi < p.n_views; ++vi) any |= slot[(size_t)vi * p.n + gidx] >= 0;
-  if (!any) {
+  if (!p.pany[gidx]) {
     if (accumulate) return;
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     g_means4[gidx] = z;
@@ -423,8 +441,12 @@ void launch_preprocess_backward(const RenderParams& p, const int32_t* slot, cons
   if (n_records_max > 0)
     hipLaunchKernelGGL(k_bwd_pairs, dim3((n_records_max + 255) / 256), dim3(256), 0, s, p, n_records_dev,
                        n_records_max, ids, recs, grad2d, geo, col);
-  hipLaunchKernelGGL(k_bwd_colour, dim3((unsigned)((p.n + kColourPrims - 1) / kColourPrims)), dim3(256), 0, s, p,
-                     slot, col, cg, g_coeffs, accumulate);
+  if (!accumulate) {
+    const uint64_t total = (uint64_t)p.n * (p.t_order + 1) * (p.sh_degree + 1) * (p.sh_degree + 1) * 3;
+    const uint64_t g = (total + 255) / 256;
+    hipLaunchKernelGGL(k_zero_inactive_coeffs, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, s, p, g_coeffs);
+  }
+  hipLaunchKernelGGL(k_bwd_colour, dim3(list_grid(p.n)), dim3(256), 0, s, p, slot, col, cg, g_coeffs, accumulate);
   hipLaunchKernelGGL(k_bwd_prims, dim3((p.n + 127) / 128), dim3(128), 0, s, p, slot, geo, cg,
                      reinterpret_cast<float4*>(g_means4), reinterpret_cast<float4*>(g_log_scales4),
                      reinterpret_cast<float4*>(g_q_left), reinterpret_cast<float4*>(g_q_right), g_opacity_logit,

@@ -128,6 +128,7 @@ struct Shape4T {
   T s[4];
   T M[4][4];
   T S[4][4];  // symmetric
+  T inv44;    // 1 / Sigma_44
 };
 using Shape4 = Shape4T<float>;
 
@@ -162,6 +163,7 @@ __device__ __forceinline__ void build_shape(float4 qlf, float4 qrf, float4 ls, S
       sh.S[i][j] = acc;
       sh.S[j][i] = acc;
     }
+  sh.inv44 = (T)1 / sh.S[3][3];
 }
 
 // Everything one view needs from a primitive.
@@ -188,8 +190,8 @@ __device__ __forceinline__ void clamp_limits(const ViewDev& vw, float& lx, float
   ly = vw.lim_y;
 }
 __device__ __forceinline__ void clamp_limits(const ViewDev& vw, double& lx, double& ly) {
-  lx = kFrustumSlack64 * (0.5 * vw.width) / (double)vw.fx;
-  ly = kFrustumSlack64 * (0.5 * vw.height) / (double)vw.fy;
+  lx = vw.lim_x64;
+  ly = vw.lim_y64;
 }
 
 // Slice, camera transform and EWA projection (Sec. 3.2, Eqs. 3-4) in
@@ -200,14 +202,14 @@ __device__ __forceinline__ bool view_geometry(const float4 mu, const Shape4T<T>&
                                               T near_plane, ViewGeomT<T>& g) {
   g.dt = (T)vw.t - (T)mu.w;
   g.s44 = sh.S[3][3];
-  g.pt = sc_exp((T)-0.5 * g.dt * g.dt / g.s44);
+  const T inv44 = sh.inv44;
+  g.pt = sc_exp((T)-0.5 * g.dt * g.dt * inv44);
   if (!(g.pt >= t_cull)) return false;
-  g.lam = g.dt / g.s44;
+  g.lam = g.dt * inv44;
   g.v3[0] = sh.S[0][3]; g.v3[1] = sh.S[1][3]; g.v3[2] = sh.S[2][3];
   g.muc[0] = sc_fma(g.v3[0], g.lam, (T)mu.x);
   g.muc[1] = sc_fma(g.v3[1], g.lam, (T)mu.y);
   g.muc[2] = sc_fma(g.v3[2], g.lam, (T)mu.z);
-  const T inv44 = (T)1 / g.s44;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -324,6 +326,49 @@ __device__ __forceinline__ void copy_in_active(float* __restrict__ lds, const fl
   } else {
     for (int i = threadIdx.x; i < count; i += blockDim.x)
       if (on[i / k3]) lds[i] = g[i];
+  }
+}
+
+// copy_in of the coefficients (k3 floats each) of the `nprim` primitives
+// whose indices are ids[0..nprim), into consecutive LDS slots.
+__device__ __forceinline__ void copy_in_list(float* __restrict__ lds, const float* __restrict__ g,
+                                             const uint32_t* __restrict__ ids, int nprim, int k3) {
+  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
+    const int per = k3 >> 2;
+    for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
+      const int j = i / per, o = i - j * per;
+      reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(g + (size_t)ids[j] * k3)[o];
+    }
+  } else {
+    for (int i = threadIdx.x; i < nprim * k3; i += blockDim.x) {
+      const int j = i / k3, o = i - j * k3;
+      lds[i] = g[(size_t)ids[j] * k3 + o];
+    }
+  }
+}
+
+// The reverse: each listed primitive's k3 values written to (or, when
+// accumulate, added to) its place in g.
+__device__ __forceinline__ void copy_out_list(float* __restrict__ g, const float* __restrict__ lds,
+                                              const uint32_t* __restrict__ ids, int nprim, int k3, bool accumulate) {
+  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
+    const int per = k3 >> 2;
+    for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
+      const int j = i / per, o = i - j * per;
+      float4* dst = reinterpret_cast<float4*>(g + (size_t)ids[j] * k3) + o;
+      float4 v = reinterpret_cast<const float4*>(lds)[i];
+      if (accumulate) {
+        const float4 w = *dst;
+        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+      }
+      *dst = v;
+    }
+  } else {
+    for (int i = threadIdx.x; i < nprim * k3; i += blockDim.x) {
+      const int j = i / k3, o = i - j * k3;
+      float* dst = g + (size_t)ids[j] * k3 + o;
+      *dst = accumulate ? *dst + lds[i] : lds[i];
+    }
   }
 }
 
