@@ -31,6 +31,11 @@ sys.path.insert(0, HERE)
 #             per-primitive tile sums 6 (g, g m, g m^2, w dL/dC x 3)      = 27
 OPS_FWD = 16
 OPS_BWD = 27
+UNITS_NAME = ("list positions up to each pixel's last contributor (sum over pixels of pix_last; the "
+              "quadrant cull skips some of them, which still count as work the method defines)")
+# counter summaries under profiles/ (taken with the same kernel sources)
+TRAFFIC_SUMMARY = "traffic_bench_300k_8x1352x1014.md"
+SQ_SUMMARY = "sq_counters_raster_bench_300k_8x1352x1014.md"
 # FP32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
@@ -175,22 +180,60 @@ def other_workloads(log_fn, steps: int, cfgs=(2, 3, 4)):
     return res
 
 
-def profiled_traffic(kernel_source: str, summary: str):
-    """HBM bytes per launch from the counter summary under profiles/, or
-    None when the kernel source changed since the counters were taken."""
+CSRC = os.path.join(HERE, "paper_2310_10642_amd", "csrc")
+PROFILES = os.path.join(HERE, "profiles")
+
+
+def kernel_sources_sha256() -> str:
+    """SHA-256 over the library's kernel sources (every file of csrc/, by name):
+    a counter summary taken before any of them changed carries the same value."""
     import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
+
+
+def profile_fields(summary: str):
+    """The `key: value` lines of a counter summary under profiles/, or None
+    when the file is missing or the kernels changed since it was taken."""
     try:
-        text = open(summary).read()
-        sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+        text = open(os.path.join(PROFILES, summary)).read()
     except OSError:
         return None
-    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith("|"))
-    if fields.get("source_sha256", "").strip() != sha:
+    fields = {}
+    for line in text.splitlines():
+        if ": " in line and not line.startswith(("|", " ", "`", "#")):
+            k, v = line.split(": ", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != kernel_sources_sha256():
         return None
-    try:
-        return float(fields["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
+    out = {}
+    for k, v in fields.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
+def sq_figures(f, prefix: str, seconds: float, units: float):
+    """Issue figures of one kernel from its SQ counters (per launch): VALU and
+    LDS instructions per unit of work, the share of the launch the SIMDs
+    spend issuing VALU (a wave64 instruction takes 4 cycles of a 16-lane
+    SIMD; 1024 SIMDs at 2.4 GHz), and LDS bank-conflict cycles over LDS
+    active cycles."""
+    if not f or f.get(prefix + ".SQ_INSTS_VALU") is None:
         return None
+    valu, lds = f[prefix + ".SQ_INSTS_VALU"], f.get(prefix + ".SQ_INSTS_LDS", float("nan"))
+    out = dict(valu_lane_instr_per_unit=valu * 64 / units, lds_instr_per_unit=lds * 64 / units,
+               valu_issue_frac=valu * 4 / (1024 * 2.4e9 * seconds))
+    conf, act = f.get(prefix + ".SQ_LDS_BANK_CONFLICT"), f.get(prefix + ".SQ_ACTIVE_INST_LDS")
+    if conf is not None and act:
+        out["lds_bank_conflict_frac"] = conf / act
+    return out
 
 
 def main():
@@ -347,35 +390,54 @@ def main():
                      per_view_forward_mpix_per_s=P_total / fwd_pv / 1e6,
                      batched_over_per_view_fwd_bwd=step_pv / best)
 
-    # roofline of the dominant stage
-    per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
-    dom = max(per_launch, key=lambda k: per_launch[k])
+    # per-stage rooflines; the line's own roofline is the dominant stage's
+    sec_step = {k: ms * 1e-3 / args.steps for k, (ms, n) in stages.items()}
     frag = stats["fragments"]
+    A, I, N = stats["active_total"], stats["instances"], sc.n
+    F = sc.coeffs.shape[1] * 3                   # 4DSH coefficient floats per primitive
+    traffic_f = profile_fields(TRAFFIC_SUMMARY)
+    sq_f = profile_fields(SQ_SUMMARY)
+    stage_roof = {}
+
+    def hbm(name, byts, sec, note, counter_key=None):
+        d = dict(bound="hbm", bytes=byts, ms=sec * 1e3, achieved_gb_s=byts / sec / 1e9,
+                 frac=byts / sec / HBM_PEAK, bytes_rule=note)
+        if counter_key and traffic_f and traffic_f.get(counter_key):
+            cb = traffic_f[counter_key]
+            d.update(counter_bytes=cb, counter_frac=cb / sec / HBM_PEAK)
+        stage_roof[name] = d
+    # preprocess + its colour pass: read every primitive's 17 geometry/opacity
+    # floats and F coefficients once, write one 48-byte record per active pair
+    hbm("preprocess", (17 + F) * 4 * N + 48 * A, sec_step["preprocess"] + sec_step["colour"],
+        "(17+F)*4*N + 48*sum(A), time = k_preprocess + k_colour", "preprocess_bytes_per_render")
+    # binning: the sort floor of 28 bytes per (tile, record) instance
+    hbm("binning", 28 * I, sec_step["binning"], "28*I", "binning_bytes_per_render")
+    # backward of the preprocess: parameters in and gradients out once, one
+    # 128-byte FP64 gradient line per active record
+    hbm("preprocess_bwd", (17 + F) * 4 * N * 2 + 128 * A, sec_step["preprocess_bwd"],
+        "(17+F)*4*N*2 + 128*sum(A)", "preprocess_bwd_bytes_per_step")
+    hbm("loss", 12 * 3 * P_total, sec_step["loss"], "12*3*pixels (image and target in, gradient out)")
+    for name, ops in (("raster_fwd", OPS_FWD), ("raster_bwd", OPS_BWD)):
+        sec = sec_step[name]
+        d = dict(bound="alu", ops_per_unit=ops, units=frag, ms=sec * 1e3,
+                 achieved_tops=ops * frag / sec / 1e12, frac=ops * frag / sec / ALU_PEAK_OPS)
+        sq = sq_figures(sq_f, name, sec, frag)
+        if sq:
+            d.update(sq)
+        stage_roof[name] = d
+    dom = max(("preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss"),
+              key=lambda k: sec_step[k])
     if dom in ("raster_bwd", "raster_fwd"):
         ops = frag * (OPS_BWD if dom == "raster_bwd" else OPS_FWD)
-        achieved = ops / (per_launch[dom] * 1e-3)
-        traffic = None
-        if dom == "raster_bwd":
-            traffic = profiled_traffic(os.path.join(HERE, "paper_2310_10642_amd", "csrc", "raster.hip"),
-                                       os.path.join(HERE, "profiles",
-                                                    "traffic_raster_backward_bench_300k_8x1352x1014.md"))
+        achieved = ops / sec_step[dom]
+        traffic = traffic_f.get(dom + "_bytes_per_launch") if traffic_f else None
         roof = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=ALU_PEAK_OPS / 1e12,
                     unit="Tops/s (FP32 lane ops)", frac=achieved / ALU_PEAK_OPS, traffic=traffic,
-                    ms_per_launch=per_launch[dom], units=frag,
-                    units_name="evaluated fragments (pixel x list entry up to the last contributor)")
+                    ms_per_launch=sec_step[dom] * 1e3, units=frag, units_name=UNITS_NAME)
     else:
-        # preprocess / binning: bytes the method must move, per launch
-        A, I, N = stats["active_total"], stats["instances"], sc.n
-        K3 = sc.coeffs.shape[1] * 3
-        if dom == "preprocess":
-            byts = 68 * N + (4 * K3 + 48) * A
-        elif dom == "preprocess_bwd":
-            byts = (68 + 4 * K3) * N * 2 + 48 * A
-        else:
-            byts = 28 * I
-        achieved = byts / (per_launch[dom] * 1e-3)
-        roof = dict(kernel=dom, bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=achieved / HBM_PEAK, traffic=None, ms_per_launch=per_launch[dom])
+        d = stage_roof[dom]
+        roof = dict(kernel=dom, bound="hbm", achieved=d["achieved_gb_s"], peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=d["frac"], traffic=d.get("counter_bytes"), ms_per_launch=d["ms"])
     others = None
     if not args.no_other_workloads:
         log("[bench] other workloads")
@@ -408,6 +470,7 @@ def main():
         "active_per_view": stats["active_per_view"], "instances": stats["instances"],
         "fragments": frag, "max_tile_list": stats["max_tile_list"],
         "roofline": roof,
+        "stage_roofline": stage_roof,
         "other_workloads": others,
         "cpu_baseline": cpu,
     }

@@ -301,11 +301,13 @@ enum {
   G4D_STAGE_BINNING = 1,      /* compaction, depth sort, emission, tile sort, ranges; the
                                * 4DSH colour of the active records runs on a second stream
                                * alongside, and the forward rasteriser waits for it */
-  G4D_STAGE_RASTER_FWD = 2,
-  G4D_STAGE_RASTER_BWD = 3,
-  G4D_STAGE_PREPROCESS_BWD = 4,
+  G4D_STAGE_RASTER_FWD = 2,   /* the forward rasteriser alone */
+  G4D_STAGE_RASTER_BWD = 3,   /* the backward rasteriser alone */
+  G4D_STAGE_PREPROCESS_BWD = 4, /* zeroing the gradient lines, then the per-record and
+                                 * per-primitive backward (two timed windows per round) */
   G4D_STAGE_LOSS = 5,
-  G4D_NUM_STAGES = 6
+  G4D_STAGE_COLOUR = 6,       /* the 4DSH colour pass, timed on its own (second) stream */
+  G4D_NUM_STAGES = 7
 };
 g4d_status g4d_stage_times(g4d_ctx* ctx, double* ms_out, int64_t* launches_out);
 

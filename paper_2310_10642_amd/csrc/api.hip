@@ -83,6 +83,7 @@ struct g4d_ctx {
   std::vector<EvPair> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t open_ev = nullptr;
+  hipEvent_t side_open_ev = nullptr;  // the open stage on the side stream
   double stage_ms[G4D_NUM_STAGES] = {};
   int64_t stage_n[G4D_NUM_STAGES] = {};
 };
@@ -262,6 +263,22 @@ void stage_begin(g4d_ctx* c) {
   if (c->open_ev) (void)hipEventRecord(c->open_ev, c->stream);
 }
 
+// A stage enqueued on the side stream, timed by its own pair of events.
+void side_stage_begin(g4d_ctx* c) {
+  if (!c->timing || capturing(c)) return;
+  c->side_open_ev = take_event(c);
+  if (c->side_open_ev) (void)hipEventRecord(c->side_open_ev, c->side);
+}
+
+void side_stage_end(g4d_ctx* c, int stage) {
+  if (!c->timing || !c->side_open_ev || capturing(c)) return;
+  hipEvent_t e = take_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, c->side);
+  c->pending.push_back({c->side_open_ev, e, stage});
+  c->side_open_ev = nullptr;
+}
+
 void stage_end(g4d_ctx* c, int stage) {
   if (!c->timing || !c->open_ev || capturing(c)) return;
   hipEvent_t e = take_event(c);
@@ -274,6 +291,7 @@ void stage_end(g4d_ctx* c, int stage) {
 g4d_status collect_times(g4d_ctx* c) {
   if (c->pending.empty()) return G4D_OK;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->side));
   for (auto& p : c->pending) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
@@ -327,7 +345,9 @@ g4d_status fork_colour(g4d_ctx* c, const RenderParams& p) {
   if (p.flow || p.n == 0) return G4D_OK;
   HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
   HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  side_stage_begin(c);
   launch_colour(p, P<int32_t>(c->slot), P<float4>(c->cdir), P<Record>(c->rec_sorted), c->side);
+  side_stage_end(c, G4D_STAGE_COLOUR);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev_join, c->side));
   c->side_pending = true;
@@ -955,9 +975,13 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     const uint32_t a_max = r.A == kOnDevice ? (uint32_t)((uint64_t)c->n * nv) : r.A;
     if ((st = ensure(c, c->grad2d, sizeof(double) * kGrad2dStride * (size_t)a_max))) return st;
     if ((st = ensure(c, c->bwd_scratch, sizeof(float) * preprocess_backward_scratch_floats(a_max)))) return st;
+    // the gradient lines start at zero (timed with the preprocess backward,
+    // which reads them)
     stage_begin(c);
     launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, 2 * kGrad2dStride, a_max, s);
+    stage_end(c, G4D_STAGE_PREPROCESS_BWD);
     if ((st = join_side(c))) return st;  // the records' colours of a round binned again
+    stage_begin(c);
     launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),

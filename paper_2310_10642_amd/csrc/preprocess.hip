@@ -157,98 +157,62 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, int lanes, u
   }
 }
 
-constexpr int kColourViews = 8;  // views whose loads k_colour issues together
-
-// 4D spherindrical-harmonic colour (Sec. 3.2) of the primitives active in
-// some view (the list the preprocess built), 64 per block step: a quad of
-// lanes per primitive, lane `sub` owning the basis functions lm = 4 sub + i.
-// The 64 primitives' coefficients (576 contiguous bytes each at SH degree 3 x
-// Fourier order 2) are staged through LDS with 16-byte loads, and each lane
-// takes its [n][4 sub + i][3] from there. Per active view every lane evaluates
-// the basis, weights its four functions by the Fourier terms, and a quad sum
-// gives c = max(0, 0.5 + sum). A primitive with a non-finite coefficient gets
-// a NaN colour, which the rasterisers read as fully transparent (and the pair
-// is counted as culled).
+// 4D spherindrical-harmonic colour (Sec. 3.2) of every active (view,
+// primitive) pair, a thread per pair: the block stages the coefficients of
+// 64 primitives of the active list in LDS and lists their active pairs four
+// views at a time, and each pair's thread evaluates the SH basis in its view
+// direction and the Fourier terms of t - mu_t and contracts them with the
+// coefficients: c = max(0, 0.5 + sum_n cos_n sum_lm Y_lm k[n][lm]). A
+// primitive with a non-finite coefficient gets a NaN colour, which the
+// rasterisers read as fully transparent (and the pair is counted as culled).
 __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                 const float4* __restrict__ cdir, Record* __restrict__ rec_sorted) {
-  __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
-  __shared__ uint32_t s_id[kColourPrims];
+  __shared__ ColourStage cs;
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
   const uint32_t count = *p.plist_n;
-  const int sub = threadIdx.x & 3;
   for (uint32_t c0 = blockIdx.x * kColourPrims; c0 < count; c0 += gridDim.x * kColourPrims) {
     const int nprim = (int)min((uint32_t)kColourPrims, count - c0);
-    __syncthreads();  // the previous step's reads of s_k and s_id are done
-    if (threadIdx.x < kColourPrims) s_id[threadIdx.x] = (int)threadIdx.x < nprim ? p.plist[c0 + threadIdx.x] : 0u;
-    __syncthreads();
-    copy_in_list(s_k, p.coeffs, s_id, nprim, K3);
-    __syncthreads();
-    const int j = (int)(threadIdx.x >> 2);
-    if (j >= nprim) continue;  // uniform per quad
-    const int gidx = (int)s_id[j];
-    const float* kc = s_k + j * K3;
-    float k[3][kBasisPerLane][3];
-    bool finite = true;
-#pragma unroll
-    for (int n = 0; n < 3; ++n)
-#pragma unroll
-      for (int i = 0; i < kBasisPerLane; ++i) {
-        const int lm = sub * kBasisPerLane + i;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          k[n][i][c] = (lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
-          finite = finite && isfinite(k[n][i][c]);
-        }
-      }
-    const bool bad = quad_any(!finite);
-    // views eight at a time: all flags, then the directions of the active
-    // ones, are loaded before any is used, so the loads overlap
-    for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
-      int on[kColourViews];
-      float4 cds[kColourViews];
-#pragma unroll
-      for (int w = 0; w < kColourViews; ++w) on[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
-#pragma unroll
-      for (int w = 0; w < kColourViews; ++w)
-        cds[w] = on[w] >= 0 ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
-#pragma unroll
-      for (int w = 0; w < kColourViews; ++w) {
-        if (on[w] < 0) continue;  // uniform per quad
-        float* o = reinterpret_cast<float*>(&rec_sorted[on[w]].c);
-        if (bad) {
-          if (sub == 0) {
-            const float nan = __int_as_float(0x7FC00000);
-            o[0] = nan;
-            o[1] = nan;
-            o[2] = nan;
-            if (p.nonfinite) atomicAdd(p.nonfinite + v0 + w, 1u);
-          }
+    colour_stage(cs, p, c0, nprim, K3);
+    for (int v0 = 0; v0 < p.n_views; v0 += kColourGroup) {
+      colour_pairs(cs, p, slot, nprim, v0);
+      for (uint32_t q = threadIdx.x; q < cs.np; q += blockDim.x) {
+        const int d = cs.pd[q];
+        const int j = cs.pjw[q] >> 8, v = v0 + (cs.pjw[q] & 0xFF);
+        float* o = reinterpret_cast<float*>(&rec_sorted[d].c);
+        if (cs.bad[j]) {
+          const float nan = __int_as_float(0x7FC00000);
+          o[0] = nan;
+          o[1] = nan;
+          o[2] = nan;
+          if (p.nonfinite) atomicAdd(p.nonfinite + v, 1u);
           continue;
         }
-        const float4 cd = cds[w];
-        float Y[16], cs[3] = {0.f, 0.f, 0.f};
+        const float4 cd = cdir[(size_t)v * p.n + cs.id[j]];
+        float Y[16], cw[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) Y[jj] = 0.f;
+        for (int lm = 0; lm < 16; ++lm) Y[lm] = 0.f;
         sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
-        fourier_terms(p.t_order, cd.w, p.t_period, cs);
-        float y[kBasisPerLane];
-        own_basis(Y, sub, y);
-        float col[3];
+        fourier_terms(p.t_order, cd.w, p.t_period, cw);
+        const float* kk = cs.k + j * kKStride;
+        float c[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          float acc = 0.f;
+        for (int n = 0; n < 3; ++n) {
+          if (n >= nt) break;
+          const float* kn = kk + n * nb * 3;
 #pragma unroll
-          for (int i = 0; i < kBasisPerLane; ++i)
-            acc = fmaf(y[i], fmaf(cs[0], k[0][i][c], fmaf(cs[1], k[1][i][c], cs[2] * k[2][i][c])), acc);
-          col[c] = quad_sum(acc);
+          for (int lm = 0; lm < 16; ++lm) {
+            if (lm >= nb) break;
+            const float wgt = cw[n] * Y[lm];
+            c[0] = fmaf(wgt, kn[3 * lm], c[0]);
+            c[1] = fmaf(wgt, kn[3 * lm + 1], c[1]);
+            c[2] = fmaf(wgt, kn[3 * lm + 2], c[2]);
+          }
         }
-        if (sub == 0) {
-          o[0] = fmaxf(col[0] + kColorOffset, 0.f);
-          o[1] = fmaxf(col[1] + kColorOffset, 0.f);
-          o[2] = fmaxf(col[2] + kColorOffset, 0.f);
-        }
+        o[0] = fmaxf(c[0] + kColorOffset, 0.f);
+        o[1] = fmaxf(c[1] + kColorOffset, 0.f);
+        o[2] = fmaxf(c[2] + kColorOffset, 0.f);
       }
     }
   }
@@ -267,11 +231,12 @@ void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Rec
                      slot, cdir);
 }
 
-// Workgroups of the kernels that walk the active-primitive list (each takes
-// 64 listed primitives per step).
+// Workgroups of the kernels that walk the active-primitive list (64 listed
+// primitives per workgroup and step): one step for up to 2^20 primitives,
+// grid-stride beyond.
 unsigned list_grid(int n) {
   const unsigned need = (unsigned)((n + kColourPrims - 1) / kColourPrims);
-  return need < 1 ? 1 : (need < 2048 ? need : 2048);
+  return need < 1 ? 1 : (need < 16384 ? need : 16384);
 }
 
 void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdir, Record* rec_sorted,

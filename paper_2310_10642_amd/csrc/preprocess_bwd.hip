@@ -9,10 +9,11 @@
 //            (Sec. 3.2, Eqs. 3-4) up to dL/dSigma, dL/dmu and dL/dlogit of
 //            that view; the colour gradient is passed on (clamp decided from
 //            the record's colour).
-//   colour:  16 lanes per primitive, one per SH basis function: 4D
-//            spherindrical-harmonic coefficients (Sec. 3.2), read and written
-//            once and coalesced; per view the gradient to the view direction
-//            and to t - mu_t is reduced over the lanes and passed on.
+//   colour:  a quad of lanes per primitive active in some view, four SH
+//            basis functions per lane: 4D spherindrical-harmonic coefficients
+//            (Sec. 3.2), read and written once; per active view the gradient
+//            to the view direction and to t - mu_t is reduced over the quad
+//            and passed on.
 //   prims:   one thread per primitive: sums the views, adds the colour part
 //            through the slice, then Sigma = M M^T, M = R S, R = L(q_l) R(q_r)
 //            and the quaternion normalisation.
@@ -151,61 +152,62 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(RenderParams p, const uint32_
 
 constexpr int kBwdColourViews = 8;  // views whose slots k_bwd_colour loads together
 
-// The primitives active in some view of the call (the preprocess's list), 64
-// per block step, a quad of lanes per primitive, lane `sub` owning the basis
-// functions lm = 4 sub + i (as in the forward colour kernel): per active view
-// it adds its share of dL/dcoeffs, and quad sums give the gradients through
-// the view direction and through t - mu_t. The coefficients come in, and the
-// coefficient gradients go out (written, or added when accumulating), through
-// LDS with 16-byte accesses. A primitive with a non-finite coefficient was
+// The primitives active in some view of the call (the preprocess's list), a
+// quad of lanes per primitive, lane `sub` owning the basis functions
+// lm = 4 sub + i and reading and writing their coefficients and gradients
+// straight from and to memory. Per active view it adds its share of
+// dL/dcoeffs, and quad sums give the gradients through the view direction
+// and through t - mu_t. Each quad walks only its own active views (the k-th
+// of them in round k), so a wave takes as many rounds as its busiest
+// primitive has active views. A primitive with a non-finite coefficient was
 // rendered transparent: it gets zero gradients.
 __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                      const float4* __restrict__ colbuf, float4* __restrict__ cgbuf,
                                                      float* __restrict__ g_coeffs, bool accumulate) {
-  __shared__ __align__(16) float s_k[kColourPrims * kCoeffMax];
-  __shared__ uint32_t s_id[kColourPrims];
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
   const uint32_t count = *p.plist_n;
   const int sub = threadIdx.x & 3;
-  for (uint32_t c0 = blockIdx.x * kColourPrims; c0 < count; c0 += gridDim.x * kColourPrims) {
-    const int nprim = (int)min((uint32_t)kColourPrims, count - c0);
-    __syncthreads();  // the previous step's copy-out is done
-    if (threadIdx.x < kColourPrims) s_id[threadIdx.x] = (int)threadIdx.x < nprim ? p.plist[c0 + threadIdx.x] : 0u;
-    __syncthreads();
-    copy_in_list(s_k, p.coeffs, s_id, nprim, K3);
-    __syncthreads();
-    const int j = (int)(threadIdx.x >> 2);
-    const bool live = j < nprim;  // uniform per quad
-    const int gidx = live ? (int)s_id[j] : 0;
-    float* kc = s_k + j * K3;
+  const uint32_t stride = (gridDim.x * blockDim.x) >> 2;
+  for (uint32_t e0 = ((blockIdx.x * blockDim.x) >> 2); e0 < count; e0 += stride) {
+    const uint32_t e = e0 + (threadIdx.x >> 2);
+    const bool live = e < count;  // uniform per quad
+    const int gidx = live ? (int)p.plist[e] : 0;
     float k[3][kBasisPerLane][3], gk[3][kBasisPerLane][3];
+    if (live) load_own_coeffs(p.coeffs + (size_t)gidx * K3, sub, nb, nt, k);
     bool finite = true;
 #pragma unroll
     for (int n = 0; n < 3; ++n)
 #pragma unroll
-      for (int i = 0; i < kBasisPerLane; ++i) {
-        const int lm = sub * kBasisPerLane + i;
+      for (int i = 0; i < kBasisPerLane; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          k[n][i][c] = (live && lm < nb && n < nt) ? kc[(n * nb + lm) * 3 + c] : 0.f;
+          if (!live) k[n][i][c] = 0.f;
           finite = finite && isfinite(k[n][i][c]);
           gk[n][i][c] = 0.f;
         }
-      }
     const bool bad = quad_any(!finite);
-    __syncthreads();  // s_k is reused for the gradients below
-    // views eight at a time, their slots loaded before any is used
-    for (int v0 = 0; live && v0 < p.n_views; v0 += kBwdColourViews) {
+    for (int v0 = 0; v0 < p.n_views; v0 += kBwdColourViews) {
       int ds[kBwdColourViews];
-#pragma unroll
-      for (int w = 0; w < kBwdColourViews; ++w)
-        ds[w] = v0 + w < p.n_views ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
+      uint32_t m = 0u;
 #pragma unroll
       for (int w = 0; w < kBwdColourViews; ++w) {
-        const int d = ds[w];
-        if (d < 0) continue;
+        ds[w] = (live && v0 + w < p.n_views) ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
+        m |= (ds[w] >= 0 ? 1u : 0u) << w;
+      }
+      // rounds: the most active views of a primitive in this wave
+      uint32_t rounds = (uint32_t)__popc(m);
+#pragma unroll
+      for (int off = 4; off < 64; off <<= 1) rounds = max(rounds, (uint32_t)__shfl_xor((int)rounds, off, 64));
+      for (uint32_t r = 0; r < rounds; ++r) {
+        // this quad's next active view
+        const int w = m ? __ffs(m) - 1 : -1;
+        m &= m - 1u;
+        int d = -1;
+#pragma unroll
+        for (int ww = 0; ww < kBwdColourViews; ++ww) d = (ww == w) ? ds[ww] : d;
+        if (d < 0) continue;  // uniform per quad
         if (bad) {
           if (sub == 0) cgbuf[d] = make_float4(0.f, 0.f, 0.f, 0.f);
           continue;
@@ -260,17 +262,7 @@ __global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_
         }
       }
     }
-#pragma unroll
-    for (int n = 0; n < 3; ++n)
-#pragma unroll
-      for (int i = 0; i < kBasisPerLane; ++i) {
-        const int lm = sub * kBasisPerLane + i;
-        if (!live || lm >= nb || n >= nt) continue;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) kc[(n * nb + lm) * 3 + c] = gk[n][i][c];
-      }
-    __syncthreads();
-    copy_out_list(g_coeffs, s_k, s_id, nprim, K3, accumulate);
+    if (live) store_own_coeffs(g_coeffs + (size_t)gidx * K3, sub, nb, nt, gk, accumulate);
   }
 }
 

@@ -23,6 +23,8 @@
 // of ten lanes of a primitive's row with one value of its gradient line, and
 // those lanes add the tile's share with one FP64 atomic instruction into one
 // 128-byte line.
+#include <type_traits>
+
 #include "shade.h"
 
 namespace g4d {
@@ -159,6 +161,12 @@ __device__ __forceinline__ V row16_reduce_scatter10(const V (&q)[10], int c, int
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
   return v;
 }
 
@@ -395,6 +403,9 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   }
   s_pix[p_self] = make_float4(gC0, gC1, gC2, gD);
   const uint32_t wave_last = wave_max_u32(last);
+  // batches ending at or before every lane's last contributor need no
+  // per-entry list-position test
+  const uint32_t wave_first_last = wave_min_u32(last);
   __syncthreads();
   if (lane == 0 && wave_last) atomicMax(&s_max, wave_last);
   // Only the dot product of this pixel's output gradient with the colour,
@@ -470,9 +481,11 @@ __global__ void __launch_bounds__(256) k_raster_backward(
       todo = (uint32_t)__ballot(((qm >> wave) & 1u) && (uint32_t)(b0 + lane) < wave_last);
     }
     uint32_t blended = 0u;
-    auto entry = [&](int j, const float4& sa, const float4& sb, const float4& sc) {
+    // CHECK: test the entry's list position against this lane's last
+    // contributor (not needed when the batch ends at or before every lane's)
+    auto entry = [&](int j, const float4& sa, const float4& sb, const float4& sc, auto check) {
       const float p2 = frag_log2(fx - sa.x, fy - sa.y, sa, sb);
-      const bool valid = ((uint32_t)(b0 + j) < last) && (p2 >= kLog2AlphaMin);
+      const bool valid = (!decltype(check)::value || (uint32_t)(b0 + j) < last) && (p2 >= kLog2AlphaMin);
       if (!__any(valid)) return;
       const float G = __builtin_amdgcn_exp2f(p2);
       const float a = valid ? __builtin_amdgcn_fmed3f(G, 0.f, kAlphaMax) : 0.f;
@@ -482,17 +495,28 @@ __global__ void __launch_bounds__(256) k_raster_backward(
       if (HAS_A) dot += gA;
       const float s = dot - beta;
       beta = fmaf(a, s, beta);
-      const float g = (valid && G < kAlphaMax) ? (T * s) * G : 0.f;  // dL/dpower
+      // dL/dpower = dL/da * a for an unclamped alpha (a = G), zero where the
+      // clamp holds; a skipped fragment has a = 0
+      const float w = a * T;
+      const float g = G < kAlphaMax ? w * s : 0.f;
       s_g[j * kGwStride + q_self] = g;
-      s_w[j * kGwStride + q_self] = a * T;
+      s_w[j * kGwStride + q_self] = w;
       blended |= 1u << j;
     };
     // back to front over the set entries; j is a constant in every unrolled
     // step, so the LDS addresses are immediate offsets
+    if ((uint32_t)b0 + kBwdBatch <= wave_first_last) {
 #pragma unroll
-    for (int j = kBwdBatch - 1; j >= 0; --j) {
-      if (!((todo >> j) & 1u)) continue;
-      entry(j, s_a[j], s_b[j], s_c[j]);
+      for (int j = kBwdBatch - 1; j >= 0; --j) {
+        if (!((todo >> j) & 1u)) continue;
+        entry(j, s_a[j], s_b[j], s_c[j], std::false_type{});
+      }
+    } else {
+#pragma unroll
+      for (int j = kBwdBatch - 1; j >= 0; --j) {
+        if (!((todo >> j) & 1u)) continue;
+        entry(j, s_a[j], s_b[j], s_c[j], std::true_type{});
+      }
     }
     if (lane == 0) s_act[wave] = blended;
     __syncthreads();

@@ -298,116 +298,171 @@ __device__ __forceinline__ float quad_sum(float v) {
 // functions lm = 4 sub + i, i < kBasisPerLane, and their coefficients.
 constexpr int kBasisPerLane = 4;
 
-// Primitives per 256-thread block in the colour kernels, and the LDS floats
-// that stage their coefficients ([(Fourier term) (L+1)^2 + lm][3] each, at
-// most 3 x 16 x 3).
+// ---- colour kernels ----
+// The forward colour kernel's 256-thread block takes 64 primitives of the
+// active list at a time and stages their coefficients
+// ([(Fourier term) (L+1)^2 + lm][3] each, at most 3 x 16 x 3 floats) in LDS,
+// at an odd stride so that lanes reading different primitives hit different
+// banks; it then lists the active (view, primitive) pairs of a group of four
+// views and gives each pair a thread.
 constexpr int kColourPrims = 64;
 constexpr int kCoeffMax = 3 * 16 * 3;
+constexpr int kKStride = kCoeffMax + 1;
+constexpr int kColourGroup = 4;                              // views per pair list
+constexpr int kColourPairs = kColourPrims * kColourGroup;    // pairs per list, at most
 
-// Block copies of `count` floats between global memory and LDS (lds 16-byte
-// aligned): 16 bytes per thread and step when g is 16-byte aligned, then
-// single floats for the tail; single floats throughout otherwise.
-__device__ __forceinline__ void copy_in(float* __restrict__ lds, const float* __restrict__ g, int count) {
-  const int n4 = (reinterpret_cast<uintptr_t>(g) & 15u) ? 0 : count >> 2;
-  for (int i = threadIdx.x; i < n4; i += blockDim.x)
-    reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(g)[i];
-  for (int i = 4 * n4 + threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
-}
+struct ColourStage {
+  float k[kColourPrims * kKStride];
+  uint32_t id[kColourPrims];      // primitive index
+  uint32_t bad[kColourPrims];     // a coefficient is not finite
+  int32_t pd[kColourPairs];       // the pair's record (depth-order slot)
+  uint16_t pjw[kColourPairs];     // primitive (within the block) << 8 | view (within the group)
+  uint32_t np;                    // pairs in the list
+};
 
-// copy_in of the coefficients of `nprim` primitives (k3 floats each) whose
-// flag in `on` is set; the others' LDS slots are left as they are.
-__device__ __forceinline__ void copy_in_active(float* __restrict__ lds, const float* __restrict__ g, int nprim, int k3,
-                                               const uint8_t* __restrict__ on) {
-  const int count = nprim * k3;
-  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
-    const int per = k3 >> 2;  // 16-byte pieces per primitive
-    for (int i = threadIdx.x; i < (count >> 2); i += blockDim.x)
-      if (on[i / per]) reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(g)[i];
+// Stages listed primitives [c0, c0 + nprim) (ids, coefficients, finiteness).
+__device__ __forceinline__ void colour_stage(ColourStage& cs, const RenderParams& p, uint32_t c0, int nprim, int K3) {
+  __syncthreads();  // the previous step's readers are done
+  if (threadIdx.x < kColourPrims) {
+    cs.id[threadIdx.x] = (int)threadIdx.x < nprim ? p.plist[c0 + threadIdx.x] : 0u;
+    cs.bad[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  const bool vec = (K3 & 3) == 0 && (reinterpret_cast<uintptr_t>(p.coeffs) & 15u) == 0;
+  if (vec) {
+    const int per = K3 >> 2;
+    for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
+      const int j = i / per, o = i - j * per;
+      const float4 q = reinterpret_cast<const float4*>(p.coeffs + (size_t)cs.id[j] * K3)[o];
+      float* dst = cs.k + j * kKStride + 4 * o;
+      dst[0] = q.x;
+      dst[1] = q.y;
+      dst[2] = q.z;
+      dst[3] = q.w;
+      if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w))) atomicOr(&cs.bad[j], 1u);
+    }
   } else {
-    for (int i = threadIdx.x; i < count; i += blockDim.x)
-      if (on[i / k3]) lds[i] = g[i];
+    for (int i = threadIdx.x; i < nprim * K3; i += blockDim.x) {
+      const int j = i / K3, o = i - j * K3;
+      const float q = p.coeffs[(size_t)cs.id[j] * K3 + o];
+      cs.k[j * kKStride + o] = q;
+      if (!isfinite(q)) atomicOr(&cs.bad[j], 1u);
+    }
   }
 }
 
-// copy_in of the coefficients (k3 floats each) of the `nprim` primitives
-// whose indices are ids[0..nprim), into consecutive LDS slots.
-__device__ __forceinline__ void copy_in_list(float* __restrict__ lds, const float* __restrict__ g,
-                                             const uint32_t* __restrict__ ids, int nprim, int k3) {
-  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
-    const int per = k3 >> 2;
-    for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
-      const int j = i / per, o = i - j * per;
-      reinterpret_cast<float4*>(lds)[i] = reinterpret_cast<const float4*>(g + (size_t)ids[j] * k3)[o];
+// Lists the active pairs of the staged primitives in views [v0, v0 + 4),
+// primitive-major (a primitive's pairs are consecutive, in view order), by
+// wave 0: lane j reads primitive j's slots.
+__device__ __forceinline__ void colour_pairs(ColourStage& cs, const RenderParams& p,
+                                             const int32_t* __restrict__ slot, int nprim, int v0) {
+  __syncthreads();  // the previous list's readers are done
+  if (threadIdx.x < 64) {
+    const int j = (int)threadIdx.x;
+    int d[kColourGroup];
+    uint32_t m = 0u;
+#pragma unroll
+    for (int w = 0; w < kColourGroup; ++w) {
+      d[w] = (j < nprim && v0 + w < p.n_views) ? slot[(size_t)(v0 + w) * p.n + cs.id[j]] : -1;
+      m |= (d[w] >= 0 ? 1u : 0u) << w;
     }
-  } else {
-    for (int i = threadIdx.x; i < nprim * k3; i += blockDim.x) {
-      const int j = i / k3, o = i - j * k3;
-      lds[i] = g[(size_t)ids[j] * k3 + o];
+    const uint32_t cnt = (uint32_t)__popc(m);
+    uint32_t x = cnt;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+      if (j >= off) x += y;
     }
-  }
-}
-
-// The reverse: each listed primitive's k3 values written to (or, when
-// accumulate, added to) its place in g.
-__device__ __forceinline__ void copy_out_list(float* __restrict__ g, const float* __restrict__ lds,
-                                              const uint32_t* __restrict__ ids, int nprim, int k3, bool accumulate) {
-  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
-    const int per = k3 >> 2;
-    for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
-      const int j = i / per, o = i - j * per;
-      float4* dst = reinterpret_cast<float4*>(g + (size_t)ids[j] * k3) + o;
-      float4 v = reinterpret_cast<const float4*>(lds)[i];
-      if (accumulate) {
-        const float4 w = *dst;
-        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+    if (j == 63) cs.np = x;
+    uint32_t q = x - cnt;
+#pragma unroll
+    for (int w = 0; w < kColourGroup; ++w)
+      if ((m >> w) & 1u) {
+        cs.pd[q] = d[w];
+        cs.pjw[q] = (uint16_t)((j << 8) | w);
+        ++q;
       }
-      *dst = v;
-    }
-  } else {
-    for (int i = threadIdx.x; i < nprim * k3; i += blockDim.x) {
-      const int j = i / k3, o = i - j * k3;
-      float* dst = g + (size_t)ids[j] * k3 + o;
-      *dst = accumulate ? *dst + lds[i] : lds[i];
-    }
   }
+  __syncthreads();
+}
+
+// The backward colour kernel gives each listed primitive a quad; lane `sub`
+// owns the basis functions lm = 4 sub + i, i < 4, and their coefficients:
+// k[n][i][c] = g[(n nb + 4 sub + i) 3 + c] for Fourier term n < nt and
+// basis function 4 sub + i < nb (zero elsewhere), g the primitive's
+// [nt][nb][3] coefficients. At SH degree 3 (nb = 16) with g 16-byte aligned,
+// a lane's 12 floats per term are three 16-byte pieces and the quad reads
+// the term's 192 contiguous bytes together.
+__device__ __forceinline__ void load_own_coeffs(const float* __restrict__ g, int sub, int nb, int nt,
+                                                float (&k)[3][kBasisPerLane][3]) {
+  if (nb == 16 && (reinterpret_cast<uintptr_t>(g) & 15u) == 0) {
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+      if (n < nt) {
+        const float4* src = reinterpret_cast<const float4*>(g + n * 48 + 12 * sub);
+        q0 = src[0];
+        q1 = src[1];
+        q2 = src[2];
+      }
+      k[n][0][0] = q0.x; k[n][0][1] = q0.y; k[n][0][2] = q0.z; k[n][1][0] = q0.w;
+      k[n][1][1] = q1.x; k[n][1][2] = q1.y; k[n][2][0] = q1.z; k[n][2][1] = q1.w;
+      k[n][2][2] = q2.x; k[n][3][0] = q2.y; k[n][3][1] = q2.z; k[n][3][2] = q2.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+#pragma unroll
+    for (int i = 0; i < kBasisPerLane; ++i) {
+      const int lm = sub * kBasisPerLane + i;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) k[n][i][c] = (lm < nb && n < nt) ? g[(n * nb + lm) * 3 + c] : 0.f;
+    }
+}
+
+// The reverse for a lane's gradients: written to (or, when accumulate, added
+// to) their places in g.
+__device__ __forceinline__ void store_own_coeffs(float* __restrict__ g, int sub, int nb, int nt,
+                                                 const float (&k)[3][kBasisPerLane][3], bool accumulate) {
+  if (nb == 16 && (reinterpret_cast<uintptr_t>(g) & 15u) == 0) {
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      if (n >= nt) continue;
+      float4* dst = reinterpret_cast<float4*>(g + n * 48 + 12 * sub);
+      float4 q0 = make_float4(k[n][0][0], k[n][0][1], k[n][0][2], k[n][1][0]);
+      float4 q1 = make_float4(k[n][1][1], k[n][1][2], k[n][2][0], k[n][2][1]);
+      float4 q2 = make_float4(k[n][2][2], k[n][3][0], k[n][3][1], k[n][3][2]);
+      if (accumulate) {
+        const float4 o0 = dst[0], o1 = dst[1], o2 = dst[2];
+        q0.x += o0.x; q0.y += o0.y; q0.z += o0.z; q0.w += o0.w;
+        q1.x += o1.x; q1.y += o1.y; q1.z += o1.z; q1.w += o1.w;
+        q2.x += o2.x; q2.y += o2.y; q2.z += o2.z; q2.w += o2.w;
+      }
+      dst[0] = q0;
+      dst[1] = q1;
+      dst[2] = q2;
+    }
+    return;
+  }
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+#pragma unroll
+    for (int i = 0; i < kBasisPerLane; ++i) {
+      const int lm = sub * kBasisPerLane + i;
+      if (lm >= nb || n >= nt) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float* dst = g + (n * nb + lm) * 3 + c;
+        *dst = accumulate ? *dst + k[n][i][c] : k[n][i][c];
+      }
+    }
 }
 
 // Whether b holds on some lane of this lane's quad (all four lanes active).
 __device__ __forceinline__ bool quad_any(bool b) {
   const uint64_t m = __ballot(b);
   return ((m >> (threadIdx.x & 60u)) & 0xFull) != 0ull;
-}
-
-// Whether the primitive is active in some view of the batch (by its slots).
-__device__ __forceinline__ bool any_view_active(const RenderParams& p, const int32_t* __restrict__ slot, int gidx) {
-  bool any = false;
-  for (int v = 0; v < p.n_views; ++v) any |= slot[(size_t)v * p.n + gidx] >= 0;
-  return any;
-}
-
-// g[i] = lds[i] for the `nprim` primitives (k3 floats each), or g[i] +=
-// lds[i] when accumulate, skipping then the primitives whose flag in `on` is
-// clear (they add nothing).
-__device__ __forceinline__ void copy_out(float* __restrict__ g, const float* __restrict__ lds, int nprim, int k3,
-                                         bool accumulate, const uint8_t* __restrict__ on) {
-  const int count = nprim * k3;
-  if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0 && (k3 & 3) == 0) {
-    const int per = k3 >> 2;
-    for (int i = threadIdx.x; i < (count >> 2); i += blockDim.x) {
-      float4 v = reinterpret_cast<const float4*>(lds)[i];
-      if (accumulate) {
-        if (!on[i / per]) continue;
-        const float4 o = reinterpret_cast<const float4*>(g)[i];
-        v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
-      }
-      reinterpret_cast<float4*>(g)[i] = v;
-    }
-  } else {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) {
-      if (accumulate && !on[i / k3]) continue;
-      g[i] = accumulate ? g[i] + lds[i] : lds[i];
-    }
-  }
 }
 
 // y[i] = Y[4 sub + i] (selects with constant indices, no register indexing).

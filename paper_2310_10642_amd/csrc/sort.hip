@@ -295,10 +295,118 @@ __global__ void __launch_bounds__(1024) k_rs_rowscan(uint32_t* __restrict__ coun
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
-// Stable scatter of one digit pass. Within a 4096-element tile each wave owns
-// 1024 consecutive elements, processed 64 at a time; a lane's rank among equal
-// digits comes from a ballot match over the digit bits. The tile is reordered
-// by digit in LDS first, so the global writes of each digit run are contiguous.
+// LDS of the stable scatter of one digit pass.
+struct ScatterShared {
+  uint32_t k[kTileElems], v[kTileElems];  // the tile reordered by digit
+  uint32_t wcnt[4][256];                  // per wave and digit: count, then start
+  uint32_t run[256];                      // per digit: next output position of the block
+  uint32_t tstart[256];                   // per digit: start of its run in the reordered tile
+  uint32_t wave[4];
+};
+
+// Output positions of the block's digit runs: run[d] = (pairs of smaller
+// digits in the whole pass) + (pairs of digit d in earlier blocks), from the
+// per-(digit, block) exclusive scan `counts` and the digit totals.
+__device__ __forceinline__ void scatter_begin(ScatterShared& sh, const uint32_t* __restrict__ counts,
+                                              const uint32_t* __restrict__ digit_tot, uint32_t grid, uint32_t block) {
+  const uint32_t dg = threadIdx.x;
+  uint32_t tot;
+  const uint32_t base = block_exclusive_scan(digit_tot[dg], sh.wave, tot);
+  sh.run[dg] = base + counts[(size_t)dg * grid + block];
+}
+
+// Stable scatter of one tile of up to 4096 (key, value) pairs: wave w holds
+// pairs [1024 w, 1024 w + 1024) of the tile, 64 at a time, step i in k[i],
+// v[i]; the first nvalid pairs of the tile are valid. A lane's rank among
+// equal digits comes from a ballot match over the digit bits; the tile is
+// reordered by digit in LDS first, so the global writes of each digit run are
+// contiguous. Pairs go to run[d] + their rank among the block's pairs of
+// digit d so far (bounded by n_out); with ranges (the last pass over the
+// whole key) the keys are not written: each key's first and last position
+// bound its range instead.
+__device__ __forceinline__ void scatter_tile(ScatterShared& sh, const uint32_t (&k)[kItems],
+                                             const uint32_t (&v)[kItems], uint32_t nvalid, int shift, int bits,
+                                             uint32_t n_out, uint32_t* __restrict__ keys_out,
+                                             uint32_t* __restrict__ vals_out, uint2* __restrict__ ranges) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint32_t dg = threadIdx.x;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < 4; ++w) sh.wcnt[w][threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t base = (uint32_t)wave * (kTileElems / 4);
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = base + (uint32_t)i * 64 + lane < nvalid;
+    const uint32_t d = (k[i] >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    // digits have at most 8 bits; bits above `bits` are zero in every lane
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool set = (d >> b) & 1u;
+      const uint64_t m = __ballot(set);
+      peers &= set ? m : ~m;
+    }
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t pre = sh.wcnt[wave][d];
+    rank[i] = pre + below;
+    if (valid && below == 0) sh.wcnt[wave][d] = pre + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // per digit: tile-local start, then each wave's start inside it
+  const uint32_t c0 = sh.wcnt[0][dg], c1 = sh.wcnt[1][dg], c2 = sh.wcnt[2][dg], c3 = sh.wcnt[3][dg];
+  const uint32_t ctot = c0 + c1 + c2 + c3;
+  uint32_t all;
+  const uint32_t ts = block_exclusive_scan(ctot, sh.wave, all);  // contains barriers
+  sh.wcnt[0][dg] = ts;
+  sh.wcnt[1][dg] = ts + c0;
+  sh.wcnt[2][dg] = ts + c0 + c1;
+  sh.wcnt[3][dg] = ts + c0 + c1 + c2;
+  sh.tstart[dg] = ts;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = base + (uint32_t)i * 64 + lane < nvalid;
+    if (valid) {
+      const uint32_t d = (k[i] >> shift) & mask;
+      const uint32_t lp = sh.wcnt[wave][d] + rank[i];
+      if (lp < (uint32_t)kTileElems) {
+        sh.k[lp] = k[i];
+        sh.v[lp] = v[i];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t nt = min(nvalid, (uint32_t)kTileElems);
+#pragma unroll 4
+  for (int i = 0; i < kItems; ++i) {
+    const uint32_t lp = (uint32_t)i * kThreads + threadIdx.x;
+    if (lp < nt) {
+      const uint32_t key = sh.k[lp];
+      const uint32_t d = (key >> shift) & mask;
+      const uint32_t p = sh.run[d] + lp - sh.tstart[d];
+      if (p < n_out) {  // always true for consistent counts; keeps a ranking fault in bounds
+        if (ranges) {
+          // the staged tile is ordered by key, so the first and last of each
+          // key's run here bound its range
+          if (lp == 0 || sh.k[lp - 1] != key) atomicMin(&ranges[key].x, p);
+          if (lp + 1 == nt || sh.k[lp + 1] != key) atomicMax(&ranges[key].y, p + 1);
+        } else {
+          keys_out[p] = key;
+        }
+        vals_out[p] = sh.v[lp];
+      }
+    }
+  }
+  __syncthreads();
+  sh.run[dg] += ctot;
+}
+
+// One digit pass over the pairs in memory: each block takes its range of
+// 4096-pair tiles in turn.
 __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in,
                                                             uint32_t* __restrict__ keys_out,
@@ -307,102 +415,23 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
                                                             const uint32_t* __restrict__ counts,
                                                             const uint32_t* __restrict__ digit_tot,
                                                             uint2* __restrict__ ranges) {
-  __shared__ uint32_t s_k[kTileElems], s_v[kTileElems];
-  __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t tstart[256];
-  __shared__ uint32_t s_wave[4];
+  __shared__ ScatterShared sh;
   const uint32_t n = dev_n(n_dev, n_max);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t mask = (1u << bits) - 1u;
-  const uint32_t dg = threadIdx.x;
-  {
-    uint32_t tot;
-    const uint32_t base = block_exclusive_scan(digit_tot[dg], s_wave, tot);
-    run[dg] = base + counts[(size_t)dg * gridDim.x + sort_block()];
-  }
+  scatter_begin(sh, counts, digit_tot, gridDim.x, sort_block());
   uint32_t t0, t1;
   block_range(n, gridDim.x, t0, t1);
   for (uint32_t t = t0; t < t1; ++t) {
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0u;
-    __syncthreads();
     const size_t base = (size_t)t * kTileElems + (size_t)wave * (kTileElems / 4);
-    uint32_t k[kItems], v[kItems], rank[kItems];
+    uint32_t k[kItems], v[kItems];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const size_t idx = base + (size_t)i * 64 + lane;
       k[i] = (idx < n) ? keys_in[idx] : 0u;
       v[i] = (idx < n) ? vals_in[idx] : 0u;
     }
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const bool valid = base + (size_t)i * 64 + lane < n;
-      const uint32_t d = (k[i] >> shift) & mask;
-      uint64_t peers = __ballot(valid);
-      // digits have at most 8 bits; bits above `bits` are zero in every lane
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool set = (d >> b) & 1u;
-        const uint64_t m = __ballot(set);
-        peers &= set ? m : ~m;
-      }
-      const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
-      const uint32_t pre = wcnt[wave][d];
-      rank[i] = pre + below;
-      if (valid && below == 0) wcnt[wave][d] = pre + (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    // per digit: tile-local start, then each wave's start inside it
-    const uint32_t c0 = wcnt[0][dg], c1 = wcnt[1][dg], c2 = wcnt[2][dg], c3 = wcnt[3][dg];
-    const uint32_t ctot = c0 + c1 + c2 + c3;
-    uint32_t all;
-    const uint32_t ts = block_exclusive_scan(ctot, s_wave, all);  // contains barriers
-    wcnt[0][dg] = ts;
-    wcnt[1][dg] = ts + c0;
-    wcnt[2][dg] = ts + c0 + c1;
-    wcnt[3][dg] = ts + c0 + c1 + c2;
-    tstart[dg] = ts;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const bool valid = base + (size_t)i * 64 + lane < n;
-      if (valid) {
-        const uint32_t d = (k[i] >> shift) & mask;
-        const uint32_t lp = wcnt[wave][d] + rank[i];
-        if (lp < (uint32_t)kTileElems) {
-          s_k[lp] = k[i];
-          s_v[lp] = v[i];
-        }
-      }
-    }
-    __syncthreads();
-    const size_t tbase = (size_t)t * kTileElems;
-    const uint32_t nvalid = (uint32_t)min((size_t)kTileElems, (size_t)n - tbase);
-#pragma unroll 4
-    for (int i = 0; i < kItems; ++i) {
-      const uint32_t lp = (uint32_t)i * kThreads + threadIdx.x;
-      if (lp < nvalid) {
-        const uint32_t key = s_k[lp];
-        const uint32_t d = (key >> shift) & mask;
-        const uint32_t p = run[d] + lp - tstart[d];
-        if (p < n) {  // always true for consistent counts; keeps a ranking fault in bounds
-          if (ranges) {
-            // last pass over the whole key: the staged tile is ordered by key,
-            // so the first and last of each key's run here bound its range
-            if (lp == 0 || s_k[lp - 1] != key) atomicMin(&ranges[key].x, p);
-            if (lp + 1 == nvalid || s_k[lp + 1] != key) atomicMax(&ranges[key].y, p + 1);
-          } else {
-            keys_out[p] = key;
-          }
-          vals_out[p] = s_v[lp];
-        }
-      }
-    }
-    __syncthreads();
-    run[dg] += ctot;
+    const uint32_t nvalid = (uint32_t)min((size_t)kTileElems, (size_t)n - (size_t)t * kTileElems);
+    scatter_tile(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
   }
 }
 

@@ -23,7 +23,7 @@ G4D_TUNE_SYNC_FREE, G4D_TUNE_ARENA_INSTANCES, G4D_TUNE_TILE_ORDER, G4D_TUNE_AUTO
 G4D_TUNE_ELLIPSE_CULL = 9
 G4D_GRAD_ACCUMULATE = 1
 G4D_LOSS_L1, G4D_LOSS_L2 = 1, 2
-STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss"]
+STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss", "colour"]
 DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_last=7, grad2d=8)
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
