@@ -278,16 +278,37 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *                          (slower, same images; for checking that the
  *                          ellipse tests are conservative). Changing it
  *                          invalidates the state kept for render_backward.
+ *   G4D_TUNE_PERSISTENT_BLOCKS  0 (default): one rasteriser workgroup per
+ *                          tile, dispatched in the tile order; -1: as many
+ *                          workgroups as stay resident on the device, each
+ *                          taking the next tile (in the tile order) from a
+ *                          device counter until none is left; N > 0: N such
+ *                          workgroups. Results are identical.
+ *   G4D_TUNE_LDS_BATCH     list entries the forward rasteriser stages in
+ *                          LDS at a time: 64, 128 or 256 (default). Results
+ *                          are identical.
  *   G4D_TUNE_AUTOTUNE      1: the next render that is not being captured
- *                          first renders its batch under every combination
- *                          of G4D_TUNE_SORT_BLOCKS in {256, 512, 1024, 2048}
- *                          and G4D_TUNE_TILE_ORDER in {0, 1} (once, then
- *                          twice timed with HIP events), keeps the fastest,
- *                          then renders normally. One-shot.              */
+ *                          first times its batch (once, then twice with HIP
+ *                          events per candidate) under, in turn,
+ *                          G4D_TUNE_SORT_BLOCKS in {256, 512, 1024, 2048},
+ *                          G4D_TUNE_TILE_ORDER x G4D_TUNE_PERSISTENT_BLOCKS
+ *                          in {0, 1} x {0, -1}, and G4D_TUNE_LDS_BATCH in
+ *                          {64, 128, 256}, keeping the fastest of each group
+ *                          before the next, then renders normally. One-shot.
+ *
+ * The rasteriser knobs of a (lds_batch, split_threshold, persistent_blocks)
+ * tuning call map to these keys: lds_batch -> G4D_TUNE_LDS_BATCH (the
+ * backward stages 16 entries at a time, fixed by its 16-primitive x
+ * 16-column second phase); persistent_blocks -> G4D_TUNE_PERSISTENT_BLOCKS;
+ * split_threshold has no key: heavy tiles are not split. A wave owns an 8x8
+ * quarter of its tile, so a split would not shorten its longest walk, and
+ * with the tiles taken heaviest first the launch does not end on one heavy
+ * tile (the heaviest carries at most an eighth of a resident workgroup's
+ * share of the work on the workloads measured).                          */
 enum {
   G4D_TUNE_SORT_BLOCKS = 1, G4D_TUNE_STAGE_TIMING = 2, G4D_TUNE_ROUND_PAIRS = 3, G4D_TUNE_ROUND_INSTANCES = 4,
   G4D_TUNE_SYNC_FREE = 5, G4D_TUNE_ARENA_INSTANCES = 6, G4D_TUNE_TILE_ORDER = 7, G4D_TUNE_AUTOTUNE = 8,
-  G4D_TUNE_ELLIPSE_CULL = 9
+  G4D_TUNE_ELLIPSE_CULL = 9, G4D_TUNE_PERSISTENT_BLOCKS = 10, G4D_TUNE_LDS_BATCH = 11
 };
 g4d_status g4d_set_tuning(g4d_ctx* ctx, int32_t key, int32_t value);
 /* Current value of a tuning key (G4D_TUNE_ARENA_INSTANCES: the arena's

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -62,6 +63,8 @@ struct g4d_ctx {
   bool sync_free = false;          // no host read of device counts inside render/backward
   bool totals_on_device = false;   // the last render was sync-free: its totals are device counters
   bool heavy_first = true;         // rasterise tiles by decreasing list length
+  int persistent_blocks = 0;       // rasteriser workgroups taking tiles from a queue (0: one per tile)
+  int lds_batch = 256;             // forward rasteriser: list entries staged in LDS at a time
   bool ellipse_cull = true;        // bin and walk by the alpha-floor ellipse, not its rectangle
   bool autotune_pending = false;   // the next uncaptured render tunes the knobs first
   bool flow_mode = false;          // the render in progress blends flow (Sec. 4.4), not colour
@@ -106,6 +109,7 @@ constexpr int kCntTot = kCntViews + kMaxViews;
 constexpr int kCntNF = kCntTot + 4;
 // then the length of the round's list of primitives active in some view
 constexpr int kCntPList = kCntNF + kMaxViews;
+constexpr int kCntQueue = kCntPList + 1;  // the rasterisers' tile queue head
 constexpr int kCntWords = kCntPList + 4;
 constexpr uint32_t kOnDevice = 0xFFFFFFFFu;  // a round count known only on the device
 // Tiles per round (unless one view alone has more): tile ids then fit 16
@@ -525,7 +529,9 @@ g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, 
   // 9. rasterise the round's views into their places in the outputs
   stage_begin(c);
   static const float kZero3[3] = {0.f, 0.f, 0.f};
-  launch_raster_forward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, r.v1 - r.v0,
+  launch_raster_forward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr,
+                        c->persistent_blocks ? P<uint32_t>(c->counters) + kCntQueue : nullptr, c->persistent_blocks,
+                        c->lds_batch, r.v1 - r.v0,
                         P<ViewDev>(c->views_d), P<uint2>(c->ranges), P<uint32_t>(c->ival), P<Record>(c->rec_sorted),
                         c->flow_mode ? kZero3 : c->opts.bg, c->flow_mode ? 2 : 3, c->ellipse_cull, out_rgb,
                         out_depth, out_alpha,
@@ -556,9 +562,12 @@ void render_bufs(g4d_ctx* c, DevBuf** b) {
   for (int i = 0; i < kNABufs; ++i) b[i] = l[i];
 }
 
-// Times the render of this batch under every combination of the knobs that
-// do not change results (radix-sort workgroups, tile order) and keeps the
-// fastest. Each candidate renders once to size its scratch, then twice timed.
+// Times the render of this batch under the knobs that do not change results
+// and keeps the fastest, one knob group at a time with the others at their
+// best so far: radix-sort workgroups; tile order x persistent rasteriser
+// (queue of resident workgroups or one workgroup per tile); the forward
+// rasteriser's LDS batch. Each candidate renders once to size its scratch,
+// then twice timed.
 g4d_status autotune(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const float* times, float* rgb, float* dep,
                     float* alp) {
   const bool timing = c->timing;
@@ -566,36 +575,50 @@ g4d_status autotune(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const f
   hipEvent_t e0 = nullptr, e1 = nullptr;
   g4d_status st = check_hip(c, hipEventCreate(&e0), "hipEventCreate");
   if (!st) st = check_hip(c, hipEventCreate(&e1), "hipEventCreate");
-  const int blocks[] = {256, 512, 1024, 2048};
+  // time the render with the knobs as set
+  const auto time_it = [&](float& ms) -> g4d_status {
+    g4d_status s2;
+    if ((s2 = g4d_render(c, n_views, cams, times, rgb, dep, alp))) return s2;
+    if ((s2 = check_hip(c, hipEventRecord(e0, c->stream), "hipEventRecord"))) return s2;
+    for (int k = 0; k < 2; ++k)
+      if ((s2 = g4d_render(c, n_views, cams, times, rgb, dep, alp))) return s2;
+    if ((s2 = check_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord"))) return s2;
+    if ((s2 = check_hip(c, hipEventSynchronize(e1), "hipEventSynchronize"))) return s2;
+    return check_hip(c, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  };
   float best = 0.f;
-  int best_blocks = c->sort_blocks;
-  bool best_order = c->heavy_first;
   bool first = true;
-  for (int order = 0; order < 2 && !st; ++order) {
-    for (int b : blocks) {
-      c->sort_blocks = b;
-      c->heavy_first = order == 1;
-      if ((st = g4d_render(c, n_views, cams, times, rgb, dep, alp))) break;
-      if ((st = check_hip(c, hipEventRecord(e0, c->stream), "hipEventRecord"))) break;
-      for (int k = 0; k < 2 && !st; ++k) st = g4d_render(c, n_views, cams, times, rgb, dep, alp);
-      if (st) break;
-      if ((st = check_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord"))) break;
-      if ((st = check_hip(c, hipEventSynchronize(e1), "hipEventSynchronize"))) break;
+  // candidate -> knobs; keeps the fastest
+  const auto pick = [&](int n, const std::function<void(int)>& set) -> g4d_status {
+    int best_i = -1;
+    float best_here = 0.f;
+    for (int i = 0; i < n; ++i) {
+      set(i);
       float ms = 0.f;
-      if ((st = check_hip(c, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime"))) break;
-      if (first || ms < best) {
-        best = ms;
-        best_blocks = b;
-        best_order = order == 1;
-        first = false;
+      const g4d_status s2 = time_it(ms);
+      if (s2) return s2;
+      if (best_i < 0 || ms < best_here) {
+        best_here = ms;
+        best_i = i;
       }
     }
-  }
+    set(best_i);
+    if (first || best_here < best) best = best_here;
+    first = false;
+    return G4D_OK;
+  };
+  const int blocks[] = {256, 512, 1024, 2048};
+  const int batches[] = {64, 128, 256};
+  if (!st) st = pick(4, [&](int i) { c->sort_blocks = blocks[i]; });
+  if (!st)
+    st = pick(4, [&](int i) {
+      c->heavy_first = (i & 1) != 0;
+      c->persistent_blocks = (i & 2) ? -1 : 0;
+    });
+  if (!st) st = pick(3, [&](int i) { c->lds_batch = batches[i]; });
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   c->timing = timing;
-  c->sort_blocks = best_blocks;
-  c->heavy_first = best_order;
   return st;
 }
 
@@ -982,7 +1005,9 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     stage_end(c, G4D_STAGE_PREPROCESS_BWD);
     if ((st = join_side(c))) return st;  // the records' colours of a round binned again
     stage_begin(c);
-    launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr, nv, P<ViewDev>(c->views_d),
+    launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr,
+                           c->persistent_blocks ? cnt + kCntQueue : nullptr, c->persistent_blocks, nv,
+                           P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
                            P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
                            P<uint32_t>(c->pix_last), P<double>(c->grad2d), c->densify.blend_count != nullptr,
@@ -1169,6 +1194,16 @@ g4d_status g4d_set_tuning(g4d_ctx* c, int32_t key, int32_t value) {
     c->have_render = false;  // the last render's bins would come out otherwise
     return G4D_OK;
   }
+  if (key == G4D_TUNE_PERSISTENT_BLOCKS) {
+    if (value < -1) return fail(c, G4D_EINVAL, "persistent blocks is -1, 0 or a workgroup count");
+    c->persistent_blocks = value;
+    return G4D_OK;
+  }
+  if (key == G4D_TUNE_LDS_BATCH) {
+    if (value != 64 && value != 128 && value != 256) return fail(c, G4D_EINVAL, "LDS batch is 64, 128 or 256");
+    c->lds_batch = value;
+    return G4D_OK;
+  }
   if (key == G4D_TUNE_SYNC_FREE) {
     if (value != 0 && value != 1) return fail(c, G4D_EINVAL, "sync-free is 0 or 1");
     c->sync_free = value == 1;
@@ -1202,6 +1237,8 @@ g4d_status g4d_get_tuning(g4d_ctx* c, int32_t key, int32_t* value) {
     case G4D_TUNE_ARENA_INSTANCES: *value = clamp32((int64_t)arena_instances(c)); break;
     case G4D_TUNE_TILE_ORDER: *value = c->heavy_first ? 1 : 0; break;
     case G4D_TUNE_AUTOTUNE: *value = c->autotune_pending ? 1 : 0; break;
+    case G4D_TUNE_PERSISTENT_BLOCKS: *value = c->persistent_blocks; break;
+    case G4D_TUNE_LDS_BATCH: *value = c->lds_batch; break;
     default: return fail(c, G4D_EINVAL, "unknown tuning key");
   }
   return G4D_OK;

@@ -147,20 +147,23 @@ void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, co
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s);
 
 // ---- launchers (raster.hip) ----
-// order (nullable): the tile each workgroup takes, e.g. heaviest lists first.
+// order (nullable): the tiles in the order workgroups take them, e.g.
+// heaviest lists first. queue (nullable): a device counter; then `blocks`
+// workgroups (-1: as many as stay resident) take tiles from it in that order
+// until they run out (zeroed before the launch); otherwise one workgroup per
+// tile. batch (forward): list entries staged in LDS at a time, 64, 128 or 256.
 // channels: 3 (rgb planes) or 2 (the first two record colour values, e.g. flow).
 // cull: waves walk only the entries whose alpha-floor ellipse meets their
 // quadrant (false: every entry; same results).
-void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
-                           const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
-                           int channels, bool cull, float* out_rgb,
+void launch_raster_forward(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int batch,
+                           int n_views, const ViewDev* views, const uint2* ranges, const uint32_t* ival,
+                           const Record* rec_sorted, const float* bg, int channels, bool cull, float* out_rgb,
                            float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s);
-void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
-                            const uint2* ranges,
-                            const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
-                            const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, double* grad2d, bool mark_blended, bool cull,
-                            hipStream_t s);
+void launch_raster_backward(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int n_views,
+                            const ViewDev* views, const uint2* ranges, const uint32_t* ival,
+                            const Record* rec_sorted, const float* bg, const float* dl_rgb, const float* dl_depth,
+                            const float* dl_alpha, const float* pix_t, const uint32_t* pix_last, double* grad2d,
+                            bool mark_blended, bool cull, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
 // Tile ids by decreasing list length (stable within ~4.4 % length bins) into vals.

@@ -23,6 +23,7 @@
 // of ten lanes of a primitive's row with one value of its gradient line, and
 // those lanes add the tile's share with one FP64 atomic instruction into one
 // 128-byte line.
+#include <algorithm>
 #include <type_traits>
 
 #include "shade.h"
@@ -32,7 +33,6 @@ namespace {
 
 using shade::sc_fma;
 
-constexpr int kFwdBatch = 256;
 constexpr int kBwdBatch = 16;
 // Backward LDS slots of one primitive's per-pixel values: pixel (row, col) of
 // the tile sits at 16 row + (col ^ 8 [(row >> 1) & 1]); the x-halves of rows
@@ -170,9 +170,32 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return v;
 }
 
-// DEPTH: whether the depth plane is written (otherwise its sum is compiled out).
-template <bool DEPTH>
-__global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restrict__ order, int n_views,
+// Work items of a launch: tile order[i] (or i) for i < n_items. Without a
+// queue, workgroup b takes item b; with one, every workgroup of a grid sized
+// to stay resident takes items from the counter at *queue (zero at launch)
+// until they run out.
+__device__ __forceinline__ bool next_item(const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* queue,
+                                          uint32_t* s_item, bool first, int& tile) {
+  uint32_t item;
+  if (queue) {
+    __syncthreads();  // the previous item's LDS readers are done
+    if (threadIdx.x == 0) *s_item = atomicAdd(queue, 1u);
+    __syncthreads();
+    item = *s_item;
+  } else {
+    if (!first) return false;
+    item = blockIdx.x;
+  }
+  if (item >= n_items) return false;
+  tile = order ? (int)order[item] : (int)item;
+  return true;
+}
+
+// DEPTH: whether the depth plane is written (otherwise its sum is compiled
+// out). BATCH: list entries staged in LDS at a time (64, 128 or 256).
+template <bool DEPTH, int BATCH>
+__global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restrict__ order, uint32_t n_items,
+                                                         uint32_t* queue, int n_views,
                                                          const ViewDev* __restrict__ views,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ ival,
@@ -181,9 +204,11 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
                                                          float* __restrict__ out_rgb,
                                                          float* __restrict__ out_depth, float* __restrict__ out_alpha,
                                                          float* __restrict__ pix_t, uint32_t* __restrict__ pix_last) {
-  __shared__ float4 s_a[kFwdBatch], s_b[kFwdBatch], s_c[kFwdBatch];
-  __shared__ __align__(16) uint8_t s_mask[kFwdBatch];
-  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
+  __shared__ __align__(16) uint8_t s_mask[BATCH];
+  __shared__ uint32_t s_item;
+  int tile;
+  for (bool first = true; next_item(order, n_items, queue, &s_item, first, tile); first = false) {
   const int vi = find_view(views, n_views, tile);
   const ViewDev& vw = views[vi];
   const int lt = tile - vw.tile_base;
@@ -200,11 +225,11 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t last = 0;
   bool done = !inside;
-  for (int b0 = 0; b0 < count; b0 += kFwdBatch) {
+  for (int b0 = 0; b0 < count; b0 += BATCH) {
     if (__syncthreads_count(done) == 256) break;
     const int e = b0 + threadIdx.x;
     uint32_t mask = 0u;
-    if (e < count) {
+    if (threadIdx.x < BATCH && e < count) {
       const Record r = recs[ival[rg.x + e]];
       float4 sa, sb, sc;
       stage_record(r, sa, sb, sc);
@@ -218,12 +243,12 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
         mask = 0xFu;
       }
     }
-    s_mask[threadIdx.x] = (uint8_t)mask;
+    if (threadIdx.x < BATCH) s_mask[threadIdx.x] = (uint8_t)mask;
     __syncthreads();
     if (__all(done)) continue;
     // chunks of 16 entries: a wave-uniform mask of those that can touch this
     // wave's quadrant, walked with constant LDS offsets
-    const int nb = min(kFwdBatch, count - b0);
+    const int nb = min(BATCH, count - b0);
     for (int c0 = 0; c0 < nb; c0 += 16) {
       const uint32_t m = lane < 16 ? (uint32_t)s_mask[c0 + lane] : 0u;
       const uint32_t todo = (uint32_t)__ballot((m >> wave) & 1u);
@@ -261,18 +286,20 @@ __global__ void __launch_bounds__(256) k_raster_forward(const uint32_t* __restri
       if (__all(done)) break;
     }
   }
-  if (!inside) return;
-  const long long hw = (long long)vw.width * vw.height;
-  const long long pl = (long long)py * vw.width + px;
-  const long long pix = vw.pix_base + pl;
-  float* rgb = out_rgb + channels * vw.pix_base + pl;
-  rgb[0] = fmaf(T, bg0, C0);
-  rgb[hw] = fmaf(T, bg1, C1);
-  if (channels == 3) rgb[2 * hw] = fmaf(T, bg2, C2);
-  if (DEPTH) out_depth[pix] = D;
-  if (out_alpha) out_alpha[pix] = 1.f - T;
-  pix_t[pix] = T;
-  pix_last[pix] = last;
+  if (inside) {
+    const long long hw = (long long)vw.width * vw.height;
+    const long long pl = (long long)py * vw.width + px;
+    const long long pix = vw.pix_base + pl;
+    float* rgb = out_rgb + channels * vw.pix_base + pl;
+    rgb[0] = fmaf(T, bg0, C0);
+    rgb[hw] = fmaf(T, bg1, C1);
+    if (channels == 3) rgb[2 * hw] = fmaf(T, bg2, C2);
+    if (DEPTH) out_depth[pix] = D;
+    if (out_alpha) out_alpha[pix] = 1.f - T;
+    pix_t[pix] = T;
+    pix_last[pix] = last;
+  }
+  }  // items
 }
 
 // Whether a record's footprint is so elongated (condition number of its
@@ -355,7 +382,7 @@ __device__ __forceinline__ void phase2_line(G (&q)[10], bool live, int j2, int c
 // their terms are compiled out).
 template <bool HAS_D, bool HAS_A>
 __global__ void __launch_bounds__(256) k_raster_backward(
-    const uint32_t* __restrict__ order, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
+    const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* queue, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
     const uint32_t* __restrict__ pix_last, double* __restrict__ grad2d, bool mark_blended, bool cull) {
@@ -368,8 +395,10 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   __shared__ float s_w[kBwdBatch * kGwStride];   // a_i T_i per (primitive, pixel)
   __shared__ float4 s_pix[256];
   __shared__ uint32_t s_max;
+  __shared__ uint32_t s_item;
 
-  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  int tile;
+  for (bool first = true; next_item(order, n_items, queue, &s_item, first, tile); first = false) {
   const int vi = find_view(views, n_views, tile);
   const ViewDev& vw = views[vi];
   const int lt = tile - vw.tile_base;
@@ -557,37 +586,94 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     if (live && slot_q >= 0 && val != 0.0)
       unsafeAtomicAdd(grad2d + (size_t)d_atom * kGrad2dStride + slot_q, val);
   }
+  }  // items
+}
+
+// Workgroups of `kernel` that stay resident on the current device (looked
+// up once per kernel and device).
+template <typename K>
+unsigned resident_grid(K kernel) {
+  constexpr int kDevs = 64;
+  static unsigned cached[kDevs] = {};
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (dev >= 0 && dev < kDevs && cached[dev]) return cached[dev];
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1 || cus < 1)
+    return 1024;
+  const unsigned g = (unsigned)(per_cu * cus);
+  if (dev >= 0 && dev < kDevs) cached[dev] = g;
+  return g;
+}
+
+// Grid of a launch over total_tiles items: one workgroup per item, or with
+// a queue, `blocks` workgroups (-1: as many as stay resident).
+template <typename K>
+unsigned item_grid(K kernel, int total_tiles, uint32_t* queue, int blocks, hipStream_t s) {
+  unsigned grid = (unsigned)total_tiles;
+  if (queue) {
+    const unsigned want = blocks > 0 ? (unsigned)blocks : resident_grid(kernel);
+    grid = std::min(grid, want);
+    launch_fill_u32(queue, 1, 0u, s);
+  }
+  return grid;
+}
+
+template <bool DEPTH, int BATCH>
+void launch_fwd(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int n_views,
+                const ViewDev* views, const uint2* ranges, const uint32_t* ival, const Record* rec_sorted,
+                const float* bg, int channels, bool cull, float* out_rgb, float* out_depth, float* out_alpha,
+                float* pix_t, uint32_t* pix_last, hipStream_t s) {
+  const unsigned grid = item_grid(k_raster_forward<DEPTH, BATCH>, total_tiles, queue, blocks, s);
+  hipLaunchKernelGGL((k_raster_forward<DEPTH, BATCH>), dim3(grid), dim3(256), 0, s, order, (uint32_t)total_tiles,
+                     queue, n_views, views, ranges, ival, rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb,
+                     out_depth, out_alpha, pix_t, pix_last);
 }
 
 }  // namespace
 
-void launch_raster_forward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
-                           const uint2* ranges, const uint32_t* ival, const Record* rec_sorted, const float* bg,
-                           int channels, bool cull, float* out_rgb, float* out_depth, float* out_alpha,
-                           float* pix_t, uint32_t* pix_last, hipStream_t s) {
+void launch_raster_forward(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int batch,
+                           int n_views, const ViewDev* views, const uint2* ranges, const uint32_t* ival,
+                           const Record* rec_sorted, const float* bg, int channels, bool cull, float* out_rgb,
+                           float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s) {
   if (total_tiles == 0) return;
-  if (out_depth)
-    hipLaunchKernelGGL(k_raster_forward<true>, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges,
-                       ival, rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb, out_depth, out_alpha, pix_t,
-                       pix_last);
-  else
-    hipLaunchKernelGGL(k_raster_forward<false>, dim3(total_tiles), dim3(256), 0, s, order, n_views, views, ranges,
-                       ival, rec_sorted, bg[0], bg[1], bg[2], channels, cull, out_rgb, out_depth, out_alpha, pix_t,
-                       pix_last);
+#define G4D_FWD(D, B)                                                                                            \
+  launch_fwd<D, B>(total_tiles, order, queue, blocks, n_views, views, ranges, ival, rec_sorted, bg, channels, cull, \
+                   out_rgb, out_depth, out_alpha, pix_t, pix_last, s)
+  const bool d = out_depth != nullptr;
+  if (batch == 64) {
+    if (d) G4D_FWD(true, 64); else G4D_FWD(false, 64);
+  } else if (batch == 128) {
+    if (d) G4D_FWD(true, 128); else G4D_FWD(false, 128);
+  } else {
+    if (d) G4D_FWD(true, 256); else G4D_FWD(false, 256);
+  }
+#undef G4D_FWD
 }
 
-void launch_raster_backward(int total_tiles, const uint32_t* order, int n_views, const ViewDev* views,
-                            const uint2* ranges,
-                            const uint32_t* ival, const Record* rec_sorted, const float* bg, const float* dl_rgb,
-                            const float* dl_depth, const float* dl_alpha, const float* pix_t,
-                            const uint32_t* pix_last, double* grad2d, bool mark_blended, bool cull,
-                            hipStream_t s) {
+namespace {
+template <bool HD, bool HA>
+void launch_bwd(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int n_views,
+                const ViewDev* views, const uint2* ranges, const uint32_t* ival, const Record* rec_sorted,
+                const float* bg, const float* dl_rgb, const float* dl_depth, const float* dl_alpha,
+                const float* pix_t, const uint32_t* pix_last, double* grad2d, bool mark_blended, bool cull,
+                hipStream_t s) {
+  const unsigned grid = item_grid(k_raster_backward<HD, HA>, total_tiles, queue, blocks, s);
+  hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(grid), dim3(256), 0, s, order, (uint32_t)total_tiles, queue,
+                     n_views, views, ranges, ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t,
+                     pix_last, grad2d, mark_blended, cull);
+}
+}  // namespace
+
+void launch_raster_backward(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int n_views,
+                            const ViewDev* views, const uint2* ranges, const uint32_t* ival,
+                            const Record* rec_sorted, const float* bg, const float* dl_rgb, const float* dl_depth,
+                            const float* dl_alpha, const float* pix_t, const uint32_t* pix_last, double* grad2d,
+                            bool mark_blended, bool cull, hipStream_t s) {
   if (total_tiles == 0) return;
 #define G4D_BWD(HD, HA)                                                                                          \
-  hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(total_tiles), dim3(256), 0, s, order, n_views, views,     \
-                     ranges,                                                                                      \
-                     ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t, pix_last, grad2d,      \
-                     mark_blended, cull)
+  launch_bwd<HD, HA>(total_tiles, order, queue, blocks, n_views, views, ranges, ival, rec_sorted, bg, dl_rgb,      \
+                     dl_depth, dl_alpha, pix_t, pix_last, grad2d, mark_blended, cull, s)
   if (dl_depth && dl_alpha) G4D_BWD(true, true);
   else if (dl_depth) G4D_BWD(true, false);
   else if (dl_alpha) G4D_BWD(false, true);

@@ -20,7 +20,7 @@ G4D_OK, G4D_EINVAL, G4D_ENOMEM, G4D_EHIP, G4D_ESTATE, G4D_ECAPACITY = 0, -1, -2,
 G4D_TUNE_SORT_BLOCKS, G4D_TUNE_STAGE_TIMING = 1, 2
 G4D_TUNE_ROUND_PAIRS, G4D_TUNE_ROUND_INSTANCES = 3, 4
 G4D_TUNE_SYNC_FREE, G4D_TUNE_ARENA_INSTANCES, G4D_TUNE_TILE_ORDER, G4D_TUNE_AUTOTUNE = 5, 6, 7, 8
-G4D_TUNE_ELLIPSE_CULL = 9
+G4D_TUNE_ELLIPSE_CULL, G4D_TUNE_PERSISTENT_BLOCKS, G4D_TUNE_LDS_BATCH = 9, 10, 11
 G4D_GRAD_ACCUMULATE = 1
 G4D_LOSS_L1, G4D_LOSS_L2 = 1, 2
 STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss", "colour"]

@@ -45,6 +45,8 @@ def test_header_constants_match_binding():
     assert val("G4D_TUNE_TILE_ORDER") == g4d.G4D_TUNE_TILE_ORDER
     assert val("G4D_TUNE_AUTOTUNE") == g4d.G4D_TUNE_AUTOTUNE
     assert val("G4D_TUNE_ELLIPSE_CULL") == g4d.G4D_TUNE_ELLIPSE_CULL
+    assert val("G4D_TUNE_PERSISTENT_BLOCKS") == g4d.G4D_TUNE_PERSISTENT_BLOCKS
+    assert val("G4D_TUNE_LDS_BATCH") == g4d.G4D_TUNE_LDS_BATCH
     assert val("G4D_NUM_STAGES") == len(g4d.STAGES)
     for k, v in g4d.DBG.items():
         assert val("G4D_DBG_" + k.upper()) == v

@@ -845,8 +845,10 @@ def test_densify_stats_parity():
 
 
 def test_tile_order_and_autotune():
-    """Heavy-first tile order and the autotuner's knobs change no result:
-    images bit for bit, gradients up to the order of the atomic sums."""
+    """Heavy-first tile order, the rasterisers' tile queue (resident or a
+    given number of workgroups), the forward's LDS batch and the
+    autotuner's choice among them change no result: images bit for bit,
+    gradients up to the order of the atomic sums."""
     _say("[tile order and autotune, 300k x 2 views]")
     from paper_2310_10642_amd import g4d
     wl = scenegen.bench_workload(2)
@@ -863,13 +865,26 @@ def test_tile_order_and_autotune():
     for a, b in zip(ref, out):
         assert torch.equal(a, b)
     _close_grads(r.backward(dl), g_ref)
+    for key, val in ((g4d.G4D_TUNE_PERSISTENT_BLOCKS, -1), (g4d.G4D_TUNE_PERSISTENT_BLOCKS, 37),
+                     (g4d.G4D_TUNE_LDS_BATCH, 64), (g4d.G4D_TUNE_LDS_BATCH, 128)):
+        r.set_tuning(key, val)
+        assert r.get_tuning(key) == val
+        out = r.render(wl.cameras, times)
+        for a, b in zip(ref, out):
+            assert torch.equal(a, b), (key, val)
+        _close_grads(r.backward(dl), g_ref)
+    r.set_tuning(g4d.G4D_TUNE_PERSISTENT_BLOCKS, 0)
+    r.set_tuning(g4d.G4D_TUNE_LDS_BATCH, 256)
+    with pytest.raises(g4d.G4DError):
+        r.set_tuning(g4d.G4D_TUNE_LDS_BATCH, 100)
     r.set_tuning(g4d.G4D_TUNE_AUTOTUNE, 1)
     assert r.get_tuning(g4d.G4D_TUNE_AUTOTUNE) == 1
     out = r.render(wl.cameras, times)
     assert r.get_tuning(g4d.G4D_TUNE_AUTOTUNE) == 0
     blocks, order = r.get_tuning(g4d.G4D_TUNE_SORT_BLOCKS), r.get_tuning(g4d.G4D_TUNE_TILE_ORDER)
-    _say(f"  autotune chose sort blocks {blocks}, tile order {order}")
-    assert blocks in (256, 512, 1024, 2048) and order in (0, 1)
+    pers, batch = r.get_tuning(g4d.G4D_TUNE_PERSISTENT_BLOCKS), r.get_tuning(g4d.G4D_TUNE_LDS_BATCH)
+    _say(f"  autotune chose sort blocks {blocks}, tile order {order}, persistent {pers}, LDS batch {batch}")
+    assert blocks in (256, 512, 1024, 2048) and order in (0, 1) and pers in (0, -1) and batch in (64, 128, 256)
     for a, b in zip(ref, out):
         assert torch.equal(a, b)
     _close_grads(r.backward(dl), g_ref)
