@@ -329,7 +329,35 @@ __device__ __forceinline__ void colour_stage(ColourStage& cs, const RenderParams
   }
   __syncthreads();
   const bool vec = (K3 & 3) == 0 && (reinterpret_cast<uintptr_t>(p.coeffs) & 15u) == 0;
-  if (vec) {
+  if (vec && blockDim.x == 256) {
+    // every 16-byte piece of the block's coefficients loaded before any is
+    // stored, so the block waits for memory once
+    constexpr int kIters = (kColourPrims * kCoeffMax / 4 + 255) / 256;
+    const int per = K3 >> 2, total = nprim * per;
+    float4 q[kIters];
+    int jo[kIters];
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+      const int i = (int)threadIdx.x + 256 * it;
+      jo[it] = -1;
+      if (i < total) {
+        const int j = i / per, o = i - j * per;
+        jo[it] = j * kKStride + 4 * o;
+        q[it] = reinterpret_cast<const float4*>(p.coeffs + (size_t)cs.id[j] * K3)[o];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+      if (jo[it] < 0) continue;
+      float* dst = cs.k + jo[it];
+      dst[0] = q[it].x;
+      dst[1] = q[it].y;
+      dst[2] = q[it].z;
+      dst[3] = q[it].w;
+      if (!(isfinite(q[it].x) && isfinite(q[it].y) && isfinite(q[it].z) && isfinite(q[it].w)))
+        atomicOr(&cs.bad[jo[it] / kKStride], 1u);
+    }
+  } else if (vec) {
     const int per = K3 >> 2;
     for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
       const int j = i / per, o = i - j * per;
