@@ -70,30 +70,46 @@ def cpu_oracle_baseline(wl, seconds: float):
         loss.backward()
         return time.perf_counter() - t0
 
-    # samples of 4, 8, 16, ... tiles until the next one would overrun `seconds`;
-    # the last two fix the per-tile slope and the fixed cost
-    ks, ts = [], []
-    k = 4
-    while True:
-        ks.append(k)
-        ts.append(run(k))
-        if k >= n_tiles or (len(ks) >= 2 and sum(ts) + 2.2 * ts[-1] > seconds):
-            break
-        k = min(2 * k, n_tiles)
-    if len(ks) == 1:  # the sample was the whole view
-        b, a = ts[0] / ks[0], 0.0
-    else:
-        b = max((ts[-1] - ts[-2]) / (ks[-1] - ks[-2]), 1e-9)
-        a = max(ts[-1] - b * ks[-1], 0.0)
-    full = a + b * n_tiles
+    def fit(budget):
+        # samples of 4, 8, 16, ... tiles until the next one would overrun the
+        # budget; the last two fix the per-tile slope and the fixed cost
+        ks, ts = [], []
+        k = 4
+        while True:
+            ks.append(k)
+            ts.append(run(k))
+            if k >= n_tiles or (len(ks) >= 2 and sum(ts) + 2.2 * ts[-1] > budget):
+                break
+            k = min(2 * k, n_tiles)
+        if len(ks) == 1:  # the sample was the whole view
+            b, a = ts[0] / ks[0], 0.0
+        else:
+            b = max((ts[-1] - ts[-2]) / (ks[-1] - ks[-2]), 1e-9)
+            a = max(ts[-1] - b * ks[-1], 0.0)
+        return ks, ts, a, b
+
     px = cam.width * cam.height
+    threads = int(torch.get_num_threads())
+    ks, ts, a, b = fit(seconds)
+    full = a + b * n_tiles
+    # the same oracle on one thread, over a smaller sample
+    torch.set_num_threads(1)
+    try:
+        ks1, ts1, a1, b1 = fit(seconds / 2)
+    finally:
+        torch.set_num_threads(threads)
+    full1 = a1 + b1 * n_tiles
     return dict(value=px / full / 1e6, unit="Mpix/s (fwd+bwd, one view, extrapolated)",
-                cores=int(torch.get_num_threads()), kind="oracle",
+                cores=threads, kind="oracle",
                 sample=(f"1 of {len(wl.cameras)} views at {cam.width}x{cam.height}, {wl.scene.n} primitives: "
                         f"FP64 preprocess of all primitives + fwd/bwd of random 16x16 tiles, samples of "
                         f"{ks} tiles took {[round(x, 2) for x in ts]} s; full view = {a:.2f}s + {b:.4f}s x "
                         f"{n_tiles} tiles"),
-                seconds=round(sum(ts), 2))
+                seconds=round(sum(ts), 2),
+                value_1_thread=px / full1 / 1e6,
+                sample_1_thread=(f"samples of {ks1} tiles took {[round(x, 2) for x in ts1]} s on one thread; "
+                                 f"full view = {a1:.2f}s + {b1:.4f}s x {n_tiles} tiles"),
+                seconds_1_thread=round(sum(ts1), 2))
 
 
 def other_workloads(log_fn, steps: int, cfgs=(2, 3, 4)):

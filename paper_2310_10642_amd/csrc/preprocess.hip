@@ -157,62 +157,102 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, int lanes, u
   }
 }
 
-// 4D spherindrical-harmonic colour (Sec. 3.2) of every active (view,
-// primitive) pair, a thread per pair: the block stages the coefficients of
-// 64 primitives of the active list in LDS and lists their active pairs four
-// views at a time, and each pair's thread evaluates the SH basis in its view
-// direction and the Fourier terms of t - mu_t and contracts them with the
-// coefficients: c = max(0, 0.5 + sum_n cos_n sum_lm Y_lm k[n][lm]). A
-// primitive with a non-finite coefficient gets a NaN colour, which the
-// rasterisers read as fully transparent (and the pair is counted as culled).
+constexpr int kColourViews = 8;  // views whose slots k_colour loads together
+
+// 4D spherindrical-harmonic colour (Sec. 3.2) of the primitives active in
+// some view (the list the preprocess built): a quad of lanes per listed
+// primitive, lane `sub` owning the basis functions lm = 4 sub + i and reading
+// their coefficients straight from memory (the quad reads the primitive's
+// 192-byte Fourier terms together). Each quad walks only its own active
+// views, the k-th in round k (a wave takes as many rounds as its busiest
+// primitive has active views), with the next view's direction loaded while
+// the current one is evaluated. Per view every lane evaluates the basis,
+// weights its four functions by the Fourier terms, and a quad sum gives
+// c = max(0, 0.5 + sum). A primitive with a non-finite coefficient gets a
+// NaN colour, which the rasterisers read as fully transparent (and the pair
+// is counted as culled).
 __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                 const float4* __restrict__ cdir, Record* __restrict__ rec_sorted) {
-  __shared__ ColourStage cs;
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
   const uint32_t count = *p.plist_n;
-  for (uint32_t c0 = blockIdx.x * kColourPrims; c0 < count; c0 += gridDim.x * kColourPrims) {
-    const int nprim = (int)min((uint32_t)kColourPrims, count - c0);
-    colour_stage(cs, p, c0, nprim, K3);
-    for (int v0 = 0; v0 < p.n_views; v0 += kColourGroup) {
-      colour_pairs(cs, p, slot, nprim, v0);
-      for (uint32_t q = threadIdx.x; q < cs.np; q += blockDim.x) {
-        const int d = cs.pd[q];
-        const int j = cs.pjw[q] >> 8, v = v0 + (cs.pjw[q] & 0xFF);
+  const int sub = threadIdx.x & 3;
+  const uint32_t stride = (gridDim.x * blockDim.x) >> 2;
+  for (uint32_t e0 = ((blockIdx.x * blockDim.x) >> 2); e0 < count; e0 += stride) {
+    const uint32_t e = e0 + (threadIdx.x >> 2);
+    const bool live = e < count;  // uniform per quad
+    const int gidx = live ? (int)p.plist[e] : 0;
+    float k[3][kBasisPerLane][3];
+    if (live) load_own_coeffs(p.coeffs + (size_t)gidx * K3, sub, nb, nt, k);
+    bool finite = true;
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+      for (int i = 0; i < kBasisPerLane; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (!live) k[n][i][c] = 0.f;
+          finite = finite && isfinite(k[n][i][c]);
+        }
+    const bool bad = quad_any(!finite);
+    for (int v0 = 0; v0 < p.n_views; v0 += kColourViews) {
+      int ds[kColourViews];
+      uint32_t m = 0u;
+#pragma unroll
+      for (int w = 0; w < kColourViews; ++w) {
+        ds[w] = (live && v0 + w < p.n_views) ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
+        m |= (ds[w] >= 0 ? 1u : 0u) << w;
+      }
+      uint32_t rounds = (uint32_t)__popc(m);
+#pragma unroll
+      for (int off = 4; off < 64; off <<= 1) rounds = max(rounds, (uint32_t)__shfl_xor((int)rounds, off, 64));
+      // the quad's next active view, its record slot and its direction (in flight)
+      int w = m ? __ffs(m) - 1 : -1;
+      m = m ? m & (m - 1u) : 0u;
+      float4 cd = w >= 0 ? cdir[(size_t)(v0 + w) * p.n + gidx] : make_float4(0.f, 0.f, 1.f, 0.f);
+      for (uint32_t r = 0; r < rounds; ++r) {
+        const int wc = w;
+        const float4 cdc = cd;
+        w = m ? __ffs(m) - 1 : -1;
+        m = m ? m & (m - 1u) : 0u;
+        if (w >= 0) cd = cdir[(size_t)(v0 + w) * p.n + gidx];
+        if (wc < 0) continue;  // uniform per quad
+        int d = -1;
+#pragma unroll
+        for (int ww = 0; ww < kColourViews; ++ww) d = (ww == wc) ? ds[ww] : d;
         float* o = reinterpret_cast<float*>(&rec_sorted[d].c);
-        if (cs.bad[j]) {
-          const float nan = __int_as_float(0x7FC00000);
-          o[0] = nan;
-          o[1] = nan;
-          o[2] = nan;
-          if (p.nonfinite) atomicAdd(p.nonfinite + v, 1u);
+        if (bad) {
+          if (sub == 0) {
+            const float nan = __int_as_float(0x7FC00000);
+            o[0] = nan;
+            o[1] = nan;
+            o[2] = nan;
+            if (p.nonfinite) atomicAdd(p.nonfinite + v0 + wc, 1u);
+          }
           continue;
         }
-        const float4 cd = cdir[(size_t)v * p.n + cs.id[j]];
-        float Y[16], cw[3] = {0.f, 0.f, 0.f};
+        float Y[16], cs[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int lm = 0; lm < 16; ++lm) Y[lm] = 0.f;
-        sh_eval(p.sh_degree, cd.x, cd.y, cd.z, Y);
-        fourier_terms(p.t_order, cd.w, p.t_period, cw);
-        const float* kk = cs.k + j * kKStride;
-        float c[3] = {0.f, 0.f, 0.f};
+        for (int jj = 0; jj < 16; ++jj) Y[jj] = 0.f;
+        sh_eval(p.sh_degree, cdc.x, cdc.y, cdc.z, Y);
+        fourier_terms(p.t_order, cdc.w, p.t_period, cs);
+        float y[kBasisPerLane];
+        own_basis(Y, sub, y);
+        float col[3];
 #pragma unroll
-        for (int n = 0; n < 3; ++n) {
-          if (n >= nt) break;
-          const float* kn = kk + n * nb * 3;
+        for (int c = 0; c < 3; ++c) {
+          float acc = 0.f;
 #pragma unroll
-          for (int lm = 0; lm < 16; ++lm) {
-            if (lm >= nb) break;
-            const float wgt = cw[n] * Y[lm];
-            c[0] = fmaf(wgt, kn[3 * lm], c[0]);
-            c[1] = fmaf(wgt, kn[3 * lm + 1], c[1]);
-            c[2] = fmaf(wgt, kn[3 * lm + 2], c[2]);
-          }
+          for (int i = 0; i < kBasisPerLane; ++i)
+            acc = fmaf(y[i], fmaf(cs[0], k[0][i][c], fmaf(cs[1], k[1][i][c], cs[2] * k[2][i][c])), acc);
+          col[c] = quad_sum(acc);
         }
-        o[0] = fmaxf(c[0] + kColorOffset, 0.f);
-        o[1] = fmaxf(c[1] + kColorOffset, 0.f);
-        o[2] = fmaxf(c[2] + kColorOffset, 0.f);
+        if (sub == 0) {
+          o[0] = fmaxf(col[0] + kColorOffset, 0.f);
+          o[1] = fmaxf(col[1] + kColorOffset, 0.f);
+          o[2] = fmaxf(col[2] + kColorOffset, 0.f);
+        }
       }
     }
   }

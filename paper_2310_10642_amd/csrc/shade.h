@@ -298,124 +298,11 @@ __device__ __forceinline__ float quad_sum(float v) {
 // functions lm = 4 sub + i, i < kBasisPerLane, and their coefficients.
 constexpr int kBasisPerLane = 4;
 
-// ---- colour kernels ----
-// The forward colour kernel's 256-thread block takes 64 primitives of the
-// active list at a time and stages their coefficients
-// ([(Fourier term) (L+1)^2 + lm][3] each, at most 3 x 16 x 3 floats) in LDS,
-// at an odd stride so that lanes reading different primitives hit different
-// banks; it then lists the active (view, primitive) pairs of a group of four
-// views and gives each pair a thread.
+// Primitives per 256-thread block in the colour kernels (a quad each).
 constexpr int kColourPrims = 64;
-constexpr int kCoeffMax = 3 * 16 * 3;
-constexpr int kKStride = kCoeffMax + 1;
-constexpr int kColourGroup = 4;                              // views per pair list
-constexpr int kColourPairs = kColourPrims * kColourGroup;    // pairs per list, at most
 
-struct ColourStage {
-  float k[kColourPrims * kKStride];
-  uint32_t id[kColourPrims];      // primitive index
-  uint32_t bad[kColourPrims];     // a coefficient is not finite
-  int32_t pd[kColourPairs];       // the pair's record (depth-order slot)
-  uint16_t pjw[kColourPairs];     // primitive (within the block) << 8 | view (within the group)
-  uint32_t np;                    // pairs in the list
-};
-
-// Stages listed primitives [c0, c0 + nprim) (ids, coefficients, finiteness).
-__device__ __forceinline__ void colour_stage(ColourStage& cs, const RenderParams& p, uint32_t c0, int nprim, int K3) {
-  __syncthreads();  // the previous step's readers are done
-  if (threadIdx.x < kColourPrims) {
-    cs.id[threadIdx.x] = (int)threadIdx.x < nprim ? p.plist[c0 + threadIdx.x] : 0u;
-    cs.bad[threadIdx.x] = 0u;
-  }
-  __syncthreads();
-  const bool vec = (K3 & 3) == 0 && (reinterpret_cast<uintptr_t>(p.coeffs) & 15u) == 0;
-  if (vec && blockDim.x == 256) {
-    // every 16-byte piece of the block's coefficients loaded before any is
-    // stored, so the block waits for memory once
-    constexpr int kIters = (kColourPrims * kCoeffMax / 4 + 255) / 256;
-    const int per = K3 >> 2, total = nprim * per;
-    float4 q[kIters];
-    int jo[kIters];
-#pragma unroll
-    for (int it = 0; it < kIters; ++it) {
-      const int i = (int)threadIdx.x + 256 * it;
-      jo[it] = -1;
-      if (i < total) {
-        const int j = i / per, o = i - j * per;
-        jo[it] = j * kKStride + 4 * o;
-        q[it] = reinterpret_cast<const float4*>(p.coeffs + (size_t)cs.id[j] * K3)[o];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < kIters; ++it) {
-      if (jo[it] < 0) continue;
-      float* dst = cs.k + jo[it];
-      dst[0] = q[it].x;
-      dst[1] = q[it].y;
-      dst[2] = q[it].z;
-      dst[3] = q[it].w;
-      if (!(isfinite(q[it].x) && isfinite(q[it].y) && isfinite(q[it].z) && isfinite(q[it].w)))
-        atomicOr(&cs.bad[jo[it] / kKStride], 1u);
-    }
-  } else if (vec) {
-    const int per = K3 >> 2;
-    for (int i = threadIdx.x; i < nprim * per; i += blockDim.x) {
-      const int j = i / per, o = i - j * per;
-      const float4 q = reinterpret_cast<const float4*>(p.coeffs + (size_t)cs.id[j] * K3)[o];
-      float* dst = cs.k + j * kKStride + 4 * o;
-      dst[0] = q.x;
-      dst[1] = q.y;
-      dst[2] = q.z;
-      dst[3] = q.w;
-      if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w))) atomicOr(&cs.bad[j], 1u);
-    }
-  } else {
-    for (int i = threadIdx.x; i < nprim * K3; i += blockDim.x) {
-      const int j = i / K3, o = i - j * K3;
-      const float q = p.coeffs[(size_t)cs.id[j] * K3 + o];
-      cs.k[j * kKStride + o] = q;
-      if (!isfinite(q)) atomicOr(&cs.bad[j], 1u);
-    }
-  }
-}
-
-// Lists the active pairs of the staged primitives in views [v0, v0 + 4),
-// primitive-major (a primitive's pairs are consecutive, in view order), by
-// wave 0: lane j reads primitive j's slots.
-__device__ __forceinline__ void colour_pairs(ColourStage& cs, const RenderParams& p,
-                                             const int32_t* __restrict__ slot, int nprim, int v0) {
-  __syncthreads();  // the previous list's readers are done
-  if (threadIdx.x < 64) {
-    const int j = (int)threadIdx.x;
-    int d[kColourGroup];
-    uint32_t m = 0u;
-#pragma unroll
-    for (int w = 0; w < kColourGroup; ++w) {
-      d[w] = (j < nprim && v0 + w < p.n_views) ? slot[(size_t)(v0 + w) * p.n + cs.id[j]] : -1;
-      m |= (d[w] >= 0 ? 1u : 0u) << w;
-    }
-    const uint32_t cnt = (uint32_t)__popc(m);
-    uint32_t x = cnt;  // inclusive scan over the wave
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
-      if (j >= off) x += y;
-    }
-    if (j == 63) cs.np = x;
-    uint32_t q = x - cnt;
-#pragma unroll
-    for (int w = 0; w < kColourGroup; ++w)
-      if ((m >> w) & 1u) {
-        cs.pd[q] = d[w];
-        cs.pjw[q] = (uint16_t)((j << 8) | w);
-        ++q;
-      }
-  }
-  __syncthreads();
-}
-
-// The backward colour kernel gives each listed primitive a quad; lane `sub`
-// owns the basis functions lm = 4 sub + i, i < 4, and their coefficients:
+// The colour kernels give each listed primitive a quad; lane `sub` owns the
+// basis functions lm = 4 sub + i, i < 4, and their coefficients:
 // k[n][i][c] = g[(n nb + 4 sub + i) 3 + c] for Fourier term n < nt and
 // basis function 4 sub + i < nb (zero elsewhere), g the primitive's
 // [nt][nb][3] coefficients. At SH degree 3 (nb = 16) with g 16-byte aligned,
