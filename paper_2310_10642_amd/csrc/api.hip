@@ -417,9 +417,7 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1, bool count) {
   // 2. compaction of active records
   stage_begin(c);
   launch_scan(P<uint32_t>(c->act), P<uint32_t>(c->pos), nullptr, (uint32_t)vn, (uint32_t)vn, cnt + kCntA,
-              P<uint32_t>(c->scan_scratch), s);
-  launch_compact(P<uint32_t>(c->act), P<uint32_t>(c->pos), P<uint32_t>(c->dkey), (uint32_t)vn, P<uint32_t>(c->ckey),
-                 P<uint32_t>(c->cval), s);
+              P<uint32_t>(c->scan_scratch), s, P<uint32_t>(c->dkey), P<uint32_t>(c->ckey), P<uint32_t>(c->cval));
   // per-view counts: at the round's place for a sync-free render, which
   // reads them only after its last round
   launch_view_counts(P<uint32_t>(c->pos), nv, (uint32_t)c->n, cnt + kCntA,

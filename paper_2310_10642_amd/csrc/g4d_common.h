@@ -114,11 +114,12 @@ void launch_image_loss(int kind, uint64_t n, const float* img, const float* tgt,
 
 // ---- launchers (sort.hip) ----
 // Exclusive scan of n u32 (n read from n_dev when non-null, else n_host); writes total to *total.
+// With ckey: the input is a 0/1 flag per element, and every flagged element i
+// is also compacted: ckey[out[i]] = dkey[i], cval[out[i]] = i.
 size_t scan_scratch_words(size_t n_max);
 void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint32_t n_host, uint32_t n_max,
-                 uint32_t* total, uint32_t* scratch, hipStream_t s);
-void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dkey, uint32_t n,
-                    uint32_t* ckey, uint32_t* cval, hipStream_t s);
+                 uint32_t* total, uint32_t* scratch, hipStream_t s, const uint32_t* dkey = nullptr,
+                 uint32_t* ckey = nullptr, uint32_t* cval = nullptr);
 // LSD radix sort of (key, value) pairs on bits [bit0, bit1) in 8-bit passes
 // that ping-pong via alt; the result ends in keys/vals, copied back after an
 // odd number of passes unless copy_back is false (then it is in the alt pair).

@@ -137,41 +137,27 @@ __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __rest
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block sums in place; total to *total.
-__global__ void __launch_bounds__(1024) k_scan_blocks(uint32_t* __restrict__ bsum, const uint32_t* n_dev,
-                                                      uint32_t n_max, uint32_t* __restrict__ total) {
-  __shared__ uint32_t s_part[1024];
-  const uint32_t n = dev_n(n_dev, n_max);
-  const uint32_t nb = (n + kTileElems - 1) / kTileElems;
-  const uint32_t per = (nb + 1023) / 1024;
-  const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
-  uint32_t acc = 0;
-  for (uint32_t b = b0; b < b1; ++b) acc += bsum[b];
-  s_part[threadIdx.x] = acc;
-  __syncthreads();
-  // Hillis-Steele over 1024 partials
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t y = threadIdx.x >= (unsigned)off ? s_part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    s_part[threadIdx.x] += y;
-    __syncthreads();
-  }
-  uint32_t run = s_part[threadIdx.x] - acc;
-  for (uint32_t b = b0; b < b1; ++b) {
-    const uint32_t c = bsum[b];
-    bsum[b] = run;
-    run += c;
-  }
-  if (threadIdx.x == 1023) *total = s_part[1023];
-}
-
+// Exclusive scan of the tile: each block's offset is the sum of the block
+// sums before it, added up by the block's own threads (no separate pass over
+// the block sums), and the last block writes the total. With ckey, the input
+// is a 0/1 flag per element and every flagged element i also lands in the
+// compacted arrays: ckey[out[i]] = dkey[i], cval[out[i]] = i.
 __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                           const uint32_t* n_dev, uint32_t n_max,
-                                                          const uint32_t* __restrict__ bsum) {
+                                                          const uint32_t* __restrict__ bsum,
+                                                          uint32_t* __restrict__ total,
+                                                          const uint32_t* __restrict__ dkey,
+                                                          uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval) {
   __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
+  const uint32_t nb = (n + kTileElems - 1) / kTileElems;
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *total = 0u;
+  if (blockIdx.x >= nb) return;
+  uint32_t part = 0;
+  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kThreads) part += bsum[b];
+  uint32_t prefix;
+  block_exclusive_scan(part, s_wave, prefix);  // contains barriers; prefix = the block sums before this block
   const size_t base = (size_t)blockIdx.x * kTileElems + (size_t)threadIdx.x * kItems;
-  if ((size_t)blockIdx.x * kTileElems >= n) return;
   uint32_t v[kItems];
   uint32_t acc = 0;
 #pragma unroll
@@ -179,25 +165,20 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restr
     v[i] = (base + i < n) ? in[base + i] : 0u;
     acc += v[i];
   }
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(acc, s_wave, total) + bsum[blockIdx.x];
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(acc, s_wave, tot) + prefix;
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    if (base + i < n) out[base + i] = run;
+    if (base + i < n) {
+      out[base + i] = run;
+      if (ckey && v[i]) {
+        ckey[run] = dkey[base + i];
+        cval[run] = (uint32_t)(base + i);
+      }
+    }
     run += v[i];
   }
-}
-
-__global__ void k_compact(const uint32_t* __restrict__ act, const uint32_t* __restrict__ pos,
-                          const uint32_t* __restrict__ dkey, uint32_t n, uint32_t* __restrict__ ckey,
-                          uint32_t* __restrict__ cval) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (act[i]) {
-    const uint32_t p = pos[i];
-    ckey[p] = dkey[i];
-    cval[p] = (uint32_t)i;
-  }
+  if (blockIdx.x + 1 == nb && threadIdx.x == 0) *total = prefix + tot;
 }
 
 // ---------------------------------------------------------- radix sort ----
@@ -692,7 +673,8 @@ inline unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 
 size_t scan_scratch_words(size_t n_max) { return (n_max + kTileElems - 1) / kTileElems + 1; }
 
 void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint32_t n_host, uint32_t n_max,
-                 uint32_t* total, uint32_t* scratch, hipStream_t s) {
+                 uint32_t* total, uint32_t* scratch, hipStream_t s, const uint32_t* dkey, uint32_t* ckey,
+                 uint32_t* cval) {
   const uint32_t cap = n_dev ? n_max : n_host;
   const unsigned nb = grid_for(cap, kTileElems);
   if (nb == 0) {
@@ -700,14 +682,8 @@ void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint3
     return;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n_dev, cap, scratch);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, scratch, n_dev, cap, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, in, out, n_dev, cap, scratch);
-}
-
-void launch_compact(const uint32_t* act, const uint32_t* pos, const uint32_t* dkey, uint32_t n, uint32_t* ckey,
-                    uint32_t* cval, hipStream_t s) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, act, pos, dkey, n, ckey, cval);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kThreads), 0, s, in, out, n_dev, cap, scratch, total, dkey, ckey,
+                     cval);
 }
 
 size_t radix_scratch_words(int grid) { return (size_t)256 * grid + 256; }
