@@ -344,13 +344,13 @@ g4d_status join_side(g4d_ctx* c) {
 }
 
 // Starts the colour pass of the enqueued pairs on the side stream, after
-// everything enqueued so far on the main stream (the gather in particular).
+// everything enqueued so far on the main stream (the preprocess in particular).
 g4d_status fork_colour(g4d_ctx* c, const RenderParams& p) {
   if (p.flow || p.n == 0) return G4D_OK;
   HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
   HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
   side_stage_begin(c);
-  launch_colour(p, P<int32_t>(c->slot), P<float4>(c->cdir), P<Record>(c->rec_sorted), c->side);
+  launch_colour(p, P<uint32_t>(c->act), P<float4>(c->cdir), P<Record>(c->rec), c->side);
   side_stage_end(c, G4D_STAGE_COLOUR);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev_join, c->side));
@@ -414,6 +414,9 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1, bool count) {
   launch_preprocess(p, P<uint32_t>(c->act), P<uint32_t>(c->dkey), P<Record>(c->rec), P<int32_t>(c->slot),
                     P<float4>(c->cdir), s);
   stage_end(c, G4D_STAGE_PREPROCESS);
+  // the records' colours on the second stream, beside the scans and the
+  // depth sort (joined before the gather copies the records)
+  if ((st = fork_colour(c, p))) return st;
   // 2. compaction of active records
   stage_begin(c);
   launch_scan(P<uint32_t>(c->act), P<uint32_t>(c->pos), nullptr, (uint32_t)vn, (uint32_t)vn, cnt + kCntA,
@@ -430,9 +433,9 @@ g4d_status enqueue_pairs(g4d_ctx* c, int v0, int v1, bool count) {
   radix_sort(P<uint32_t>(c->ckey), P<uint32_t>(c->cval), P<uint32_t>(c->ckey2), P<uint32_t>(c->cval2), cnt + kCntA,
              (uint32_t)vn, 0, 32, g_depth, P<uint32_t>(c->radix_scratch), s);
   // 4. depth-ordered records, slot map, tiles per record; 5. instance offsets
+  if ((st = join_side(c))) return st;
   launch_gather(cnt + kCntA, (uint32_t)vn, P<uint32_t>(c->cval), P<Record>(c->rec), P<Record>(c->rec_sorted),
                 P<int32_t>(c->slot), P<uint32_t>(c->tcount), c->ellipse_cull, cnt + kCntInst64, s);
-  if ((st = fork_colour(c, p))) return st;
   launch_scan(P<uint32_t>(c->tcount), P<uint32_t>(c->toff), cnt + kCntA, 0, (uint32_t)vn, cnt + kCntI,
               P<uint32_t>(c->scan_scratch), s);
   stage_end(c, G4D_STAGE_BINNING);

@@ -92,10 +92,10 @@ struct DensifyStats {
 // cdir: per (view, primitive) scratch [n_views * n] of (view direction, t - mu_t).
 void launch_preprocess(const RenderParams& p, uint32_t* act, uint32_t* dkey, Record* rec, int32_t* slot,
                        float4* cdir, hipStream_t s);
-// 4DSH colour of every active pair into rec_sorted[slot[pair]].c.xyz (after
-// the gather has placed the records and the slots); nothing in flow mode.
-void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdir, Record* rec_sorted,
-                   hipStream_t s);
+// 4DSH colour of every active pair (act[pair] set by the preprocess) into
+// rec[pair].c.xyz, pair = view * n + primitive, before the gather orders the
+// records by depth; nothing in flow mode.
+void launch_colour(const RenderParams& p, const uint32_t* act, const float4* cdir, Record* rec, hipStream_t s);
 // ---- launchers (preprocess_bwd.hip) ----
 size_t preprocess_backward_scratch_floats(size_t n_records);
 // Lanes per primitive in k_preprocess for a call of n_views views.

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_preprocess(RenderParams p, int lanes, u
   }
 }
 
-constexpr int kColourViews = 8;  // views whose slots k_colour loads together
+constexpr int kColourViews = 8;  // views whose activity flags k_colour loads together
 
 // 4D spherindrical-harmonic colour (Sec. 3.2) of the primitives active in
 // some view (the list the preprocess built): a quad of lanes per listed
@@ -166,13 +166,15 @@ constexpr int kColourViews = 8;  // views whose slots k_colour loads together
 // 192-byte Fourier terms together). Each quad walks only its own active
 // views, the k-th in round k (a wave takes as many rounds as its busiest
 // primitive has active views), with the next view's direction loaded while
-// the current one is evaluated. Per view every lane evaluates the basis,
+// the current one is evaluated. The colour goes into the pair's record in
+// (view, primitive) order, before the depth sort moves it (the pass runs
+// beside the scans and the depth sort). Per view every lane evaluates the basis,
 // weights its four functions by the Fourier terms, and a quad sum gives
 // c = max(0, 0.5 + sum). A primitive with a non-finite coefficient gets a
 // NaN colour, which the rasterisers read as fully transparent (and the pair
 // is counted as culled).
-__global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* __restrict__ slot,
-                                                const float4* __restrict__ cdir, Record* __restrict__ rec_sorted) {
+__global__ void __launch_bounds__(256) k_colour(RenderParams p, const uint32_t* __restrict__ act,
+                                                const float4* __restrict__ cdir, Record* __restrict__ rec) {
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
   const int nt = p.t_order + 1;
   const int K3 = nt * nb * 3;
@@ -201,7 +203,7 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* _
       uint32_t m = 0u;
 #pragma unroll
       for (int w = 0; w < kColourViews; ++w) {
-        ds[w] = (live && v0 + w < p.n_views) ? slot[(size_t)(v0 + w) * p.n + gidx] : -1;
+        ds[w] = (live && v0 + w < p.n_views && act[(size_t)(v0 + w) * p.n + gidx]) ? 1 : -1;
         m |= (ds[w] >= 0 ? 1u : 0u) << w;
       }
       uint32_t rounds = (uint32_t)__popc(m);
@@ -218,10 +220,7 @@ __global__ void __launch_bounds__(256) k_colour(RenderParams p, const int32_t* _
         m = m ? m & (m - 1u) : 0u;
         if (w >= 0) cd = cdir[(size_t)(v0 + w) * p.n + gidx];
         if (wc < 0) continue;  // uniform per quad
-        int d = -1;
-#pragma unroll
-        for (int ww = 0; ww < kColourViews; ++ww) d = (ww == wc) ? ds[ww] : d;
-        float* o = reinterpret_cast<float*>(&rec_sorted[d].c);
+        float* o = reinterpret_cast<float*>(&rec[(size_t)(v0 + wc) * p.n + gidx].c);
         if (bad) {
           if (sub == 0) {
             const float nan = __int_as_float(0x7FC00000);
@@ -279,10 +278,9 @@ unsigned list_grid(int n) {
   return need < 1 ? 1 : (need < 16384 ? need : 16384);
 }
 
-void launch_colour(const RenderParams& p, const int32_t* slot, const float4* cdir, Record* rec_sorted,
-                   hipStream_t s) {
+void launch_colour(const RenderParams& p, const uint32_t* act, const float4* cdir, Record* rec, hipStream_t s) {
   if (p.n == 0 || p.flow) return;
-  hipLaunchKernelGGL(k_colour, dim3(list_grid(p.n)), dim3(256), 0, s, p, slot, cdir, rec_sorted);
+  hipLaunchKernelGGL(k_colour, dim3(list_grid(p.n)), dim3(256), 0, s, p, act, cdir, rec);
 }
 
 }  // namespace g4d
