@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   __shared__ float4 s_a2[2][kBwdBatch], s_b2[2][kBwdBatch], s_c2[2][kBwdBatch];
   __shared__ uint32_t s_d2[2][kBwdBatch];
   __shared__ uint32_t s_qm2[2][kBwdBatch];
-  __shared__ uint32_t s_ill2[2];  // the staged batch holds an ill-conditioned footprint (FP64 phase 2)
+  __shared__ uint32_t s_ill2[2];  // per staged batch: bit j when entry j's footprint is ill-conditioned
   __shared__ uint32_t s_act[4];  // per quadrant: bit j when entry j blended somewhere in it
   __shared__ float s_g[kBwdBatch * kGwStride];   // dL/dpower per (primitive, pixel)
   __shared__ float s_w[kBwdBatch * kGwStride];   // a_i T_i per (primitive, pixel)
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const uint64_t bits = __ballot(hit);
     if (t < kBwdBatch) s_qm2[bb][t] = (uint32_t)(bits >> (4 * t)) & 0xFu;
     const uint64_t ill = __ballot(t < kBwdBatch && e0 + t < count && ill_conditioned(nxt));
-    if (t == 0) s_ill2[bb] = ill != 0ull ? 1u : 0u;
+    if (t == 0) s_ill2[bb] = (uint32_t)ill & 0xFFFFu;
   };
   if (wave == 0 && b_first >= 0) {
     if (threadIdx.x < kBwdBatch && b_first + (int)threadIdx.x < count) {
@@ -554,7 +554,9 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const bool live = e2 < count;
     int slot_q;
     double val;
-    if (s_ill2[buf]) {  // block-uniform
+    // FP64 sums for the waves whose four primitives include an ill-conditioned
+    // footprint (wave-uniform)
+    if ((s_ill2[buf] >> (4 * wave)) & 0xFu) {
       double q[10];
       phase2_line<double, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
       val = row16_reduce_scatter10(q, c2, slot_q);
