@@ -15,10 +15,11 @@
 // The forward pass keeps only the final transmittance and the number of list
 // entries up to the last contributor per pixel. The backward pass walks the
 // list back to front from there, recovering T_i = T_{i+1} / (1 - a_i), and
-// works in two phases per batch of 16 primitives: (1) each lane (pixel)
-// writes dL/dpower and a_i T_i for the batch into LDS; (2) the lanes regroup
-// as 16 primitives x 16 pixel columns and accumulate the per-primitive sums
-// over the tile's pixels (only over quadrants where the primitive blended).
+// works in two phases per batch of 12 primitives: (1) each lane (pixel)
+// writes dL/dpower and a_i T_i for the batch into LDS; (2) three of the four
+// waves regroup as 12 primitives x 16 pixel columns and accumulate the
+// per-primitive sums over the tile's pixels (only over quadrants where the
+// primitive blended).
 // A 16-lane DPP reduce-scatter per batch combines the columns, leaving each
 // of ten lanes of a primitive's row with one value of its gradient line, and
 // those lanes add the tile's share with one FP64 atomic instruction into one
@@ -33,13 +34,18 @@ namespace {
 
 using shade::sc_fma;
 
-constexpr int kBwdBatch = 16;
+// List entries per backward batch (a multiple of 4). 12 rather than 16: the
+// per-(primitive, pixel) buffers then take 26 KB, the workgroup 31.6 KB of LDS,
+// and with at most 96 VGPRs (the launch bound) five workgroups share a CU
+// instead of four; the backward is bound by issue stalls more than by its
+// instruction count, so the fifth wave per SIMD outweighs the third more
+// barriers per entry.
+constexpr int kBwdBatch = 12;
 // Backward LDS slots of one primitive's per-pixel values: pixel (row, col) of
 // the tile sits at 16 row + (col ^ 8 [(row >> 1) & 1]); the x-halves of rows
 // 2-3 of every four are swapped so that a wave's 8x8 quadrant (4 rows per
 // half-wave) hits 32 distinct banks when writing, and 16 columns x 2
-// primitives (stride 272 = 16 mod 32) do when reading. Unpadded rows keep the
-// workgroup at <= 40 KB of LDS, i.e. 4 workgroups per CU.
+// primitives (stride 272 = 16 mod 32) do when reading.
 constexpr int kGwStride = 256 + 16;
 __device__ __forceinline__ int gw_slot(int row, int col) { return 16 * row + (col ^ (((row >> 1) & 1) << 3)); }
 
@@ -381,7 +387,7 @@ __device__ __forceinline__ void phase2_line(G (&q)[10], bool live, int j2, int c
 // HAS_D / HAS_A: whether dL/d(depth) and dL/d(alpha) are given (otherwise
 // their terms are compiled out).
 template <bool HAS_D, bool HAS_A>
-__global__ void __launch_bounds__(256) k_raster_backward(
+__global__ void __launch_bounds__(256, 5) k_raster_backward(
     const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* queue, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
@@ -444,7 +450,6 @@ __global__ void __launch_bounds__(256) k_raster_backward(
   __syncthreads();
   const int max_last = (int)s_max;
 
-  const int j2 = threadIdx.x >> 4;  // phase 2: primitive within the batch
   const int c2 = threadIdx.x & 15;  // phase 2: pixel column
   const int b_first = ((max_last + kBwdBatch - 1) / kBwdBatch - 1) * kBwdBatch;
   // Staging pipeline (threads < 16): the record of the batch after the one in
@@ -490,8 +495,8 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     const int e2n = e1 - kBwdBatch;
     if (threadIdx.x < kBwdBatch && e2n >= 0) nn_d = ival[rg.x + e2n];
   }
-  int buf = 0;
-  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1) {
+  int buf = 0, rot = 0;
+  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1, rot = (rot + 1) & 3) {
     // the stage buffer's first entry as a vector register, so each entry's
     // LDS reads in phase 1 are immediate offsets from it
     int bv;
@@ -550,27 +555,35 @@ __global__ void __launch_bounds__(256) k_raster_backward(
     if (lane == 0) s_act[wave] = blended;
     __syncthreads();
     // ---- phase 2: primitive j2, pixel column c2, rows of active quadrants ----
+    // Wave w takes primitives 4 r .. 4 r + 3, r = (w + batch index) mod 4: in a
+    // batch of fewer than 16 entries a different wave (so a different SIMD)
+    // has no primitive in each batch.
+    const int rank = (wave + rot) & 3;
+    const int j2 = 4 * rank + (lane >> 4);
+    const bool p2 = j2 < kBwdBatch;  // wave-uniform
     const int e2 = b0 + j2;
-    const bool live = e2 < count;
-    int slot_q;
-    double val;
-    // FP64 sums for the waves whose four primitives include an ill-conditioned
-    // footprint (wave-uniform)
-    if ((s_ill2[buf] >> (4 * wave)) & 0xFu) {
-      double q[10];
-      phase2_line<double, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
-      val = row16_reduce_scatter10(q, c2, slot_q);
-    } else {
-      float q[10];
-      phase2_line<float, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
-      val = (double)row16_reduce_scatter10(q, c2, slot_q);
+    const bool live = p2 && e2 < count;
+    int slot_q = -1;
+    double val = 0.0;
+    uint32_t d_atom = 0u;
+    if (p2) {
+      // FP64 sums for the waves whose four primitives include an
+      // ill-conditioned footprint (wave-uniform)
+      if ((s_ill2[buf] >> (4 * rank)) & 0xFu) {
+        double q[10];
+        phase2_line<double, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
+        val = row16_reduce_scatter10(q, c2, slot_q);
+      } else {
+        float q[10];
+        phase2_line<float, HAS_D>(q, live, j2, c2, tx, ty, s_a, s_b, s_act, s_g, s_w, s_pix);
+        val = (double)row16_reduce_scatter10(q, c2, slot_q);
+      }
+      // the record blended in this tile: flag it in the gradient line's last
+      // float (the same 1 from every tile, so plain stores suffice)
+      if (mark_blended && c2 == 15 && live && (((s_act[0] | s_act[1] | s_act[2] | s_act[3]) >> j2) & 1u))
+        grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.0;
+      d_atom = s_d[j2];
     }
-    // the record blended in this tile: flag it in the gradient line's last
-    // float (the same 1 from every tile, so plain stores suffice)
-    if (mark_blended && c2 == 15 && e2 < count &&
-        (((s_act[0] | s_act[1] | s_act[2] | s_act[3]) >> j2) & 1u))
-      grad2d[(size_t)s_d[j2] * kGrad2dStride + 15] = 1.0;
-    const uint32_t d_atom = s_d[j2];
     // stage the next batch into the other buffer (read by nobody until the
     // next loop-top barrier) and advance the loads, before this batch's atomics
     if (wave == 0 && b0 >= kBwdBatch) {
