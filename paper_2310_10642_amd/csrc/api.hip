@@ -495,20 +495,31 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   const bool odd = passes & 1;
   if (passes) launch_ranges_init(P<uint2>(c->ranges), (uint32_t)tiles, s);
   else launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
-  uint32_t* ek = P<uint32_t>(odd ? c->ikey2 : c->ikey);
+  void* ek = (odd ? c->ikey2 : c->ikey).ptr;
+  void* ak = (odd ? c->ikey : c->ikey2).ptr;
   uint32_t* ev = P<uint32_t>(odd ? c->ival2 : c->ival);
-  uint32_t* ak = P<uint32_t>(odd ? c->ikey : c->ikey2);
   uint32_t* av = P<uint32_t>(odd ? c->ival : c->ival2);
-  launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, P<Record>(c->rec_sorted),
-              P<uint32_t>(c->cval), (int)c->n, P<ViewDev>(c->views_d), c->ellipse_cull, ek, ev, s);
+  const uint32_t* ids = P<uint32_t>(c->cval);
+  const Record* rs = P<Record>(c->rec_sorted);
+  const ViewDev* vd = P<ViewDev>(c->views_d);
   const int g_tile = radix_grid(cap, c->sort_blocks);
-  if (passes) {
-    radix_sort(ek, ev, ak, av, cnt + kCntI, cap, 0, tile_bits, g_tile, P<uint32_t>(c->radix_scratch), s,
-               /*copy_back=*/false, P<uint2>(c->ranges));
-    launch_ranges_fix(P<uint2>(c->ranges), (uint32_t)tiles, s);
+  uint32_t* rsc = P<uint32_t>(c->radix_scratch);
+  uint2* rg = P<uint2>(c->ranges);
+  // a round's tile ids fit 16 bits unless one view alone has more tiles;
+  // 16-bit keys take a quarter off the sort's bytes per instance
+  if (tile_bits <= 16) {
+    uint16_t *k16 = static_cast<uint16_t*>(ek), *a16 = static_cast<uint16_t*>(ak);
+    launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, rs, ids, (int)c->n, vd,
+                c->ellipse_cull, k16, ev, s);
+    if (passes) radix_sort16(k16, ev, a16, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, rg);
+    else launch_ranges(cnt + kCntI, cap, k16, rg, s);
   } else {
-    launch_ranges(cnt + kCntI, cap, P<uint32_t>(c->ikey), P<uint2>(c->ranges), s);
+    uint32_t *k32 = static_cast<uint32_t*>(ek), *a32 = static_cast<uint32_t*>(ak);
+    launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, rs, ids, (int)c->n, vd,
+                c->ellipse_cull, k32, ev, s);
+    radix_sort(k32, ev, a32, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, /*copy_back=*/false, rg);
   }
+  if (passes) launch_ranges_fix(rg, (uint32_t)tiles, s);
   if (c->heavy_first) {
     // workgroups take the tiles with the longest lists first, so the launch
     // does not end on a few heavy tiles

@@ -132,6 +132,11 @@ int radix_passes(int bit0, int bit1);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                 uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
                 bool copy_back = true, uint2* last_ranges = nullptr);
+// The same with 16-bit keys (bit1 <= 16), without the copy back: after an odd
+// number of passes the result is in (keys_alt, vals_alt).
+void radix_sort16(uint16_t* keys, uint32_t* vals, uint16_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
+                  uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
+                  uint2* last_ranges = nullptr);
 void launch_ranges_init(uint2* ranges, uint32_t tiles, hipStream_t s);
 void launch_ranges_fix(uint2* ranges, uint32_t tiles, hipStream_t s);
 // Depth-ordered records, slot map (view*n + index -> depth position), tiles per record,
@@ -142,10 +147,15 @@ void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, c
 void launch_view_counts(const uint32_t* pos, int n_views, uint32_t n, const uint32_t* total, uint32_t* out,
                         hipStream_t s);
 // Instances beyond min(*total, cap) are not written; exact as for launch_gather.
+// Keys are 16-bit when the round's tile ids are below 2^16, else 32-bit.
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
                  uint32_t* ikey, uint32_t* ival, hipStream_t s);
+void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
+                 const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
+                 uint16_t* ikey, uint32_t* ival, hipStream_t s);
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s);
+void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint16_t* ikey, uint2* ranges, hipStream_t s);
 
 // ---- launchers (raster.hip) ----
 // order (nullable): the tiles in the order workgroups take them, e.g.

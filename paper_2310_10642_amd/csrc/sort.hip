@@ -12,6 +12,7 @@
 //   3. stable radix sort of the instances by global tile id.
 // Every pass is stable, so the result equals a stable sort by (tile, depth)
 // of the instances emitted in (view, index) order.
+#include <utility>
 #include "g4d_common.h"
 
 namespace g4d {
@@ -197,7 +198,9 @@ __device__ __forceinline__ void block_range(uint32_t n, int grid, uint32_t& t0, 
   t1 = min(t0 + tpb, tiles);
 }
 
-__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
+// K: uint32_t, or uint16_t for keys below 2^16 (the tile ids of a round).
+template <typename K>
+__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const K* __restrict__ keys, const uint32_t* n_dev,
                                                           uint32_t n_max, int shift, int bits,
                                                           uint32_t* __restrict__ counts) {
   __shared__ uint32_t hist[4][256];
@@ -212,22 +215,29 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restr
   for (uint32_t t = t0; t < t1; ++t) {
     const size_t tb = (size_t)t * kTileElems;
     if (tb + kTileElems <= n) {
-      // full tile: four 16-byte loads per thread, all in flight together
-      uint4 q[kItems / 4];
+      // full tile: 16-byte loads (four, or two of 16-bit keys), all in flight together
+      constexpr int kVec = 16 / (int)sizeof(K);
+      uint4 q[kItems / kVec];
 #pragma unroll
-      for (int i = 0; i < kItems / 4; ++i)
+      for (int i = 0; i < kItems / kVec; ++i)
         q[i] = reinterpret_cast<const uint4*>(keys + tb)[i * kThreads + threadIdx.x];
 #pragma unroll
-      for (int i = 0; i < kItems / 4; ++i) {
-        atomicAdd(&hist[wave][(q[i].x >> shift) & mask], 1u);
-        atomicAdd(&hist[wave][(q[i].y >> shift) & mask], 1u);
-        atomicAdd(&hist[wave][(q[i].z >> shift) & mask], 1u);
-        atomicAdd(&hist[wave][(q[i].w >> shift) & mask], 1u);
+      for (int i = 0; i < kItems / kVec; ++i) {
+        const uint32_t w[4] = {q[i].x, q[i].y, q[i].z, q[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (sizeof(K) == 4) {
+            atomicAdd(&hist[wave][(w[j] >> shift) & mask], 1u);
+          } else {
+            atomicAdd(&hist[wave][((w[j] & 0xFFFFu) >> shift) & mask], 1u);
+            atomicAdd(&hist[wave][(w[j] >> (16 + shift)) & mask], 1u);
+          }
+        }
       }
     } else {
       for (int i = 0; i < kItems; ++i) {
         const size_t idx = tb + (size_t)i * kThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&hist[wave][(keys[idx] >> shift) & mask], 1u);
+        if (idx < n) atomicAdd(&hist[wave][((uint32_t)keys[idx] >> shift) & mask], 1u);
       }
     }
   }
@@ -276,9 +286,12 @@ __global__ void __launch_bounds__(1024) k_rs_rowscan(uint32_t* __restrict__ coun
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
-// LDS of the stable scatter of one digit pass.
+// LDS of the stable scatter of one digit pass (30.7 KB with 16-bit keys, five
+// workgroups per CU; 39.4 KB with 32-bit keys, four).
+template <typename K>
 struct ScatterShared {
-  uint32_t k[kTileElems], v[kTileElems];  // the tile reordered by digit
+  K k[kTileElems];                        // the tile reordered by digit
+  uint32_t v[kTileElems];
   uint32_t wcnt[4][256];                  // per wave and digit: count, then start
   uint32_t run[256];                      // per digit: next output position of the block
   uint32_t tstart[256];                   // per digit: start of its run in the reordered tile
@@ -288,7 +301,8 @@ struct ScatterShared {
 // Output positions of the block's digit runs: run[d] = (pairs of smaller
 // digits in the whole pass) + (pairs of digit d in earlier blocks), from the
 // per-(digit, block) exclusive scan `counts` and the digit totals.
-__device__ __forceinline__ void scatter_begin(ScatterShared& sh, const uint32_t* __restrict__ counts,
+template <typename K>
+__device__ __forceinline__ void scatter_begin(ScatterShared<K>& sh, const uint32_t* __restrict__ counts,
                                               const uint32_t* __restrict__ digit_tot, uint32_t grid, uint32_t block) {
   const uint32_t dg = threadIdx.x;
   uint32_t tot;
@@ -305,9 +319,10 @@ __device__ __forceinline__ void scatter_begin(ScatterShared& sh, const uint32_t*
 // digit d so far (bounded by n_out); with ranges (the last pass over the
 // whole key) the keys are not written: each key's first and last position
 // bound its range instead.
-__device__ __forceinline__ void scatter_tile(ScatterShared& sh, const uint32_t (&k)[kItems],
+template <typename K>
+__device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_t (&k)[kItems],
                                              const uint32_t (&v)[kItems], uint32_t nvalid, int shift, int bits,
-                                             uint32_t n_out, uint32_t* __restrict__ keys_out,
+                                             uint32_t n_out, K* __restrict__ keys_out,
                                              uint32_t* __restrict__ vals_out, uint2* __restrict__ ranges) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -355,7 +370,7 @@ __device__ __forceinline__ void scatter_tile(ScatterShared& sh, const uint32_t (
       const uint32_t d = (k[i] >> shift) & mask;
       const uint32_t lp = sh.wcnt[wave][d] + rank[i];
       if (lp < (uint32_t)kTileElems) {
-        sh.k[lp] = k[i];
+        sh.k[lp] = (K)k[i];
         sh.v[lp] = v[i];
       }
     }
@@ -376,7 +391,7 @@ __device__ __forceinline__ void scatter_tile(ScatterShared& sh, const uint32_t (
           if (lp == 0 || sh.k[lp - 1] != key) atomicMin(&ranges[key].x, p);
           if (lp + 1 == nt || sh.k[lp + 1] != key) atomicMax(&ranges[key].y, p + 1);
         } else {
-          keys_out[p] = key;
+          keys_out[p] = (K)key;
         }
         vals_out[p] = sh.v[lp];
       }
@@ -388,15 +403,16 @@ __device__ __forceinline__ void scatter_tile(ScatterShared& sh, const uint32_t (
 
 // One digit pass over the pairs in memory: each block takes its range of
 // 4096-pair tiles in turn.
-__global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+template <typename K>
+__global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in,
-                                                            uint32_t* __restrict__ keys_out,
+                                                            K* __restrict__ keys_out,
                                                             uint32_t* __restrict__ vals_out, const uint32_t* n_dev,
                                                             uint32_t n_max, int shift, int bits,
                                                             const uint32_t* __restrict__ counts,
                                                             const uint32_t* __restrict__ digit_tot,
                                                             uint2* __restrict__ ranges) {
-  __shared__ ScatterShared sh;
+  __shared__ ScatterShared<K> sh;
   const uint32_t n = dev_n(n_dev, n_max);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   scatter_begin(sh, counts, digit_tot, gridDim.x, sort_block());
@@ -408,7 +424,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const uint32_t* __res
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const size_t idx = base + (size_t)i * 64 + lane;
-      k[i] = (idx < n) ? keys_in[idx] : 0u;
+      k[i] = (idx < n) ? (uint32_t)keys_in[idx] : 0u;
       v[i] = (idx < n) ? vals_in[idx] : 0u;
     }
     const uint32_t nvalid = (uint32_t)min((size_t)kTileElems, (size_t)n - (size_t)t * kTileElems);
@@ -470,12 +486,14 @@ constexpr int kEmitRecs = 64;
 constexpr int kEmitRows = 1024;
 constexpr int kEmitInst = 4096;
 
+// K: the key type, uint16_t when the round's tile ids are below 2^16.
+template <typename K>
 __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32_t n_max,
                                                     const uint32_t* __restrict__ toff, const uint32_t* total,
                                                     uint32_t cap, const Record* __restrict__ rec_sorted,
                                                     const uint32_t* __restrict__ ids, uint32_t n_prims,
                                                     const ViewDev* __restrict__ views, bool exact,
-                                                    uint32_t* __restrict__ ikey, uint32_t* __restrict__ ival) {
+                                                    K* __restrict__ ikey, uint32_t* __restrict__ ival) {
   __shared__ uint32_t offs[kEmitRecs + 1];
   __shared__ uint32_t s_rbase[kEmitRecs + 1];
   __shared__ uint32_t s_tb[kEmitRecs], s_tw[kEmitRecs];
@@ -551,7 +569,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
       const uint32_t ie = min(iend, start + c1);
       for (uint32_t i = start + c0 + threadIdx.x; i < ie; i += kThreads) {
         const uint32_t k = i - start, j = s_inst_row[k - c0];
-        ikey[i] = s_row_tile[j] + (k - s_row_off[j]);
+        ikey[i] = (K)(s_row_tile[j] + (k - s_row_off[j]));
         ival[i] = d0 + s_row_rec[j];
       }
     }
@@ -573,7 +591,7 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
         }
         k -= xb - xa;
       }
-      ikey[i] = s_tb[lo] + tile;
+      ikey[i] = (K)(s_tb[lo] + tile);
       ival[i] = d0 + (uint32_t)lo;
     }
   }
@@ -593,21 +611,17 @@ __global__ void k_ranges_fix(uint2* __restrict__ ranges, uint32_t tiles) {
   if (r.x > r.y) ranges[t] = make_uint2(0u, 0u);
 }
 
-__global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* __restrict__ ikey,
+template <typename K>
+__global__ void k_ranges(const uint32_t* n_dev, uint32_t n_max, const K* __restrict__ ikey,
                          uint2* __restrict__ ranges) {
-  // four consecutive keys per thread (one 16-byte load when in bounds)
+  // four consecutive keys per thread
   const uint32_t n = dev_n(n_dev, n_max);
   const uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
   if (i0 >= n) return;
   uint32_t k[6];  // k[0] = key before i0 (or none), k[1..4] = keys i0..i0+3, k[5] = key after
-  if (i0 + 4 <= n) {
-    const uint4 q = *reinterpret_cast<const uint4*>(ikey + i0);
-    k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
-  } else {
-    for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? ikey[i0 + j] : 0xFFFFFFFFu;
-  }
-  k[0] = i0 > 0 ? ikey[i0 - 1] : 0xFFFFFFFFu;
-  k[5] = (i0 + 4 < n) ? ikey[i0 + 4] : 0xFFFFFFFFu;
+  for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? (uint32_t)ikey[i0 + j] : 0xFFFFFFFFu;
+  k[0] = i0 > 0 ? (uint32_t)ikey[i0 - 1] : 0xFFFFFFFFu;
+  k[5] = (i0 + 4 < n) ? (uint32_t)ikey[i0 + 4] : 0xFFFFFFFFu;
 #pragma unroll
   for (int j = 1; j <= 4; ++j) {
     const uint32_t i = i0 + j - 1;
@@ -695,25 +709,40 @@ int radix_grid(uint32_t n_max, int max_blocks) {
 
 int radix_passes(int bit0, int bit1) { return bit1 > bit0 ? (bit1 - bit0 + 7) / 8 : 0; }
 
+// The digit passes, ping-ponging between the two buffer pairs; returns the
+// pair that holds the result.
+template <typename K>
+std::pair<K*, uint32_t*> radix_passes_run(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt,
+                                          const uint32_t* n_dev, uint32_t n_max, int bit0, int bit1, int grid,
+                                          uint32_t* scratch, hipStream_t s, uint2* last_ranges) {
+  K *kin = keys, *kout = keys_alt;
+  uint32_t *vin = vals, *vout = vals_alt;
+  for (int b = bit0; b < bit1; b += 8) {
+    const int bits = (bit1 - b) < 8 ? (bit1 - b) : 8;
+    hipLaunchKernelGGL(k_rs_upsweep<K>, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, scratch, grid, scratch + (size_t)256 * grid);
+    hipLaunchKernelGGL(k_rs_downsweep<K>, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b,
+                       bits, scratch, scratch + (size_t)256 * grid, b + 8 >= bit1 ? last_ranges : nullptr);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  return {kin, vin};
+}
+
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                 uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s, bool copy_back,
                 uint2* last_ranges) {
-  // Passes ping-pong between the two buffers; an odd pass count ends with a
-  // copy back so the result is in (keys, vals), unless the caller takes it
-  // from (keys_alt, vals_alt).
-  uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
-  int passes = 0;
-  for (int b = bit0; b < bit1; b += 8) {
-    const int bits = (bit1 - b) < 8 ? (bit1 - b) : 8;
-    hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
-    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, scratch, grid, scratch + (size_t)256 * grid);
-    hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b, bits,
-                       scratch, scratch + (size_t)256 * grid, b + 8 >= bit1 ? last_ranges : nullptr);
-    uint32_t* t = kin; kin = kout; kout = t;
-    t = vin; vin = vout; vout = t;
-    ++passes;
-  }
-  if ((passes & 1) && copy_back) launch_copy_pairs(kin, vin, keys, vals, n_dev, n_max, s);
+  // an odd pass count ends with a copy back so the result is in (keys, vals),
+  // unless the caller takes it from (keys_alt, vals_alt)
+  const auto out = radix_passes_run(keys, vals, keys_alt, vals_alt, n_dev, n_max, bit0, bit1, grid, scratch, s,
+                                    last_ranges);
+  if (out.first != keys && copy_back) launch_copy_pairs(out.first, out.second, keys, vals, n_dev, n_max, s);
+}
+
+void radix_sort16(uint16_t* keys, uint32_t* vals, uint16_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
+                  uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
+                  uint2* last_ranges) {
+  radix_passes_run(keys, vals, keys_alt, vals_alt, n_dev, n_max, bit0, bit1, grid, scratch, s, last_ranges);
 }
 
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
@@ -728,12 +757,25 @@ void launch_view_counts(const uint32_t* pos, int n_views, uint32_t n, const uint
   hipLaunchKernelGGL(k_view_counts, dim3(grid_for(n_views, 64)), dim3(64), 0, s, pos, n_views, n, total, out);
 }
 
+template <typename K>
+void emit_keys(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
+               const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact, K* ikey,
+               uint32_t* ival, hipStream_t s) {
+  if (n_max == 0) return;
+  hipLaunchKernelGGL(k_emit<K>, dim3(grid_for(n_max, kEmitRecs)), dim3(kThreads), 0, s, n_dev, n_max, toff, total,
+                     cap, rec_sorted, ids, (uint32_t)n_prims, views, exact, ikey, ival);
+}
+
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
                  uint32_t* ikey, uint32_t* ival, hipStream_t s) {
-  if (n_max == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(n_max, kEmitRecs)), dim3(kThreads), 0, s, n_dev, n_max, toff, total, cap,
-                     rec_sorted, ids, (uint32_t)n_prims, views, exact, ikey, ival);
+  emit_keys(n_dev, n_max, toff, total, cap, rec_sorted, ids, n_prims, views, exact, ikey, ival, s);
+}
+
+void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
+                 const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
+                 uint16_t* ikey, uint32_t* ival, hipStream_t s) {
+  emit_keys(n_dev, n_max, toff, total, cap, rec_sorted, ids, n_prims, views, exact, ikey, ival, s);
 }
 
 void launch_ranges_init(uint2* ranges, uint32_t tiles, hipStream_t s) {
@@ -746,7 +788,14 @@ void launch_ranges_fix(uint2* ranges, uint32_t tiles, hipStream_t s) {
 
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s) {
   if (n_max == 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for((n_max + 3) / 4, 256)), dim3(256), 0, s, n_dev, n_max, ikey, ranges);
+  hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid_for((n_max + 3) / 4, 256)), dim3(256), 0, s, n_dev, n_max, ikey,
+                     ranges);
+}
+
+void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint16_t* ikey, uint2* ranges, hipStream_t s) {
+  if (n_max == 0) return;
+  hipLaunchKernelGGL(k_ranges<uint16_t>, dim3(grid_for((n_max + 3) / 4, 256)), dim3(256), 0, s, n_dev, n_max, ikey,
+                     ranges);
 }
 
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s) {

@@ -369,6 +369,35 @@ def test_round_tile_cap():
     _close_grads(gb, gsum)
 
 
+def test_single_view_beyond_16_bit_tile_ids():
+    """One 4128x4112 view has 66 306 tiles: its round's tile ids need 17 bits,
+    so the instance sort takes its 32-bit-key path (three passes) instead of
+    the 16-bit one every smaller round uses. The lists are a stable sort by
+    (tile, depth position) and sampled tiles match the oracle."""
+    _say("[one view of 66 306 tiles, 32-bit instance keys]")
+    scene = scenegen.random_scene(31, 20000, sh_degree=2, t_order=1, spread=1.2)
+    cam = scenegen.look_at_camera((0.0, 0.3, 3.5), 4128, 4112)
+    r, _ = PT.gpu_setup(scene)
+    rgb, dep, alp = r.render([cam], [0.45])
+    stats = r.stats()
+    _say(f"  rounds {stats['rounds']}, tiles {stats['tiles']}, instances {stats['instances']}")
+    assert stats["rounds"] == 1 and stats["tiles"] == 258 * 257 > 1 << 16
+    keys = r.debug("tile_keys").astype(np.int64)
+    vals = r.debug("tile_vals").astype(np.int64)
+    assert len(keys) == stats["instances"] > 0
+    assert keys.max() >= 1 << 16  # ids past 16 bits did occur
+    step = (keys[1:] > keys[:-1]) | ((keys[1:] == keys[:-1]) & (vals[1:] > vals[:-1]))
+    assert step.all()
+    tiles = scenegen.sample_pixels_dlddi(32, [cam], 8)[0]
+    # half of the samples from the tiles past id 2^16
+    far = np.arange(1 << 16, 258 * 257)
+    tiles = np.concatenate([tiles[:4], np.random.default_rng(33).choice(far, 4, replace=False)]).tolist()
+    _, img = PT.oracle_view(scene, cam, 0.45, tiles=tiles)
+    res = PT.compare_images(_np(rgb).reshape(3, cam.height, cam.width), _np(dep).reshape(cam.height, cam.width),
+                            _np(alp).reshape(cam.height, cam.width), img)
+    _say(f"  tiles {tiles}: {res}")
+
+
 def test_sync_free_rounds_and_graph():
     """A sync-free render of thirteen full-size views plans its two rounds
     from the tile cap alone: images, per-view counts and totals equal the
