@@ -427,7 +427,9 @@ def main():
     # floats and F coefficients once, write one 48-byte record per active pair
     hbm("preprocess", (17 + F) * 4 * N + 48 * A, sec_step["preprocess"] + sec_step["colour"],
         "(17+F)*4*N + 48*sum(A), time = k_preprocess + k_colour", "preprocess_bytes_per_render")
-    # binning: the sort floor of 28 bytes per (tile, record) instance
+    # binning: 28 bytes per (tile, record) instance, what the two-pass instance
+    # sort moves with 16-bit tile keys (emission writes 6 B, the first pass
+    # reads and writes 6 B, the last reads 6 B and writes the 4-byte record)
     hbm("binning", 28 * I, sec_step["binning"], "28*I", "binning_bytes_per_render")
     # backward of the preprocess: parameters in and gradients out once, one
     # 128-byte FP64 gradient line per active record
