@@ -129,9 +129,12 @@ __device__ __forceinline__ int find_view(const ViewDev* views, int n_views, int 
   return lo;
 }
 
+// (the controls used here, row mirrors and quad permutations, read a lane of
+// the same row for every lane, so the bound control changes nothing; with it
+// set the compiler can fold the move into the add that uses it)
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {

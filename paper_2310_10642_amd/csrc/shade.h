@@ -287,10 +287,12 @@ __device__ __forceinline__ int fourier_terms(int t_order, float dt, float period
   return t_order + 1;
 }
 
-// Sum over the four lanes of a DPP quad (quad_perm [1,0,3,2], then [2,3,0,1]).
+// Sum over the four lanes of a DPP quad (quad_perm [1,0,3,2], then [2,3,0,1];
+// every lane reads within its quad, so the bound control changes nothing, and
+// with it set each move folds into its add).
 __device__ __forceinline__ float quad_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
   return v;
 }
 
