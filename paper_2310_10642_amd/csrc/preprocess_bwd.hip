@@ -161,7 +161,10 @@ constexpr int kBwdColourViews = 8;  // views whose slots k_bwd_colour loads toge
 // of them in round k), so a wave takes as many rounds as its busiest
 // primitive has active views. A primitive with a non-finite coefficient was
 // rendered transparent: it gets zero gradients.
-__global__ void __launch_bounds__(256) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
+// Three waves per SIMD (at most 168 VGPRs, a few spilled values) rather than
+// the two its 178 registers allow: it streams every listed primitive's
+// coefficients in and their gradients out.
+__global__ void __launch_bounds__(256, 3) k_bwd_colour(RenderParams p, const int32_t* __restrict__ slot,
                                                      const float4* __restrict__ colbuf, float4* __restrict__ cgbuf,
                                                      float* __restrict__ g_coeffs, bool accumulate) {
   const int nb = (p.sh_degree + 1) * (p.sh_degree + 1);
@@ -281,7 +284,10 @@ __global__ void __launch_bounds__(256) k_zero_inactive_coeffs(RenderParams p, fl
   }
 }
 
-__global__ void __launch_bounds__(128) k_bwd_prims(RenderParams p, const int32_t* __restrict__ slot,
+// Three waves per SIMD (at most 168 VGPRs, a few spilled values) rather than
+// the two its 174 registers allow: it streams every primitive's parameters in
+// and their gradients out.
+__global__ void __launch_bounds__(128, 3) k_bwd_prims(RenderParams p, const int32_t* __restrict__ slot,
                                                    const float4* __restrict__ geo, const float4* __restrict__ cgbuf,
                                                    float4* __restrict__ g_means4, float4* __restrict__ g_log_scales4,
                                                    float4* __restrict__ g_q_left, float4* __restrict__ g_q_right,
