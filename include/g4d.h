@@ -353,10 +353,14 @@ const char* g4d_last_error(const g4d_ctx* ctx);
  *   G4D_DBG_PIX_LAST  per pixel, uint32 list entries up to the last contributor
  *   G4D_DBG_GRAD2D    after a backward: per active pair, 16 x float64
  *                     dL/du, dL/dv, dL/dconic00, 01, 11, dL/d(opacity*p), dL/dr, g, b, dL/dz, 0 x 5,
- *                     blended flag (1 when densification statistics are on and the pair blended) */
+ *                     blended flag (1 when densification statistics are on and the pair blended)
+ *   G4D_DBG_TILE_ORDER per global tile, uint32 tile id in the order the
+ *                     rasterisers' workgroups take them (heavy-first: by
+ *                     decreasing list-length bin); G4D_ESTATE when that order
+ *                     is off (G4D_TUNE_TILE_ORDER = 0) */
 enum {
   G4D_DBG_RECORDS = 1, G4D_DBG_IDS = 2, G4D_DBG_TILE_KEYS = 3, G4D_DBG_TILE_VALS = 4,
-  G4D_DBG_RANGES = 5, G4D_DBG_PIX_T = 6, G4D_DBG_PIX_LAST = 7, G4D_DBG_GRAD2D = 8
+  G4D_DBG_RANGES = 5, G4D_DBG_PIX_T = 6, G4D_DBG_PIX_LAST = 7, G4D_DBG_GRAD2D = 8, G4D_DBG_TILE_ORDER = 9
 };
 g4d_status g4d_debug_size(g4d_ctx* ctx, int32_t what, int64_t* bytes);
 g4d_status g4d_debug_copy(g4d_ctx* ctx, int32_t what, void* host_dst, int64_t bytes);

@@ -519,14 +519,17 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
                 c->ellipse_cull, k32, ev, s);
     radix_sort(k32, ev, a32, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, /*copy_back=*/false, rg);
   }
-  if (passes) launch_ranges_fix(rg, (uint32_t)tiles, s);
   if (c->heavy_first) {
     // workgroups take the tiles with the longest lists first, so the launch
-    // does not end on a few heavy tiles
+    // does not end on a few heavy tiles (its key pass also fixes the ranges
+    // and finds the longest list); the order lands in oval
     for (DevBuf* b : {&c->okey, &c->oval, &c->okey2, &c->oval2})
       if ((st = ensure(c, *b, 4 * (size_t)tiles))) return st;
-    launch_tile_order(P<uint2>(c->ranges), (uint32_t)tiles, P<uint32_t>(c->okey), P<uint32_t>(c->oval),
-                      P<uint32_t>(c->okey2), P<uint32_t>(c->oval2), c->sort_blocks, P<uint32_t>(c->radix_scratch), s);
+    launch_tile_order(rg, (uint32_t)tiles, passes > 0, P<uint32_t>(c->okey), P<uint32_t>(c->oval2),
+                      P<uint32_t>(c->okey2), P<uint32_t>(c->oval), cnt + kCntMaxList, c->sort_blocks, rsc, s);
+  } else {
+    if (passes) launch_ranges_fix(rg, (uint32_t)tiles, s);
+    launch_range_max(rg, (uint32_t)tiles, cnt + kCntMaxList, s);
   }
   stage_end(c, G4D_STAGE_BINNING);
   HIPCHK(c, hipGetLastError());
@@ -537,7 +540,6 @@ g4d_status rasterise_round(g4d_ctx* c, const g4d_ctx::Round& r, float* out_rgb, 
   hipStream_t s = c->stream;
   g4d_status st = join_side(c);  // the records' colours
   if (st) return st;
-  launch_range_max(P<uint2>(c->ranges), (uint32_t)r.tiles, P<uint32_t>(c->counters) + kCntMaxList, s);
   // 9. rasterise the round's views into their places in the outputs
   stage_begin(c);
   static const float kZero3[3] = {0.f, 0.f, 0.f};
@@ -1272,6 +1274,10 @@ g4d_status g4d_debug_size(g4d_ctx* c, int32_t what, int64_t* bytes) {
     case G4D_DBG_RANGES: *bytes = 8ll * r.tiles; break;
     case G4D_DBG_PIX_T: case G4D_DBG_PIX_LAST: *bytes = 4ll * c->total_pix; break;
     case G4D_DBG_GRAD2D: *bytes = 8ll * kGrad2dStride * r.A; break;
+    case G4D_DBG_TILE_ORDER:
+      if (!c->heavy_first) return fail(c, G4D_ESTATE, "the heavy-first tile order is off");
+      *bytes = 4ll * r.tiles;
+      break;
     default: return fail(c, G4D_EINVAL, "unknown debug item");
   }
   return G4D_OK;
@@ -1307,6 +1313,7 @@ g4d_status g4d_debug_copy(g4d_ctx* c, int32_t what, void* host_dst, int64_t byte
     case G4D_DBG_RANGES: src = c->ranges.ptr; break;
     case G4D_DBG_PIX_T: src = c->pix_t.ptr; break;
     case G4D_DBG_PIX_LAST: src = c->pix_last.ptr; break;
+    case G4D_DBG_TILE_ORDER: src = c->oval.ptr; break;
     case G4D_DBG_GRAD2D:
       if (c->grad2d.cap < (size_t)bytes) return fail(c, G4D_ESTATE, "no backward");
       src = c->grad2d.ptr;

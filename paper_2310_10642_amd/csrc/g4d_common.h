@@ -177,9 +177,12 @@ void launch_raster_backward(int total_tiles, const uint32_t* order, uint32_t* qu
                             bool mark_blended, bool cull, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
-// Tile ids by decreasing list length (stable within ~4.4 % length bins) into vals.
-void launch_tile_order(const uint2* ranges, uint32_t tiles, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
-                       uint32_t* vals_alt, int sort_blocks, uint32_t* scratch, hipStream_t s);
+// Tile ids by decreasing list length (stable within ~4.4 % length bins) into
+// order, through the scratch keys, vals and keys_alt. With fix it first
+// empties the ranges the last radix pass did not reach (as launch_ranges_fix),
+// and it raises *max_len to the longest list (as launch_range_max).
+void launch_tile_order(uint2* ranges, uint32_t tiles, bool fix, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                       uint32_t* order, uint32_t* max_len, int sort_blocks, uint32_t* scratch, hipStream_t s);
 
 // ---- launchers (optim.hip) ----
 constexpr int kAdamGroups = 6;

@@ -668,16 +668,34 @@ __global__ void __launch_bounds__(256) k_range_max(const uint2* __restrict__ ran
 
 // Heavy-first tile order: key 255 - floor(16 log2(len + 1)), so that a
 // stable sort of the keys lists tiles by decreasing list length in bins of
-// ~4.4 %, keeping the natural order within a bin.
-__global__ void k_order_keys(const uint2* __restrict__ ranges, uint32_t tiles, uint32_t* __restrict__ keys,
-                             uint32_t* __restrict__ vals) {
+// ~4.4 %, keeping the natural order within a bin. The same pass empties the
+// ranges the last radix pass did not reach (fix, as k_ranges_fix) and raises
+// *max_len to the longest list (as k_range_max).
+__global__ void __launch_bounds__(256) k_order_keys(uint2* __restrict__ ranges, uint32_t tiles, bool fix,
+                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                    uint32_t* max_len) {
+  __shared__ uint32_t s_part[4];
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= tiles) return;
-  const uint2 r = ranges[t];
-  const uint32_t len = r.y - r.x;
-  const uint32_t b = (uint32_t)(16.f * __log2f((float)len + 1.f));
-  keys[t] = 255u - min(b, 255u);
-  vals[t] = t;
+  uint32_t len = 0;
+  if (t < tiles) {
+    uint2 r = ranges[t];
+    if (fix && r.x > r.y) {
+      r = make_uint2(0u, 0u);
+      ranges[t] = r;
+    }
+    len = r.y - r.x;
+    const uint32_t b = (uint32_t)(16.f * __log2f((float)len + 1.f));
+    keys[t] = 255u - min(b, 255u);
+    vals[t] = t;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) len = max(len, (uint32_t)__shfl_xor((int)len, off, 64));
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t m = max(max(s_part[0], s_part[1]), max(s_part[2], s_part[3]));
+    if (m) atomicMax(max_len, m);
+  }
 }
 
 inline unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -805,11 +823,14 @@ void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hip
   hipLaunchKernelGGL(k_sum_u32, dim3(g), dim3(256), 0, s, in, n, out);
 }
 
-void launch_tile_order(const uint2* ranges, uint32_t tiles, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
-                       uint32_t* vals_alt, int sort_blocks, uint32_t* scratch, hipStream_t s) {
+void launch_tile_order(uint2* ranges, uint32_t tiles, bool fix, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                       uint32_t* order, uint32_t* max_len, int sort_blocks, uint32_t* scratch, hipStream_t s) {
   if (tiles == 0) return;
-  hipLaunchKernelGGL(k_order_keys, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles, keys, vals);
-  radix_sort(keys, vals, keys_alt, vals_alt, nullptr, tiles, 0, 8, radix_grid(tiles, sort_blocks), scratch, s);
+  hipLaunchKernelGGL(k_order_keys, dim3(grid_for(tiles, 256)), dim3(256), 0, s, ranges, tiles, fix, keys, vals,
+                     max_len);
+  // one 8-bit pass: the result lands in (keys_alt, order), no copy back
+  radix_sort(keys, vals, keys_alt, order, nullptr, tiles, 0, 8, radix_grid(tiles, sort_blocks), scratch, s,
+             /*copy_back=*/false);
 }
 
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s) {

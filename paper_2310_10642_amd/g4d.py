@@ -24,7 +24,7 @@ G4D_TUNE_ELLIPSE_CULL, G4D_TUNE_PERSISTENT_BLOCKS, G4D_TUNE_LDS_BATCH = 9, 10, 1
 G4D_GRAD_ACCUMULATE = 1
 G4D_LOSS_L1, G4D_LOSS_L2 = 1, 2
 STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd", "loss", "colour"]
-DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_last=7, grad2d=8)
+DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_last=7, grad2d=8, tile_order=9)
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
             "g4d_render", "g4d_render_noalloc", "g4d_render_flow", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",

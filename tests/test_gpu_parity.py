@@ -887,12 +887,24 @@ def test_tile_order_and_autotune():
     ref = r.render(wl.cameras, times)
     dl = torch.from_numpy(np.random.default_rng(56).uniform(-1, 1, ref[0].numel()).astype(np.float32)).cuda()
     g_ref = [x.clone() for x in r.backward(dl)]
+    with pytest.raises(g4d.G4DError):             # no heavy-first order to read
+        r.debug("tile_order")
     r.set_tuning(g4d.G4D_TUNE_TILE_ORDER, 1)
     with pytest.raises(g4d.G4DError):             # the order change invalidated the kept state
         r.backward(dl)
     out = r.render(wl.cameras, times)
     for a, b in zip(ref, out):
         assert torch.equal(a, b)
+    # the order: every tile once, by non-increasing list-length bin
+    order, ranges = r.debug("tile_order").astype(np.int64), r.debug("ranges").astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(len(ranges)))
+    lengths = (ranges[:, 1] - ranges[:, 0])[order].astype(np.float64)
+    # bins of 2^(1/16) in len + 1, heaviest first; one bin of slack for the
+    # device's fast log2 at a bin edge
+    assert (lengths[1:] + 1 <= (lengths[:-1] + 1) * 2 ** (2 / 16)).all()
+    # the longest list is the one the stats report, and the first tile is in its bin
+    assert lengths.max() == r.stats()["max_tile_list"]
+    assert lengths[0] + 1 >= (lengths.max() + 1) * 2 ** (-2 / 16)
     _close_grads(r.backward(dl), g_ref)
     for key, val in ((g4d.G4D_TUNE_PERSISTENT_BLOCKS, -1), (g4d.G4D_TUNE_PERSISTENT_BLOCKS, 37),
                      (g4d.G4D_TUNE_LDS_BATCH, 64), (g4d.G4D_TUNE_LDS_BATCH, 128)):
