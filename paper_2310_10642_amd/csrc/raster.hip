@@ -16,10 +16,10 @@
 // entries up to the last contributor per pixel. The backward pass walks the
 // list back to front from there, recovering T_i = T_{i+1} / (1 - a_i), and
 // works in two phases per batch of 12 primitives: (1) each lane (pixel)
-// writes dL/dpower and a_i T_i for the batch into LDS; (2) three of the four
-// waves regroup as 12 primitives x 16 pixel columns and accumulate the
-// per-primitive sums over the tile's pixels (only over quadrants where the
-// primitive blended).
+// writes dL/dpower and a_i T_i for the batch into LDS; (2) waves 1-3 regroup
+// as 12 primitives x 16 pixel columns and accumulate the per-primitive sums
+// over the tile's pixels (only over quadrants where the primitive blended),
+// while wave 0 stages the next batch.
 // A 16-lane DPP reduce-scatter per batch combines the columns, leaving each
 // of ten lanes of a primitive's row with one value of its gradient line, and
 // those lanes add the tile's share with one FP64 atomic instruction into one
@@ -34,13 +34,14 @@ namespace {
 
 using shade::sc_fma;
 
-// List entries per backward batch (a multiple of 4). 12 rather than 16: the
-// per-(primitive, pixel) buffers then take 26 KB, the workgroup 31.6 KB of LDS,
-// and with at most 96 VGPRs (the launch bound) five workgroups share a CU
-// instead of four; the backward is bound by issue stalls more than by its
-// instruction count, so the fifth wave per SIMD outweighs the third more
-// barriers per entry.
+// List entries per backward batch. 12 rather than 16: the per-(primitive,
+// pixel) buffers then take 26 KB, the workgroup 31.6 KB of LDS, and with at
+// most 96 VGPRs (the launch bound) five workgroups share a CU instead of four;
+// the backward is bound by issue stalls more than by its instruction count,
+// so the fifth wave per SIMD outweighs the third more barriers per entry. The
+// batch's 12 primitives also leave wave 0 free for the staging in phase 2.
 constexpr int kBwdBatch = 12;
+static_assert(kBwdBatch == 12, "phase 2 maps the batch's primitives onto waves 1-3, four each");
 // Backward LDS slots of one primitive's per-pixel values: pixel (row, col) of
 // the tile sits at 16 row + (col ^ 8 [(row >> 1) & 1]); the x-halves of rows
 // 2-3 of every four are swapped so that a wave's 8x8 quadrant (4 rows per
@@ -498,8 +499,8 @@ __global__ void __launch_bounds__(256, 5) k_raster_backward(
     const int e2n = e1 - kBwdBatch;
     if (threadIdx.x < kBwdBatch && e2n >= 0) nn_d = ival[rg.x + e2n];
   }
-  int buf = 0, rot = 0;
-  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1, rot = (rot + 1) & 3) {
+  int buf = 0;
+  for (int b0 = b_first; b0 >= 0; b0 -= kBwdBatch, buf ^= 1) {
     // the stage buffer's first entry as a vector register, so each entry's
     // LDS reads in phase 1 are immediate offsets from it
     int bv;
@@ -558,12 +559,12 @@ __global__ void __launch_bounds__(256, 5) k_raster_backward(
     if (lane == 0) s_act[wave] = blended;
     __syncthreads();
     // ---- phase 2: primitive j2, pixel column c2, rows of active quadrants ----
-    // Wave w takes primitives 4 r .. 4 r + 3, r = (w + batch index) mod 4: in a
-    // batch of fewer than 16 entries a different wave (so a different SIMD)
-    // has no primitive in each batch.
-    const int rank = (wave + rot) & 3;
+    // Waves 1-3 take primitives 4 (w - 1) .. 4 (w - 1) + 3; wave 0, which
+    // stages the next batch below, takes none, so the waves reach the next
+    // barrier together.
+    const int rank = wave - 1;
     const int j2 = 4 * rank + (lane >> 4);
-    const bool p2 = j2 < kBwdBatch;  // wave-uniform
+    const bool p2 = wave > 0;  // wave-uniform
     const int e2 = b0 + j2;
     const bool live = p2 && e2 < count;
     int slot_q = -1;
