@@ -325,7 +325,6 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
                                              uint32_t n_out, K* __restrict__ keys_out,
                                              uint32_t* __restrict__ vals_out, uint2* __restrict__ ranges) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t mask = (1u << bits) - 1u;
   const uint32_t dg = threadIdx.x;
   __syncthreads();
@@ -338,18 +337,26 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
   for (int i = 0; i < kItems; ++i) {
     const bool valid = base + (uint32_t)i * 64 + lane < nvalid;
     const uint32_t d = (k[i] >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    // digits have at most 8 bits; bits above `bits` are zero in every lane
+    // the lanes holding the same digit (a lane mask in two halves): per digit
+    // bit, a lane keeps the lanes whose bit equals its own. S is the lane's
+    // bit b as a whole-word mask, so each step is one compare for the ballot
+    // and one three-input bit operation per half. Digits have at most 8
+    // bits; bits above `bits` are zero in every lane.
+    const uint64_t vb = __ballot(valid);
+    uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool set = (d >> b) & 1u;
-      const uint64_t m = __ballot(set);
-      peers &= set ? m : ~m;
+      const int32_t S = (int32_t)(d << (31 - b)) >> 31;
+      const uint64_t m = __ballot(S < 0);
+      // x & ~(y ^ z): truth table 0x90 with operands (x, y, z)
+      plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)m, (uint32_t)S, 0x90);
+      phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(m >> 32), (uint32_t)S, 0x90);
     }
-    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    // equal-digit lanes below this one
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
     const uint32_t pre = sh.wcnt[wave][d];
     rank[i] = pre + below;
-    if (valid && below == 0) sh.wcnt[wave][d] = pre + (uint32_t)__popcll(peers);
+    if (valid && below == 0) sh.wcnt[wave][d] = pre + (uint32_t)(__popc(plo) + __popc(phi));
   }
   __syncthreads();
   // per digit: tile-local start, then each wave's start inside it
