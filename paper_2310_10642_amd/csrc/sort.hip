@@ -37,7 +37,9 @@ struct Footprint {
 };
 
 // Footprint and row_span are written with explicit rounding and no
-// contraction, so the instance count of a record and its emission agree.
+// contraction, so the instance count of a record and its emission agree. The
+// square roots are the hardware instruction (within about an ulp; it is the
+// same instruction in both kernels, and far inside the spans' slack).
 __device__ __forceinline__ Footprint footprint(const Record& r) {
 #pragma clang fp contract(off)
   Footprint f;
@@ -52,8 +54,8 @@ __device__ __forceinline__ Footprint footprint(const Record& r) {
   f.D = __fsub_rn(__fmaf_rn(a, c, -p), __fmaf_rn(f.b, f.b, -p));  // product error recovered
   f.ia = __builtin_amdgcn_rcpf(a);
   const float iD = __builtin_amdgcn_rcpf(f.D);
-  f.ymax = __fsqrt_rn(fmaxf(__fmul_rn(__fmul_rn(f.L, a), iD), 0.f));
-  const float xmax = __fsqrt_rn(fmaxf(__fmul_rn(__fmul_rn(f.L, c), iD), 0.f));
+  f.ymax = __builtin_amdgcn_sqrtf(fmaxf(__fmul_rn(__fmul_rn(f.L, a), iD), 0.f));
+  const float xmax = __builtin_amdgcn_sqrtf(fmaxf(__fmul_rn(__fmul_rn(f.L, c), iD), 0.f));
   f.ey = __fmul_rn(__fmul_rn(f.b, xmax), __builtin_amdgcn_rcpf(c));
   if (!(f.L > 0.f) || !(f.D > 0.f) || !(f.ymax >= 0.f)) f.ymax = -1.f;  // no tile
   f.L = __fmul_rn(a, f.L);                           // kept as a L from here on
@@ -85,8 +87,8 @@ __device__ __forceinline__ void row_span(const Footprint& f, uint32_t ty, bool e
   const float lo = fmaxf(band0, -f.ymax), hi = fminf(band1, f.ymax);
   if (!(lo <= hi)) return;
   const float dl = fminf(fmaxf(f.ey, lo), hi), dr = fminf(fmaxf(-f.ey, lo), hi);
-  const float sl = __fsqrt_rn(fmaxf(__fsub_rn(f.L, __fmul_rn(f.D, __fmul_rn(dl, dl))), 0.f));
-  const float sr = __fsqrt_rn(fmaxf(__fsub_rn(f.L, __fmul_rn(f.D, __fmul_rn(dr, dr))), 0.f));
+  const float sl = __builtin_amdgcn_sqrtf(fmaxf(__fsub_rn(f.L, __fmul_rn(f.D, __fmul_rn(dl, dl))), 0.f));
+  const float sr = __builtin_amdgcn_sqrtf(fmaxf(__fsub_rn(f.L, __fmul_rn(f.D, __fmul_rn(dr, dr))), 0.f));
   const float left = __fadd_rn(f.u, __fmul_rn(__fsub_rn(-__fmul_rn(f.b, dl), sl), f.ia));
   const float right = __fadd_rn(f.u, __fmul_rn(__fadd_rn(-__fmul_rn(f.b, dr), sr), f.ia));
   // tile tx holds centres 16 tx + [0.5, 15.5]
