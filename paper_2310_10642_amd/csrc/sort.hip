@@ -430,13 +430,23 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__
   for (uint32_t t = t0; t < t1; ++t) {
     const size_t base = (size_t)t * kTileElems + (size_t)wave * (kTileElems / 4);
     uint32_t k[kItems], v[kItems];
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const size_t idx = base + (size_t)i * 64 + lane;
-      k[i] = (idx < n) ? (uint32_t)keys_in[idx] : 0u;
-      v[i] = (idx < n) ? vals_in[idx] : 0u;
-    }
     const uint32_t nvalid = (uint32_t)min((size_t)kTileElems, (size_t)n - (size_t)t * kTileElems);
+    if (nvalid == (uint32_t)kTileElems) {
+      // a full tile (all but the last): no per-key bounds test
+#pragma unroll
+      for (int i = 0; i < kItems; ++i) {
+        const size_t idx = base + (size_t)i * 64 + lane;
+        k[i] = (uint32_t)keys_in[idx];
+        v[i] = vals_in[idx];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kItems; ++i) {
+        const size_t idx = base + (size_t)i * 64 + lane;
+        k[i] = (idx < n) ? (uint32_t)keys_in[idx] : 0u;
+        v[i] = (idx < n) ? vals_in[idx] : 0u;
+      }
+    }
     scatter_tile(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
   }
 }
