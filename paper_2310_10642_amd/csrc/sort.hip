@@ -321,7 +321,8 @@ __device__ __forceinline__ void scatter_begin(ScatterShared<K>& sh, const uint32
 // digit d so far (bounded by n_out); with ranges (the last pass over the
 // whole key) the keys are not written: each key's first and last position
 // bound its range instead.
-template <typename K>
+// FULL: the tile holds kTileElems valid pairs (the validity tests compile out).
+template <bool FULL, typename K>
 __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_t (&k)[kItems],
                                              const uint32_t (&v)[kItems], uint32_t nvalid, int shift, int bits,
                                              uint32_t n_out, K* __restrict__ keys_out,
@@ -337,7 +338,7 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
   uint32_t rank[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    const bool valid = base + (uint32_t)i * 64 + lane < nvalid;
+    const bool valid = FULL || base + (uint32_t)i * 64 + lane < nvalid;
     const uint32_t d = (k[i] >> shift) & mask;
     // the lanes holding the same digit (a lane mask in two halves): per digit
     // bit, a lane keeps the lanes whose bit equals its own. S is the lane's
@@ -374,7 +375,7 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    const bool valid = base + (uint32_t)i * 64 + lane < nvalid;
+    const bool valid = FULL || base + (uint32_t)i * 64 + lane < nvalid;
     if (valid) {
       const uint32_t d = (k[i] >> shift) & mask;
       const uint32_t lp = sh.wcnt[wave][d] + rank[i];
@@ -385,7 +386,7 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
     }
   }
   __syncthreads();
-  const uint32_t nt = min(nvalid, (uint32_t)kTileElems);
+  const uint32_t nt = FULL ? (uint32_t)kTileElems : min(nvalid, (uint32_t)kTileElems);
 #pragma unroll 4
   for (int i = 0; i < kItems; ++i) {
     const uint32_t lp = (uint32_t)i * kThreads + threadIdx.x;
@@ -439,6 +440,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__
         k[i] = (uint32_t)keys_in[idx];
         v[i] = vals_in[idx];
       }
+      scatter_tile<true>(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
     } else {
 #pragma unroll
       for (int i = 0; i < kItems; ++i) {
@@ -446,8 +448,8 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__
         k[i] = (idx < n) ? (uint32_t)keys_in[idx] : 0u;
         v[i] = (idx < n) ? vals_in[idx] : 0u;
       }
+      scatter_tile<false>(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
     }
-    scatter_tile(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
   }
 }
 
