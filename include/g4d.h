@@ -298,8 +298,9 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *
  * The rasteriser knobs of a (lds_batch, split_threshold, persistent_blocks)
  * tuning call map to these keys: lds_batch -> G4D_TUNE_LDS_BATCH (the
- * backward stages 16 entries at a time, fixed by its 16-primitive x
- * 16-column second phase); persistent_blocks -> G4D_TUNE_PERSISTENT_BLOCKS;
+ * forward's batch; the backward stages 12 entries at a time, fixed by its
+ * LDS budget of five workgroups per CU and its 12-primitive x 16-column
+ * second phase); persistent_blocks -> G4D_TUNE_PERSISTENT_BLOCKS;
  * split_threshold has no key: heavy tiles are not split. A wave owns an 8x8
  * quarter of its tile, so a split would not shorten its longest walk, and
  * with the tiles taken heaviest first the launch does not end on one heavy
