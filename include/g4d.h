@@ -241,7 +241,8 @@ g4d_status g4d_image_loss(g4d_ctx* ctx, int32_t kind, int64_t n, const float* im
 g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view);
 
 /* Tuning knobs (key, value); unknown keys give G4D_EINVAL.
- *   G4D_TUNE_SORT_BLOCKS   max workgroups of each radix-sort pass (>= 1)
+ *   G4D_TUNE_SORT_BLOCKS   max workgroups of each radix-sort pass (>= 1;
+ *                          default 1280)
  *   G4D_TUNE_STAGE_TIMING  1: bracket every stage with HIP events on the
  *                          context's stream (resets the totals); 0: off
  *   G4D_TUNE_ROUND_PAIRS     max (view, primitive) pairs per round (>= 1;
@@ -290,7 +291,7 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
  *   G4D_TUNE_AUTOTUNE      1: the next render that is not being captured
  *                          first times its batch (once, then twice with HIP
  *                          events per candidate) under, in turn,
- *                          G4D_TUNE_SORT_BLOCKS in {256, 512, 1024, 2048},
+ *                          G4D_TUNE_SORT_BLOCKS in {512, 1024, 1280, 2048},
  *                          G4D_TUNE_TILE_ORDER x G4D_TUNE_PERSISTENT_BLOCKS
  *                          in {0, 1} x {0, -1}, and G4D_TUNE_LDS_BATCH in
  *                          {64, 128, 256}, keeping the fastest of each group

@@ -57,7 +57,9 @@ struct g4d_ctx {
   uint64_t A_total = 0, I_total = 0;
   std::vector<uint32_t> view_active;
   uint32_t active_hint = 0;      // most active records seen in one view (sizes the depth sort's grid)
-  int sort_blocks = 1024;
+  // five radix-sort workgroups per CU: the 16-bit downsweep's LDS (30 KB) and
+  // registers (83) let five share a CU, and its blocks then fill them at once
+  int sort_blocks = 1280;
   int64_t round_pairs = int64_t(1) << 28;
   int64_t round_instances = int64_t(1) << 30;
   bool sync_free = false;          // no host read of device counts inside render/backward
@@ -493,8 +495,8 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   const int tile_bits = ceil_log2((uint32_t)tiles);
   const int passes = radix_passes(0, tile_bits);
   const bool odd = passes & 1;
-  if (passes) launch_ranges_init(P<uint2>(c->ranges), (uint32_t)tiles, s);
-  else launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
+  // with sort passes the emission starts the ranges (see launch_emit)
+  if (!passes) launch_fill_u32(P<uint32_t>(c->ranges), 2 * (uint64_t)tiles, 0u, s);
   void* ek = (odd ? c->ikey2 : c->ikey).ptr;
   void* ak = (odd ? c->ikey : c->ikey2).ptr;
   uint32_t* ev = P<uint32_t>(odd ? c->ival2 : c->ival);
@@ -505,19 +507,21 @@ g4d_status bin_tiles(g4d_ctx* c, int tiles, uint32_t a_max, uint32_t cap) {
   const int g_tile = radix_grid(cap, c->sort_blocks);
   uint32_t* rsc = P<uint32_t>(c->radix_scratch);
   uint2* rg = P<uint2>(c->ranges);
+  uint2* rg_init = passes ? rg : nullptr;
   // a round's tile ids fit 16 bits unless one view alone has more tiles;
   // 16-bit keys take a quarter off the sort's bytes per instance
   if (tile_bits <= 16) {
     uint16_t *k16 = static_cast<uint16_t*>(ek), *a16 = static_cast<uint16_t*>(ak);
     launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, rs, ids, (int)c->n, vd,
-                c->ellipse_cull, k16, ev, s);
-    if (passes) radix_sort16(k16, ev, a16, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, rg);
+                c->ellipse_cull, k16, ev, rg_init, (uint32_t)tiles, s);
+    if (passes) radix_sort16(k16, ev, a16, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, rg, (uint32_t)tiles);
     else launch_ranges(cnt + kCntI, cap, k16, rg, s);
   } else {
     uint32_t *k32 = static_cast<uint32_t*>(ek), *a32 = static_cast<uint32_t*>(ak);
     launch_emit(cnt + kCntA, a_max, P<uint32_t>(c->toff), cnt + kCntI, cap, rs, ids, (int)c->n, vd,
-                c->ellipse_cull, k32, ev, s);
-    radix_sort(k32, ev, a32, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, /*copy_back=*/false, rg);
+                c->ellipse_cull, k32, ev, rg_init, (uint32_t)tiles, s);
+    radix_sort(k32, ev, a32, av, cnt + kCntI, cap, 0, tile_bits, g_tile, rsc, s, /*copy_back=*/false, rg,
+               (uint32_t)tiles);
   }
   if (c->heavy_first) {
     // workgroups take the tiles with the longest lists first, so the launch
@@ -621,7 +625,7 @@ g4d_status autotune(g4d_ctx* c, int32_t n_views, const g4d_camera* cams, const f
     first = false;
     return G4D_OK;
   };
-  const int blocks[] = {256, 512, 1024, 2048};
+  const int blocks[] = {512, 1024, 1280, 2048};
   const int batches[] = {64, 128, 256};
   if (!st) st = pick(4, [&](int i) { c->sort_blocks = blocks[i]; });
   if (!st)
@@ -919,8 +923,8 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
       const int k = cap_round_tiles(c, v0, std::min(by_pairs, n_views - v0));
       g4d_ctx::Round r{v0, v0 + k, round_tiles(c, v0, v0 + k), kOnDevice, kOnDevice};
       if ((st = enqueue_pairs(c, v0, v0 + k, true))) return st;
-      launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s);
-      launch_add_totals(cnt + kCntA, cnt + kCntI, cnt + kCntTot, cnt + kCntTot + 2, s);
+      launch_cap_check(cnt + kCntInst64, cnt + kCntI, cnt + kCntOverflow, cap, s, cnt + kCntA, cnt + kCntTot,
+                       cnt + kCntTot + 2);
       if ((st = bin_tiles(c, r.tiles, (uint32_t)((uint64_t)c->n * k), (uint32_t)cap))) return st;
       c->rounds.push_back(r);
       c->bound = (int)c->rounds.size() - 1;

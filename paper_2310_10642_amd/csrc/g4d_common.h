@@ -123,20 +123,21 @@ void launch_scan(const uint32_t* in, uint32_t* out, const uint32_t* n_dev, uint3
 // LSD radix sort of (key, value) pairs on bits [bit0, bit1) in 8-bit passes
 // that ping-pong via alt; the result ends in keys/vals, copied back after an
 // odd number of passes unless copy_back is false (then it is in the alt pair).
-// With last_ranges (keys < 2^bit1, bit0 = 0, at least one pass, ranges set up
-// by launch_ranges_init) the last pass writes no keys: it bounds each key's
-// run in last_ranges[key] instead (launch_ranges_fix then empties the unused).
+// With last_ranges (n_ranges entries, keys < 2^bit1, bit0 = 0, at least one
+// pass, ranges set to (~0u, 0) by launch_ranges_init or the emission) the last
+// pass writes no keys: it bounds each key's run in last_ranges[key] instead
+// (launch_ranges_fix then empties the unused); a key >= n_ranges is skipped.
 size_t radix_scratch_words(int grid);
 int radix_grid(uint32_t n_max, int max_blocks);
 int radix_passes(int bit0, int bit1);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                 uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
-                bool copy_back = true, uint2* last_ranges = nullptr);
+                bool copy_back = true, uint2* last_ranges = nullptr, uint32_t n_ranges = 0);
 // The same with 16-bit keys (bit1 <= 16), without the copy back: after an odd
 // number of passes the result is in (keys_alt, vals_alt).
 void radix_sort16(uint16_t* keys, uint32_t* vals, uint16_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                   uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
-                  uint2* last_ranges = nullptr);
+                  uint2* last_ranges = nullptr, uint32_t n_ranges = 0);
 void launch_ranges_init(uint2* ranges, uint32_t tiles, hipStream_t s);
 void launch_ranges_fix(uint2* ranges, uint32_t tiles, hipStream_t s);
 // Depth-ordered records, slot map (view*n + index -> depth position), tiles per record,
@@ -147,13 +148,15 @@ void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, c
 void launch_view_counts(const uint32_t* pos, int n_views, uint32_t n, const uint32_t* total, uint32_t* out,
                         hipStream_t s);
 // Instances beyond min(*total, cap) are not written; exact as for launch_gather.
-// Keys are 16-bit when the round's tile ids are below 2^16, else 32-bit.
+// Keys are 16-bit when the round's tile ids are below 2^16, else 32-bit. With
+// ranges_init, the launch also sets ranges_init[0..tiles) to (~0u, 0), the
+// start state of the ranges the sort's last pass fills.
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
-                 uint32_t* ikey, uint32_t* ival, hipStream_t s);
+                 uint32_t* ikey, uint32_t* ival, uint2* ranges_init, uint32_t tiles, hipStream_t s);
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
-                 uint16_t* ikey, uint32_t* ival, hipStream_t s);
+                 uint16_t* ikey, uint32_t* ival, uint2* ranges_init, uint32_t tiles, hipStream_t s);
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ikey, uint2* ranges, hipStream_t s);
 void launch_ranges(const uint32_t* n_dev, uint32_t n_max, const uint16_t* ikey, uint2* ranges, hipStream_t s);
 
@@ -206,10 +209,11 @@ void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t s);
 // Zeroes floats_per_item (a multiple of 4) floats per item for min(*n_dev, max_items) items.
 void launch_zero_counted(float* p, const uint32_t* n_dev, uint32_t floats_per_item, uint64_t max_items,
                          hipStream_t s);
-// If the 64-bit instance total at inst64 exceeds cap: *overflow = 1 and *n_inst = 0.
-void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s);
-// *a_tot += *a; *(uint64*)i_tot64 += *i (one thread).
-void launch_add_totals(const uint32_t* a, const uint32_t* i, uint32_t* a_tot, uint32_t* i_tot64, hipStream_t s);
+// If the 64-bit instance total at inst64 exceeds cap: *overflow = 1 and
+// *n_inst = 0. Then, with a_tot: *a_tot += *a and *(uint64*)i_tot64 += *n_inst
+// (one thread).
+void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s,
+                      const uint32_t* a = nullptr, uint32_t* a_tot = nullptr, uint32_t* i_tot64 = nullptr);
 void launch_copy_pairs(const uint32_t* ka, const uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
                        uint32_t n_max, hipStream_t s);
 

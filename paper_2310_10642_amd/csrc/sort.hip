@@ -12,6 +12,7 @@
 //   3. stable radix sort of the instances by global tile id.
 // Every pass is stable, so the result equals a stable sort by (tile, depth)
 // of the instances emitted in (view, index) order.
+#include <algorithm>
 #include <utility>
 #include "g4d_common.h"
 
@@ -21,6 +22,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kTileElems = kThreads * kItems;  // 4096 elements per block tile
+static_assert(kTileElems == 4 * 1024, "the scan tile is four waves of 1024 elements");
 
 __device__ __forceinline__ uint32_t dev_n(const uint32_t* n_dev, uint32_t n_max) {
   return n_dev ? min(*n_dev, n_max) : n_max;
@@ -123,17 +125,42 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 }
 
 // ---------------------------------------------------------------- scan ----
+// The scan's block tile: wave w holds elements [1024 w, 1024 w + 1024) of the
+// tile, and lane l the four 16-byte groups 256 j + 4 l (j = 0..3), so every
+// load and store instruction of a wave covers 1 KB of consecutive words and
+// the element order is (wave, group, lane, word). The arrays are the
+// library's own 256-byte-aligned buffers, so a full tile's groups are aligned.
+__device__ __forceinline__ size_t scan_group(int j) {
+  return (size_t)(threadIdx.x >> 6) * 1024 + (size_t)j * 256 + (size_t)(threadIdx.x & 63) * 4;
+}
+
+__device__ __forceinline__ uint4 load_group(const uint32_t* __restrict__ p, size_t e, size_t n, bool full) {
+  if (full) return *reinterpret_cast<const uint4*>(p + e);
+  return make_uint4(e < n ? p[e] : 0u, e + 1 < n ? p[e + 1] : 0u, e + 2 < n ? p[e + 2] : 0u, e + 3 < n ? p[e + 3] : 0u);
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
 __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* n_dev,
                                                            uint32_t n_max, uint32_t* __restrict__ bsum) {
   __shared__ uint32_t s_wave[4];
   const uint32_t n = dev_n(n_dev, n_max);
   const size_t base = (size_t)blockIdx.x * kTileElems;
   if (base >= n) return;
+  const bool full = base + kTileElems <= n;
   uint32_t acc = 0;
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const size_t idx = base + (size_t)i * kThreads + threadIdx.x;
-    if (idx < n) acc += in[idx];
+  for (int j = 0; j < 4; ++j) {
+    const uint4 g = load_group(in, base + scan_group(j), n, full);
+    acc += g.x + g.y + g.z + g.w;
   }
   uint32_t total;
   block_exclusive_scan(acc, s_wave, total);
@@ -144,7 +171,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __rest
 // sums before it, added up by the block's own threads (no separate pass over
 // the block sums), and the last block writes the total. With ckey, the input
 // is a 0/1 flag per element and every flagged element i also lands in the
-// compacted arrays: ckey[out[i]] = dkey[i], cval[out[i]] = i.
+// compacted arrays: ckey[out[i]] = dkey[i], cval[out[i]] = i (the flagged
+// lanes of one store instruction write a short increasing run of positions).
 __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                           const uint32_t* n_dev, uint32_t n_max,
                                                           const uint32_t* __restrict__ bsum,
@@ -160,26 +188,56 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restr
   for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kThreads) part += bsum[b];
   uint32_t prefix;
   block_exclusive_scan(part, s_wave, prefix);  // contains barriers; prefix = the block sums before this block
-  const size_t base = (size_t)blockIdx.x * kTileElems + (size_t)threadIdx.x * kItems;
-  uint32_t v[kItems];
-  uint32_t acc = 0;
+  const size_t base = (size_t)blockIdx.x * kTileElems;
+  const bool full = base + kTileElems <= n;
+  uint4 g[4];
+  uint32_t gx[4];  // each group's exclusive offset within the wave
+  uint32_t wsum = 0;
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : 0u;
-    acc += v[i];
+  for (int j = 0; j < 4; ++j) {
+    g[j] = load_group(in, base + scan_group(j), n, full);
+    const uint32_t s = g[j].x + g[j].y + g[j].z + g[j].w;
+    const uint32_t inc = wave_inclusive_scan(s);
+    gx[j] = wsum + inc - s;
+    wsum += __shfl(inc, 63, 64);
   }
-  uint32_t tot;
-  uint32_t run = block_exclusive_scan(acc, s_wave, tot) + prefix;
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_wave[wave] = wsum;
+  __syncthreads();
+  uint32_t wbase = prefix, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    if (base + i < n) {
-      out[base + i] = run;
-      if (ckey && v[i]) {
-        ckey[run] = dkey[base + i];
-        cval[run] = (uint32_t)(base + i);
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint32_t c = s_wave[w];
+    wbase += (w < wave) ? c : 0u;
+    tot += c;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const size_t e = base + scan_group(j);
+    const uint32_t v[4] = {g[j].x, g[j].y, g[j].z, g[j].w};
+    uint32_t o[4];
+    uint32_t run = wbase + gx[j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[i] = run;
+      run += v[i];
+    }
+    if (full) {
+      *reinterpret_cast<uint4*>(out + e) = make_uint4(o[0], o[1], o[2], o[3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (e + i < n) out[e + i] = o[i];
+    }
+    if (ckey) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (v[i]) {  // a flagged element lies below n
+          ckey[o[i]] = dkey[e + i];
+          cval[o[i]] = (uint32_t)(e + i);
+        }
       }
     }
-    run += v[i];
   }
   if (blockIdx.x + 1 == nb && threadIdx.x == 0) *total = prefix + tot;
 }
@@ -323,10 +381,11 @@ __device__ __forceinline__ void scatter_begin(ScatterShared<K>& sh, const uint32
 // bound its range instead.
 // FULL: the tile holds kTileElems valid pairs (the validity tests compile out).
 template <bool FULL, typename K>
-__device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_t (&k)[kItems],
+__device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, uint32_t (&k)[kItems],
                                              const uint32_t (&v)[kItems], uint32_t nvalid, int shift, int bits,
                                              uint32_t n_out, K* __restrict__ keys_out,
-                                             uint32_t* __restrict__ vals_out, uint2* __restrict__ ranges) {
+                                             uint32_t* __restrict__ vals_out, uint2* __restrict__ ranges,
+                                             uint32_t n_ranges) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t mask = (1u << bits) - 1u;
   const uint32_t dg = threadIdx.x;
@@ -335,6 +394,7 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
   for (int w = 0; w < 4; ++w) sh.wcnt[w][threadIdx.x] = 0u;
   __syncthreads();
   const uint32_t base = (uint32_t)wave * (kTileElems / 4);
+  constexpr bool kPacked = sizeof(K) == 2;
   uint32_t rank[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
@@ -358,8 +418,21 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
     // equal-digit lanes below this one
     const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
     const uint32_t pre = sh.wcnt[wave][d];
-    rank[i] = pre + below;
-    if (valid && below == 0) sh.wcnt[wave][d] = pre + (uint32_t)(__popc(plo) + __popc(phi));
+    // a 16-bit key shares its register with its rank (< 4096). The empty asm
+    // makes the rank final here: left to itself the compiler defers the sum
+    // past the barrier and keeps each step's masks and count live until then
+    if (kPacked) {
+      k[i] |= (pre + below) << 16;
+      asm volatile("" : "+v"(k[i]));
+    } else {
+      rank[i] = pre + below;
+      asm volatile("" : "+v"(rank[i]));
+    }
+    // every lane of a digit writes the same count; in a full tile without a
+    // branch, so the next step's ballots can overlap this step's LDS access
+    const uint32_t cnt = pre + (uint32_t)(__popc(plo) + __popc(phi));
+    if (FULL) sh.wcnt[wave][d] = cnt;
+    else if (valid && below == 0) sh.wcnt[wave][d] = cnt;
   }
   __syncthreads();
   // per digit: tile-local start, then each wave's start inside it
@@ -377,10 +450,11 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
   for (int i = 0; i < kItems; ++i) {
     const bool valid = FULL || base + (uint32_t)i * 64 + lane < nvalid;
     if (valid) {
-      const uint32_t d = (k[i] >> shift) & mask;
-      const uint32_t lp = sh.wcnt[wave][d] + rank[i];
+      const uint32_t key = kPacked ? (k[i] & 0xFFFFu) : k[i];
+      const uint32_t d = (key >> shift) & mask;
+      const uint32_t lp = sh.wcnt[wave][d] + (kPacked ? k[i] >> 16 : rank[i]);
       if (lp < (uint32_t)kTileElems) {
-        sh.k[lp] = (K)k[i];
+        sh.k[lp] = (K)key;
         sh.v[lp] = v[i];
       }
     }
@@ -398,8 +472,10 @@ __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, const uint32_
         if (ranges) {
           // the staged tile is ordered by key, so the first and last of each
           // key's run here bound its range
-          if (lp == 0 || sh.k[lp - 1] != key) atomicMin(&ranges[key].x, p);
-          if (lp + 1 == nt || sh.k[lp + 1] != key) atomicMax(&ranges[key].y, p + 1);
+          if (key < n_ranges) {
+            if (lp == 0 || sh.k[lp - 1] != key) atomicMin(&ranges[key].x, p);
+            if (lp + 1 == nt || sh.k[lp + 1] != key) atomicMax(&ranges[key].y, p + 1);
+          }
         } else {
           keys_out[p] = (K)key;
         }
@@ -421,7 +497,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__
                                                             uint32_t n_max, int shift, int bits,
                                                             const uint32_t* __restrict__ counts,
                                                             const uint32_t* __restrict__ digit_tot,
-                                                            uint2* __restrict__ ranges) {
+                                                            uint2* __restrict__ ranges, uint32_t n_ranges) {
   __shared__ ScatterShared<K> sh;
   const uint32_t n = dev_n(n_dev, n_max);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -440,7 +516,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__
         k[i] = (uint32_t)keys_in[idx];
         v[i] = vals_in[idx];
       }
-      scatter_tile<true>(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
+      scatter_tile<true>(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges, n_ranges);
     } else {
 #pragma unroll
       for (int i = 0; i < kItems; ++i) {
@@ -448,7 +524,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_downsweep(const K* __restrict__
         k[i] = (idx < n) ? (uint32_t)keys_in[idx] : 0u;
         v[i] = (idx < n) ? vals_in[idx] : 0u;
       }
-      scatter_tile<false>(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges);
+      scatter_tile<false>(sh, k, v, nvalid, shift, bits, n, keys_out, vals_out, ranges, n_ranges);
     }
   }
 }
@@ -514,7 +590,8 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
                                                     uint32_t cap, const Record* __restrict__ rec_sorted,
                                                     const uint32_t* __restrict__ ids, uint32_t n_prims,
                                                     const ViewDev* __restrict__ views, bool exact,
-                                                    K* __restrict__ ikey, uint32_t* __restrict__ ival) {
+                                                    K* __restrict__ ikey, uint32_t* __restrict__ ival,
+                                                    uint2* __restrict__ ranges_init, uint32_t tiles) {
   __shared__ uint32_t offs[kEmitRecs + 1];
   __shared__ uint32_t s_rbase[kEmitRecs + 1];
   __shared__ uint32_t s_tb[kEmitRecs], s_tw[kEmitRecs];
@@ -525,6 +602,10 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
   __shared__ uint16_t s_inst_row[kEmitInst];     // row of each instance of the chunk (< kEmitRows)
   static_assert(kEmitRecs <= 256 && kEmitRows <= 65536, "narrow LDS maps: 21 KB, 7 workgroups per CU");
   __shared__ uint32_t s_wave[4];
+  // the tile ranges that the sort's last pass fills start empty
+  if (ranges_init)
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < tiles; t += gridDim.x * kThreads)
+      ranges_init[t] = make_uint2(0xFFFFFFFFu, 0u);
   const uint32_t n = dev_n(n_dev, n_max);
   const uint32_t d0 = blockIdx.x * kEmitRecs;
   if (d0 >= n) return;
@@ -753,15 +834,22 @@ int radix_passes(int bit0, int bit1) { return bit1 > bit0 ? (bit1 - bit0 + 7) / 
 template <typename K>
 std::pair<K*, uint32_t*> radix_passes_run(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt,
                                           const uint32_t* n_dev, uint32_t n_max, int bit0, int bit1, int grid,
-                                          uint32_t* scratch, hipStream_t s, uint2* last_ranges) {
+                                          uint32_t* scratch, hipStream_t s, uint2* last_ranges,
+                                          uint32_t n_ranges) {
   K *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
+  // the row scan's block is as wide as a row of the count matrix (one count
+  // per sort block, at most 1024 threads), so a small grid's scan leaves the
+  // CUs to the other stream's waves
+  const unsigned scan_threads = (unsigned)std::min(1024, std::max(64, (grid + 63) / 64 * 64));
   for (int b = bit0; b < bit1; b += 8) {
     const int bits = (bit1 - b) < 8 ? (bit1 - b) : 8;
     hipLaunchKernelGGL(k_rs_upsweep<K>, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
-    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(1024), 0, s, scratch, grid, scratch + (size_t)256 * grid);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(scan_threads), 0, s, scratch, grid,
+                       scratch + (size_t)256 * grid);
     hipLaunchKernelGGL(k_rs_downsweep<K>, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b,
-                       bits, scratch, scratch + (size_t)256 * grid, b + 8 >= bit1 ? last_ranges : nullptr);
+                       bits, scratch, scratch + (size_t)256 * grid, b + 8 >= bit1 ? last_ranges : nullptr,
+                       b + 8 >= bit1 && last_ranges ? n_ranges : 0u);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
@@ -770,18 +858,19 @@ std::pair<K*, uint32_t*> radix_passes_run(K* keys, uint32_t* vals, K* keys_alt, 
 
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                 uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s, bool copy_back,
-                uint2* last_ranges) {
+                uint2* last_ranges, uint32_t n_ranges) {
   // an odd pass count ends with a copy back so the result is in (keys, vals),
   // unless the caller takes it from (keys_alt, vals_alt)
   const auto out = radix_passes_run(keys, vals, keys_alt, vals_alt, n_dev, n_max, bit0, bit1, grid, scratch, s,
-                                    last_ranges);
+                                    last_ranges, n_ranges);
   if (out.first != keys && copy_back) launch_copy_pairs(out.first, out.second, keys, vals, n_dev, n_max, s);
 }
 
 void radix_sort16(uint16_t* keys, uint32_t* vals, uint16_t* keys_alt, uint32_t* vals_alt, const uint32_t* n_dev,
                   uint32_t n_max, int bit0, int bit1, int grid, uint32_t* scratch, hipStream_t s,
-                  uint2* last_ranges) {
-  radix_passes_run(keys, vals, keys_alt, vals_alt, n_dev, n_max, bit0, bit1, grid, scratch, s, last_ranges);
+                  uint2* last_ranges, uint32_t n_ranges) {
+  radix_passes_run(keys, vals, keys_alt, vals_alt, n_dev, n_max, bit0, bit1, grid, scratch, s, last_ranges,
+                   n_ranges);
 }
 
 void launch_gather(const uint32_t* n_dev, uint32_t n_max, const uint32_t* ids, const Record* rec, Record* rec_sorted,
@@ -799,22 +888,27 @@ void launch_view_counts(const uint32_t* pos, int n_views, uint32_t n, const uint
 template <typename K>
 void emit_keys(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact, K* ikey,
-               uint32_t* ival, hipStream_t s) {
-  if (n_max == 0) return;
+               uint32_t* ival, uint2* ranges_init, uint32_t tiles, hipStream_t s) {
+  if (n_max == 0) {
+    if (ranges_init) launch_ranges_init(ranges_init, tiles, s);
+    return;
+  }
   hipLaunchKernelGGL(k_emit<K>, dim3(grid_for(n_max, kEmitRecs)), dim3(kThreads), 0, s, n_dev, n_max, toff, total,
-                     cap, rec_sorted, ids, (uint32_t)n_prims, views, exact, ikey, ival);
+                     cap, rec_sorted, ids, (uint32_t)n_prims, views, exact, ikey, ival, ranges_init, tiles);
 }
 
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
-                 uint32_t* ikey, uint32_t* ival, hipStream_t s) {
-  emit_keys(n_dev, n_max, toff, total, cap, rec_sorted, ids, n_prims, views, exact, ikey, ival, s);
+                 uint32_t* ikey, uint32_t* ival, uint2* ranges_init, uint32_t tiles, hipStream_t s) {
+  emit_keys(n_dev, n_max, toff, total, cap, rec_sorted, ids, n_prims, views, exact, ikey, ival, ranges_init, tiles,
+            s);
 }
 
 void launch_emit(const uint32_t* n_dev, uint32_t n_max, const uint32_t* toff, const uint32_t* total, uint32_t cap,
                  const Record* rec_sorted, const uint32_t* ids, int n_prims, const ViewDev* views, bool exact,
-                 uint16_t* ikey, uint32_t* ival, hipStream_t s) {
-  emit_keys(n_dev, n_max, toff, total, cap, rec_sorted, ids, n_prims, views, exact, ikey, ival, s);
+                 uint16_t* ikey, uint32_t* ival, uint2* ranges_init, uint32_t tiles, hipStream_t s) {
+  emit_keys(n_dev, n_max, toff, total, cap, rec_sorted, ids, n_prims, views, exact, ikey, ival, ranges_init, tiles,
+            s);
 }
 
 void launch_ranges_init(uint2* ranges, uint32_t tiles, hipStream_t s) {

@@ -34,22 +34,22 @@ __global__ void k_zero_counted(float4* __restrict__ p, const uint32_t* __restric
 }
 
 // An instance total over the arena capacity raises the sticky overflow flag
-// and empties the batch, so every later stage sees zero instances.
+// and empties the batch, so every later stage sees zero instances. With
+// a_tot, a sync-free round's active records and (checked) instances are then
+// added to the render's totals.
 __global__ void k_cap_check(const unsigned long long* __restrict__ inst64, uint32_t* __restrict__ n_inst,
-                            uint32_t* __restrict__ overflow, unsigned long long cap) {
+                            uint32_t* __restrict__ overflow, unsigned long long cap, const uint32_t* __restrict__ a,
+                            uint32_t* __restrict__ a_tot, unsigned long long* __restrict__ i_tot) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t ni = *n_inst;
   if (*inst64 > cap) {
     *overflow = 1u;
-    *n_inst = 0u;
+    *n_inst = ni = 0u;
   }
-}
-
-// A sync-free round's active records and instances added to the render's totals.
-__global__ void k_add_totals(const uint32_t* __restrict__ a, const uint32_t* __restrict__ i,
-                             uint32_t* __restrict__ a_tot, unsigned long long* __restrict__ i_tot) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  *a_tot += *a;
-  *i_tot += *i;
+  if (a_tot) {
+    *a_tot += *a;
+    *i_tot += ni;
+  }
 }
 
 __global__ void k_copy_pairs(const uint32_t* __restrict__ ka, const uint32_t* __restrict__ va,
@@ -91,13 +91,10 @@ void launch_zero_counted(float* p, const uint32_t* n_dev, uint32_t floats_per_it
                      reinterpret_cast<float4*>(p), n_dev, per, max_items);
 }
 
-void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s) {
+void launch_cap_check(const uint32_t* inst64, uint32_t* n_inst, uint32_t* overflow, uint64_t cap, hipStream_t s,
+                      const uint32_t* a, uint32_t* a_tot, uint32_t* i_tot64) {
   hipLaunchKernelGGL(k_cap_check, dim3(1), dim3(64), 0, s, reinterpret_cast<const unsigned long long*>(inst64),
-                     n_inst, overflow, (unsigned long long)cap);
-}
-
-void launch_add_totals(const uint32_t* a, const uint32_t* i, uint32_t* a_tot, uint32_t* i_tot64, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_totals, dim3(1), dim3(64), 0, s, a, i, a_tot,
+                     n_inst, overflow, (unsigned long long)cap, a, a_tot,
                      reinterpret_cast<unsigned long long*>(i_tot64));
 }
 
