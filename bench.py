@@ -325,6 +325,14 @@ def main():
         r.image_loss(g4d.G4D_LOSS_L1, rgb_b, target, scale, loss, dl)
         r.backward(dl, out=grads)
 
+    # the same training step with the loss folded into the backward
+    # (g4d_render_backward_loss: the values of image_loss + render_backward
+    # without the gradient image), reported beside the headline step
+    def step_fused():
+        r.render(cams, times, depth=False, alpha=False, out=(rgb_b, None, None))
+        loss.zero_()
+        r.backward_loss(g4d.G4D_LOSS_L1, rgb_b, target, scale, loss, out=grads)
+
     def step_per_view():
         for v in range(V):
             rgb, _, _ = r.render([cams[v]], [times[v]], depth=False, alpha=False)
@@ -382,6 +390,23 @@ def main():
     finally:
         r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
     best = min(sec, graph_sec) if graph_sec else sec
+
+    fused_sec = timed(step_fused, args.steps, args.warmup)
+    fused_graph_sec = None
+    try:
+        r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 1)
+        step_fused()
+        torch.cuda.synchronize()
+        graph_f = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph_f):
+            step_fused()
+        fused_graph_sec = timed(graph_f.replay, args.steps, args.warmup)
+        r.stats()
+    except Exception as e:
+        log(f"[bench] fused-loss graph replay unavailable: {e}")
+    finally:
+        r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
+    log(f"[bench] fused-loss step {fused_sec * 1e3:.3f} ms, graph {fused_graph_sec and fused_graph_sec * 1e3}")
 
     # the fused Adam step over every parameter group (outside the headline step)
     m_buf = torch.zeros(sc.n * (17 + 3 * sc.coeffs.shape[1]), device=dev)
@@ -482,6 +507,9 @@ def main():
         "batched_step_mode": "graph replay" if best != sec else "eager",
         "eager_ms_per_step": sec * 1e3,
         "graph_ms_per_step": graph_sec * 1e3 if graph_sec else None,
+        "fused_loss_step": {"eager_ms": fused_sec * 1e3,
+                            "graph_ms": fused_graph_sec * 1e3 if fused_graph_sec else None,
+                            "entry": "g4d_render_backward_loss"},
         "forward_mpix_per_s": P_total / fwd_b / 1e6,
         **extra,
         "stage_ms_per_step": {k: ms / args.steps for k, (ms, n) in stages.items()},

@@ -182,6 +182,21 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const float* dL_drgb, const float* 
                                float* g_q_left, float* g_q_right, float* g_opacity_logit, float* g_coeffs,
                                int32_t flags);
 
+/* The image loss and the gradient of the last render in one call: the same
+ * as g4d_image_loss(kind, 3 * (render's pixels), img, target, scale,
+ * loss_out, grad) followed by g4d_render_backward(grad, dL_ddepth, dL_dalpha,
+ * ...), without the gradient image: the backward rasteriser reads img (the
+ * render's rgb output, same layout) and target per pixel and forms dL/drgb
+ * itself, identically. The loss is summed per tile, then per round in a fixed
+ * order, and ADDED to the device float loss_out (clear it first); it can
+ * differ from g4d_image_loss's in the last bits (another summation order).
+ * Gradients, flags and errors as g4d_render_backward; kind, scale as
+ * g4d_image_loss. */
+g4d_status g4d_render_backward_loss(g4d_ctx* ctx, int32_t kind, const float* img, const float* target,
+                                    float scale, float* loss_out, const float* dL_ddepth, const float* dL_dalpha,
+                                    float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
+                                    float* g_opacity_logit, float* g_coeffs, int32_t flags);
+
 /* Densification statistics (Sec. 3.3, "Densification in spacetime"): every
  * later render_backward adds, for each primitive and each view of the render
  * in which it blended at least one pixel (a fragment with alpha >= 1/255

@@ -76,7 +76,7 @@ struct g4d_ctx {
 
   DevBuf views_d, act, pos, dkey, rec, slot, ckey, cval, ckey2, cval2, rec_sorted, tcount, toff;
   DevBuf ikey, ival, ikey2, ival2, ranges, pix_t, pix_last, grad2d, scan_scratch, radix_scratch, counters;
-  DevBuf bwd_scratch, okey, oval, okey2, oval2, cdir, pany, plist;
+  DevBuf bwd_scratch, okey, oval, okey2, oval2, cdir, pany, plist, loss_part;
   uint32_t* counters_h = nullptr;  // pinned
 
   // stage timing (HIP events on the context's stream)
@@ -701,7 +701,7 @@ g4d_status g4d_destroy(g4d_ctx* c) {
                     &c->cval2, &c->rec_sorted, &c->tcount, &c->toff, &c->ikey, &c->ival, &c->ikey2, &c->ival2,
                     &c->ranges, &c->pix_t, &c->pix_last, &c->grad2d, &c->scan_scratch, &c->radix_scratch,
                     &c->counters, &c->bwd_scratch, &c->okey, &c->oval, &c->okey2, &c->oval2, &c->cdir,
-                    &c->pany, &c->plist};
+                    &c->pany, &c->plist, &c->loss_part};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->counters_h) (void)hipHostFree(c->counters_h);
@@ -974,13 +974,24 @@ static g4d_status render_impl(g4d_ctx* c, int32_t n_views, const g4d_camera* cam
   return G4D_OK;
 }
 
-g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL_ddepth, const float* dL_dalpha,
-                               float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
-                               float* g_opacity_logit, float* g_coeffs, int32_t flags) {
+namespace {
+
+// The image loss folded into a backward (g4d_render_backward_loss); kind 0:
+// the rgb input is dL/drgb.
+struct LossSpec {
+  int kind = 0;
+  const float* target = nullptr;
+  float scale = 0.f;
+  float* loss_out = nullptr;
+};
+
+g4d_status backward_impl(g4d_ctx* c, const LossSpec& ls, const float* rgb_in, const float* dL_ddepth,
+                         const float* dL_dalpha, float* g_means4, float* g_log_scales4, float* g_q_left,
+                         float* g_q_right, float* g_opacity_logit, float* g_coeffs, int32_t flags) {
   if (!c) return G4D_EINVAL;
   if (c->hip_failed) return fail(c, G4D_EHIP, "context has a failed HIP call; destroy it");
   if (!c->have_render) return fail(c, G4D_ESTATE, "no render since the last set_primitives");
-  if (!dL_drgb) return fail(c, G4D_EINVAL, "dL_drgb is required");
+  if (!rgb_in) return fail(c, G4D_EINVAL, ls.kind ? "img is required" : "dL_drgb is required");
   if (flags & ~G4D_GRAD_ACCUMULATE) return fail(c, G4D_EINVAL, "unknown flags");
   if (c->n > 0) {
     if (!g_means4 || !g_log_scales4 || !g_q_left || !g_q_right || !g_opacity_logit || !g_coeffs)
@@ -1022,15 +1033,25 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     launch_zero_counted(P<float>(c->grad2d), cnt + kCntA, 2 * kGrad2dStride, a_max, s);
     stage_end(c, G4D_STAGE_PREPROCESS_BWD);
     if ((st = join_side(c))) return st;  // the records' colours of a round binned again
+    LossArgs la{ls.kind, ls.target, ls.scale, nullptr};
+    if (ls.kind) {
+      if ((st = ensure(c, c->loss_part, sizeof(float) * (size_t)r.tiles))) return st;
+      la.part = P<float>(c->loss_part);
+    }
     stage_begin(c);
     launch_raster_backward(r.tiles, c->heavy_first ? P<uint32_t>(c->oval) : nullptr,
                            c->persistent_blocks ? cnt + kCntQueue : nullptr, c->persistent_blocks, nv,
                            P<ViewDev>(c->views_d),
                            P<uint2>(c->ranges), P<uint32_t>(c->ival),
-                           P<Record>(c->rec_sorted), c->opts.bg, dL_drgb, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
+                           P<Record>(c->rec_sorted), c->opts.bg, rgb_in, dL_ddepth, dL_dalpha, P<float>(c->pix_t),
                            P<uint32_t>(c->pix_last), P<double>(c->grad2d), c->densify.blend_count != nullptr,
-                           c->ellipse_cull, s);
+                           c->ellipse_cull, la, s);
     stage_end(c, G4D_STAGE_RASTER_BWD);
+    if (ls.kind) {
+      stage_begin(c);
+      launch_loss_partials(la.part, (uint32_t)r.tiles, ls.scale, ls.loss_out, s);
+      stage_end(c, G4D_STAGE_LOSS);
+    }
     RenderParams p = make_params(c, nv);
     stage_begin(c);
     launch_preprocess_backward(p, P<int32_t>(c->slot), P<double>(c->grad2d), cnt + kCntA, a_max, P<uint32_t>(c->cval),
@@ -1041,6 +1062,32 @@ g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL
     accumulate = true;
   }
   return G4D_OK;
+}
+
+}  // namespace
+
+g4d_status g4d_render_backward(g4d_ctx* c, const float* dL_drgb, const float* dL_ddepth, const float* dL_dalpha,
+                               float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
+                               float* g_opacity_logit, float* g_coeffs, int32_t flags) {
+  return backward_impl(c, LossSpec{}, dL_drgb, dL_ddepth, dL_dalpha, g_means4, g_log_scales4, g_q_left, g_q_right,
+                       g_opacity_logit, g_coeffs, flags);
+}
+
+g4d_status g4d_render_backward_loss(g4d_ctx* c, int32_t kind, const float* img, const float* target, float scale,
+                                    float* loss_out, const float* dL_ddepth, const float* dL_dalpha,
+                                    float* g_means4, float* g_log_scales4, float* g_q_left, float* g_q_right,
+                                    float* g_opacity_logit, float* g_coeffs, int32_t flags) {
+  if (!c) return G4D_EINVAL;
+  if (kind != G4D_LOSS_L1 && kind != G4D_LOSS_L2) return fail(c, G4D_EINVAL, "unknown loss kind");
+  if (!std::isfinite(scale)) return fail(c, G4D_EINVAL, "non-finite scale");
+  if (!img || !target || !loss_out) return fail(c, G4D_EINVAL, "null pointer");
+  LossSpec ls;
+  ls.kind = kind;
+  ls.target = target;
+  ls.scale = scale;
+  ls.loss_out = loss_out;
+  return backward_impl(c, ls, img, dL_ddepth, dL_dalpha, g_means4, g_log_scales4, g_q_left, g_q_right,
+                       g_opacity_logit, g_coeffs, flags);
 }
 
 g4d_status g4d_set_densify_stats(g4d_ctx* c, float* uv_grad_norm_sum, float* t_grad_abs_sum,

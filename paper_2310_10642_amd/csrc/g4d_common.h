@@ -173,11 +173,23 @@ void launch_raster_forward(int total_tiles, const uint32_t* order, uint32_t* que
                            int n_views, const ViewDev* views, const uint2* ranges, const uint32_t* ival,
                            const Record* rec_sorted, const float* bg, int channels, bool cull, float* out_rgb,
                            float* out_depth, float* out_alpha, float* pix_t, uint32_t* pix_last, hipStream_t s);
+// The image loss folded into the backward rasteriser: with kind (1 = L1,
+// 2 = L2) the rgb input is the rendered image, dL/dC is formed from it and
+// target as launch_image_loss forms it, and part[tile] (the launch's tile id)
+// receives the tile's unscaled loss sum. kind 0: the rgb input is dL/dC.
+struct LossArgs {
+  int kind;
+  const float* target;
+  float scale;
+  float* part;
+};
 void launch_raster_backward(int total_tiles, const uint32_t* order, uint32_t* queue, int blocks, int n_views,
                             const ViewDev* views, const uint2* ranges, const uint32_t* ival,
                             const Record* rec_sorted, const float* bg, const float* dl_rgb, const float* dl_depth,
                             const float* dl_alpha, const float* pix_t, const uint32_t* pix_last, double* grad2d,
-                            bool mark_blended, bool cull, hipStream_t s);
+                            bool mark_blended, bool cull, const LossArgs& loss, hipStream_t s);
+// *loss += scale * sum(part[0..n)) (one workgroup, fixed order).
+void launch_loss_partials(const float* part, uint32_t n, float scale, float* loss, hipStream_t s);
 void launch_sum_u32(const uint32_t* in, uint64_t n, unsigned long long* out, hipStream_t s);
 void launch_range_max(const uint2* ranges, uint32_t tiles, uint32_t* out, hipStream_t s);
 // Tile ids by decreasing list length (stable within ~4.4 % length bins) into

@@ -1,17 +1,10 @@
 // Image loss and dL/dI for the training step (L1 or L2 against a target).
-#include "g4d_common.h"
+#include "shade.h"
 
 namespace g4d {
 namespace {
 
-__device__ __forceinline__ float loss_term(int kind, float d, float scale, float& g) {
-  if (kind == 1) {
-    g = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-    return fabsf(d);
-  }
-  g = 2.f * scale * d;
-  return d * d;
-}
+using shade::loss_term;
 
 // Grid-stride over float4 groups; one atomic per block for the loss.
 __global__ void __launch_bounds__(256) k_image_loss(int kind, uint64_t n, const float* __restrict__ img,
@@ -49,7 +42,44 @@ __global__ void __launch_bounds__(256) k_image_loss(int kind, uint64_t n, const 
   if (threadIdx.x == 0) atomicAdd(loss, scale * (s_part[0] + s_part[1] + s_part[2] + s_part[3]));
 }
 
+// One workgroup of 1024 threads: *loss += scale * (sum of the n per-tile
+// partial sums), in a fixed order. Each thread keeps four 16-byte loads in
+// flight per step (a single workgroup is latency-bound, not bandwidth-bound).
+__global__ void __launch_bounds__(1024) k_loss_partials(const float* __restrict__ part, uint32_t n, float scale,
+                                                         float* __restrict__ loss) {
+  __shared__ float s_part[16];
+  float acc = 0.f;
+  const uint32_t n4 = n / 4;  // part is 256-byte aligned
+  const float4* p4 = reinterpret_cast<const float4*>(part);
+  for (uint32_t i0 = threadIdx.x; i0 < n4; i0 += 4 * 1024) {
+    float4 q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t i = i0 + (uint32_t)j * 1024;
+      q[j] = i < n4 ? p4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc += (q[j].x + q[j].y) + (q[j].z + q[j].w);
+  }
+  if (threadIdx.x < n - 4 * n4) acc += part[4 * n4 + threadIdx.x];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += s_part[w];
+    *loss += scale * t;
+  }
+}
+
 }  // namespace
+
+void launch_loss_partials(const float* part, uint32_t n, float scale, float* loss, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_loss_partials, dim3(1), dim3(1024), 0, s, part, n, scale, loss);
+}
 
 void launch_image_loss(int kind, uint64_t n, const float* img, const float* tgt, float scale, float* loss,
                        float* grad, hipStream_t s) {

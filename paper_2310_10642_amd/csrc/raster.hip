@@ -395,7 +395,8 @@ __global__ void __launch_bounds__(256, 5) k_raster_backward(
     const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* queue, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,
     const Record* __restrict__ recs, float bg0, float bg1, float bg2, const float* __restrict__ dl_rgb,
     const float* __restrict__ dl_depth, const float* __restrict__ dl_alpha, const float* __restrict__ pix_t,
-    const uint32_t* __restrict__ pix_last, double* __restrict__ grad2d, bool mark_blended, bool cull) {
+    const uint32_t* __restrict__ pix_last, double* __restrict__ grad2d, bool mark_blended, bool cull,
+    LossArgs loss) {
   __shared__ float4 s_a2[2][kBwdBatch], s_b2[2][kBwdBatch], s_c2[2][kBwdBatch];
   __shared__ uint32_t s_d2[2][kBwdBatch];
   __shared__ uint32_t s_qm2[2][kBwdBatch];
@@ -406,6 +407,7 @@ __global__ void __launch_bounds__(256, 5) k_raster_backward(
   __shared__ float4 s_pix[256];
   __shared__ uint32_t s_max;
   __shared__ uint32_t s_item;
+  __shared__ float s_loss[4];
 
   int tile;
   for (bool first = true; next_item(order, n_items, queue, &s_item, first, tile); first = false) {
@@ -425,28 +427,45 @@ __global__ void __launch_bounds__(256, 5) k_raster_backward(
   const int count = (int)(rg.y - rg.x);
 
   if (threadIdx.x == 0) s_max = 0u;
-  float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
+  float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f, lsum = 0.f;
   uint32_t last = 0;
   if (inside) {
     const long long hw = (long long)vw.width * vw.height;
     const long long pl = (long long)py * vw.width + px;
     const long long pix = vw.pix_base + pl;
     const float* g = dl_rgb + 3 * vw.pix_base + pl;
-    gC0 = g[0];
-    gC1 = g[hw];
-    gC2 = g[2 * hw];
+    if (loss.kind) {
+      // with a folded loss the rgb input is the rendered image: the loss
+      // term and dL/dC of each channel against the target, formed as the
+      // image-loss kernel forms them
+      const float* tg = loss.target + 3 * vw.pix_base + pl;
+      lsum = shade::loss_term(loss.kind, g[0] - tg[0], loss.scale, gC0) +
+             shade::loss_term(loss.kind, g[hw] - tg[hw], loss.scale, gC1) +
+             shade::loss_term(loss.kind, g[2 * hw] - tg[2 * hw], loss.scale, gC2);
+    } else {
+      gC0 = g[0];
+      gC1 = g[hw];
+      gC2 = g[2 * hw];
+    }
     if (HAS_D) gD = dl_depth[pix];
     if (HAS_A) gA = dl_alpha[pix];
     T = pix_t[pix];
     last = pix_last[pix];
   }
   s_pix[p_self] = make_float4(gC0, gC1, gC2, gD);
+  if (loss.kind) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) s_loss[wave] = lsum;
+  }
   const uint32_t wave_last = wave_max_u32(last);
   // batches ending at or before every lane's last contributor need no
   // per-entry list-position test
   const uint32_t wave_first_last = wave_min_u32(last);
   __syncthreads();
   if (lane == 0 && wave_last) atomicMax(&s_max, wave_last);
+  // the tile's loss, summed over its pixels
+  if (loss.kind && threadIdx.x == 0) loss.part[tile] = s_loss[0] + s_loss[1] + s_loss[2] + s_loss[3];
   // Only the dot product of this pixel's output gradient with the colour,
   // depth and alpha of everything behind the current primitive (normalised by
   // the transmittance after it) enters dL/da; it starts at the background.
@@ -676,11 +695,11 @@ void launch_bwd(int total_tiles, const uint32_t* order, uint32_t* queue, int blo
                 const ViewDev* views, const uint2* ranges, const uint32_t* ival, const Record* rec_sorted,
                 const float* bg, const float* dl_rgb, const float* dl_depth, const float* dl_alpha,
                 const float* pix_t, const uint32_t* pix_last, double* grad2d, bool mark_blended, bool cull,
-                hipStream_t s) {
+                const LossArgs& loss, hipStream_t s) {
   const unsigned grid = item_grid(k_raster_backward<HD, HA>, total_tiles, queue, blocks, s);
   hipLaunchKernelGGL((k_raster_backward<HD, HA>), dim3(grid), dim3(256), 0, s, order, (uint32_t)total_tiles, queue,
                      n_views, views, ranges, ival, rec_sorted, bg[0], bg[1], bg[2], dl_rgb, dl_depth, dl_alpha, pix_t,
-                     pix_last, grad2d, mark_blended, cull);
+                     pix_last, grad2d, mark_blended, cull, loss);
 }
 }  // namespace
 
@@ -688,11 +707,11 @@ void launch_raster_backward(int total_tiles, const uint32_t* order, uint32_t* qu
                             const ViewDev* views, const uint2* ranges, const uint32_t* ival,
                             const Record* rec_sorted, const float* bg, const float* dl_rgb, const float* dl_depth,
                             const float* dl_alpha, const float* pix_t, const uint32_t* pix_last, double* grad2d,
-                            bool mark_blended, bool cull, hipStream_t s) {
+                            bool mark_blended, bool cull, const LossArgs& loss, hipStream_t s) {
   if (total_tiles == 0) return;
 #define G4D_BWD(HD, HA)                                                                                          \
   launch_bwd<HD, HA>(total_tiles, order, queue, blocks, n_views, views, ranges, ival, rec_sorted, bg, dl_rgb,      \
-                     dl_depth, dl_alpha, pix_t, pix_last, grad2d, mark_blended, cull, s)
+                     dl_depth, dl_alpha, pix_t, pix_last, grad2d, mark_blended, cull, loss, s)
   if (dl_depth && dl_alpha) G4D_BWD(true, true);
   else if (dl_depth) G4D_BWD(true, false);
   else if (dl_alpha) G4D_BWD(false, true);

@@ -390,5 +390,17 @@ __device__ __forceinline__ void own_basis(const float* Y, int sub, float* y) {
   for (int j = 0; j < 16; ++j) y[j % kBasisPerLane] = (sub == j / kBasisPerLane) ? Y[j] : y[j % kBasisPerLane];
 }
 
+// One value's image-loss term and its gradient (the paper supervises with a
+// rendering loss only, Sec. 3.3): kind 1 is L1, |d| with gradient
+// scale * sign(d); kind 2 is L2, d^2 with gradient 2 scale d; d = img - target.
+__device__ __forceinline__ float loss_term(int kind, float d, float scale, float& g) {
+  if (kind == 1) {
+    g = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+    return fabsf(d);
+  }
+  g = 2.f * scale * d;
+  return d * d;
+}
+
 }  // namespace shade
 }  // namespace g4d

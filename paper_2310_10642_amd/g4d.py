@@ -27,7 +27,7 @@ STAGES = ["preprocess", "binning", "raster_fwd", "raster_bwd", "preprocess_bwd",
 DBG = dict(records=1, ids=2, tile_keys=3, tile_vals=4, ranges=5, pix_t=6, pix_last=7, grad2d=8, tile_order=9)
 
 EXPORTED = ["g4d_default_options", "g4d_create", "g4d_destroy", "g4d_set_stream", "g4d_set_primitives",
-            "g4d_render", "g4d_render_noalloc", "g4d_render_flow", "g4d_render_backward", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
+            "g4d_render", "g4d_render_noalloc", "g4d_render_flow", "g4d_render_backward", "g4d_render_backward_loss", "g4d_image_loss", "g4d_get_stats", "g4d_set_tuning",
             "g4d_get_tuning", "g4d_set_densify_stats", "g4d_adam_step", "g4d_split_sample", "g4d_stage_times", "g4d_last_error", "g4d_debug_size", "g4d_debug_copy"]
 
 
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.g4d_render_flow.argtypes = [vp, i32, ctypes.POINTER(G4DCamera), ctypes.POINTER(ctypes.c_float), ctypes.c_float,
                                     fp]
     lib.g4d_render_backward.argtypes = [vp, fp, fp, fp, fp, fp, fp, fp, fp, fp, i32]
+    lib.g4d_render_backward_loss.argtypes = [vp, i32, fp, fp, ctypes.c_float, fp, fp, fp, fp, fp, fp, fp, fp, fp,
+                                             i32]
     lib.g4d_image_loss.argtypes = [vp, i32, i64, fp, fp, ctypes.c_float, fp, fp]
     lib.g4d_get_stats.argtypes = [vp, ctypes.POINTER(G4DStats), ctypes.POINTER(ctypes.c_int64)]
     lib.g4d_set_tuning.argtypes = [vp, i32, i32]
@@ -287,6 +289,23 @@ class Renderer:
                 None if dl_alpha is None else dl_alpha.contiguous()]
         flags = G4D_GRAD_ACCUMULATE if accumulate else 0
         self._check(self.lib.g4d_render_backward(self.ctx, *[_ptr(a) for a in args], *[_ptr(t) for t in g], flags))
+        self._keep = args
+        return g
+
+    def backward_loss(self, kind: int, img: torch.Tensor, target: torch.Tensor, scale: float,
+                      loss_out: torch.Tensor, dl_depth=None, dl_alpha=None,
+                      out: Optional[List[torch.Tensor]] = None, accumulate: bool = False) -> List[torch.Tensor]:
+        """image_loss(kind, img, target, scale, loss_out) and the backward of
+        the last render from its dL/dimg in one library call (img: the
+        render's rgb output); loss_out (1 float) is added to."""
+        self._stream()
+        g = out if out is not None else self.grad_buffers(img.device)
+        args = [img.contiguous(), target.contiguous(), None if dl_depth is None else dl_depth.contiguous(),
+                None if dl_alpha is None else dl_alpha.contiguous()]
+        flags = G4D_GRAD_ACCUMULATE if accumulate else 0
+        self._check(self.lib.g4d_render_backward_loss(self.ctx, kind, _ptr(args[0]), _ptr(args[1]), float(scale),
+                                                      _ptr(loss_out), _ptr(args[2]), _ptr(args[3]),
+                                                      *[_ptr(t) for t in g], flags))
         self._keep = args
         return g
 

@@ -1064,6 +1064,50 @@ def test_image_loss_kernel():
         assert np.allclose(_np(grad), 0.5 * ref_g, rtol=1e-6, atol=1e-7)
 
 
+def test_backward_loss_equals_loss_then_backward():
+    """The image loss folded into the backward (g4d_render_backward_loss) gives
+    what g4d_image_loss followed by g4d_render_backward gives: gradients up to
+    the order of the FP64 atomic sums, and the loss within float32 summation
+    error of its FP64 value; over one round and over several rounds, L1 and
+    L2, with and without a depth/alpha gradient."""
+    _say("[backward with the loss folded in, 300k x 8 views]")
+    from paper_2310_10642_amd import g4d
+    wl = scenegen.bench_workload(8)
+    r, _ = PT.gpu_setup(wl.scene)
+    times = [float(x) for x in wl.times]
+    n = wl.scene.means4.shape[0]
+    target_np = np.concatenate([t.reshape(-1) for t in wl.targets]).astype(np.float32)
+    target = torch.from_numpy(target_np).cuda()
+    scale = 1.0 / target.numel()
+    rng = np.random.default_rng(12)
+    for rounds, kind, with_alpha in [(False, g4d.G4D_LOSS_L1, False), (False, g4d.G4D_LOSS_L2, True),
+                                     (True, g4d.G4D_LOSS_L1, False)]:
+        if rounds:
+            r.set_tuning(g4d.G4D_TUNE_ROUND_PAIRS, 3 * n)
+        rgb, _, alpha = r.render(wl.cameras, times)
+        assert (r.stats()["rounds"] >= 3) == rounds
+        dla = (torch.from_numpy(rng.uniform(-1, 1, alpha.numel()).astype(np.float32)).cuda()
+               if with_alpha else None)
+        loss_a = torch.zeros(1, device="cuda")
+        dl = torch.empty_like(rgb)
+        r.image_loss(kind, rgb, target, scale, loss_a, dl)
+        ga = [x.clone() for x in r.backward(dl, None, dla)]
+        loss_b = torch.zeros(1, device="cuda")
+        gb = r.backward_loss(kind, rgb, target, scale, loss_b, None, dla)
+        torch.cuda.synchronize()
+        _close_grads(gb, ga, rel=1e-6)
+        d = _np(rgb).astype(np.float64) - target_np
+        ref = scale * (np.abs(d).sum() if kind == g4d.G4D_LOSS_L1 else (d * d).sum())
+        _say(f"  rounds {r.stats()['rounds']} kind {kind}: loss {float(loss_b):.7g} "
+             f"(image_loss {float(loss_a):.7g}, FP64 {ref:.7g})")
+        for lv in (float(loss_a), float(loss_b)):
+            assert abs(lv - ref) <= 1e-5 * ref
+    r.set_tuning(g4d.G4D_TUNE_ROUND_PAIRS, 1 << 28)
+    with pytest.raises(g4d.G4DError) as ei:
+        r.backward_loss(7, rgb, target, scale, loss_b)
+    assert ei.value.status == g4d.G4D_EINVAL
+
+
 def test_stage_timing_and_stats():
     _say("[stage timing]")
     sc = _big_splat_scene(8, 2000)
