@@ -343,7 +343,8 @@ enum {
   G4D_STAGE_RASTER_BWD = 3,   /* the backward rasteriser alone */
   G4D_STAGE_PREPROCESS_BWD = 4, /* zeroing the gradient lines, then the per-record and
                                  * per-primitive backward (two timed windows per round) */
-  G4D_STAGE_LOSS = 5,
+  G4D_STAGE_LOSS = 5,          /* g4d_image_loss; in g4d_render_backward_loss the per-tile
+                                 * loss sums (the per-pixel terms run in the backward rasteriser) */
   G4D_STAGE_COLOUR = 6,       /* the 4DSH colour pass, timed on its own (second) stream */
   G4D_NUM_STAGES = 7
 };
