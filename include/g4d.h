@@ -257,7 +257,8 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, int64_t* active_per_view)
 
 /* Tuning knobs (key, value); unknown keys give G4D_EINVAL.
  *   G4D_TUNE_SORT_BLOCKS   max workgroups of each radix-sort pass (>= 1;
- *                          default 1280)
+ *                          default 1280; a round of more than 2^26 tile
+ *                          instances takes at most 768 for its tile sort)
  *   G4D_TUNE_STAGE_TIMING  1: bracket every stage with HIP events on the
  *                          context's stream (resets the totals); 0: off
  *   G4D_TUNE_ROUND_PAIRS     max (view, primitive) pairs per round (>= 1;
