@@ -389,7 +389,8 @@ __device__ __forceinline__ void phase2_line(G (&q)[10], bool live, int j2, int c
 }
 
 // HAS_D / HAS_A: whether dL/d(depth) and dL/d(alpha) are given (otherwise
-// their terms are compiled out).
+// their terms are compiled out). With loss.kind set, dl_rgb is the rendered
+// image and the image loss is folded in (LossArgs).
 template <bool HAS_D, bool HAS_A>
 __global__ void __launch_bounds__(256, 5) k_raster_backward(
     const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* queue, int n_views, const ViewDev* __restrict__ views, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ival,

@@ -378,7 +378,8 @@ __device__ __forceinline__ void scatter_begin(ScatterShared<K>& sh, const uint32
 // contiguous. Pairs go to run[d] + their rank among the block's pairs of
 // digit d so far (bounded by n_out); with ranges (the last pass over the
 // whole key) the keys are not written: each key's first and last position
-// bound its range instead.
+// bound its range instead (a key >= n_ranges, which a consistent sort never
+// produces, is skipped).
 // FULL: the tile holds kTileElems valid pairs (the validity tests compile out).
 template <bool FULL, typename K>
 __device__ __forceinline__ void scatter_tile(ScatterShared<K>& sh, uint32_t (&k)[kItems],
