@@ -732,7 +732,8 @@ def test_sync_free_and_graph_replay():
     """The sync-free mode reproduces the synchronous training step (images bit
     for bit, loss and gradients up to summation order); a HIP graph captured
     around render + loss + backward replays it, three times, with eager work
-    and synchronisation between the replays."""
+    and synchronisation between the replays; the same with the loss folded
+    into the backward."""
     _say("[sync-free and graph replay, 300k x 2 views]")
     from paper_2310_10642_amd import g4d
     wl = scenegen.bench_workload(2)
@@ -787,6 +788,41 @@ def test_sync_free_and_graph_replay():
         assert abs(float(outs[3]) - float(ref[3])) <= loss_tol, rep
         _close_grads(g_gr, g_ref)
         _say(f"  replay {rep} ok")
+    del graph
+
+    # the same step with the loss folded into the backward, captured and
+    # replayed: its loss sums have a fixed order, so every replay gives the
+    # eager loss bit for bit
+    def step_folded(grads, bufs):
+        rgb, dep, alp, loss, _ = bufs
+        r.render(wl.cameras, times, out=(rgb, dep, alp))
+        loss.zero_()
+        r.backward_loss(g4d.G4D_LOSS_L1, rgb, tgt, scale, loss, out=grads)
+        return rgb, dep, alp, loss
+
+    g_fe = r.grad_buffers()
+    fe = step_folded(g_fe, buffers())
+    torch.cuda.synchronize()
+    assert abs(float(fe[3]) - float(ref[3])) <= loss_tol
+    _close_grads(g_fe, g_ref)
+    g_fg = r.grad_buffers()
+    bufs = buffers()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step_folded(g_fg, bufs)
+    for rep in range(3):
+        for t in (*outs, *g_fg):
+            t.fill_(float("nan"))
+        x = torch.randn(512, 512, device="cuda")
+        _ = float((x @ x).sum())
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(ref[:3], outs[:3]):
+            assert torch.equal(a, b), rep
+        assert torch.equal(outs[3], fe[3]), rep
+        _close_grads(g_fg, g_ref)
+        _say(f"  folded-loss replay {rep} ok")
     del graph
     r.set_tuning(g4d.G4D_TUNE_SYNC_FREE, 0)
 
