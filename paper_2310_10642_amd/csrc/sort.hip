@@ -12,7 +12,6 @@
 //   3. stable radix sort of the instances by global tile id.
 // Every pass is stable, so the result equals a stable sort by (tile, depth)
 // of the instances emitted in (view, index) order.
-#include <algorithm>
 #include <utility>
 #include "g4d_common.h"
 
@@ -306,41 +305,33 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const K* __restrict__ k
   counts[(size_t)d * gridDim.x + sort_block()] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
 }
 
-// Exclusive scan across a block of any multiple of 64 threads (<= 1024).
-__device__ __forceinline__ uint32_t block_exclusive_scan_any(uint32_t v, uint32_t* s_wave, uint32_t& total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) s_wave[wave] = x;
-  __syncthreads();
-  uint32_t base = 0;
-  total = 0;
-  for (int w = 0; w < nw; ++w) {
-    const uint32_t c = s_wave[w];
-    base += (w < wave) ? c : 0u;
-    total += c;
-  }
-  __syncthreads();
-  return base + x - v;
-}
-
-// One block per digit: exclusive scan of counts[digit][0..grid) in place and
-// the digit's total into digit_tot[digit].
-__global__ void __launch_bounds__(1024) k_rs_rowscan(uint32_t* __restrict__ counts, int grid,
-                                                     uint32_t* __restrict__ digit_tot) {
-  __shared__ uint32_t s_wave[16];
+// One 256-thread block per digit: exclusive scan of counts[digit][0..grid) in
+// place and the digit's total into digit_tot[digit]. Each thread takes eight
+// consecutive counts of a 2048-count chunk, so a row of up to 2048 blocks'
+// counts is one block-wide scan, and the small workgroup finds a CU beside
+// another stream's work.
+constexpr int kRowScanPer = 8;
+__global__ void __launch_bounds__(kThreads) k_rs_rowscan(uint32_t* __restrict__ counts, int grid,
+                                                         uint32_t* __restrict__ digit_tot) {
+  __shared__ uint32_t s_wave[4];
   uint32_t* row = counts + (size_t)blockIdx.x * grid;
   uint32_t carry = 0;
-  for (int b0 = 0; b0 < grid; b0 += blockDim.x) {
-    const int b = b0 + threadIdx.x;
-    const uint32_t v = b < grid ? row[b] : 0u;
+  for (int c0 = 0; c0 < grid; c0 += kThreads * kRowScanPer) {
+    const int b0 = c0 + (int)threadIdx.x * kRowScanPer;
+    uint32_t v[kRowScanPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kRowScanPer; ++i) {
+      v[i] = b0 + i < grid ? row[b0 + i] : 0u;
+      sum += v[i];
+    }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan_any(v, s_wave, tot);
-    if (b < grid) row[b] = carry + ex;
+    uint32_t ex = carry + block_exclusive_scan(sum, s_wave, tot);  // contains barriers
+#pragma unroll
+    for (int i = 0; i < kRowScanPer; ++i) {
+      if (b0 + i < grid) row[b0 + i] = ex;
+      ex += v[i];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
@@ -839,15 +830,10 @@ std::pair<K*, uint32_t*> radix_passes_run(K* keys, uint32_t* vals, K* keys_alt, 
                                           uint32_t n_ranges) {
   K *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
-  // the row scan's block is as wide as a row of the count matrix (one count
-  // per sort block, at most 1024 threads), so a small grid's scan leaves the
-  // CUs to the other stream's waves
-  const unsigned scan_threads = (unsigned)std::min(1024, std::max(64, (grid + 63) / 64 * 64));
   for (int b = bit0; b < bit1; b += 8) {
     const int bits = (bit1 - b) < 8 ? (bit1 - b) : 8;
     hipLaunchKernelGGL(k_rs_upsweep<K>, dim3(grid), dim3(kThreads), 0, s, kin, n_dev, n_max, b, bits, scratch);
-    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(scan_threads), 0, s, scratch, grid,
-                       scratch + (size_t)256 * grid);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, s, scratch, grid, scratch + (size_t)256 * grid);
     hipLaunchKernelGGL(k_rs_downsweep<K>, dim3(grid), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_max, b,
                        bits, scratch, scratch + (size_t)256 * grid, b + 8 >= bit1 ? last_ranges : nullptr,
                        b + 8 >= bit1 && last_ranges ? n_ranges : 0u);
