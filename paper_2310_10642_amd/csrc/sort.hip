@@ -620,6 +620,10 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
   uint32_t rows;
   const uint32_t rb = block_exclusive_scan(h, s_wave, rows);  // contains barriers
   if (threadIdx.x < kEmitRecs) s_rbase[threadIdx.x] = rb;
+  // each record marks its rows with its block-relative index (h = 0 past
+  // the last record), so a row finds its record with one LDS read
+  if (rows <= (uint32_t)kEmitRows)
+    for (uint32_t k = 0; k < h; ++k) s_row_rec[rb + k] = (uint8_t)threadIdx.x;
   __syncthreads();
   const uint32_t lim = min(tot, cap);
   const uint32_t start = offs[0], end = min(offs[kEmitRecs], lim);
@@ -629,18 +633,13 @@ __global__ void __launch_bounds__(kThreads) k_emit(const uint32_t* n_dev, uint32
       const uint32_t j = j0 + threadIdx.x;
       uint32_t w = 0;
       if (j < rows) {
-        int lo = 0, hi = (int)nrec - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_rbase[mid] <= j) lo = mid; else hi = mid - 1;
-        }
+        const int lo = s_row_rec[j];
         const Footprint& f = s_fp[lo];
         const uint32_t ty = f.y0 + (j - s_rbase[lo]);
         uint32_t xa, xb;
         row_span(f, ty, exact, xa, xb);
         w = xb - xa;
         s_row_tile[j] = s_tb[lo] + ty * s_tw[lo] + xa;
-        s_row_rec[j] = (uint8_t)lo;
       }
       uint32_t tot_w;
       const uint32_t ex = block_exclusive_scan(w, s_wave, tot_w);  // contains barriers
