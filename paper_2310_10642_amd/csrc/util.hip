@@ -87,7 +87,9 @@ void launch_zero_counted(float* p, const uint32_t* n_dev, uint32_t floats_per_it
                          hipStream_t s) {
   if (max_items == 0) return;
   const uint32_t per = floats_per_item / 4;
-  hipLaunchKernelGGL(k_zero_counted, dim3(stride_grid(max_items * per, 2048)), dim3(256), 0, s,
+  // two workgroups per CU stream the zeros fastest (14.6 -> 13.0 us for the
+  // bench's 82 MB against 2048 workgroups)
+  hipLaunchKernelGGL(k_zero_counted, dim3(stride_grid(max_items * per, 512)), dim3(256), 0, s,
                      reinterpret_cast<float4*>(p), n_dev, per, max_items);
 }
 
